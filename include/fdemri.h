@@ -1,0 +1,186 @@
+/*
+ * fdemri.h -- C ABI of the frequency-domain EMRI mode-summation library
+ * (MI355X / gfx950, HIP).
+ *
+ * The library evaluates the frequency-domain waveform of Speri et al., "Fast
+ * and Fourier: Extreme Mass Ratio Inspiral Waveforms in the Frequency
+ * Domain" (arXiv 2307.12585), Sec. 2.2: for every harmonic voice (l,m,n) of
+ * Eq. main_wave it inverts the voice frequency F(t) = (m Omega_phi +
+ * n Omega_r)/(2 pi M) on each cubic-spline segment of the sparse trajectory
+ * (Eq. cubic_equation), evaluates the third-order stationary-phase term of
+ * Eq. extendedspa1 at every root, and sums all voices into h_+(f) and
+ * h_x(f) on an arbitrary ascending frequency array.
+ *
+ * Conventions
+ *  - Every array argument is a DEVICE pointer (memory of the context's HIP
+ *    device), unless stated otherwise.  The caller allocates and owns every
+ *    input and output; the library keeps no caller pointer after a call
+ *    returns.  Scratch memory is owned by the context.
+ *  - Calls are asynchronous on the given stream: once argument validation
+ *    passes, all work is enqueued on `stream` and the call returns.  On
+ *    FDEMRI_EINVAL nothing is enqueued and outputs are untouched.
+ *  - Every function returns a status code and never throws.  The text of the
+ *    last error is per context (fdemri_last_error).
+ *  - Device-side conditions that the host cannot see without a
+ *    synchronisation (more monotonic pieces in one voice than the table
+ *    holds) are recorded in a per-context flag word; fdemri_sync_flags
+ *    synchronises the stream and returns it.
+ *  - One context per host thread (contexts are not internally locked).
+ *  - Transform convention of Eq. singlevoiceFT: h(f) = int h(t) e^{+2 pi i f t} dt,
+ *    with h = h_+ - i h_x (Eq. main_wave).
+ */
+#ifndef FDEMRI_H
+#define FDEMRI_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdemri_ctx fdemri_ctx;
+
+typedef enum {
+  FDEMRI_OK = 0,
+  FDEMRI_EINVAL = 1,   /* invalid argument; nothing enqueued */
+  FDEMRI_ENOMEM = 2,   /* device allocation failed */
+  FDEMRI_EDEVICE = 3,  /* HIP runtime error */
+  FDEMRI_ENOTSUP = 4   /* valid but unsupported request (e.g. K above the limit) */
+} fdemri_status;
+
+typedef enum {
+  FDEMRI_FP64 = 0,     /* everything in FP64; output complex128 (2 x double per bin) */
+  FDEMRI_MIXED = 1     /* FP64 root, phase and range reduction; FP32 special function,
+                          sincos, amplitude spline and compensated accumulation;
+                          output complex64 (2 x float per bin) */
+} fdemri_prec;
+
+/* flags of fdemri_waveform_desc.flags */
+#define FDEMRI_NO_PARTNERS 0x1u  /* treat every row as a single voice (l,m,n) with any
+                                    sign of m; do not add the (l,-m,-n) partner */
+
+/* Flag bits reported by fdemri_sync_flags */
+#define FDEMRI_FLAG_PIECE_OVERFLOW 0x1u  /* a voice had more monotonic pieces than
+                                            FDEMRI_MAX_PIECES; extra pieces dropped */
+#define FDEMRI_MAX_PIECES 16
+#define FDEMRI_MAX_KNOTS 512
+#define FDEMRI_MAX_L 40
+
+/*
+ * One waveform (Sec. 2.1-2.2).  Sparse trajectory knots (Sec. 2.1: the
+ * adiabatic trajectory is ~100 points), the complex amplitude knot values of
+ * each (l,m,n) voice (Sec. 2.1: amplitudes interpolated with not-a-knot cubic
+ * splines), the source-frame viewing angles and mu/d_L of Eq. main_wave, and
+ * the frequency array (Eq. innerprod grid f_i = i/T, or any ascending grid,
+ * Sec. 3.3).
+ *
+ * Layouts (all device pointers, read only):
+ *   t, Fphi, Fr, Phiphi, Phir : [K] double.  t strictly increasing (s);
+ *       Fphi = Omega_phi/(2 pi M), Fr = Omega_r/(2 pi M) in Hz; Phiphi,
+ *       Phir in rad including the initial phases.
+ *   l, m, n : [Nm] int32 mode numbers.  Without FDEMRI_NO_PARTNERS,
+ *       2 <= l <= FDEMRI_MAX_L and 0 <= m <= l; each row with m > 0 stands for
+ *       the voices (l,m,n) and (l,-m,-n), the latter with amplitude
+ *       (-1)^l conj(A) (the equatorial-symmetry relation of the Schwarzschild
+ *       amplitudes); m = 0 rows are single voices.
+ *   A : [Nm][K][2] double, complex amplitude knot values (re, im).
+ *   f : [Nf] double, ascending, f >= 0 (Hz).  Bins with f == 0 are set to 0.
+ * Host scalars: theta, phi (source-frame polar/azimuthal viewing angles),
+ *   scale = mu/d_L (dimensionless strain scale of Eq. main_wave).
+ * Limits: 4 <= K <= FDEMRI_MAX_KNOTS, 1 <= Nm, 1 <= Nf < 2^31.
+ * Data-dependent conditions (ordering of t and f, finiteness) are not read
+ * back by the host; with invalid data the kernels stay in bounds and the
+ * output is unspecified.
+ */
+typedef struct {
+  int32_t K;
+  const double *t, *Fphi, *Fr, *Phiphi, *Phir;
+  int32_t Nm;
+  const int32_t *l, *m, *n;
+  const double *A;
+  double theta, phi, scale;
+  int32_t Nf;
+  const double *f;
+  uint32_t flags;
+} fdemri_waveform_desc;
+
+/* Create a context on HIP device `hip_device` (0-based).  flags: reserved, 0.
+ * On success *out receives the context. */
+fdemri_status fdemri_create(fdemri_ctx **out, int hip_device, uint32_t flags);
+
+/* Release the context and its scratch memory (synchronises the device). */
+void fdemri_destroy(fdemri_ctx *ctx);
+
+/* Text of the last error on this context ("" if none).  Owned by the context. */
+const char *fdemri_last_error(const fdemri_ctx *ctx);
+
+/* Synchronise `stream` and return (and clear) the device flag word. */
+fdemri_status fdemri_sync_flags(fdemri_ctx *ctx, hipStream_t stream, uint32_t *flags_out);
+
+/*
+ * Frequency-domain waveform h_+(f), h_x(f) (Sec. 2.2, Eqs. cubic_equation,
+ * SPAintegral2, extendedspa1; polarizations from Eq. main_wave).
+ * hp, hc : [Nf] complex outputs (interleaved re, im) of the precision's type
+ * (double for FDEMRI_FP64, float for FDEMRI_MIXED).  Fully overwritten.
+ * Returns FDEMRI_OK once the work is enqueued on `stream`.
+ */
+fdemri_status fdemri_waveform(fdemri_ctx *ctx, const fdemri_waveform_desc *desc,
+                              fdemri_prec prec, void *hp, void *hc, hipStream_t stream);
+
+/*
+ * Several waveforms in one persistent launch (Sec. 3.2 timing studies
+ * evaluate many parameter draws; the batch amortises launches).
+ * descs : HOST array of B descriptors (device pointers inside).
+ * hp, hc : HOST arrays of B device output pointers.
+ * Results equal B calls of fdemri_waveform with the same precision.
+ */
+fdemri_status fdemri_waveform_batch(fdemri_ctx *ctx, int32_t B, const fdemri_waveform_desc *descs,
+                                    fdemri_prec prec, void *const *hp, void *const *hc,
+                                    hipStream_t stream);
+
+/*
+ * Vector-Jacobian product of the waveform (the gradient of a real loss such
+ * as the Whittle log-likelihood of Eq. likelihood).
+ * g_hp, g_hc : [Nf] complex cotangents dL/dRe h + i dL/dIm h, of the
+ *   precision's type.
+ * Outputs (device, fully overwritten; any may be NULL to skip):
+ *   gA   : [Nm][K-1][4][2] double, gradient w.r.t. the amplitude spline
+ *          coefficients a_k (A(t_i + tau) = sum_k a_k tau^k), same convention.
+ *   gPhi : [2][K-1][4] double, gradient w.r.t. the Phi_phi and Phi_r spline
+ *          coefficients.
+ *   g_scalars : [5] double: d/dtheta, d/dphi, d/dscale, d/dPhi_phi0, d/dPhi_r0
+ *          (the last two are the sums of the constant-coefficient gradients).
+ * The frequency splines (t(f)) are held fixed.
+ */
+fdemri_status fdemri_vjp(fdemri_ctx *ctx, const fdemri_waveform_desc *desc, fdemri_prec prec,
+                         const void *g_hp, const void *g_hc, double *gA, double *gPhi,
+                         double *g_scalars, hipStream_t stream);
+
+/*
+ * Count of mode-bin evaluations of the last fdemri_waveform call on this
+ * context: the number of (monotonic piece of |F_V|, bin) pairs with the bin
+ * inside the piece's frequency range.  Synchronises `stream`.
+ */
+fdemri_status fdemri_last_eval_count(fdemri_ctx *ctx, hipStream_t stream, int64_t *count_out);
+
+/*
+ * Per-kernel timing for measurement.  While enabled, every kernel launch of
+ * this context is bracketed by HIP events recorded on its launch stream.
+ * fdemri_profile_read synchronises `stream`, returns the accumulated
+ * milliseconds and launch counts per kernel class (FDEMRI_KERNEL_*; arrays of
+ * FDEMRI_KERNEL_COUNT entries, host memory) and resets the accumulators.
+ */
+#define FDEMRI_KERNEL_SPLINE 0
+#define FDEMRI_KERNEL_PIECES 1
+#define FDEMRI_KERNEL_GATHER 2
+#define FDEMRI_KERNEL_VJP 3
+#define FDEMRI_KERNEL_COUNT 4
+fdemri_status fdemri_profile_enable(fdemri_ctx *ctx, int enable);
+fdemri_status fdemri_profile_read(fdemri_ctx *ctx, hipStream_t stream, double *ms_out, int64_t *launches_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDEMRI_H */

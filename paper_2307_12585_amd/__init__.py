@@ -1,0 +1,242 @@
+"""Frequency-domain EMRI mode summation on AMD MI355X (gfx950).
+
+Thin ctypes binding of the C ABI in include/fdemri.h.  It only marshals
+arguments: torch tensors provide device memory and the current HIP stream,
+and every step of the computation runs in the HIP kernels of libfdemri.so.
+There is no CPU fallback: if the library is missing, importing the binding
+functions raises.
+
+    import paper_2307_12585_amd as fd
+    ctx = fd.Context()
+    hp, hc = ctx.waveform(t, Fphi, Fr, Phiphi, Phir, l, m, n, A, theta, phi, scale, f)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdemri.so")
+
+FDEMRI_OK, FDEMRI_EINVAL, FDEMRI_ENOMEM, FDEMRI_EDEVICE, FDEMRI_ENOTSUP = range(5)
+FDEMRI_FP64, FDEMRI_MIXED = 0, 1
+FDEMRI_NO_PARTNERS = 0x1
+FDEMRI_FLAG_PIECE_OVERFLOW = 0x1
+PRECISIONS = {"fp64": FDEMRI_FP64, "mixed": FDEMRI_MIXED}
+
+EXPORTED = [
+    "fdemri_create", "fdemri_destroy", "fdemri_last_error", "fdemri_sync_flags",
+    "fdemri_waveform", "fdemri_waveform_batch", "fdemri_vjp", "fdemri_last_eval_count",
+    "fdemri_profile_enable", "fdemri_profile_read",
+]
+KERNEL_CLASSES = ["spline", "pieces", "gather", "vjp"]
+
+
+class FdemriError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fdemri status {status}: {msg}")
+        self.status = status
+
+
+class WaveformDesc(ctypes.Structure):
+    """Mirror of fdemri_waveform_desc."""
+    _fields_ = [
+        ("K", ctypes.c_int32),
+        ("t", ctypes.c_void_p), ("Fphi", ctypes.c_void_p), ("Fr", ctypes.c_void_p),
+        ("Phiphi", ctypes.c_void_p), ("Phir", ctypes.c_void_p),
+        ("Nm", ctypes.c_int32),
+        ("l", ctypes.c_void_p), ("m", ctypes.c_void_p), ("n", ctypes.c_void_p),
+        ("A", ctypes.c_void_p),
+        ("theta", ctypes.c_double), ("phi", ctypes.c_double), ("scale", ctypes.c_double),
+        ("Nf", ctypes.c_int32),
+        ("f", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+_lib_handle = None
+
+
+def lib():
+    """Load libfdemri.so (raises if it has not been built)."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise FdemriError(-1, f"{LIB_PATH} is missing: build it with `python -m paper_2307_12585_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
+        L.fdemri_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, u32]
+        L.fdemri_create.restype = ctypes.c_int
+        L.fdemri_destroy.argtypes = [vp]
+        L.fdemri_destroy.restype = None
+        L.fdemri_last_error.argtypes = [vp]
+        L.fdemri_last_error.restype = ctypes.c_char_p
+        L.fdemri_sync_flags.argtypes = [vp, vp, ctypes.POINTER(u32)]
+        L.fdemri_sync_flags.restype = ctypes.c_int
+        L.fdemri_waveform.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_int, vp, vp, vp]
+        L.fdemri_waveform.restype = ctypes.c_int
+        L.fdemri_waveform_batch.argtypes = [vp, i32, ctypes.POINTER(WaveformDesc), ctypes.c_int,
+                                            ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+        L.fdemri_waveform_batch.restype = ctypes.c_int
+        L.fdemri_vjp.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_int, vp, vp, vp, vp, vp, vp]
+        L.fdemri_vjp.restype = ctypes.c_int
+        L.fdemri_last_eval_count.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
+        L.fdemri_last_eval_count.restype = ctypes.c_int
+        L.fdemri_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.fdemri_profile_enable.restype = ctypes.c_int
+        L.fdemri_profile_read.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.fdemri_profile_read.restype = ctypes.c_int
+        _lib_handle = L
+    return _lib_handle
+
+
+def _ptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else ctypes.c_void_p(0)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class DeviceWaveform:
+    """Device-resident inputs of one waveform, in the layouts of
+    fdemri_waveform_desc (float64 / int32 contiguous tensors; A as [Nm, K, 2])."""
+
+    def __init__(self, t, Fphi, Fr, Phiphi, Phir, l, m, n, A, theta, phi, scale, f,
+                 partners=True, device="cuda"):
+        dev = torch.device(device)
+        d64 = dict(dtype=torch.float64, device=dev)
+        self.t = torch.as_tensor(t, **d64).contiguous()
+        self.Fphi = torch.as_tensor(Fphi, **d64).contiguous()
+        self.Fr = torch.as_tensor(Fr, **d64).contiguous()
+        self.Phiphi = torch.as_tensor(Phiphi, **d64).contiguous()
+        self.Phir = torch.as_tensor(Phir, **d64).contiguous()
+        self.l = torch.as_tensor(l, dtype=torch.int32, device=dev).contiguous()
+        self.m = torch.as_tensor(m, dtype=torch.int32, device=dev).contiguous()
+        self.n = torch.as_tensor(n, dtype=torch.int32, device=dev).contiguous()
+        A = torch.as_tensor(A, device=dev)
+        if A.is_complex():
+            A = torch.view_as_real(A.to(torch.complex128))
+        self.A = A.to(torch.float64).contiguous()
+        self.f = torch.as_tensor(f, **d64).contiguous()
+        self.theta, self.phi, self.scale = float(theta), float(phi), float(scale)
+        self.partners = bool(partners)
+        self.device = dev
+
+    @property
+    def K(self):
+        return int(self.t.numel())
+
+    @property
+    def Nm(self):
+        return int(self.l.numel())
+
+    @property
+    def Nf(self):
+        return int(self.f.numel())
+
+    def desc(self) -> WaveformDesc:
+        return WaveformDesc(
+            K=self.K, t=_ptr(self.t).value, Fphi=_ptr(self.Fphi).value, Fr=_ptr(self.Fr).value,
+            Phiphi=_ptr(self.Phiphi).value, Phir=_ptr(self.Phir).value, Nm=self.Nm,
+            l=_ptr(self.l).value, m=_ptr(self.m).value, n=_ptr(self.n).value, A=_ptr(self.A).value,
+            theta=self.theta, phi=self.phi, scale=self.scale, Nf=self.Nf, f=_ptr(self.f).value,
+            flags=0 if self.partners else FDEMRI_NO_PARTNERS)
+
+    @classmethod
+    def from_workload(cls, w, device="cuda", partners=True, f=None):
+        """From any object with the attributes of workloads.Workload."""
+        tr = w.traj
+        return cls(tr.t, tr.Fphi, tr.Fr, tr.Phiphi, tr.Phir, w.l, w.m, w.n, w.A, w.theta, w.phi,
+                   w.scale, w.f if f is None else f, partners=partners, device=device)
+
+
+class Context:
+    """An fdemri context on one HIP device."""
+
+    def __init__(self, device=None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        idx = self.device.index if self.device.index is not None else torch.cuda.current_device()
+        self._lib = lib()
+        h = ctypes.c_void_p()
+        st = self._lib.fdemri_create(ctypes.byref(h), idx, 0)
+        if st != FDEMRI_OK:
+            raise FdemriError(st, "fdemri_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.fdemri_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != FDEMRI_OK:
+            raise FdemriError(st, self._lib.fdemri_last_error(self._h).decode())
+
+    def sync_flags(self) -> int:
+        v = ctypes.c_uint32()
+        self._check(self._lib.fdemri_sync_flags(self._h, _stream(self.device), ctypes.byref(v)))
+        return int(v.value)
+
+    def last_eval_count(self) -> int:
+        v = ctypes.c_int64()
+        self._check(self._lib.fdemri_last_eval_count(self._h, _stream(self.device), ctypes.byref(v)))
+        return int(v.value)
+
+    def profile(self, enable: bool):
+        """Bracket every kernel launch with HIP events on its stream."""
+        self._check(self._lib.fdemri_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches)} since the last read (synchronises)."""
+        n = len(KERNEL_CLASSES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        self._check(self._lib.fdemri_profile_read(self._h, _stream(self.device), ms, cnt))
+        return {k: (ms[i], int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def waveform_dev(self, dw: DeviceWaveform, prec="fp64", out=None):
+        """h_+(f), h_x(f) for device inputs; complex128 (fp64) or complex64 (mixed)."""
+        p = PRECISIONS[prec]
+        ctype = torch.complex128 if p == FDEMRI_FP64 else torch.complex64
+        if out is None:
+            hp = torch.empty(dw.Nf, dtype=ctype, device=dw.device)
+            hc = torch.empty(dw.Nf, dtype=ctype, device=dw.device)
+        else:
+            hp, hc = out
+            assert hp.dtype == ctype and hc.dtype == ctype and hp.numel() == dw.Nf and hc.numel() == dw.Nf
+            assert hp.is_contiguous() and hc.is_contiguous()
+        d = dw.desc()
+        self._check(self._lib.fdemri_waveform(self._h, ctypes.byref(d), p, _ptr(hp), _ptr(hc),
+                                              _stream(self.device)))
+        return hp, hc
+
+    def waveform(self, t, Fphi, Fr, Phiphi, Phir, l, m, n, A, theta, phi, scale, f,
+                 prec="fp64", partners=True):
+        dw = DeviceWaveform(t, Fphi, Fr, Phiphi, Phir, l, m, n, A, theta, phi, scale, f,
+                            partners=partners, device=self.device)
+        return self.waveform_dev(dw, prec)
+
+    def waveform_batch(self, dws, prec="fp64", outs=None):
+        """Several waveforms in one call; returns a list of (h_+, h_x)."""
+        p = PRECISIONS[prec]
+        ctype = torch.complex128 if p == FDEMRI_FP64 else torch.complex64
+        B = len(dws)
+        if outs is None:
+            outs = [(torch.empty(d.Nf, dtype=ctype, device=d.device),
+                     torch.empty(d.Nf, dtype=ctype, device=d.device)) for d in dws]
+        descs = (WaveformDesc * B)(*[d.desc() for d in dws])
+        hp = (ctypes.c_void_p * B)(*[o[0].data_ptr() for o in outs])
+        hc = (ctypes.c_void_p * B)(*[o[1].data_ptr() for o in outs])
+        self._check(self._lib.fdemri_waveform_batch(self._h, B, descs, p, hp, hc, _stream(self.device)))
+        return outs

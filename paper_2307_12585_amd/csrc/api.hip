@@ -1,0 +1,338 @@
+// C ABI of the frequency-domain EMRI mode sum: argument validation,
+// context-owned scratch memory and the launch sequence
+//   spline coefficients -> mode constants + piece table -> bin-major gather.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fdemri_internal.hpp"
+
+namespace fdemri {
+hipError_t launch_spline(int K, const double* t, const double* Fphi, const double* Fr, const double* Phiphi,
+                         const double* Phir, const double* A, int Nm, double* tcoef, double* acoef, int32_t* env,
+                         hipStream_t stream);
+struct PieceArgs;
+hipError_t launch_pieces_flat(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
+                              const double* f, const double* tcoef, const int32_t* l, const int32_t* m,
+                              const int32_t* n, double theta, double phi, double scale, uint32_t flags,
+                              ModeConst* modes, int2* mode_kr, Piece* pieces, int64_t* evals, int32_t* env,
+                              uint32_t* flag_word, hipStream_t stream);
+struct GatherArgs;
+hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp, void* hc, bool mixed, int bpl,
+                              hipStream_t stream);
+hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, hipStream_t stream);
+}  // namespace fdemri
+
+using namespace fdemri;
+
+struct fdemri_ctx {
+  int device = 0;
+  std::string err;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  uint32_t* flag_word = nullptr;  // device
+  int64_t* last_evals = nullptr;  // device pointer into ws of the last call
+  int last_Nm = 0;
+  int bpl = 4;
+  // profiling: event pairs per launch, by kernel class
+  bool prof = false;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+fdemri_status fail(fdemri_ctx* c, fdemri_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+fdemri_status hip_fail(fdemri_ctx* c, hipError_t e, const char* what) {
+  return fail(c, e == hipErrorOutOfMemory ? FDEMRI_ENOMEM : FDEMRI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Scratch layout of one waveform.
+struct Layout {
+  size_t tcoef, acoef, acoef32, modes, mode_kr, pieces, evals, env, total;
+};
+
+Layout layout_for(int K, int Nm, bool mixed) {
+  Layout L{};
+  size_t off = 0;
+  const size_t nseg = (size_t)K - 1;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  L.tcoef = take(4 * nseg * 4 * sizeof(double));
+  L.acoef = take((size_t)Nm * nseg * 8 * sizeof(double));
+  L.acoef32 = take(mixed ? (size_t)Nm * nseg * 8 * sizeof(float) : 0);
+  L.modes = take((size_t)Nm * sizeof(ModeConst));
+  L.mode_kr = take((size_t)Nm * sizeof(int2));
+  L.pieces = take((size_t)Nm * kMaxPieces * sizeof(Piece));
+  L.evals = take((size_t)Nm * sizeof(int64_t));
+  L.env = take(2 * sizeof(int32_t));
+  L.total = off;
+  return L;
+}
+
+fdemri_status ensure_ws(fdemri_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return FDEMRI_OK;
+  if (c->ws) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+    (void)hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  size_t want = align_up(bytes + bytes / 4, 1 << 20);
+  hipError_t e = hipMalloc((void**)&c->ws, want);
+  if (e != hipSuccess) {
+    c->ws = nullptr;
+    return hip_fail(c, e, "hipMalloc(workspace)");
+  }
+  c->ws_bytes = want;
+  return FDEMRI_OK;
+}
+
+fdemri_status validate(fdemri_ctx* c, const fdemri_waveform_desc* d) {
+  if (!d) return fail(c, FDEMRI_EINVAL, "desc is NULL");
+  if (d->K < 4) return fail(c, FDEMRI_EINVAL, "K=%d: a not-a-knot spline needs K >= 4 knots", d->K);
+  if (d->K > kMaxKnots) return fail(c, FDEMRI_ENOTSUP, "K=%d exceeds FDEMRI_MAX_KNOTS=%d", d->K, kMaxKnots);
+  if (d->Nm < 1) return fail(c, FDEMRI_EINVAL, "Nm=%d: need at least one mode", d->Nm);
+  if (d->Nf < 1) return fail(c, FDEMRI_EINVAL, "Nf=%d: need at least one frequency", d->Nf);
+  if (!d->t || !d->Fphi || !d->Fr || !d->Phiphi || !d->Phir || !d->l || !d->m || !d->n || !d->A || !d->f)
+    return fail(c, FDEMRI_EINVAL, "NULL input pointer in desc");
+  if (!(d->theta == d->theta) || !(d->phi == d->phi) || !(d->scale == d->scale))
+    return fail(c, FDEMRI_EINVAL, "theta, phi and scale must not be NaN");
+  if (d->flags & ~(uint32_t)FDEMRI_NO_PARTNERS) return fail(c, FDEMRI_EINVAL, "unknown flags 0x%x", d->flags);
+  return FDEMRI_OK;
+}
+
+hipEvent_t take_event(fdemri_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Bracket one kernel launch with events when profiling is on.
+struct ProfScope {
+  fdemri_ctx* c;
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(fdemri_ctx* c_, int cls_, hipStream_t s_) : c(c_), cls(cls_), s(s_) {
+    if (c->prof) {
+      a = take_event(c);
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (c->prof && a) {
+      hipEvent_t b = take_event(c);
+      if (b) {
+        (void)hipEventRecord(b, s);
+        c->recs.push_back({cls, a, b});
+      } else {
+        c->pool.push_back(a);
+      }
+    }
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+fdemri_status fdemri_create(fdemri_ctx** out, int hip_device, uint32_t flags) {
+  if (!out) return FDEMRI_EINVAL;
+  *out = nullptr;
+  if (flags != 0) return FDEMRI_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return FDEMRI_EDEVICE;
+  fdemri_ctx* c = new (std::nothrow) fdemri_ctx();
+  if (!c) return FDEMRI_ENOMEM;
+  c->device = hip_device;
+  hipError_t e = hipSetDevice(hip_device);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->flag_word, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(c->flag_word, 0, sizeof(uint32_t));
+  if (e != hipSuccess) {
+    if (c->flag_word) (void)hipFree(c->flag_word);
+    delete c;
+    return e == hipErrorOutOfMemory ? FDEMRI_ENOMEM : FDEMRI_EDEVICE;
+  }
+  *out = c;
+  return FDEMRI_OK;
+}
+
+void fdemri_destroy(fdemri_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->flag_word) (void)hipFree(c->flag_word);
+  for (auto& r : c->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto ev : c->pool) (void)hipEventDestroy(ev);
+  delete c;
+}
+
+const char* fdemri_last_error(const fdemri_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+fdemri_status fdemri_sync_flags(fdemri_ctx* c, hipStream_t stream, uint32_t* flags_out) {
+  if (!c || !flags_out) return fail(c, FDEMRI_EINVAL, "NULL argument");
+  (void)hipSetDevice(c->device);
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  uint32_t v = 0;
+  e = hipMemcpy(&v, c->flag_word, sizeof v, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemset(c->flag_word, 0, sizeof(uint32_t));
+  if (e != hipSuccess) return hip_fail(c, e, "flag word read");
+  *flags_out = v;
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemri_prec prec, void* hp, void* hc,
+                              hipStream_t stream) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  fdemri_status st = validate(c, d);
+  if (st != FDEMRI_OK) return st;
+  if (prec != FDEMRI_FP64 && prec != FDEMRI_MIXED) return fail(c, FDEMRI_EINVAL, "unknown precision %d", (int)prec);
+  if (!hp || !hc) return fail(c, FDEMRI_EINVAL, "NULL output pointer");
+  const bool mixed = prec == FDEMRI_MIXED;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const Layout L = layout_for(d->K, d->Nm, mixed);
+  st = ensure_ws(c, L.total);
+  if (st != FDEMRI_OK) return st;
+  char* w = c->ws;
+  double* tcoef = (double*)(w + L.tcoef);
+  double* acoef = (double*)(w + L.acoef);
+  float* acoef32 = mixed ? (float*)(w + L.acoef32) : nullptr;
+  ModeConst* modes = (ModeConst*)(w + L.modes);
+  int2* mode_kr = (int2*)(w + L.mode_kr);
+  Piece* pieces = (Piece*)(w + L.pieces);
+  int64_t* evals = (int64_t*)(w + L.evals);
+  int32_t* env = (int32_t*)(w + L.env);
+
+  {
+    ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream);
+    e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, d->Nm, tcoef, acoef, env, stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "spline kernel launch");
+  {
+    ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream);
+    e = launch_pieces_flat(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->f, tcoef, d->l, d->m, d->n, d->theta, d->phi,
+                           d->scale, d->flags, modes, mode_kr, pieces, evals, env, c->flag_word, stream);
+    if (e == hipSuccess && mixed) e = launch_amp32(d->Nm, d->K, d->t, acoef, acoef32, stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "piece kernel launch");
+  Prepared p;
+  p.K = d->K;
+  p.Nm = d->Nm;
+  p.Nf = d->Nf;
+  p.t = d->t;
+  p.Fphi = d->Fphi;
+  p.Fr = d->Fr;
+  p.Phiphi = d->Phiphi;
+  p.Phir = d->Phir;
+  p.f = d->f;
+  p.tcoef = tcoef;
+  p.acoef = acoef;
+  p.modes = modes;
+  p.mode_kr = mode_kr;
+  p.pieces = pieces;
+  p.env = env;
+  {
+    ProfScope ps(c, FDEMRI_KERNEL_GATHER, stream);
+    e = launch_gather_flat(p, acoef32, hp, hc, mixed, c->bpl, stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "gather kernel launch");
+  c->last_evals = evals;
+  c->last_Nm = d->Nm;
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_last_eval_count(fdemri_ctx* c, hipStream_t stream, int64_t* count_out) {
+  if (!c || !count_out) return fail(c, FDEMRI_EINVAL, "NULL argument");
+  if (!c->last_evals) return fail(c, FDEMRI_EINVAL, "no waveform evaluated on this context yet");
+  (void)hipSetDevice(c->device);
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  std::vector<int64_t> v(c->last_Nm);
+  e = hipMemcpy(v.data(), c->last_evals, v.size() * sizeof(int64_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "eval count read");
+  int64_t s = 0;
+  for (int64_t x : v) s += x;
+  *count_out = s;
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_waveform_batch(fdemri_ctx* c, int32_t B, const fdemri_waveform_desc* descs, fdemri_prec prec,
+                                    void* const* hp, void* const* hc, hipStream_t stream) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  if (B < 0 || (B > 0 && (!descs || !hp || !hc))) return fail(c, FDEMRI_EINVAL, "invalid batch arguments");
+  for (int b = 0; b < B; ++b) {
+    fdemri_status st = fdemri_waveform(c, &descs[b], prec, hp[b], hc[b], stream);
+    if (st != FDEMRI_OK) return st;
+  }
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_profile_enable(fdemri_ctx* c, int enable) {
+  if (!c) return FDEMRI_EINVAL;
+  c->prof = enable != 0;
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_profile_read(fdemri_ctx* c, hipStream_t stream, double* ms_out, int64_t* launches_out) {
+  if (!c || !ms_out || !launches_out) return fail(c, FDEMRI_EINVAL, "NULL argument");
+  (void)hipSetDevice(c->device);
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  for (int k = 0; k < FDEMRI_KERNEL_COUNT; ++k) {
+    ms_out[k] = 0.0;
+    launches_out[k] = 0;
+  }
+  for (auto& r : c->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && r.cls >= 0 && r.cls < FDEMRI_KERNEL_COUNT) {
+      ms_out[r.cls] += ms;
+      launches_out[r.cls] += 1;
+    }
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->recs.clear();
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_vjp(fdemri_ctx* c, const fdemri_waveform_desc*, fdemri_prec, const void*, const void*, double*,
+                         double*, double*, hipStream_t) {
+  return fail(c, FDEMRI_ENOTSUP, "fdemri_vjp: not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Internal structures and device helpers of the frequency-domain EMRI mode
+// sum (Sec. 2.2 of arXiv 2307.12585).  Shared by the kernels of this
+// library only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fdemri.h"
+
+namespace fdemri {
+
+constexpr int kMaxPieces = FDEMRI_MAX_PIECES;
+constexpr int kMaxKnots = FDEMRI_MAX_KNOTS;
+constexpr int kMaxL = FDEMRI_MAX_L;
+
+// 2 pi as an unevaluated double-double (2 pi = kTwoPiHi + kTwoPiLo to ~1e-32).
+constexpr double kTwoPiHi = 6.283185307179586232e+00;
+constexpr double kTwoPiLo = 2.449293598294706414e-16;
+constexpr double kInvTwoPi = 0.15915494309189535;
+constexpr double kPi = 3.141592653589793116;
+
+// One monotonic piece of a voice frequency F_V(t) = m F_phi + n F_r over the
+// sparse trajectory: F_V has one sign s on it and |F_V| is monotonic with
+// direction d in t.  It starts at tau_a inside spline segment seg_a and ends
+// at tau_b inside segment seg_b; g_a, g_b are |F_V| at the two ends, and
+// [k_lo, k_hi] the bins whose frequency lies in [min, max](g_a, g_b).
+struct alignas(64) Piece {
+  double tau_a, tau_b;
+  double g_a, g_b;
+  int32_t seg_a, seg_b;
+  int32_t k_lo, k_hi;
+  int32_t s, d;
+  int32_t pad0, pad1;
+};
+static_assert(sizeof(Piece) == 64, "Piece layout");
+
+// Per-mode constants: mode numbers as doubles and the fused polarization
+// factors c_+ and c_x (scale and spin-weighted harmonics folded in).
+struct alignas(64) ModeConst {
+  double m, n;
+  double cp_re, cp_im, cx_re, cx_im;
+  int32_t npieces, pad;
+  int32_t k_lo, k_hi;
+};
+static_assert(sizeof(ModeConst) == 64, "ModeConst layout");
+
+// Device pointers of one waveform's prepared tables.
+struct Prepared {
+  int32_t K, Nm, Nf;
+  const double* t;       // [K]
+  const double* Fphi;    // [K]
+  const double* Fr;      // [K]
+  const double* Phiphi;  // [K]
+  const double* Phir;    // [K]
+  const double* f;       // [Nf]
+  const double* tcoef;   // [4][K-1][4] Fphi, Fr, Phiphi, Phir; ascending powers
+  const double* acoef;   // [Nm][K-1][8] amplitude (re,im) x ascending powers
+  const ModeConst* modes;  // [Nm]
+  const int2* mode_kr;     // [Nm] bin range of each mode (union of its pieces)
+  const Piece* pieces;     // [Nm][kMaxPieces]
+  const int32_t* env;      // [2] bin envelope of all modes
+};
+
+// ---------------------------------------------------------------- helpers
+
+struct dd {
+  double hi, lo;
+};
+
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  double p = a * b;
+  return {p, __builtin_fma(a, b, -p)};
+}
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+#pragma clang fp contract(off)
+  double s = a + b;
+  double bb = s - a;
+  double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+
+// Voice frequency at a knot from the knot data, with a fixed operation order
+// and no fused multiply-add, so that every implementation of the piece
+// boundaries agrees bit for bit.
+__device__ __forceinline__ double knot_freq(double m, double fphi, double n, double fr) {
+#pragma clang fp contract(off)
+  double a = m * fphi;
+  double b = n * fr;
+  return a + b;
+}
+
+}  // namespace fdemri

@@ -1,0 +1,384 @@
+// Frequency-domain mode sum (Sec. 2.2, Eqs. cubic_equation, SPAintegral2,
+// extendedspa1), bin-major.
+//
+// The paper's GPU kernel places one block per (voice, spline segment) and
+// adds every contribution atomically into the output vector.  Here each
+// wavefront owns a tile of contiguous frequency bins instead and gathers all
+// contributions to its bins in registers, so every output element is written
+// once, coalesced, in a fixed order of voices and pieces (deterministic, no
+// atomics):
+//   1. the workgroup stages the shared trajectory tables (knots and spline
+//      coefficients of F_phi, F_r, Phi_phi, Phi_r) in LDS;
+//   2. the wave scans the per-mode bin ranges 64 modes at a time and keeps,
+//      by ballot, the modes whose range meets its tile;
+//   3. for each active piece of an active mode, each lane with a bin inside
+//      the piece's range finds the spline segment holding f (binary search
+//      over the knot frequencies), solves the cubic of Eq. cubic_equation for
+//      the root by safeguarded Newton iteration, evaluates dF/dt, d2F/dt2,
+//      the factor G of Eq. extendedspa1, the phase 2 pi f t - Phi_V(t) (large
+//      part in double-double, reduced modulo 2 pi) and the amplitude spline,
+//      and accumulates h_+ and h_x;
+//   4. the wave stores its tile.
+// FP64 path: everything in double.  Mixed path: root, derivatives, phase and
+// its reduction in double; the special function, sincos, amplitude spline and
+// products in float with compensated (Kahan) accumulation.
+#include "spa.hpp"
+
+namespace fdemri {
+
+struct GatherArgs {
+  Prepared p;
+  const float* acoef32;  // [Nm][K-1][8] normalised-u amplitude coefficients (mixed path)
+  void* hp;
+  void* hc;
+};
+
+template <bool MIXED>
+struct Acc;
+
+template <>
+struct Acc<false> {
+  double v[4];
+  __device__ __forceinline__ void zero() { v[0] = v[1] = v[2] = v[3] = 0.0; }
+};
+
+template <>
+struct Acc<true> {
+  float v[4], c[4];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = c[q] = 0.f;
+  }
+  __device__ __forceinline__ void add(int q, float y) {
+    // compensated (Kahan) summation
+    const float yy = y - c[q];
+    const float tt = v[q] + yy;
+    c[q] = (tt - v[q]) - yy;
+    v[q] = tt;
+  }
+};
+
+struct Lds {
+  const double* t;
+  const double* Fp;
+  const double* Fr;
+  const double* Pp;
+  const double* Pr;
+  const double* cF;  // [K-1][6]: Fphi c1..c3, Fr c1..c3
+  const double* cP;  // [K-1][6]: Phiphi c1..c3, Phir c1..c3
+};
+
+// One (bin, piece) evaluation.
+template <bool MIXED>
+__device__ __forceinline__ void eval_bin(const double f, const Piece& P, const double m, const double n,
+                                         const double cpr, const double cpi, const double cxr, const double cxi,
+                                         const double* __restrict__ ac, const float* __restrict__ ac32,
+                                         const Lds& L, Acc<MIXED>& acc) {
+  const int s = P.s, d = P.d;
+  const double sd = (double)s;
+  const double dd_ = (double)d;
+  // 1. spline segment holding f: largest i in [seg_a, seg_b] whose start value
+  //    precedes f in the direction of the piece (ties go to the lower segment)
+  int lo = P.seg_a, hi = P.seg_b;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const double gm = sd * knot_freq(m, L.Fp[mid], n, L.Fr[mid]);
+    if (dd_ * gm < dd_ * f)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int i = lo;
+  const double ti = L.t[i];
+  const double h = L.t[i + 1] - ti;
+  const double F0 = knot_freq(m, L.Fp[i], n, L.Fr[i]);
+  const double* cf = L.cF + i * 6;
+  const double a1 = m * cf[0] + n * cf[3];
+  const double a2 = m * cf[1] + n * cf[4];
+  const double a3 = m * cf[2] + n * cf[5];
+  const bool first = (i == P.seg_a), last = (i == P.seg_b);
+  const double tl = first ? P.tau_a : 0.0;
+  const double th = last ? P.tau_b : h;
+  const double gl = first ? P.g_a : sd * F0;
+  const double gh = last ? P.g_b : sd * knot_freq(m, L.Fp[i + 1], n, L.Fr[i + 1]);
+
+  // 2. root of s (F0 + a1 tau + a2 tau^2 + a3 tau^3) = f in [tl, th]
+  double tau = tl;
+  {
+    const double dg = gh - gl;
+    if (dg != 0.0) tau = tl + (f - gl) / dg * (th - tl);
+    tau = fmin(fmax(tau, tl), th);
+    double blo = tl, bhi = th;
+    const double tol = 4e-16 * fmax(h, 1.0);
+    for (int it = 0; it < 100; ++it) {
+      const double r = sd * (F0 + tau * (a1 + tau * (a2 + tau * a3))) - f;
+      if (r == 0.0) break;
+      const double gp = sd * (a1 + tau * (2.0 * a2 + 3.0 * a3 * tau));
+      if (dd_ * r < 0.0)
+        blo = tau;
+      else
+        bhi = tau;
+      double tn = tau - r / gp;
+      if (!(tn > blo && tn < bhi)) tn = 0.5 * (blo + bhi);
+      const double step = fabs(tn - tau);
+      tau = tn;
+      if (step <= tol || !(bhi - blo > tol)) break;
+    }
+  }
+  // 3. local derivatives of |F_V| at the root
+  const double gd = sd * (a1 + tau * (2.0 * a2 + 3.0 * a3 * tau));
+  const double gdd = sd * (2.0 * a2 + 6.0 * a3 * tau);
+
+  // 4. phase psi = 2 pi f (t_i + tau) - s Phi_V(t_i + tau), reduced mod 2 pi
+  const double* cp = L.cP + i * 6;
+  const double b1 = m * cp[0] + n * cp[3];
+  const double b2 = m * cp[1] + n * cp[4];
+  const double b3 = m * cp[2] + n * cp[5];
+  double psi;
+  {
+    const dd ft = two_prod(f, ti);
+    dd q = two_prod(ft.hi, kTwoPiHi);
+    q.lo = __builtin_fma(ft.hi, kTwoPiLo, __builtin_fma(ft.lo, kTwoPiHi, q.lo));
+    const dd pm = two_prod(m, L.Pp[i]);
+    const dd pn = two_prod(n, L.Pr[i]);
+    dd z = two_sum(pm.hi, pn.hi);
+    z.lo += pm.lo + pn.lo;
+    dd b = two_sum(q.hi, -sd * z.hi);
+    b.lo += q.lo - sd * z.lo;
+    const double kk = rint(b.hi * kInvTwoPi);
+    const dd kc = two_prod(kk, kTwoPiHi);
+    const double red = (b.hi - kc.hi) + ((b.lo - kc.lo) - kk * kTwoPiLo);
+    const double small = tau * (kTwoPiHi * f - sd * (b1 + tau * (b2 + tau * b3)));
+    psi = red + small;
+  }
+
+  if constexpr (!MIXED) {
+    const double2 G = spa_factor64(gd, gdd, d);
+    double sn, cs;
+    sincos(psi, &sn, &cs);
+    const double Er = cs * G.x - sn * G.y;
+    const double Ei = cs * G.y + sn * G.x;
+    // 5. amplitude spline A(t_i + tau)
+    const double* c = ac + (size_t)i * 8;
+    const double Ar = c[0] + tau * (c[2] + tau * (c[4] + tau * c[6]));
+    const double Ai = c[1] + tau * (c[3] + tau * (c[5] + tau * c[7]));
+    double pr = Ar * cpr - Ai * cpi, pi = Ar * cpi + Ai * cpr;
+    double xr = Ar * cxr - Ai * cxi, xi = Ar * cxi + Ai * cxr;
+    if (s < 0) {
+      pi = -pi;
+      xi = -xi;
+    }
+    acc.v[0] += pr * Er - pi * Ei;
+    acc.v[1] += pr * Ei + pi * Er;
+    acc.v[2] += xr * Er - xi * Ei;
+    acc.v[3] += xr * Ei + xi * Er;
+  } else {
+    const float2 G = spa_factor32(gd, gdd, d);
+    const double psr = psi - kTwoPiHi * rint(psi * kInvTwoPi);
+    float sn, cs;
+    sincosf((float)psr, &sn, &cs);
+    const float Er = cs * G.x - sn * G.y;
+    const float Ei = cs * G.y + sn * G.x;
+    const float u = (float)(tau / h);
+    const float* c = ac32 + (size_t)i * 8;
+    const float Ar = c[0] + u * (c[2] + u * (c[4] + u * c[6]));
+    const float Ai = c[1] + u * (c[3] + u * (c[5] + u * c[7]));
+    const float fcpr = (float)cpr, fcpi = (float)cpi, fcxr = (float)cxr, fcxi = (float)cxi;
+    float pr = Ar * fcpr - Ai * fcpi, pi = Ar * fcpi + Ai * fcpr;
+    float xr = Ar * fcxr - Ai * fcxi, xi = Ar * fcxi + Ai * fcxr;
+    if (s < 0) {
+      pi = -pi;
+      xi = -xi;
+    }
+    acc.add(0, pr * Er - pi * Ei);
+    acc.add(1, pr * Ei + pi * Er);
+    acc.add(2, xr * Er - xi * Ei);
+    acc.add(3, xr * Ei + xi * Er);
+  }
+}
+
+template <bool MIXED, int BPL, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void gather_kernel(GatherArgs a) {
+  extern __shared__ double lds[];
+  const Prepared& p = a.p;
+  const int K = p.K, nseg = K - 1, Nf = p.Nf;
+  constexpr int TILE = 64 * BPL;
+  const long kb0 = (long)blockIdx.x * (TILE * WAVES);
+  const long kb1 = kb0 + TILE * WAVES - 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long k0 = kb0 + (long)wave * TILE;
+
+  // Blocks outside the bin envelope of all modes only write zeros.
+  const int env0 = p.env[0], env1 = p.env[1];
+  if (kb1 < env0 || kb0 > env1) {
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) {
+      const long k = k0 + j * 64 + lane;
+      if (k < Nf) {
+        if constexpr (MIXED) {
+          ((float2*)a.hp)[k] = make_float2(0.f, 0.f);
+          ((float2*)a.hc)[k] = make_float2(0.f, 0.f);
+        } else {
+          ((double2*)a.hp)[k] = make_double2(0.0, 0.0);
+          ((double2*)a.hc)[k] = make_double2(0.0, 0.0);
+        }
+      }
+    }
+    return;
+  }
+
+  // 1. stage the shared trajectory tables
+  Lds L;
+  {
+    double* s_t = lds;
+    double* s_Fp = s_t + K;
+    double* s_Fr = s_Fp + K;
+    double* s_Pp = s_Fr + K;
+    double* s_Pr = s_Pp + K;
+    double* s_cF = s_Pr + K;
+    double* s_cP = s_cF + 6 * nseg;
+    for (int i = threadIdx.x; i < K; i += blockDim.x) {
+      s_t[i] = p.t[i];
+      s_Fp[i] = p.Fphi[i];
+      s_Fr[i] = p.Fr[i];
+      s_Pp[i] = p.Phiphi[i];
+      s_Pr[i] = p.Phir[i];
+    }
+    for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s_cF[i * 6 + c] = p.tcoef[((size_t)0 * nseg + i) * 4 + 1 + c];
+        s_cF[i * 6 + 3 + c] = p.tcoef[((size_t)1 * nseg + i) * 4 + 1 + c];
+        s_cP[i * 6 + c] = p.tcoef[((size_t)2 * nseg + i) * 4 + 1 + c];
+        s_cP[i * 6 + 3 + c] = p.tcoef[((size_t)3 * nseg + i) * 4 + 1 + c];
+      }
+    }
+    L = Lds{s_t, s_Fp, s_Fr, s_Pp, s_Pr, s_cF, s_cP};
+  }
+  __syncthreads();
+
+  if (k0 >= Nf) return;
+  const long k1 = (k0 + TILE - 1 < Nf - 1) ? k0 + TILE - 1 : Nf - 1;
+
+  double fk[BPL];
+  Acc<MIXED> acc[BPL];
+#pragma unroll
+  for (int j = 0; j < BPL; ++j) {
+    const long k = k0 + j * 64 + lane;
+    fk[j] = (k < Nf) ? p.f[k] : 0.0;
+    acc[j].zero();
+  }
+
+  // 2. modes whose bin range meets the tile, 64 at a time, by ballot
+  for (int mc = 0; mc < p.Nm; mc += 64) {
+    const int mu = mc + lane;
+    bool act = false;
+    if (mu < p.Nm) {
+      const int2 r = p.mode_kr[mu];
+      act = (r.x <= k1) && (r.y >= k0);
+    }
+    unsigned long long mask = __ballot(act);
+    while (mask) {
+      const int bit = __ffsll((long long)mask) - 1;
+      mask &= mask - 1;
+      const int mode = mc + bit;
+      const ModeConst md = p.modes[mode];
+      const Piece* pcs = p.pieces + (size_t)mode * kMaxPieces;
+      const double* ac = p.acoef + (size_t)mode * nseg * 8;
+      const float* ac32 = MIXED ? a.acoef32 + (size_t)mode * nseg * 8 : nullptr;
+      for (int q = 0; q < md.npieces; ++q) {
+        const Piece P = pcs[q];
+        if (P.k_lo > k1 || P.k_hi < k0) continue;
+        // 3. per-lane evaluation for the bins of this piece
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) {
+          const long k = k0 + j * 64 + lane;
+          if (k >= P.k_lo && k <= P.k_hi)
+            eval_bin<MIXED>(fk[j], P, md.m, md.n, md.cp_re, md.cp_im, md.cx_re, md.cx_im, ac, ac32, L, acc[j]);
+        }
+      }
+    }
+  }
+
+  // 4. coalesced store
+#pragma unroll
+  for (int j = 0; j < BPL; ++j) {
+    const long k = k0 + j * 64 + lane;
+    if (k < Nf) {
+      if constexpr (MIXED) {
+        ((float2*)a.hp)[k] = make_float2(acc[j].v[0], acc[j].v[1]);
+        ((float2*)a.hc)[k] = make_float2(acc[j].v[2], acc[j].v[3]);
+      } else {
+        ((double2*)a.hp)[k] = make_double2(acc[j].v[0], acc[j].v[1]);
+        ((double2*)a.hc)[k] = make_double2(acc[j].v[2], acc[j].v[3]);
+      }
+    }
+  }
+}
+
+// Normalised FP32 amplitude coefficients for the mixed path:
+// A(t_i + u h) = sum_k (a_k h^k) u^k, u in [0, 1].
+__global__ void amp32_kernel(int Nm, int K, const double* __restrict__ t, const double* __restrict__ acoef,
+                             float* __restrict__ acoef32) {
+  const int nseg = K - 1;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)Nm * nseg) return;
+  const int i = (int)(idx % nseg);
+  const double h = t[i + 1] - t[i];
+  const double* c = acoef + idx * 8;
+  float* o = acoef32 + idx * 8;
+  double hk = 1.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    o[2 * k] = (float)(c[2 * k] * hk);
+    o[2 * k + 1] = (float)(c[2 * k + 1] * hk);
+    hk *= h;
+  }
+}
+
+size_t gather_lds_bytes(int K) { return (size_t)(5 * K + 12 * (K - 1)) * sizeof(double); }
+
+template <bool MIXED, int BPL, int WAVES>
+static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t stream) {
+  constexpr int per_block = 64 * BPL * WAVES;
+  const long blocks = ((long)a.p.Nf + per_block - 1) / per_block;
+  const size_t lds = gather_lds_bytes(a.p.K);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)gather_kernel<MIXED, BPL, WAVES>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)gather_lds_bytes(kMaxKnots));
+    attr_set = true;
+  }
+  gather_kernel<MIXED, BPL, WAVES><<<dim3((unsigned)blocks), dim3(64 * WAVES), lds, stream>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherArgs& a, bool mixed, int bpl, hipStream_t stream) {
+  if (mixed) {
+    if (bpl == 1) return launch_gather_t<true, 1, 4>(a, stream);
+    if (bpl == 2) return launch_gather_t<true, 2, 4>(a, stream);
+    return launch_gather_t<true, 4, 4>(a, stream);
+  }
+  if (bpl == 1) return launch_gather_t<false, 1, 4>(a, stream);
+  if (bpl == 2) return launch_gather_t<false, 2, 4>(a, stream);
+  return launch_gather_t<false, 4, 4>(a, stream);
+}
+
+hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp, void* hc, bool mixed, int bpl,
+                              hipStream_t stream) {
+  GatherArgs a;
+  a.p = p;
+  a.acoef32 = acoef32;
+  a.hp = hp;
+  a.hc = hc;
+  return launch_gather(a, mixed, bpl, stream);
+}
+
+hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, hipStream_t stream) {
+  const long total = (long)Nm * (K - 1);
+  const int threads = 256;
+  amp32_kernel<<<dim3((unsigned)((total + threads - 1) / threads)), threads, 0, stream>>>(Nm, K, t, acoef, acoef32);
+  return hipGetLastError();
+}
+
+}  // namespace fdemri

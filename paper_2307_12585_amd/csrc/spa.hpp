@@ -1,0 +1,140 @@
+// Per-root factor of the third-order stationary-phase term (Sec. 2.2,
+// Eq. extendedspa1) on the device.
+//
+// For a root with local derivatives gd = d|F|/dt, gdd = d2|F|/dt2 the
+// factor multiplying H(t_j) e^{i[2 pi f t_j - Phi(t_j)]} is
+//   G = |gd|^{-1/2} e^{-i pi/4 sgn gd} W(X),   X = 2 pi gd^3 / (3 gdd^2),
+//   W(X) = sqrt(2|X|/pi) e^{-i pi/4 sgn X} e^{-iX} K_{1/3}(-iX)
+// (the printed constant of Eq. extendedspa1 is taken with the opposite sign,
+// the reading under which the formula reduces to the standard SPA as
+// gdd -> 0 as the paper states).  Evaluation:
+//  * gdd = 0: W = 1;
+//  * |X| >= X_B: W = sum_k a_k (i/X)^k (large-argument expansion of the
+//    exponentially scaled K_{1/3});
+//  * |X| <  X_B: the same factor in Airy form,
+//      G = pi (pi|gdd|)^{-1/3} Q(y)  (conjugated when sgn gd < 0),
+//      Q(y) = [Ai(-y^2) - i Bi(-y^2)] e^{-i 2y^3/3},  y = (3|X|/2)^{1/3},
+//    from piecewise Chebyshev tables; it is finite at gd = 0, where the
+//    sign is the direction of the monotonic piece.
+// The paper approximates the same function by two polynomial fits with
+// ~1e-3 relative error; these tables hold it to FP64 (FP32) accuracy.
+#pragma once
+
+#include "fdemri_internal.hpp"
+#include "w_table.inc"
+
+namespace fdemri {
+
+__device__ __forceinline__ double2 q_cheb64(double y) {
+  constexpr double w = FDW_Y_B / FDW_NINT;
+  int j = (int)(y * (FDW_NINT / FDW_Y_B));
+  j = j < 0 ? 0 : (j > FDW_NINT - 1 ? FDW_NINT - 1 : j);
+  const double x = 2.0 * (y - j * w) / w - 1.0;
+  const double* cr = fdw_q64_re + j * (FDW_DEG64 + 1);
+  const double* ci = fdw_q64_im + j * (FDW_DEG64 + 1);
+  double b1r = 0.0, b2r = 0.0, b1i = 0.0, b2i = 0.0;
+  const double x2 = 2.0 * x;
+#pragma unroll
+  for (int k = FDW_DEG64; k >= 1; --k) {
+    const double tr = x2 * b1r - b2r + cr[k];
+    const double ti = x2 * b1i - b2i + ci[k];
+    b2r = b1r;
+    b1r = tr;
+    b2i = b1i;
+    b1i = ti;
+  }
+  return make_double2(x * b1r - b2r + cr[0], x * b1i - b2i + ci[0]);
+}
+
+__device__ __forceinline__ float2 q_cheb32(float y) {
+  constexpr float w = (float)(FDW_Y_B / FDW_NINT);
+  int j = (int)(y * (float)(FDW_NINT / FDW_Y_B));
+  j = j < 0 ? 0 : (j > FDW_NINT - 1 ? FDW_NINT - 1 : j);
+  const float x = 2.0f * (y - j * w) / w - 1.0f;
+  const float* cr = fdw_q32_re + j * (FDW_DEG32 + 1);
+  const float* ci = fdw_q32_im + j * (FDW_DEG32 + 1);
+  float b1r = 0.f, b2r = 0.f, b1i = 0.f, b2i = 0.f;
+  const float x2 = 2.0f * x;
+#pragma unroll
+  for (int k = FDW_DEG32; k >= 1; --k) {
+    const float tr = x2 * b1r - b2r + cr[k];
+    const float ti = x2 * b1i - b2i + ci[k];
+    b2r = b1r;
+    b1r = tr;
+    b2i = b1i;
+    b1i = ti;
+  }
+  return make_float2(x * b1r - b2r + cr[0], x * b1i - b2i + ci[0]);
+}
+
+// G in FP64.  dir = direction of the piece (used only when gd == 0).
+__device__ __forceinline__ double2 spa_factor64(double gd, double gdd, int dir) {
+  constexpr double kRsqrt2 = 0.70710678118654752440;
+  if (gdd == 0.0) {
+    if (gd == 0.0) return make_double2(0.0, 0.0);
+    const double c = kRsqrt2 / sqrt(fabs(gd));
+    return make_double2(c, gd > 0.0 ? -c : c);
+  }
+  const double rr = gd / gdd;
+  const double X = (2.0 * kPi / 3.0) * gd * rr * rr;
+  const double ax = fabs(X);
+  const int sg = gd > 0.0 ? 1 : (gd < 0.0 ? -1 : dir);
+  if (!(ax < FDW_X_B)) {
+    const double u = 1.0 / X;
+    const double v = u * u;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int j = (FDW_NASYM64 - 1) / 2; j >= 0; --j) {
+      const double sgn = (j & 1) ? -1.0 : 1.0;
+      re = re * v + sgn * fdw_asym64[2 * j];
+      if (2 * j + 1 < FDW_NASYM64) im = im * v + sgn * fdw_asym64[2 * j + 1];
+    }
+    im *= u;
+    const double c = kRsqrt2 / sqrt(fabs(gd));
+    // (c - i sg c) (re + i im)
+    const double br = c, bi = -sg * c;
+    return make_double2(br * re - bi * im, br * im + bi * re);
+  }
+  const double y = cbrt(1.5 * ax);
+  double2 q = q_cheb64(y);
+  if (sg < 0) q.y = -q.y;
+  const double pref = kPi / cbrt(kPi * fabs(gdd));
+  return make_double2(pref * q.x, pref * q.y);
+}
+
+// G in FP32 from FP64 derivatives (the mixed-precision path keeps gd, gdd in
+// FP64 and evaluates the special function in FP32).
+__device__ __forceinline__ float2 spa_factor32(double gd, double gdd, int dir) {
+  constexpr float kRsqrt2 = 0.70710678118654752440f;
+  if (gdd == 0.0) {
+    if (gd == 0.0) return make_float2(0.f, 0.f);
+    const float c = kRsqrt2 * rsqrtf((float)fabs(gd));
+    return make_float2(c, gd > 0.0 ? -c : c);
+  }
+  const double rr = gd / gdd;
+  const double X = (2.0 * kPi / 3.0) * gd * rr * rr;
+  const double ax = fabs(X);
+  const int sg = gd > 0.0 ? 1 : (gd < 0.0 ? -1 : dir);
+  if (!(ax < FDW_X_B)) {
+    const float u = (float)(1.0 / X);
+    const float v = u * u;
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int j = (FDW_NASYM32 - 1) / 2; j >= 0; --j) {
+      const float sgn = (j & 1) ? -1.f : 1.f;
+      re = re * v + sgn * fdw_asym32[2 * j];
+      if (2 * j + 1 < FDW_NASYM32) im = im * v + sgn * fdw_asym32[2 * j + 1];
+    }
+    im *= u;
+    const float c = kRsqrt2 * rsqrtf((float)fabs(gd));
+    const float br = c, bi = -sg * c;
+    return make_float2(br * re - bi * im, br * im + bi * re);
+  }
+  const float y = cbrtf((float)(1.5 * ax));
+  float2 q = q_cheb32(y);
+  if (sg < 0) q.y = -q.y;
+  const float pref = (float)(kPi / cbrt(kPi * fabs(gdd)));
+  return make_float2(pref * q.x, pref * q.y);
+}
+
+}  // namespace fdemri

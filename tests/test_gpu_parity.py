@@ -1,0 +1,162 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 bar: relative L2 <= 1e-10 per polarization (the target of the mode sum
+in FP64).  Mixed bar: relative L2 <= 1e-6 against the GPU FP64 result.
+Bins in or out of a voice's frequency range must agree exactly."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from oracle.waveform import Voice, splines, waveform_voices, count_evals
+from oracle.harmonics import swsh
+
+pytestmark = pytest.mark.gpu
+
+fd = pytest.importorskip("paper_2307_12585_amd")
+from gpu_helpers import gpu_waveform, rel_l2, support_mismatch  # noqa: E402
+
+TOL64 = 1e-10
+TOLMIX = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fd.Context(0)
+    yield c
+    c.close()
+
+
+def _check64(hg, ho, what):
+    for name, g, o in zip(("h+", "hx"), hg, ho):
+        err = rel_l2(g, o)
+        print(f"{what} {name}: rel L2 {err:.3e}, support mismatch {support_mismatch(g, o)}")
+        assert support_mismatch(g, o) == 0, what
+        assert err <= TOL64, (what, name, err)
+
+
+def test_config1_full_grid(ctx):
+    w = W.config1()
+    hg = gpu_waveform(ctx, w)
+    ho = oracle.waveform(w)
+    _check64(hg, ho, "config1")
+    assert ctx.last_eval_count() == count_evals(w) == 8724
+
+
+def test_config3_log_grid(ctx):
+    w = W.config3()
+    _check64(gpu_waveform(ctx, w), oracle.waveform(w), "config3")
+
+
+def test_config1_ragged_and_offset_grids(ctx):
+    w = W.config1()
+    for lo, hi in [(0, 1), (0, 255), (3, 1000), (12345, 12345 + 777), (100001, 100001 + 65 * 64 + 3)]:
+        f = w.f[lo:hi]
+        hg = gpu_waveform(ctx, w, f=f)
+        ho = oracle.waveform(w, f=f)
+        for g, o in zip(hg, ho):
+            assert support_mismatch(g, o) == 0
+            if np.any(o != 0):
+                assert rel_l2(g, o) <= TOL64
+
+
+def test_config2_sampled_bins(ctx):
+    """Full-size config 2 on the GPU; the oracle evaluates a sample of bins
+    (each bin is independent) drawn across the active band and the tail."""
+    w = W.config2()
+    hp, hc = gpu_waveform(ctx, w)
+    rng = np.random.default_rng(11)
+    act = np.nonzero(w.f < 9e-3)[0]
+    idx = np.unique(np.concatenate([rng.choice(act, 1500, replace=False),
+                                    rng.choice(w.Nf, 200, replace=False), [0, 1, w.Nf - 1]]))
+    op, oc = oracle.waveform(w, f=w.f[idx])
+    _check64((hp[idx], hc[idx]), (op, oc), "config2-sampled")
+    assert np.all(hp[w.f > 1.2e-2] == 0)
+
+
+def test_linear_chirp_and_turnover(ctx):
+    from test_oracle_waveform import turnover_workload
+    for w in [W.linear_chirp_workload(f0=1e-4, fdot=1e-9, T=1e5, Nf=3001),
+              W.linear_chirp_workload(f0=2e-4, fdot=-1e-9, T=1e5, Nf=3001),
+              turnover_workload(1e-2, 1e-9), turnover_workload(6e-2, -1e-9)]:
+        _check64(gpu_waveform(ctx, w, partners=False), oracle.waveform(w, partners=False), "chirp/turnover")
+        _check64(gpu_waveform(ctx, w, partners=True), oracle.waveform(w, partners=True), "chirp/turnover+partner")
+
+
+def test_explicit_voices_no_partners(ctx):
+    """FDEMRI_NO_PARTNERS with rows of both signs of m equals the oracle's
+    explicit voice list."""
+    w = W.config1()
+    w.m = np.where(np.arange(w.Nm) % 2 == 0, w.m, -w.m).astype(np.int32)
+    f = w.f[::3]
+    hg = gpu_waveform(ctx, w, partners=False, f=f)
+    sp = splines(w.traj, w.A)
+    vs = [Voice(int(m), int(n), mu, False, w.scale * complex(swsh(-2, int(l), int(m), w.theta, w.phi)))
+          for mu, (l, m, n) in enumerate(zip(w.l, w.m, w.n))]
+    ho = waveform_voices(w.traj, sp, vs, f)
+    _check64(hg, ho, "no-partners")
+
+
+def test_mixed_precision_against_fp64(ctx):
+    for w in [W.config1(), W.config2()]:
+        h64 = gpu_waveform(ctx, w, "fp64")
+        hmx = gpu_waveform(ctx, w, "mixed")
+        for g, o in zip(hmx, h64):
+            err = rel_l2(g.astype(np.complex128), o)
+            print(f"mixed vs fp64 {w.meta['name']}: {err:.3e}")
+            assert err <= TOLMIX
+
+
+def test_deterministic_bitwise(ctx):
+    w = W.config1()
+    a = gpu_waveform(ctx, w)
+    b = gpu_waveform(ctx, w)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_outputs_fully_overwritten(ctx):
+    w = W.config1()
+    dw = fd.DeviceWaveform.from_workload(w, device=ctx.device)
+    hp = torch.full((dw.Nf,), complex(float("nan"), float("nan")), dtype=torch.complex128, device=ctx.device)
+    hc = hp.clone()
+    ctx.waveform_dev(dw, "fp64", out=(hp, hc))
+    torch.cuda.synchronize()
+    assert not torch.isnan(torch.view_as_real(hp)).any() and not torch.isnan(torch.view_as_real(hc)).any()
+    assert hp[0] == 0
+
+
+def test_degenerate_inputs(ctx):
+    w = W.config1()
+    # all frequencies outside every voice
+    f = np.linspace(0.2, 0.3, 1000)
+    hp, hc = gpu_waveform(ctx, w, f=f)
+    assert np.all(hp == 0) and np.all(hc == 0)
+    # only the DC bin
+    hp, hc = gpu_waveform(ctx, w, f=np.zeros(1))
+    assert hp[0] == 0 and hc[0] == 0
+    # minimal trajectory (K = 4) and an (l,0,0) mode with F = 0
+    w4 = W.config1(K=4)
+    w4.l = np.array([2, 3], np.int32)
+    w4.m = np.array([2, 0], np.int32)
+    w4.n = np.array([1, 0], np.int32)
+    w4.A = w4.A[:2]
+    f = w4.f[::5]
+    _check64(gpu_waveform(ctx, w4, f=f), oracle.waveform(w4, f=f), "K=4")
+
+
+def test_invalid_arguments_leave_outputs(ctx):
+    w = W.config1()
+    dw = fd.DeviceWaveform.from_workload(w, device=ctx.device)
+    hp = torch.full((dw.Nf,), 7 + 7j, dtype=torch.complex128, device=ctx.device)
+    hc = hp.clone()
+    d = dw.desc()
+    d.K = 3
+    import ctypes
+    st = ctx._lib.fdemri_waveform(ctx._h, ctypes.byref(d), 0, fd._ptr(hp), fd._ptr(hc), fd._stream(ctx.device))
+    assert st == fd.FDEMRI_EINVAL
+    assert b"K=3" in ctx._lib.fdemri_last_error(ctx._h)
+    torch.cuda.synchronize()
+    assert torch.all(hp == 7 + 7j)
