@@ -150,47 +150,56 @@ def _roots_in_piece(t, cF, knotF, ta, tb, Fa, Fb, y):
     return seg, 0.5 * (lo + hi)
 
 
+def root_terms(traj, sp, v, f):
+    """O3-O6 for one voice: yields, for each monotonic piece, the side s
+    (+1: the terms feed h(+f); -1: h(-f)), the bin indices k, the spline
+    segment and tau of each root, the amplitude spline value A(t_j) (before
+    conjugation) and E = e^{i psi} G, so that the voice adds
+    factor * (A or conj A) * E to h(s f_k)."""
+    t = traj.t
+    f = np.asarray(f, np.float64)
+    pos_f = f > 0
+    cF = v.m * sp["Fphi"] + v.n * sp["Fr"]
+    knotF = v.m * traj.Fphi + v.n * traj.Fr
+    cPphi = sp["Phiphi"].astype(np.longdouble)
+    cPr = sp["Phir"].astype(np.longdouble)
+    t_ld = t.astype(np.longdouble)
+    for ta, tb, Fa, Fb in voice_pieces(t, cF, knotF):
+        lo_F, hi_F = min(Fa, Fb), max(Fa, Fb)
+        s = 1.0 if (Fa + Fb) > 0 else -1.0        # sign of F_V on the piece
+        dirV = 1.0 if Fb > Fa else -1.0          # direction of F_V on the piece
+        k = np.nonzero(pos_f & (s * f >= lo_F) & (s * f <= hi_F))[0]
+        if k.size == 0:
+            continue
+        y = s * f[k]
+        seg, tau = _roots_in_piece(t, cF, knotF, ta, tb, Fa, Fb, y)
+        c = cF[:, seg]
+        Fd = (3.0 * c[0] * tau + 2.0 * c[1]) * tau + c[2]
+        Fdd = 6.0 * c[0] * tau + 2.0 * c[1]
+        Gj = G(Fd, Fdd, dirV)
+        # O6 phase in extended precision
+        tau_ld = tau.astype(np.longdouble)
+        phiV = (v.m * _horner(cPphi[:, seg], tau_ld) + v.n * _horner(cPr[:, seg], tau_ld))
+        psi = TWO_PI_LD * y.astype(np.longdouble) * (t_ld[seg] + tau_ld) - phiV
+        psi = psi - TWO_PI_LD * np.round(psi / TWO_PI_LD)
+        psi = psi.astype(np.float64)
+        amp = _horner(sp["A"][:, seg, v.mode], tau)
+        E = (np.cos(psi) + 1j * np.sin(psi)) * Gj
+        yield s, k, seg, tau, amp, E
+
+
 def waveform_voices(traj, sp, voices, f, return_sides=False):
     """O3-O7 for an explicit voice list.  Returns (h_plus, h_cross) on f."""
-    t = traj.t
     f = np.asarray(f, np.float64)
     hpos = np.zeros(f.size, np.complex128)
     hneg = np.zeros(f.size, np.complex128)
-    pos_f = f > 0
-    cFphi, cFr = sp["Fphi"], sp["Fr"]
-    cPphi = sp["Phiphi"].astype(np.longdouble)
-    cPr = sp["Phir"].astype(np.longdouble)
-    cA = sp["A"]
-    t_ld = t.astype(np.longdouble)
     for v in voices:
-        cF = v.m * cFphi + v.n * cFr
-        knotF = v.m * traj.Fphi + v.n * traj.Fr
-        for ta, tb, Fa, Fb in voice_pieces(t, cF, knotF):
-            lo_F, hi_F = min(Fa, Fb), max(Fa, Fb)
-            s = 1.0 if (Fa + Fb) > 0 else -1.0        # sign of F_V on the piece
-            dirV = 1.0 if Fb > Fa else -1.0          # direction of F_V on the piece
-            k = np.nonzero(pos_f & (s * f >= lo_F) & (s * f <= hi_F))[0]
-            if k.size == 0:
-                continue
-            y = s * f[k]
-            seg, tau = _roots_in_piece(t, cF, knotF, ta, tb, Fa, Fb, y)
-            c = cF[:, seg]
-            Fd = (3.0 * c[0] * tau + 2.0 * c[1]) * tau + c[2]
-            Fdd = 6.0 * c[0] * tau + 2.0 * c[1]
-            Gj = G(Fd, Fdd, dirV)
-            # O6 phase in extended precision
-            tau_ld = tau.astype(np.longdouble)
-            phiV = (v.m * _horner(cPphi[:, seg], tau_ld) + v.n * _horner(cPr[:, seg], tau_ld))
-            psi = TWO_PI_LD * y.astype(np.longdouble) * (t_ld[seg] + tau_ld) - phiV
-            psi = psi - TWO_PI_LD * np.round(psi / TWO_PI_LD)
-            psi = psi.astype(np.float64)
-            amp = _horner(cA[:, seg, v.mode], tau)
-            if v.conj:
-                amp = np.conj(amp)
-            term = v.factor * amp * (np.cos(psi) + 1j * np.sin(psi)) * Gj
+        for s, k, seg, tau, amp, E in root_terms(traj, sp, v, f):
+            term = v.factor * (np.conj(amp) if v.conj else amp) * E
             np.add.at(hpos if s > 0 else hneg, k, term)
     hp = 0.5 * (hpos + np.conj(hneg))
     hc = 0.5j * (hpos - np.conj(hneg))
+    pos_f = f > 0
     hp[~pos_f] = 0
     hc[~pos_f] = 0
     if return_sides:
