@@ -25,7 +25,7 @@ METRIC = "waveforms/s + mode·bin evals/s (fwd, fwd+adjoint) at stated error vs 
 # the per-root factor of Eq. extendedspa1, the phase, the amplitude spline and
 # the two complex accumulations), in FP64 operations; see the design notes for
 # the breakdown.
-FLOPS_PER_EVAL = 182
+FLOPS_PER_EVAL = 186
 PEAK_FP64_VALU = 78.6e12
 
 

@@ -140,22 +140,30 @@ fdemri_status fdemri_waveform_batch(fdemri_ctx *ctx, int32_t B, const fdemri_wav
                                     hipStream_t stream);
 
 /*
- * Vector-Jacobian product of the waveform (the gradient of a real loss such
- * as the Whittle log-likelihood of Eq. likelihood).
- * g_hp, g_hc : [Nf] complex cotangents dL/dRe h + i dL/dIm h, of the
- *   precision's type.
- * Outputs (device, fully overwritten; any may be NULL to skip):
- *   gA   : [Nm][K-1][4][2] double, gradient w.r.t. the amplitude spline
- *          coefficients a_k (A(t_i + tau) = sum_k a_k tau^k), same convention.
- *   gPhi : [2][K-1][4] double, gradient w.r.t. the Phi_phi and Phi_r spline
- *          coefficients.
- *   g_scalars : [5] double: d/dtheta, d/dphi, d/dscale, d/dPhi_phi0, d/dPhi_r0
- *          (the last two are the sums of the constant-coefficient gradients).
- * The frequency splines (t(f)) are held fixed.
+ * Vector-Jacobian product of the waveform: the gradient of a real loss L of
+ * h_+ and h_x, such as the Whittle log-likelihood of Eq. likelihood, with
+ * respect to the amplitude and phase splines, the viewing angles, the scale
+ * and the initial phases.  The forward terms of Eq. extendedspa1 are
+ * recomputed (not stored); the frequency splines, and hence the root times
+ * t(f) of Eq. cubic_equation, are held fixed.
+ * g_hp, g_hc : [Nf] complex cotangents dL/dRe h + i dL/dIm h, interleaved,
+ *   of the precision's type (double for FDEMRI_FP64, float for FDEMRI_MIXED).
+ * Outputs (device, fully overwritten; each may be NULL to skip):
+ *   gA        : [Nm][K-1][4][2] double, dL/d(amplitude spline coefficients)
+ *               a_k of A(t_i + tau) = sum_k a_k tau^k, same complex convention.
+ *   gPhi      : [2][K-1][4] double, dL/d(Phi_phi and Phi_r spline coefficients),
+ *               ascending powers of tau.
+ *   gA_knots  : [Nm][K][2] double, dL/d(amplitude knot values A of the desc),
+ *               through the transposed not-a-knot spline.
+ *   gPhi_knots: [2][K] double, dL/d(Phi_phi and Phi_r knot values).
+ *   g_scalars : [5] double: dL/dtheta, dL/dphi, dL/dscale, dL/dPhi_phi0,
+ *               dL/dPhi_r0 (the last two: a common offset of all Phi knots).
+ * The result is deterministic (fixed reduction order, no atomics).
  */
 fdemri_status fdemri_vjp(fdemri_ctx *ctx, const fdemri_waveform_desc *desc, fdemri_prec prec,
                          const void *g_hp, const void *g_hc, double *gA, double *gPhi,
-                         double *g_scalars, hipStream_t stream);
+                         double *gA_knots, double *gPhi_knots, double *g_scalars,
+                         hipStream_t stream);
 
 /*
  * Count of mode-bin evaluations of the last fdemri_waveform call on this

@@ -80,7 +80,7 @@ def lib():
         L.fdemri_waveform_batch.argtypes = [vp, i32, ctypes.POINTER(WaveformDesc), ctypes.c_int,
                                             ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         L.fdemri_waveform_batch.restype = ctypes.c_int
-        L.fdemri_vjp.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_int, vp, vp, vp, vp, vp, vp]
+        L.fdemri_vjp.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
         L.fdemri_vjp.restype = ctypes.c_int
         L.fdemri_last_eval_count.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
         L.fdemri_last_eval_count.restype = ctypes.c_int
@@ -226,6 +226,34 @@ class Context:
         dw = DeviceWaveform(t, Fphi, Fr, Phiphi, Phir, l, m, n, A, theta, phi, scale, f,
                             partners=partners, device=self.device)
         return self.waveform_dev(dw, prec)
+
+    def vjp_dev(self, dw: DeviceWaveform, g_hp, g_hc, prec="fp64", coef=True, knots=True):
+        """Gradients of a real loss from the cotangents g = dL/dRe h + i dL/dIm h.
+        Returns a dict with (as requested) gA [Nm, K-1, 4] complex128 (spline
+        coefficients), gPhi [2, K-1, 4], gA_knots [Nm, K] complex128,
+        gPhi_knots [2, K] and g_scalars [5] (theta, phi, scale, Phi_phi0, Phi_r0)."""
+        p = PRECISIONS[prec]
+        ctype = torch.complex128 if p == FDEMRI_FP64 else torch.complex64
+        g_hp = g_hp.to(ctype).contiguous()
+        g_hc = g_hc.to(ctype).contiguous()
+        assert g_hp.numel() == dw.Nf and g_hc.numel() == dw.Nf
+        K, Nm, dev = dw.K, dw.Nm, dw.device
+        out = {"g_scalars": torch.empty(5, dtype=torch.float64, device=dev)}
+        if coef:
+            out["gA"] = torch.empty(Nm, K - 1, 4, 2, dtype=torch.float64, device=dev)
+            out["gPhi"] = torch.empty(2, K - 1, 4, dtype=torch.float64, device=dev)
+        if knots:
+            out["gA_knots"] = torch.empty(Nm, K, 2, dtype=torch.float64, device=dev)
+            out["gPhi_knots"] = torch.empty(2, K, dtype=torch.float64, device=dev)
+        d = dw.desc()
+        self._check(self._lib.fdemri_vjp(
+            self._h, ctypes.byref(d), p, _ptr(g_hp), _ptr(g_hc), _ptr(out.get("gA")), _ptr(out.get("gPhi")),
+            _ptr(out.get("gA_knots")), _ptr(out.get("gPhi_knots")), _ptr(out["g_scalars"]), _stream(self.device)))
+        if coef:
+            out["gA"] = torch.view_as_complex(out["gA"])
+        if knots:
+            out["gA_knots"] = torch.view_as_complex(out["gA_knots"])
+        return out
 
     def waveform_batch(self, dws, prec="fp64", outs=None):
         """Several waveforms in one call; returns a list of (h_+, h_x)."""

@@ -23,6 +23,12 @@ struct GatherArgs;
 hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp, void* hc, bool mixed, int bpl,
                               hipStream_t stream);
 hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, hipStream_t stream);
+hipError_t launch_vjp(const Prepared& p, const float* acoef32, bool mixed, const void* g_hp, const void* g_hc,
+                      double* gA_coef, double* PZ, double* Upart, double* T3, double* gPhi_coef,
+                      double* g_scalars, const int32_t* l, const int32_t* m, double theta, double phi, double scale,
+                      uint32_t flags, hipStream_t stream);
+hipError_t launch_spline_adjoint(int K, const double* t, int Nm, const double* gPhi_coef, const double* gA_coef,
+                                 double* gPhi_knots, double* gA_knots, hipStream_t stream);
 }  // namespace fdemri
 
 using namespace fdemri;
@@ -66,10 +72,12 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Scratch layout of one waveform.
 struct Layout {
-  size_t tcoef, acoef, acoef32, modes, mode_kr, pieces, evals, env, total;
+  size_t tcoef, acoef, acoef32, modes, mode_kr, pieces, evals, env;
+  size_t gA, PZ, Upart, T3, gPhi, gsc;  // adjoint scratch (0 bytes unless requested)
+  size_t total;
 };
 
-Layout layout_for(int K, int Nm, bool mixed) {
+Layout layout_for(int K, int Nm, bool mixed, bool vjp = false) {
   Layout L{};
   size_t off = 0;
   const size_t nseg = (size_t)K - 1;
@@ -86,6 +94,13 @@ Layout layout_for(int K, int Nm, bool mixed) {
   L.pieces = take((size_t)Nm * kMaxPieces * sizeof(Piece));
   L.evals = take((size_t)Nm * sizeof(int64_t));
   L.env = take(2 * sizeof(int32_t));
+  const size_t units = vjp ? (size_t)Nm * nseg : 0;
+  L.gA = take(units * 8 * sizeof(double));
+  L.PZ = take(units * 4 * sizeof(double));
+  L.Upart = take(units * 4 * sizeof(double));
+  L.T3 = take(vjp ? (size_t)Nm * 4 * sizeof(double) : 0);
+  L.gPhi = take(vjp ? 2 * nseg * 4 * sizeof(double) : 0);
+  L.gsc = take(vjp ? 8 * sizeof(double) : 0);
   L.total = off;
   return L;
 }
@@ -213,30 +228,24 @@ fdemri_status fdemri_sync_flags(fdemri_ctx* c, hipStream_t stream, uint32_t* fla
   return FDEMRI_OK;
 }
 
-fdemri_status fdemri_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemri_prec prec, void* hp, void* hc,
-                              hipStream_t stream) {
-  if (!c) return FDEMRI_EINVAL;
-  c->err.clear();
-  fdemri_status st = validate(c, d);
-  if (st != FDEMRI_OK) return st;
-  if (prec != FDEMRI_FP64 && prec != FDEMRI_MIXED) return fail(c, FDEMRI_EINVAL, "unknown precision %d", (int)prec);
-  if (!hp || !hc) return fail(c, FDEMRI_EINVAL, "NULL output pointer");
-  const bool mixed = prec == FDEMRI_MIXED;
-  hipError_t e = hipSetDevice(c->device);
-  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-  const Layout L = layout_for(d->K, d->Nm, mixed);
-  st = ensure_ws(c, L.total);
-  if (st != FDEMRI_OK) return st;
+}  // extern "C"
+
+namespace {
+
+// Enqueue the per-waveform preparation (spline coefficients, mode constants,
+// piece table, FP32 amplitude table) into the workspace described by L.
+fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, const Layout& L, Prepared& p,
+                      float*& acoef32, hipStream_t stream) {
   char* w = c->ws;
   double* tcoef = (double*)(w + L.tcoef);
   double* acoef = (double*)(w + L.acoef);
-  float* acoef32 = mixed ? (float*)(w + L.acoef32) : nullptr;
+  acoef32 = mixed ? (float*)(w + L.acoef32) : nullptr;
   ModeConst* modes = (ModeConst*)(w + L.modes);
   int2* mode_kr = (int2*)(w + L.mode_kr);
   Piece* pieces = (Piece*)(w + L.pieces);
   int64_t* evals = (int64_t*)(w + L.evals);
   int32_t* env = (int32_t*)(w + L.env);
-
+  hipError_t e;
   {
     ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream);
     e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, d->Nm, tcoef, acoef, env, stream);
@@ -249,7 +258,6 @@ fdemri_status fdemri_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, fdem
     if (e == hipSuccess && mixed) e = launch_amp32(d->Nm, d->K, d->t, acoef, acoef32, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "piece kernel launch");
-  Prepared p;
   p.K = d->K;
   p.Nm = d->Nm;
   p.Nf = d->Nf;
@@ -265,13 +273,72 @@ fdemri_status fdemri_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, fdem
   p.mode_kr = mode_kr;
   p.pieces = pieces;
   p.env = env;
+  c->last_evals = evals;
+  c->last_Nm = d->Nm;
+  return FDEMRI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fdemri_status fdemri_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemri_prec prec, void* hp, void* hc,
+                              hipStream_t stream) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  fdemri_status st = validate(c, d);
+  if (st != FDEMRI_OK) return st;
+  if (prec != FDEMRI_FP64 && prec != FDEMRI_MIXED) return fail(c, FDEMRI_EINVAL, "unknown precision %d", (int)prec);
+  if (!hp || !hc) return fail(c, FDEMRI_EINVAL, "NULL output pointer");
+  const bool mixed = prec == FDEMRI_MIXED;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const Layout L = layout_for(d->K, d->Nm, mixed);
+  st = ensure_ws(c, L.total);
+  if (st != FDEMRI_OK) return st;
+  Prepared p;
+  float* acoef32 = nullptr;
+  st = prepare(c, d, mixed, L, p, acoef32, stream);
+  if (st != FDEMRI_OK) return st;
   {
     ProfScope ps(c, FDEMRI_KERNEL_GATHER, stream);
     e = launch_gather_flat(p, acoef32, hp, hc, mixed, c->bpl, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "gather kernel launch");
-  c->last_evals = evals;
-  c->last_Nm = d->Nm;
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_vjp(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemri_prec prec, const void* g_hp,
+                         const void* g_hc, double* gA, double* gPhi, double* gA_knots, double* gPhi_knots,
+                         double* g_scalars, hipStream_t stream) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  fdemri_status st = validate(c, d);
+  if (st != FDEMRI_OK) return st;
+  if (prec != FDEMRI_FP64 && prec != FDEMRI_MIXED) return fail(c, FDEMRI_EINVAL, "unknown precision %d", (int)prec);
+  if (!g_hp || !g_hc) return fail(c, FDEMRI_EINVAL, "NULL cotangent pointer");
+  const bool mixed = prec == FDEMRI_MIXED;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const Layout L = layout_for(d->K, d->Nm, mixed, true);
+  st = ensure_ws(c, L.total);
+  if (st != FDEMRI_OK) return st;
+  Prepared p;
+  float* acoef32 = nullptr;
+  st = prepare(c, d, mixed, L, p, acoef32, stream);
+  if (st != FDEMRI_OK) return st;
+  char* w = c->ws;
+  double* gA_coef = gA ? gA : (double*)(w + L.gA);
+  double* gPhi_coef = gPhi ? gPhi : (double*)(w + L.gPhi);
+  double* gsc = g_scalars ? g_scalars : (double*)(w + L.gsc);
+  {
+    ProfScope ps(c, FDEMRI_KERNEL_VJP, stream);
+    e = launch_vjp(p, acoef32, mixed, g_hp, g_hc, gA_coef, (double*)(w + L.PZ), (double*)(w + L.Upart),
+                   (double*)(w + L.T3), gPhi_coef, gsc, d->l, d->m, d->theta, d->phi, d->scale, d->flags, stream);
+    if (e == hipSuccess && (gA_knots || gPhi_knots))
+      e = launch_spline_adjoint(d->K, d->t, d->Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "vjp kernel launch");
   return FDEMRI_OK;
 }
 
@@ -330,9 +397,5 @@ fdemri_status fdemri_profile_read(fdemri_ctx* c, hipStream_t stream, double* ms_
   return FDEMRI_OK;
 }
 
-fdemri_status fdemri_vjp(fdemri_ctx* c, const fdemri_waveform_desc*, fdemri_prec, const void*, const void*, double*,
-                         double*, double*, hipStream_t) {
-  return fail(c, FDEMRI_ENOTSUP, "fdemri_vjp: not available in this build");
-}
 
 }  // extern "C"

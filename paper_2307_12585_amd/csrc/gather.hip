@@ -22,7 +22,7 @@
 // FP64 path: everything in double.  Mixed path: root, derivatives, phase and
 // its reduction in double; the special function, sincos, amplitude spline and
 // products in float with compensated (Kahan) accumulation.
-#include "spa.hpp"
+#include "evalcore.hpp"
 
 namespace fdemri {
 
@@ -77,8 +77,8 @@ __device__ __forceinline__ void eval_bin(const double f, const Piece& P, const d
   const int s = P.s, d = P.d;
   const double sd = (double)s;
   const double dd_ = (double)d;
-  // 1. spline segment holding f: largest i in [seg_a, seg_b] whose start value
-  //    precedes f in the direction of the piece (ties go to the lower segment)
+  // spline segment holding f: largest i in [seg_a, seg_b] whose start value
+  // precedes f in the direction of the piece (ties go to the lower segment)
   int lo = P.seg_a, hi = P.seg_b;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -89,111 +89,51 @@ __device__ __forceinline__ void eval_bin(const double f, const Piece& P, const d
       hi = mid - 1;
   }
   const int i = lo;
-  const double ti = L.t[i];
-  const double h = L.t[i + 1] - ti;
-  const double F0 = knot_freq(m, L.Fp[i], n, L.Fr[i]);
+  SegData S;
+  S.ti = L.t[i];
+  S.h = L.t[i + 1] - S.ti;
+  S.F0 = knot_freq(m, L.Fp[i], n, L.Fr[i]);
+  S.F1 = knot_freq(m, L.Fp[i + 1], n, L.Fr[i + 1]);
   const double* cf = L.cF + i * 6;
-  const double a1 = m * cf[0] + n * cf[3];
-  const double a2 = m * cf[1] + n * cf[4];
-  const double a3 = m * cf[2] + n * cf[5];
-  const bool first = (i == P.seg_a), last = (i == P.seg_b);
-  const double tl = first ? P.tau_a : 0.0;
-  const double th = last ? P.tau_b : h;
-  const double gl = first ? P.g_a : sd * F0;
-  const double gh = last ? P.g_b : sd * knot_freq(m, L.Fp[i + 1], n, L.Fr[i + 1]);
-
-  // 2. root of s (F0 + a1 tau + a2 tau^2 + a3 tau^3) = f in [tl, th]
-  double tau = tl;
-  {
-    const double dg = gh - gl;
-    if (dg != 0.0) tau = tl + (f - gl) / dg * (th - tl);
-    tau = fmin(fmax(tau, tl), th);
-    double blo = tl, bhi = th;
-    const double tol = 4e-16 * fmax(h, 1.0);
-    for (int it = 0; it < 100; ++it) {
-      const double r = sd * (F0 + tau * (a1 + tau * (a2 + tau * a3))) - f;
-      if (r == 0.0) break;
-      const double gp = sd * (a1 + tau * (2.0 * a2 + 3.0 * a3 * tau));
-      if (dd_ * r < 0.0)
-        blo = tau;
-      else
-        bhi = tau;
-      double tn = tau - r / gp;
-      if (!(tn > blo && tn < bhi)) tn = 0.5 * (blo + bhi);
-      const double step = fabs(tn - tau);
-      tau = tn;
-      if (step <= tol || !(bhi - blo > tol)) break;
-    }
-  }
-  // 3. local derivatives of |F_V| at the root
-  const double gd = sd * (a1 + tau * (2.0 * a2 + 3.0 * a3 * tau));
-  const double gdd = sd * (2.0 * a2 + 6.0 * a3 * tau);
-
-  // 4. phase psi = 2 pi f (t_i + tau) - s Phi_V(t_i + tau), reduced mod 2 pi
+  S.a1 = m * cf[0] + n * cf[3];
+  S.a2 = m * cf[1] + n * cf[4];
+  S.a3 = m * cf[2] + n * cf[5];
   const double* cp = L.cP + i * 6;
-  const double b1 = m * cp[0] + n * cp[3];
-  const double b2 = m * cp[1] + n * cp[4];
-  const double b3 = m * cp[2] + n * cp[5];
-  double psi;
-  {
-    const dd ft = two_prod(f, ti);
-    dd q = two_prod(ft.hi, kTwoPiHi);
-    q.lo = __builtin_fma(ft.hi, kTwoPiLo, __builtin_fma(ft.lo, kTwoPiHi, q.lo));
-    const dd pm = two_prod(m, L.Pp[i]);
-    const dd pn = two_prod(n, L.Pr[i]);
-    dd z = two_sum(pm.hi, pn.hi);
-    z.lo += pm.lo + pn.lo;
-    dd b = two_sum(q.hi, -sd * z.hi);
-    b.lo += q.lo - sd * z.lo;
-    const double kk = rint(b.hi * kInvTwoPi);
-    const dd kc = two_prod(kk, kTwoPiHi);
-    const double red = (b.hi - kc.hi) + ((b.lo - kc.lo) - kk * kTwoPiLo);
-    const double small = tau * (kTwoPiHi * f - sd * (b1 + tau * (b2 + tau * b3)));
-    psi = red + small;
-  }
+  S.b1 = m * cp[0] + n * cp[3];
+  S.b2 = m * cp[1] + n * cp[4];
+  S.b3 = m * cp[2] + n * cp[5];
+  S.Ppi = L.Pp[i];
+  S.Pri = L.Pr[i];
+  const Bracket B = make_bracket(P, i, sd, S);
+  const double tau = solve_root(f, sd, dd_, S, B);
 
   if constexpr (!MIXED) {
-    const double2 G = spa_factor64(gd, gdd, d);
-    double sn, cs;
-    sincos(psi, &sn, &cs);
-    const double Er = cs * G.x - sn * G.y;
-    const double Ei = cs * G.y + sn * G.x;
-    // 5. amplitude spline A(t_i + tau)
-    const double* c = ac + (size_t)i * 8;
-    const double Ar = c[0] + tau * (c[2] + tau * (c[4] + tau * c[6]));
-    const double Ai = c[1] + tau * (c[3] + tau * (c[5] + tau * c[7]));
-    double pr = Ar * cpr - Ai * cpi, pi = Ar * cpi + Ai * cpr;
-    double xr = Ar * cxr - Ai * cxi, xi = Ar * cxi + Ai * cxr;
+    double2 E, A;
+    root_terms64(f, tau, sd, d, m, n, S, ac + (size_t)i * 8, E, A);
+    double pr = A.x * cpr - A.y * cpi, pi = A.x * cpi + A.y * cpr;
+    double xr = A.x * cxr - A.y * cxi, xi = A.x * cxi + A.y * cxr;
     if (s < 0) {
       pi = -pi;
       xi = -xi;
     }
-    acc.v[0] += pr * Er - pi * Ei;
-    acc.v[1] += pr * Ei + pi * Er;
-    acc.v[2] += xr * Er - xi * Ei;
-    acc.v[3] += xr * Ei + xi * Er;
+    acc.v[0] += pr * E.x - pi * E.y;
+    acc.v[1] += pr * E.y + pi * E.x;
+    acc.v[2] += xr * E.x - xi * E.y;
+    acc.v[3] += xr * E.y + xi * E.x;
   } else {
-    const float2 G = spa_factor32(gd, gdd, d);
-    const double psr = psi - kTwoPiHi * rint(psi * kInvTwoPi);
-    float sn, cs;
-    sincosf((float)psr, &sn, &cs);
-    const float Er = cs * G.x - sn * G.y;
-    const float Ei = cs * G.y + sn * G.x;
-    const float u = (float)(tau / h);
-    const float* c = ac32 + (size_t)i * 8;
-    const float Ar = c[0] + u * (c[2] + u * (c[4] + u * c[6]));
-    const float Ai = c[1] + u * (c[3] + u * (c[5] + u * c[7]));
+    float2 E, A;
+    root_terms32(f, tau, sd, d, m, n, S, ac32 + (size_t)i * 8, E, A);
     const float fcpr = (float)cpr, fcpi = (float)cpi, fcxr = (float)cxr, fcxi = (float)cxi;
-    float pr = Ar * fcpr - Ai * fcpi, pi = Ar * fcpi + Ai * fcpr;
-    float xr = Ar * fcxr - Ai * fcxi, xi = Ar * fcxi + Ai * fcxr;
+    float pr = A.x * fcpr - A.y * fcpi, pi = A.x * fcpi + A.y * fcpr;
+    float xr = A.x * fcxr - A.y * fcxi, xi = A.x * fcxi + A.y * fcxr;
     if (s < 0) {
       pi = -pi;
       xi = -xi;
     }
-    acc.add(0, pr * Er - pi * Ei);
-    acc.add(1, pr * Ei + pi * Er);
-    acc.add(2, xr * Er - xi * Ei);
-    acc.add(3, xr * Ei + xi * Er);
+    acc.add(0, pr * E.x - pi * E.y);
+    acc.add(1, pr * E.y + pi * E.x);
+    acc.add(2, xr * E.x - xi * E.y);
+    acc.add(3, xr * E.y + xi * E.x);
   }
 }
 

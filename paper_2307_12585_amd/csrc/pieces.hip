@@ -22,48 +22,9 @@
 #include <climits>
 
 #include "fdemri_internal.hpp"
+#include "harmonics.hpp"
 
 namespace fdemri {
-
-// ---------------------------------------------------------------- harmonics
-// -2Y_lm(theta, phi) by the Goldberg explicit sum.
-__device__ double2 swsh_m2(int l, int m, double theta, double phi) {
-  const int s = -2;
-  // (l+m)!(l-m)! / ((l+s)!(l-s)!) as a product of consecutive integers
-  double ratio = 1.0;
-  {
-    // (l+m)!/(l-s)!  (l-s = l+2)
-    int a = l + m, b = l - s;
-    if (a >= b)
-      for (int j = b + 1; j <= a; ++j) ratio *= (double)j;
-    else
-      for (int j = a + 1; j <= b; ++j) ratio /= (double)j;
-    // (l-m)!/(l+s)!  (l+s = l-2)
-    a = l - m;
-    b = l + s;
-    if (a >= b)
-      for (int j = b + 1; j <= a; ++j) ratio *= (double)j;
-    else
-      for (int j = a + 1; j <= b; ++j) ratio /= (double)j;
-  }
-  const double pref = ((m & 1) ? -1.0 : 1.0) * sqrt(ratio * (2 * l + 1) / (4.0 * kPi));
-  const double sh = sin(0.5 * theta), ch = cos(0.5 * theta);
-  double acc = 0.0;
-  for (int r = 0; r <= l - s; ++r) {
-    const int b2 = r + s - m;
-    if (b2 < 0 || b2 > l + s) continue;
-    // binomials C(l-s, r) C(l+s, b2), exact in int64 for l <= 40
-    long long c1 = 1, c2 = 1;
-    for (int j = 1; j <= r; ++j) c1 = c1 * (l - s - r + j) / j;
-    for (int j = 1; j <= b2; ++j) c2 = c2 * (l + s - b2 + j) / j;
-    const int k = 2 * r + s - m;
-    const double sign = ((l - r - s) & 1) ? -1.0 : 1.0;
-    acc += sign * (double)c1 * (double)c2 * pow(sh, (double)(2 * l - k)) * pow(ch, (double)k);
-  }
-  double sp, cp;
-  sincos((double)m * phi, &sp, &cp);
-  return make_double2(pref * acc * cp, pref * acc * sp);
-}
 
 struct PieceArgs {
   int32_t K, Nm, Nf;

@@ -1,0 +1,493 @@
+// Adjoint of the frequency-domain mode sum: the gradient of a real loss L
+// of h_+(f), h_x(f) (e.g. the Whittle log-likelihood of Eq. likelihood) with
+// respect to the amplitude and phase spline coefficients, the viewing angles,
+// the distance scale and the initial phases, given the cotangents
+// g = dL/dRe h + i dL/dIm h.
+//
+// Per root (fused partner form, E = e^{i psi} G, A the amplitude spline):
+//   h_+ += (A c_+)^(s) E,  h_x += (A c_x)^(s) E   ((.)^(s): conjugate when s < 0)
+//   dL/da_k    = tau^k [g_+ conj(c_+) + g_x conj(c_x)] conj(E)     (s > 0)
+//              = tau^k conj(g_+ c_+ + g_x c_x) E                   (s < 0)
+//   dL/dc^phi_k = s m tau^k Im Z, dL/dc^r_k = s n tau^k Im Z,
+//              Z = conj(g_+)(A c_+)^(s) E + conj(g_x)(A c_x)^(s) E
+//              (psi depends on -s (m Phi_phi + n Phi_r))
+//   dL = Re(U_+ dc_+) + Re(U_x dc_x),
+//   U_+ = sum conj(g_+) A E (s > 0) + g_+ A conj(E) (s < 0), likewise U_x,
+// and c_+, c_x depend on theta, phi and the scale (d/dphi c = i m c).
+//
+// The forward terms are recomputed, not stored: one wavefront per
+// (mode, spline segment) re-evaluates the roots of every bin whose root lies
+// in that segment (the same segment assignment, bracket and arithmetic as
+// the forward gather) and reduces its contributions in registers.  All
+// further reductions run in a fixed order, so the gradient is deterministic
+// and no atomics are used.
+#include "evalcore.hpp"
+#include "harmonics.hpp"
+
+namespace fdemri {
+
+struct VjpArgs {
+  Prepared p;
+  const float* acoef32;
+  const void* g_hp;
+  const void* g_hc;
+  double* gA;     // [Nm][nseg][8] coefficient gradient (re, im per power)
+  double* PZ;     // [Nm][nseg][4]  sum s tau^k Im Z
+  double* Upart;  // [Nm][nseg][4]  partial U_+ (re, im), U_x (re, im)
+};
+
+__device__ __forceinline__ int first_gt(const double* f, int Nf, double x) {
+  int lo = 0, hi = Nf;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (f[mid] <= x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int first_ge(const double* f, int Nf, double x) {
+  int lo = 0, hi = Nf;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (f[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
+  const Prepared& p = a.p;
+  const int nseg = p.K - 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long unit = (long)blockIdx.x * 4 + wave;
+  if (unit >= (long)p.Nm * nseg) return;
+  const int mu = (int)(unit / nseg), i = (int)(unit % nseg);
+  const ModeConst md = p.modes[mu];
+  const double m = md.m, n = md.n;
+
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+
+  // segment data of this unit (wave-uniform)
+  SegData S;
+  S.ti = p.t[i];
+  S.h = p.t[i + 1] - S.ti;
+  S.F0 = knot_freq(m, p.Fphi[i], n, p.Fr[i]);
+  S.F1 = knot_freq(m, p.Fphi[i + 1], n, p.Fr[i + 1]);
+  {
+    const double* cFp = p.tcoef + ((size_t)0 * nseg + i) * 4;
+    const double* cFr = p.tcoef + ((size_t)1 * nseg + i) * 4;
+    const double* cPp = p.tcoef + ((size_t)2 * nseg + i) * 4;
+    const double* cPr = p.tcoef + ((size_t)3 * nseg + i) * 4;
+    S.a1 = m * cFp[1] + n * cFr[1];
+    S.a2 = m * cFp[2] + n * cFr[2];
+    S.a3 = m * cFp[3] + n * cFr[3];
+    S.b1 = m * cPp[1] + n * cPr[1];
+    S.b2 = m * cPp[2] + n * cPr[2];
+    S.b3 = m * cPp[3] + n * cPr[3];
+  }
+  S.Ppi = p.Phiphi[i];
+  S.Pri = p.Phir[i];
+  const double* acs = p.acoef + ((size_t)mu * nseg + i) * 8;
+  const float* acs32 = MIXED ? a.acoef32 + ((size_t)mu * nseg + i) * 8 : nullptr;
+
+  for (int q = 0; q < md.npieces; ++q) {
+    const Piece P = p.pieces[(size_t)mu * kMaxPieces + q];
+    if (i < P.seg_a || i > P.seg_b || P.k_lo > P.k_hi) continue;
+    const int s = P.s, d = P.d;
+    const double sd = (double)s, dd_ = (double)d;
+    // bins whose root the forward search places in segment i of this piece:
+    // the largest segment j in [seg_a, seg_b] with j == seg_a or d g_j < d f
+    int kA = P.k_lo, kB = P.k_hi;
+    const double gi = sd * S.F0, gi1 = sd * S.F1;
+    if (d > 0) {
+      if (i > P.seg_a) kA = max(kA, first_gt(p.f, p.Nf, gi));
+      if (i < P.seg_b) kB = min(kB, first_gt(p.f, p.Nf, gi1) - 1);
+    } else {
+      if (i > P.seg_a) kB = min(kB, first_ge(p.f, p.Nf, gi) - 1);
+      if (i < P.seg_b) kA = max(kA, first_ge(p.f, p.Nf, gi1));
+    }
+    if (kA > kB) continue;
+    const Bracket B = make_bracket(P, i, sd, S);
+    for (int k = kA + lane; k <= kB; k += 64) {
+      const double f = p.f[k];
+      const double tau = solve_root(f, sd, dd_, S, B);
+      double Er, Ei, Ar, Ai, gpr, gpi, gcr, gci;
+      if constexpr (MIXED) {
+        float2 E, A;
+        root_terms32(f, tau, sd, d, m, n, S, acs32, E, A);
+        Er = E.x;
+        Ei = E.y;
+        // the FP32 amplitude is in the normalised variable u = tau / h
+        Ar = A.x;
+        Ai = A.y;
+        const float2 gp = ((const float2*)a.g_hp)[k];
+        const float2 gc = ((const float2*)a.g_hc)[k];
+        gpr = gp.x;
+        gpi = gp.y;
+        gcr = gc.x;
+        gci = gc.y;
+      } else {
+        double2 E, A;
+        root_terms64(f, tau, sd, d, m, n, S, acs, E, A);
+        Er = E.x;
+        Ei = E.y;
+        Ar = A.x;
+        Ai = A.y;
+        const double2 gp = ((const double2*)a.g_hp)[k];
+        const double2 gc = ((const double2*)a.g_hc)[k];
+        gpr = gp.x;
+        gpi = gp.y;
+        gcr = gc.x;
+        gci = gc.y;
+      }
+      // Q multiplies tau^k in dL/da_k
+      double Qr, Qi;
+      // W = A E (A conj(E) for s < 0) enters U_+, U_x and Z
+      double Wr, Wi;
+      if (s > 0) {
+        // (g_+ conj(c_+) + g_x conj(c_x)) conj(E)
+        const double hr = gpr * md.cp_re + gpi * md.cp_im + gcr * md.cx_re + gci * md.cx_im;
+        const double hi = gpi * md.cp_re - gpr * md.cp_im + gci * md.cx_re - gcr * md.cx_im;
+        Qr = hr * Er + hi * Ei;
+        Qi = hi * Er - hr * Ei;
+        Wr = Ar * Er - Ai * Ei;
+        Wi = Ar * Ei + Ai * Er;
+      } else {
+        // conj(g_+ c_+ + g_x c_x) E
+        const double hr = gpr * md.cp_re - gpi * md.cp_im + gcr * md.cx_re - gci * md.cx_im;
+        const double hi = -(gpr * md.cp_im + gpi * md.cp_re + gcr * md.cx_im + gci * md.cx_re);
+        Qr = hr * Er - hi * Ei;
+        Qi = hr * Ei + hi * Er;
+        Wr = Ar * Er + Ai * Ei;
+        Wi = Ai * Er - Ar * Ei;
+      }
+      // U_+ += conj(g_+) W (s > 0) or g_+ W (s < 0), likewise U_x
+      const double sgi = (s > 0) ? -1.0 : 1.0;
+      const double upr = gpr * Wr - sgi * gpi * Wi, upi = gpr * Wi + sgi * gpi * Wr;
+      const double uxr = gcr * Wr - sgi * gci * Wi, uxi = gcr * Wi + sgi * gci * Wr;
+      // Z = conj(g_+) (A c_+)^(s) E + conj(g_x) (A c_x)^(s) E; Im Z
+      double ImZ;
+      {
+        // (A c)^(s) E: s > 0: A c E = c W; s < 0: conj(A c) E = conj(c) conj(A) E = conj(c) conj(W')
+        double tpr, tpi, txr, txi;
+        if (s > 0) {
+          tpr = md.cp_re * Wr - md.cp_im * Wi;
+          tpi = md.cp_re * Wi + md.cp_im * Wr;
+          txr = md.cx_re * Wr - md.cx_im * Wi;
+          txi = md.cx_re * Wi + md.cx_im * Wr;
+        } else {
+          // conj(A) E = conj(A conj(E)) = conj(W)
+          const double vr = Wr, vi = -Wi;
+          tpr = md.cp_re * vr + md.cp_im * vi;
+          tpi = md.cp_re * vi - md.cp_im * vr;
+          txr = md.cx_re * vr + md.cx_im * vi;
+          txi = md.cx_re * vi - md.cx_im * vr;
+        }
+        ImZ = (gpr * tpi - gpi * tpr) + (gcr * txi - gci * txr);
+      }
+      double pw = 1.0;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        acc[2 * kk] += pw * Qr;
+        acc[2 * kk + 1] += pw * Qi;
+        acc[8 + kk] += sd * pw * ImZ;
+        pw *= tau;
+      }
+      acc[12] += upr;
+      acc[13] += upi;
+      acc[14] += uxr;
+      acc[15] += uxi;
+    }
+  }
+  // wave reduction (fixed butterfly order)
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    acc[q] = v;
+  }
+  if (lane == 0) {
+    if (a.gA) {
+      double* o = a.gA + ((size_t)mu * nseg + i) * 8;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) o[q] = acc[q];
+    }
+    double* z = a.PZ + ((size_t)mu * nseg + i) * 4;
+    double* u = a.Upart + ((size_t)mu * nseg + i) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      z[q] = acc[8 + q];
+      u[q] = acc[12 + q];
+    }
+  }
+}
+
+// gPhi[0][i][k] = sum_mu m_mu PZ[mu][i][k], gPhi[1][i][k] = sum_mu n_mu PZ[mu][i][k]
+__global__ __launch_bounds__(256) void vjp_phi_kernel(int Nm, int nseg, const ModeConst* __restrict__ modes,
+                                                      const double* __restrict__ PZ, double* __restrict__ gPhi) {
+  __shared__ double red[8][256];
+  const int i = blockIdx.x;
+  double v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = 0.0;
+  for (int mu = threadIdx.x; mu < Nm; mu += blockDim.x) {
+    const double m = modes[mu].m, n = modes[mu].n;
+    const double* z = PZ + ((size_t)mu * nseg + i) * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] += m * z[k];
+      v[4 + k] += n * z[k];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = v[q];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) {
+    const int q = threadIdx.x;
+    gPhi[((size_t)(q / 4) * nseg + i) * 4 + (q % 4)] = red[q][0];
+  }
+}
+
+// Per mode: U = sum over segments; contributions to dL/dtheta, dL/dphi, dL/dscale.
+__global__ __launch_bounds__(64) void vjp_modes_kernel(int Nm, int nseg, const int32_t* __restrict__ l,
+                                                       const int32_t* __restrict__ mm, double theta, double phi,
+                                                       double scale, uint32_t flags, const ModeConst* __restrict__ modes,
+                                                       const double* __restrict__ Upart, double* __restrict__ T3) {
+  const int mu = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mu >= Nm) return;
+  double u[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < nseg; ++i) {
+    const double* up = Upart + ((size_t)mu * nseg + i) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] += up[q];
+  }
+  const int li = l[mu], mi = mm[mu];
+  const double4 y = swsh_m2_with_dtheta(li, mi, theta, phi);
+  double4 yp = make_double4(0.0, 0.0, 0.0, 0.0);  // (-1)^l conj(Y_{l,-m}) and its theta derivative
+  if (mi > 0 && !(flags & FDEMRI_NO_PARTNERS)) {
+    const double4 ym = swsh_m2_with_dtheta(li, -mi, theta, phi);
+    const double sg = (li & 1) ? -1.0 : 1.0;
+    yp = make_double4(sg * ym.x, -sg * ym.y, sg * ym.z, -sg * ym.w);
+  }
+  // unit-scale factors cu_+ = (Y + Yp)/2, cu_x = i (Y - Yp)/2 and their theta derivatives
+  const double cpr = 0.5 * (y.x + yp.x), cpi = 0.5 * (y.y + yp.y);
+  const double cxr = -0.5 * (y.y - yp.y), cxi = 0.5 * (y.x - yp.x);
+  const double dpr = 0.5 * (y.z + yp.z), dpi = 0.5 * (y.w + yp.w);
+  const double dxr = -0.5 * (y.w - yp.w), dxi = 0.5 * (y.z - yp.z);
+  auto re_mul = [](double ar, double ai, double br, double bi) { return ar * br - ai * bi; };
+  const double g_scale = re_mul(u[0], u[1], cpr, cpi) + re_mul(u[2], u[3], cxr, cxi);
+  const double g_theta = scale * (re_mul(u[0], u[1], dpr, dpi) + re_mul(u[2], u[3], dxr, dxi));
+  // d c / d phi = i m c
+  const double mphi = (double)mi * scale;
+  const double g_phi = mphi * (re_mul(u[0], u[1], -cpi, cpr) + re_mul(u[2], u[3], -cxi, cxr));
+  double* o = T3 + (size_t)mu * 4;
+  o[0] = g_theta;
+  o[1] = g_phi;
+  o[2] = g_scale;
+  o[3] = 0.0;
+}
+
+// g_scalars = [sum_mu T3 (theta, phi, scale), sum_i gPhi[0][i][0], sum_i gPhi[1][i][0]]
+__global__ __launch_bounds__(256) void vjp_final_kernel(int Nm, int nseg, const double* __restrict__ T3,
+                                                        const double* __restrict__ gPhi, double* __restrict__ out) {
+  __shared__ double red[5][256];
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int mu = threadIdx.x; mu < Nm; mu += blockDim.x) {
+    v[0] += T3[(size_t)mu * 4 + 0];
+    v[1] += T3[(size_t)mu * 4 + 1];
+    v[2] += T3[(size_t)mu * 4 + 2];
+  }
+  for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
+    v[3] += gPhi[((size_t)0 * nseg + i) * 4];
+    v[4] += gPhi[((size_t)1 * nseg + i) * 4];
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = v[q];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int q = 0; q < 5; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Transposed not-a-knot spline: gradient w.r.t. knot values from the
+// gradient w.r.t. segment coefficients (the adjoint of the slope solve of the
+// spline kernel: coefficient terms -> slope and divided-difference adjoints,
+// a transposed tridiagonal solve by parallel cyclic reduction, then the
+// divided differences back to knots).  One workgroup per real series:
+// series 0, 1 = Phi_phi, Phi_r; 2 + 2 mu + part = amplitude mode mu (re, im).
+template <int NT>
+__global__ __launch_bounds__(NT) void spline_adjoint_kernel(int K, const double* __restrict__ t, int Nm,
+                                                            const double* __restrict__ gPhi_coef,
+                                                            const double* __restrict__ gA_coef,
+                                                            double* __restrict__ gPhi_knots,
+                                                            double* __restrict__ gA_knots) {
+  __shared__ double sa[NT], sb[NT], sc[NT], sr[NT], sh[NT], sdb[NT];
+  const int i = threadIdx.x;
+  const int series = blockIdx.x;
+  const int n = K - 1;
+  const bool amp = series >= 2;
+  if (!amp && gPhi_knots == nullptr) return;
+  if (amp && gA_knots == nullptr) return;
+  const int mode = amp ? (series - 2) >> 1 : 0, part = amp ? (series - 2) & 1 : 0;
+  auto gcoef = [&](int seg, int k) -> double {
+    if (amp) return gA_coef[(((size_t)mode * n + seg) * 4 + k) * 2 + part];
+    return gPhi_coef[((size_t)series * n + seg) * 4 + k];
+  };
+  if (i < n) sh[i] = t[i + 1] - t[i];
+  __syncthreads();
+  // transposed tridiagonal rows: sub = c_{i-1}, diag = b_i, super = a_{i+1} of the forward matrix
+  auto fa = [&](int j) -> double {  // forward sub-diagonal a_j
+    if (j <= 0 || j > n) return 0.0;
+    if (j == n) return sh[n - 2] + sh[n - 1];
+    return sh[j];
+  };
+  auto fb = [&](int j) -> double {
+    if (j == 0) return sh[1];
+    if (j == n) return sh[n - 2];
+    return 2.0 * (sh[j - 1] + sh[j]);
+  };
+  auto fc = [&](int j) -> double {  // forward super-diagonal c_j
+    if (j < 0 || j >= n) return 0.0;
+    if (j == 0) return sh[0] + sh[1];
+    return sh[j - 1];
+  };
+  double a = 0.0, b = 1.0, c = 0.0, r = 0.0;
+  double dbar = 0.0;
+  if (i < K) {
+    a = (i >= 1) ? fc(i - 1) : 0.0;
+    b = fb(i);
+    c = (i <= n - 1) ? fa(i + 1) : 0.0;
+    double v = 0.0;
+    if (i < n) {
+      const double h = sh[i];
+      v += gcoef(i, 1) - 2.0 * gcoef(i, 2) / h + gcoef(i, 3) / (h * h);
+      dbar = 3.0 * gcoef(i, 2) / h - 2.0 * gcoef(i, 3) / (h * h);
+    }
+    if (i >= 1) {
+      const double h = sh[i - 1];
+      v += -gcoef(i - 1, 2) / h + gcoef(i - 1, 3) / (h * h);
+    }
+    r = v;
+  }
+  sa[i] = a;
+  sb[i] = b;
+  sc[i] = c;
+  sr[i] = r;
+  __syncthreads();
+  for (int s = 1; s < NT; s <<= 1) {
+    const int im = i - s, ip = i + s;
+    double am = 0.0, bm = 1.0, cm = 0.0, rm = 0.0, ap = 0.0, bp = 1.0, cp = 0.0, rp = 0.0;
+    if (im >= 0) {
+      am = sa[im];
+      bm = sb[im];
+      cm = sc[im];
+      rm = sr[im];
+    }
+    if (ip < NT) {
+      ap = sa[ip];
+      bp = sb[ip];
+      cp = sc[ip];
+      rp = sr[ip];
+    }
+    const double k1 = a / bm, k2 = c / bp;
+    const double na = -am * k1, nc = -cp * k2, nb = b - cm * k1 - ap * k2, nr = r - rm * k1 - rp * k2;
+    __syncthreads();
+    a = na;
+    b = nb;
+    c = nc;
+    r = nr;
+    sa[i] = a;
+    sb[i] = b;
+    sc[i] = c;
+    sr[i] = r;
+    __syncthreads();
+  }
+  const double rbar = r / b;
+  __syncthreads();
+  sr[i] = rbar;
+  __syncthreads();
+  // divided-difference adjoints
+  if (i < n) {
+    double v = 0.0;
+    if (i == 0) v += (2.0 * sh[1] * sh[1] + 3.0 * sh[0] * sh[1]) / (sh[0] + sh[1]) * sr[0];
+    if (i >= 1 && i <= n - 1) v += 3.0 * sh[i - 1] * sr[i];
+    if (i + 1 <= n - 1) v += 3.0 * sh[i + 1] * sr[i + 1];
+    if (i == 1) v += sh[0] * sh[0] / (sh[0] + sh[1]) * sr[0];
+    if (i == n - 2) v += sh[n - 1] * sh[n - 1] / (sh[n - 2] + sh[n - 1]) * sr[n];
+    if (i == n - 1) v += (2.0 * sh[n - 2] * sh[n - 2] + 3.0 * sh[n - 2] * sh[n - 1]) / (sh[n - 2] + sh[n - 1]) * sr[n];
+    dbar += v;
+  }
+  sdb[i] = dbar;
+  __syncthreads();
+  if (i < K) {
+    double y = (i < n) ? gcoef(i, 0) : 0.0;
+    if (i >= 1) y += sdb[i - 1] / sh[i - 1];
+    if (i < n) y -= sdb[i] / sh[i];
+    if (amp)
+      gA_knots[((size_t)mode * K + i) * 2 + part] = y;
+    else
+      gPhi_knots[(size_t)series * K + i] = y;
+  }
+}
+
+hipError_t launch_vjp(const Prepared& p, const float* acoef32, bool mixed, const void* g_hp, const void* g_hc,
+                      double* gA_coef, double* PZ, double* Upart, double* T3, double* gPhi_coef,
+                      double* g_scalars, const int32_t* l, const int32_t* m, double theta, double phi, double scale,
+                      uint32_t flags, hipStream_t stream) {
+  VjpArgs a;
+  a.p = p;
+  a.acoef32 = acoef32;
+  a.g_hp = g_hp;
+  a.g_hc = g_hc;
+  a.gA = gA_coef;
+  a.PZ = PZ;
+  a.Upart = Upart;
+  const int nseg = p.K - 1;
+  const long units = (long)p.Nm * nseg;
+  const unsigned blocks = (unsigned)((units + 3) / 4);
+  if (mixed)
+    vjp_unit_kernel<true><<<blocks, 256, 0, stream>>>(a);
+  else
+    vjp_unit_kernel<false><<<blocks, 256, 0, stream>>>(a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  vjp_phi_kernel<<<nseg, 256, 0, stream>>>(p.Nm, nseg, p.modes, PZ, gPhi_coef);
+  vjp_modes_kernel<<<(p.Nm + 63) / 64, 64, 0, stream>>>(p.Nm, nseg, l, m, theta, phi, scale, flags, p.modes, Upart, T3);
+  vjp_final_kernel<<<1, 256, 0, stream>>>(p.Nm, nseg, T3, gPhi_coef, g_scalars);
+  return hipGetLastError();
+}
+
+hipError_t launch_spline_adjoint(int K, const double* t, int Nm, const double* gPhi_coef, const double* gA_coef,
+                                 double* gPhi_knots, double* gA_knots, hipStream_t stream) {
+  dim3 grid(2 + 2 * Nm);
+  if (K <= 64)
+    spline_adjoint_kernel<64><<<grid, 64, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots);
+  else if (K <= 128)
+    spline_adjoint_kernel<128><<<grid, 128, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots);
+  else if (K <= 256)
+    spline_adjoint_kernel<256><<<grid, 256, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots);
+  else
+    spline_adjoint_kernel<512><<<grid, 512, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots);
+  return hipGetLastError();
+}
+
+}  // namespace fdemri
