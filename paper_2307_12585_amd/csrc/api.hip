@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "fdemri_internal.hpp"
@@ -23,6 +24,14 @@ struct GatherArgs;
 hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp, void* hc, bool mixed, int bpl,
                               hipStream_t stream);
 hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, hipStream_t stream);
+hipError_t launch_spline_batch(const WaveItem* items, int B, const int32_t* series_prefix, int total_series, int Kmax,
+                               hipStream_t stream);
+hipError_t launch_pieces_batch(const WaveItem* items, int B, const int32_t* mode_prefix, int total_modes,
+                               uint32_t* flag_word, hipStream_t stream);
+hipError_t launch_amp32_batch(const WaveItem* items, int B, const int32_t* amp_prefix, int total, hipStream_t stream);
+hipError_t launch_gather_batch(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
+                               int* counter, int Kmax, bool mixed, int bpl, hipStream_t stream);
+int gather_items_per_waveform(int Nf, int bpl);
 hipError_t launch_vjp(const Prepared& p, const float* acoef32, bool mixed, const void* g_hp, const void* g_hc,
                       double* gA_coef, double* PZ, double* Upart, double* T3, double* gPhi_coef,
                       double* g_scalars, const int32_t* l, const int32_t* m, double theta, double phi, double scale,
@@ -39,8 +48,13 @@ struct fdemri_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   uint32_t* flag_word = nullptr;  // device
-  int64_t* last_evals = nullptr;  // device pointer into ws of the last call
-  int last_Nm = 0;
+  // per-mode evaluation counts of the last call: (device pointer, Nm) per waveform
+  std::vector<std::pair<int64_t*, int>> last_evals;
+  // pinned staging of batch records (reused; guarded by an event)
+  char* stage = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_ev = nullptr;
+  bool stage_pending = false;
   int bpl = 4;
   // profiling: event pairs per launch, by kernel class
   bool prof = false;
@@ -210,6 +224,8 @@ void fdemri_destroy(fdemri_ctx* c) {
     (void)hipEventDestroy(r.b);
   }
   for (auto ev : c->pool) (void)hipEventDestroy(ev);
+  if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
+  if (c->stage) (void)hipHostFree(c->stage);
   delete c;
 }
 
@@ -273,8 +289,7 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   p.mode_kr = mode_kr;
   p.pieces = pieces;
   p.env = env;
-  c->last_evals = evals;
-  c->last_Nm = d->Nm;
+  c->last_evals.assign(1, {evals, d->Nm});
   return FDEMRI_OK;
 }
 
@@ -344,15 +359,17 @@ fdemri_status fdemri_vjp(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemri_pr
 
 fdemri_status fdemri_last_eval_count(fdemri_ctx* c, hipStream_t stream, int64_t* count_out) {
   if (!c || !count_out) return fail(c, FDEMRI_EINVAL, "NULL argument");
-  if (!c->last_evals) return fail(c, FDEMRI_EINVAL, "no waveform evaluated on this context yet");
+  if (c->last_evals.empty()) return fail(c, FDEMRI_EINVAL, "no waveform evaluated on this context yet");
   (void)hipSetDevice(c->device);
   hipError_t e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
-  std::vector<int64_t> v(c->last_Nm);
-  e = hipMemcpy(v.data(), c->last_evals, v.size() * sizeof(int64_t), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(c, e, "eval count read");
   int64_t s = 0;
-  for (int64_t x : v) s += x;
+  for (auto& pr : c->last_evals) {
+    std::vector<int64_t> v(pr.second);
+    e = hipMemcpy(v.data(), pr.first, v.size() * sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "eval count read");
+    for (int64_t x : v) s += x;
+  }
   *count_out = s;
   return FDEMRI_OK;
 }
@@ -362,10 +379,128 @@ fdemri_status fdemri_waveform_batch(fdemri_ctx* c, int32_t B, const fdemri_wavef
   if (!c) return FDEMRI_EINVAL;
   c->err.clear();
   if (B < 0 || (B > 0 && (!descs || !hp || !hc))) return fail(c, FDEMRI_EINVAL, "invalid batch arguments");
+  if (B == 0) return FDEMRI_OK;
+  if (prec != FDEMRI_FP64 && prec != FDEMRI_MIXED) return fail(c, FDEMRI_EINVAL, "unknown precision %d", (int)prec);
+  const bool mixed = prec == FDEMRI_MIXED;
+  int Kmax = 0;
+  int64_t n_series = 0, n_modes = 0, n_amp = 0, n_items = 0;
+  std::vector<Layout> Ls(B);
+  std::vector<size_t> base(B);
+  size_t off = 0;
   for (int b = 0; b < B; ++b) {
-    fdemri_status st = fdemri_waveform(c, &descs[b], prec, hp[b], hc[b], stream);
-    if (st != FDEMRI_OK) return st;
+    fdemri_status st = validate(c, &descs[b]);
+    if (st != FDEMRI_OK) return fail(c, st, "waveform %d: %s", b, c->err.c_str());
+    if (!hp[b] || !hc[b]) return fail(c, FDEMRI_EINVAL, "waveform %d: NULL output pointer", b);
+    Ls[b] = layout_for(descs[b].K, descs[b].Nm, mixed);
+    base[b] = off;
+    off = align_up(off + Ls[b].total, 256);
+    Kmax = std::max(Kmax, (int)descs[b].K);
+    n_series += 4 + descs[b].Nm;
+    n_modes += descs[b].Nm;
+    n_amp += (int64_t)descs[b].Nm * (descs[b].K - 1);
+    n_items += gather_items_per_waveform(descs[b].Nf, c->bpl);
   }
+  if (n_amp > 0x7fffffff || n_items > 0x7fffffff || n_series > 0x7fffffff)
+    return fail(c, FDEMRI_ENOTSUP, "batch too large for 32-bit work indices");
+  // device records and prefixes after the per-waveform scratch
+  const size_t items_off = off;
+  const size_t items_bytes = (size_t)B * sizeof(WaveItem);
+  const size_t pref_off = align_up(items_off + items_bytes, 256);
+  const size_t pref_bytes = 4 * (size_t)(B + 1) * sizeof(int32_t);
+  const size_t counter_off = align_up(pref_off + pref_bytes, 256);
+  const size_t total = counter_off + 256;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  fdemri_status st = ensure_ws(c, total);
+  if (st != FDEMRI_OK) return st;
+  // pinned staging of the records (wait for the previous upload to finish first)
+  const size_t stage_need = (pref_off - items_off) + pref_bytes;
+  if (c->stage_pending) {
+    e = hipEventSynchronize(c->stage_ev);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    c->stage_pending = false;
+  }
+  if (stage_need > c->stage_bytes) {
+    if (c->stage) (void)hipHostFree(c->stage);
+    c->stage = nullptr;
+    c->stage_bytes = 0;
+    e = hipHostMalloc((void**)&c->stage, stage_need);
+    if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc(staging)");
+    c->stage_bytes = stage_need;
+  }
+  if (!c->stage_ev) {
+    e = hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+  }
+  char* w = c->ws;
+  WaveItem* hitems = (WaveItem*)c->stage;
+  int32_t* hpref = (int32_t*)(c->stage + (pref_off - items_off));
+  int32_t *series_prefix = hpref, *mode_prefix = hpref + (B + 1), *amp_prefix = hpref + 2 * (B + 1),
+          *item_prefix = hpref + 3 * (B + 1);
+  series_prefix[0] = mode_prefix[0] = amp_prefix[0] = item_prefix[0] = 0;
+  c->last_evals.clear();
+  for (int b = 0; b < B; ++b) {
+    const fdemri_waveform_desc& d = descs[b];
+    const Layout& L = Ls[b];
+    char* wb = w + base[b];
+    WaveItem it;
+    it.K = d.K;
+    it.Nm = d.Nm;
+    it.Nf = d.Nf;
+    it.flags = d.flags;
+    it.t = d.t;
+    it.Fphi = d.Fphi;
+    it.Fr = d.Fr;
+    it.Phiphi = d.Phiphi;
+    it.Phir = d.Phir;
+    it.A = d.A;
+    it.f = d.f;
+    it.l = d.l;
+    it.m = d.m;
+    it.n = d.n;
+    it.theta = d.theta;
+    it.phi = d.phi;
+    it.scale = d.scale;
+    it.tcoef = (double*)(wb + L.tcoef);
+    it.acoef = (double*)(wb + L.acoef);
+    it.acoef32 = mixed ? (float*)(wb + L.acoef32) : nullptr;
+    it.modes = (ModeConst*)(wb + L.modes);
+    it.mode_kr = (int2*)(wb + L.mode_kr);
+    it.pieces = (Piece*)(wb + L.pieces);
+    it.evals = (int64_t*)(wb + L.evals);
+    it.env = (int32_t*)(wb + L.env);
+    it.hp = hp[b];
+    it.hc = hc[b];
+    hitems[b] = it;
+    series_prefix[b + 1] = series_prefix[b] + 4 + d.Nm;
+    mode_prefix[b + 1] = mode_prefix[b] + d.Nm;
+    amp_prefix[b + 1] = amp_prefix[b] + d.Nm * (d.K - 1);
+    item_prefix[b + 1] = item_prefix[b] + gather_items_per_waveform(d.Nf, c->bpl);
+    c->last_evals.push_back({it.evals, d.Nm});
+  }
+  const WaveItem* ditems = (const WaveItem*)(w + items_off);
+  int32_t* dpref = (int32_t*)(w + pref_off);
+  e = hipMemcpyAsync(w + items_off, c->stage, stage_need, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipEventRecord(c->stage_ev, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "batch record upload");
+  c->stage_pending = true;
+  {
+    ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream);
+    e = launch_spline_batch(ditems, B, dpref, (int)n_series, Kmax, stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "batched spline launch");
+  {
+    ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream);
+    e = launch_pieces_batch(ditems, B, dpref + (B + 1), (int)n_modes, c->flag_word, stream);
+    if (e == hipSuccess && mixed) e = launch_amp32_batch(ditems, B, dpref + 2 * (B + 1), (int)n_amp, stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "batched piece launch");
+  {
+    ProfScope ps(c, FDEMRI_KERNEL_GATHER, stream);
+    e = launch_gather_batch(ditems, B, dpref + 3 * (B + 1), (int)n_items, (int*)(w + counter_off), Kmax, mixed,
+                            c->bpl, stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "batched gather launch");
   return FDEMRI_OK;
 }
 

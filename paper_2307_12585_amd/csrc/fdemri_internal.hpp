@@ -62,6 +62,46 @@ struct Prepared {
   const int32_t* env;      // [2] bin envelope of all modes
 };
 
+// Device-resident record of one waveform of a batch: caller inputs, the
+// library's scratch tables for it, and its outputs.
+struct WaveItem {
+  int32_t K, Nm, Nf;
+  uint32_t flags;
+  const double *t, *Fphi, *Fr, *Phiphi, *Phir, *A, *f;
+  const int32_t *l, *m, *n;
+  double theta, phi, scale;
+  double* tcoef;
+  double* acoef;
+  float* acoef32;
+  ModeConst* modes;
+  int2* mode_kr;
+  Piece* pieces;
+  int64_t* evals;
+  int32_t* env;
+  void* hp;
+  void* hc;
+};
+
+__host__ __device__ inline Prepared prepared_of(const WaveItem& w) {
+  Prepared p;
+  p.K = w.K;
+  p.Nm = w.Nm;
+  p.Nf = w.Nf;
+  p.t = w.t;
+  p.Fphi = w.Fphi;
+  p.Fr = w.Fr;
+  p.Phiphi = w.Phiphi;
+  p.Phir = w.Phir;
+  p.f = w.f;
+  p.tcoef = w.tcoef;
+  p.acoef = w.acoef;
+  p.modes = w.modes;
+  p.mode_kr = w.mode_kr;
+  p.pieces = w.pieces;
+  p.env = w.env;
+  return p;
+}
+
 // ---------------------------------------------------------------- helpers
 
 struct dd {

@@ -137,66 +137,59 @@ __device__ __forceinline__ void eval_bin(const double f, const Piece& P, const d
   }
 }
 
-template <bool MIXED, int BPL, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void gather_kernel(GatherArgs a) {
-  extern __shared__ double lds[];
-  const Prepared& p = a.p;
-  const int K = p.K, nseg = K - 1, Nf = p.Nf;
+// Cooperative copy of one waveform's shared trajectory tables into LDS
+// (caller synchronises).
+__device__ __forceinline__ Lds stage_lds(const Prepared& p, double* lds) {
+  const int K = p.K, nseg = K - 1;
+  double* s_t = lds;
+  double* s_Fp = s_t + K;
+  double* s_Fr = s_Fp + K;
+  double* s_Pp = s_Fr + K;
+  double* s_Pr = s_Pp + K;
+  double* s_cF = s_Pr + K;
+  double* s_cP = s_cF + 6 * nseg;
+  for (int i = threadIdx.x; i < K; i += blockDim.x) {
+    s_t[i] = p.t[i];
+    s_Fp[i] = p.Fphi[i];
+    s_Fr[i] = p.Fr[i];
+    s_Pp[i] = p.Phiphi[i];
+    s_Pr[i] = p.Phir[i];
+  }
+  for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      s_cF[i * 6 + c] = p.tcoef[((size_t)0 * nseg + i) * 4 + 1 + c];
+      s_cF[i * 6 + 3 + c] = p.tcoef[((size_t)1 * nseg + i) * 4 + 1 + c];
+      s_cP[i * 6 + c] = p.tcoef[((size_t)2 * nseg + i) * 4 + 1 + c];
+      s_cP[i * 6 + 3 + c] = p.tcoef[((size_t)3 * nseg + i) * 4 + 1 + c];
+    }
+  }
+  return Lds{s_t, s_Fp, s_Fr, s_Pp, s_Pr, s_cF, s_cP};
+}
+
+template <bool MIXED, int BPL>
+__device__ __forceinline__ void zero_tile(void* hp, void* hc, int Nf, long k0, int lane) {
+#pragma unroll
+  for (int j = 0; j < BPL; ++j) {
+    const long k = k0 + j * 64 + lane;
+    if (k < Nf) {
+      if constexpr (MIXED) {
+        ((float2*)hp)[k] = make_float2(0.f, 0.f);
+        ((float2*)hc)[k] = make_float2(0.f, 0.f);
+      } else {
+        ((double2*)hp)[k] = make_double2(0.0, 0.0);
+        ((double2*)hc)[k] = make_double2(0.0, 0.0);
+      }
+    }
+  }
+}
+
+// One wavefront's tile of 64 * BPL contiguous bins starting at k0.
+template <bool MIXED, int BPL>
+__device__ __forceinline__ void process_tile(const Prepared& p, const float* __restrict__ acoef32, void* hp, void* hc,
+                                             long k0, int lane, const Lds& L) {
   constexpr int TILE = 64 * BPL;
-  const long kb0 = (long)blockIdx.x * (TILE * WAVES);
-  const long kb1 = kb0 + TILE * WAVES - 1;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long k0 = kb0 + (long)wave * TILE;
-
-  // Blocks outside the bin envelope of all modes only write zeros.
-  const int env0 = p.env[0], env1 = p.env[1];
-  if (kb1 < env0 || kb0 > env1) {
-#pragma unroll
-    for (int j = 0; j < BPL; ++j) {
-      const long k = k0 + j * 64 + lane;
-      if (k < Nf) {
-        if constexpr (MIXED) {
-          ((float2*)a.hp)[k] = make_float2(0.f, 0.f);
-          ((float2*)a.hc)[k] = make_float2(0.f, 0.f);
-        } else {
-          ((double2*)a.hp)[k] = make_double2(0.0, 0.0);
-          ((double2*)a.hc)[k] = make_double2(0.0, 0.0);
-        }
-      }
-    }
-    return;
-  }
-
-  // 1. stage the shared trajectory tables
-  Lds L;
-  {
-    double* s_t = lds;
-    double* s_Fp = s_t + K;
-    double* s_Fr = s_Fp + K;
-    double* s_Pp = s_Fr + K;
-    double* s_Pr = s_Pp + K;
-    double* s_cF = s_Pr + K;
-    double* s_cP = s_cF + 6 * nseg;
-    for (int i = threadIdx.x; i < K; i += blockDim.x) {
-      s_t[i] = p.t[i];
-      s_Fp[i] = p.Fphi[i];
-      s_Fr[i] = p.Fr[i];
-      s_Pp[i] = p.Phiphi[i];
-      s_Pr[i] = p.Phir[i];
-    }
-    for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        s_cF[i * 6 + c] = p.tcoef[((size_t)0 * nseg + i) * 4 + 1 + c];
-        s_cF[i * 6 + 3 + c] = p.tcoef[((size_t)1 * nseg + i) * 4 + 1 + c];
-        s_cP[i * 6 + c] = p.tcoef[((size_t)2 * nseg + i) * 4 + 1 + c];
-        s_cP[i * 6 + 3 + c] = p.tcoef[((size_t)3 * nseg + i) * 4 + 1 + c];
-      }
-    }
-    L = Lds{s_t, s_Fp, s_Fr, s_Pp, s_Pr, s_cF, s_cP};
-  }
-  __syncthreads();
-
+  const int Nf = p.Nf, nseg = p.K - 1;
   if (k0 >= Nf) return;
   const long k1 = (k0 + TILE - 1 < Nf - 1) ? k0 + TILE - 1 : Nf - 1;
 
@@ -209,7 +202,7 @@ __global__ __launch_bounds__(64 * WAVES) void gather_kernel(GatherArgs a) {
     acc[j].zero();
   }
 
-  // 2. modes whose bin range meets the tile, 64 at a time, by ballot
+  // modes whose bin range meets the tile, 64 at a time, by ballot
   for (int mc = 0; mc < p.Nm; mc += 64) {
     const int mu = mc + lane;
     bool act = false;
@@ -225,11 +218,10 @@ __global__ __launch_bounds__(64 * WAVES) void gather_kernel(GatherArgs a) {
       const ModeConst md = p.modes[mode];
       const Piece* pcs = p.pieces + (size_t)mode * kMaxPieces;
       const double* ac = p.acoef + (size_t)mode * nseg * 8;
-      const float* ac32 = MIXED ? a.acoef32 + (size_t)mode * nseg * 8 : nullptr;
+      const float* ac32 = MIXED ? acoef32 + (size_t)mode * nseg * 8 : nullptr;
       for (int q = 0; q < md.npieces; ++q) {
         const Piece P = pcs[q];
         if (P.k_lo > k1 || P.k_hi < k0) continue;
-        // 3. per-lane evaluation for the bins of this piece
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
           const long k = k0 + j * 64 + lane;
@@ -240,21 +232,91 @@ __global__ __launch_bounds__(64 * WAVES) void gather_kernel(GatherArgs a) {
     }
   }
 
-  // 4. coalesced store
+  // coalesced store
 #pragma unroll
   for (int j = 0; j < BPL; ++j) {
     const long k = k0 + j * 64 + lane;
     if (k < Nf) {
       if constexpr (MIXED) {
-        ((float2*)a.hp)[k] = make_float2(acc[j].v[0], acc[j].v[1]);
-        ((float2*)a.hc)[k] = make_float2(acc[j].v[2], acc[j].v[3]);
+        ((float2*)hp)[k] = make_float2(acc[j].v[0], acc[j].v[1]);
+        ((float2*)hc)[k] = make_float2(acc[j].v[2], acc[j].v[3]);
       } else {
-        ((double2*)a.hp)[k] = make_double2(acc[j].v[0], acc[j].v[1]);
-        ((double2*)a.hc)[k] = make_double2(acc[j].v[2], acc[j].v[3]);
+        ((double2*)hp)[k] = make_double2(acc[j].v[0], acc[j].v[1]);
+        ((double2*)hc)[k] = make_double2(acc[j].v[2], acc[j].v[3]);
       }
     }
   }
 }
+
+template <bool MIXED, int BPL, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void gather_kernel(GatherArgs a) {
+  extern __shared__ double lds[];
+  const Prepared& p = a.p;
+  constexpr int TILE = 64 * BPL;
+  const long kb0 = (long)blockIdx.x * (TILE * WAVES);
+  const long kb1 = kb0 + TILE * WAVES - 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long k0 = kb0 + (long)wave * TILE;
+  // blocks outside the bin envelope of all modes only write zeros
+  if (kb1 < p.env[0] || kb0 > p.env[1]) {
+    zero_tile<MIXED, BPL>(a.hp, a.hc, p.Nf, k0, lane);
+    return;
+  }
+  const Lds L = stage_lds(p, lds);
+  __syncthreads();
+  process_tile<MIXED, BPL>(p, a.acoef32, a.hp, a.hc, k0, lane, L);
+}
+
+// Persistent gather over a batch: every workgroup repeatedly takes the next
+// block-tile (waveform b, bins [j * TILE * WAVES, ...)) from a device counter
+// and evaluates it exactly as the single-waveform kernel would, restaging the
+// LDS tables when the waveform changes.  The counter only schedules; every
+// output element is still computed by one lane in a fixed order, so results
+// do not depend on the schedule.  Every workgroup leaves the loop once the
+// counter passes the last item.
+template <bool MIXED, int BPL, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void gather_batch_kernel(const WaveItem* __restrict__ items, int B,
+                                                                  const int32_t* __restrict__ item_prefix,
+                                                                  int total_items, int* __restrict__ counter) {
+  extern __shared__ double lds[];
+  __shared__ int s_item;
+  constexpr int TILE = 64 * BPL;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int cached = -1;
+  Lds L{};
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= total_items) break;
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (item_prefix[mid] <= it)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const WaveItem& w = items[lo];
+    const Prepared p = prepared_of(w);
+    const long kb0 = (long)(it - item_prefix[lo]) * (TILE * WAVES);
+    const long kb1 = kb0 + TILE * WAVES - 1;
+    const long k0 = kb0 + (long)wave * TILE;
+    if (kb1 < p.env[0] || kb0 > p.env[1]) {
+      zero_tile<MIXED, BPL>(w.hp, w.hc, p.Nf, k0, lane);
+      continue;
+    }
+    if (lo != cached) {
+      L = stage_lds(p, lds);
+      __syncthreads();
+      cached = lo;
+    }
+    process_tile<MIXED, BPL>(p, w.acoef32, w.hp, w.hc, k0, lane, L);
+  }
+}
+
+__global__ void reset_counter_kernel(int* counter) { *counter = 0; }
 
 // Normalised FP32 amplitude coefficients for the mixed path:
 // A(t_i + u h) = sum_k (a_k h^k) u^k, u in [0, 1].
@@ -267,6 +329,35 @@ __global__ void amp32_kernel(int Nm, int K, const double* __restrict__ t, const 
   const double h = t[i + 1] - t[i];
   const double* c = acoef + idx * 8;
   float* o = acoef32 + idx * 8;
+  double hk = 1.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    o[2 * k] = (float)(c[2 * k] * hk);
+    o[2 * k + 1] = (float)(c[2 * k + 1] * hk);
+    hk *= h;
+  }
+}
+
+// Batched: one thread per (waveform, mode, segment) through the prefix of Nm_b (K_b - 1).
+__global__ void amp32_batch_kernel(const WaveItem* __restrict__ items, int B, const int32_t* __restrict__ amp_prefix,
+                                   int total) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (amp_prefix[mid] <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const WaveItem& w = items[lo];
+  const int idx = g - amp_prefix[lo];
+  const int nseg = w.K - 1;
+  const int i = idx % nseg;
+  const double h = w.t[i + 1] - w.t[i];
+  const double* c = w.acoef + (size_t)idx * 8;
+  float* o = w.acoef32 + (size_t)idx * 8;
   double hk = 1.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -312,6 +403,68 @@ hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp,
   a.hp = hp;
   a.hc = hc;
   return launch_gather(a, mixed, bpl, stream);
+}
+
+template <bool MIXED, int BPL, int WAVES>
+static hipError_t launch_gather_batch_t(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
+                                        int* counter, int Kmax, int grid, hipStream_t stream) {
+  const size_t lds = gather_lds_bytes(Kmax);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)gather_batch_kernel<MIXED, BPL, WAVES>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)gather_lds_bytes(kMaxKnots));
+    attr_set = true;
+  }
+  reset_counter_kernel<<<1, 1, 0, stream>>>(counter);
+  gather_batch_kernel<MIXED, BPL, WAVES><<<dim3(grid), dim3(64 * WAVES), lds, stream>>>(items, B, item_prefix,
+                                                                                     total_items, counter);
+  return hipGetLastError();
+}
+
+// Number of workgroups of the persistent kernel: enough to fill every CU.
+template <bool MIXED, int BPL, int WAVES>
+static int persistent_grid(int Kmax) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)gather_batch_kernel<MIXED, BPL, WAVES>,
+                                                     64 * WAVES, gather_lds_bytes(Kmax));
+  if (ncu <= 0) ncu = 256;
+  if (per_cu <= 0) per_cu = 1;
+  return ncu * per_cu;
+}
+
+int gather_items_per_waveform(int Nf, int bpl) {
+  const int per_block = 64 * bpl * 4;
+  return (Nf + per_block - 1) / per_block;
+}
+
+hipError_t launch_gather_batch(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
+                               int* counter, int Kmax, bool mixed, int bpl, hipStream_t stream) {
+  if (mixed) {
+    if (bpl == 1)
+      return launch_gather_batch_t<true, 1, 4>(items, B, item_prefix, total_items, counter, Kmax,
+                                               persistent_grid<true, 1, 4>(Kmax), stream);
+    if (bpl == 2)
+      return launch_gather_batch_t<true, 2, 4>(items, B, item_prefix, total_items, counter, Kmax,
+                                               persistent_grid<true, 2, 4>(Kmax), stream);
+    return launch_gather_batch_t<true, 4, 4>(items, B, item_prefix, total_items, counter, Kmax,
+                                             persistent_grid<true, 4, 4>(Kmax), stream);
+  }
+  if (bpl == 1)
+    return launch_gather_batch_t<false, 1, 4>(items, B, item_prefix, total_items, counter, Kmax,
+                                              persistent_grid<false, 1, 4>(Kmax), stream);
+  if (bpl == 2)
+    return launch_gather_batch_t<false, 2, 4>(items, B, item_prefix, total_items, counter, Kmax,
+                                              persistent_grid<false, 2, 4>(Kmax), stream);
+  return launch_gather_batch_t<false, 4, 4>(items, B, item_prefix, total_items, counter, Kmax,
+                                            persistent_grid<false, 4, 4>(Kmax), stream);
+}
+
+hipError_t launch_amp32_batch(const WaveItem* items, int B, const int32_t* amp_prefix, int total, hipStream_t stream) {
+  const int threads = 256;
+  amp32_batch_kernel<<<(total + threads - 1) / threads, threads, 0, stream>>>(items, B, amp_prefix, total);
+  return hipGetLastError();
 }
 
 hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, hipStream_t stream) {

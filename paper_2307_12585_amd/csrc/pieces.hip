@@ -72,9 +72,7 @@ __device__ __forceinline__ int upper_bound(const double* f, int Nf, double x) {
   return lo;
 }
 
-__global__ __launch_bounds__(64) void pieces_kernel(PieceArgs a) {
-  const int mu = blockIdx.x * blockDim.x + threadIdx.x;
-  if (mu >= a.Nm) return;
+__device__ void piece_mode(const PieceArgs& a, const int mu) {
   const int li = a.l[mu], mi = a.m[mu], ni = a.n[mu];
   const double m = (double)mi, n = (double)ni;
 
@@ -235,6 +233,64 @@ __global__ __launch_bounds__(64) void pieces_kernel(PieceArgs a) {
     atomicMax(&a.env[1], kr_hi);
   }
   if (overflow) atomicOr(a.flag_word, (uint32_t)FDEMRI_FLAG_PIECE_OVERFLOW);
+}
+
+__global__ __launch_bounds__(64) void pieces_kernel(PieceArgs a) {
+  const int mu = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mu >= a.Nm) return;
+  piece_mode(a, mu);
+}
+
+__device__ PieceArgs piece_args_of(const WaveItem& w, uint32_t* flag_word) {
+  PieceArgs a;
+  a.K = w.K;
+  a.Nm = w.Nm;
+  a.Nf = w.Nf;
+  a.t = w.t;
+  a.Fphi = w.Fphi;
+  a.Fr = w.Fr;
+  a.f = w.f;
+  a.tcoef = w.tcoef;
+  a.l = w.l;
+  a.m = w.m;
+  a.n = w.n;
+  a.theta = w.theta;
+  a.phi = w.phi;
+  a.scale = w.scale;
+  a.flags = w.flags;
+  a.modes = w.modes;
+  a.mode_kr = w.mode_kr;
+  a.pieces = w.pieces;
+  a.evals = w.evals;
+  a.env = w.env;
+  a.flag_word = flag_word;
+  return a;
+}
+
+// Batched: thread -> (waveform, mode) through the prefix of Nm_b.
+__global__ __launch_bounds__(64) void pieces_batch_kernel(const WaveItem* __restrict__ items, int B,
+                                                          const int32_t* __restrict__ mode_prefix, int total,
+                                                          uint32_t* flag_word) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (mode_prefix[mid] <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const PieceArgs a = piece_args_of(items[lo], flag_word);
+  piece_mode(a, g - mode_prefix[lo]);
+}
+
+hipError_t launch_pieces_batch(const WaveItem* items, int B, const int32_t* mode_prefix, int total_modes,
+                               uint32_t* flag_word, hipStream_t stream) {
+  const int threads = 64;
+  pieces_batch_kernel<<<(total_modes + threads - 1) / threads, threads, 0, stream>>>(items, B, mode_prefix,
+                                                                                     total_modes, flag_word);
+  return hipGetLastError();
 }
 
 hipError_t launch_pieces_flat(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,

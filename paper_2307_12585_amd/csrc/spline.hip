@@ -23,14 +23,28 @@
 namespace fdemri {
 
 template <int NT>
-__global__ __launch_bounds__(NT) void spline_pcr_kernel(
-    int K, const double* __restrict__ t, const double* __restrict__ y0, const double* __restrict__ y1,
-    const double* __restrict__ y2, const double* __restrict__ y3, const double* __restrict__ A, int Nm,
-    double* __restrict__ tcoef, double* __restrict__ acoef, int32_t* __restrict__ env) {
-  __shared__ double sa[NT], sb[NT], sc[NT], sr[NT], si[NT];
-  __shared__ double sy_re[NT], sy_im[NT], sh[NT];
+struct SplineLds {
+  double sa[NT], sb[NT], sc[NT], sr[NT], si[NT];
+  double sy_re[NT], sy_im[NT], sh[NT];
+};
+
+// One series (0..3 trajectory, real; 4 + mode: complex amplitude) of one
+// waveform, solved by the NT threads of the calling workgroup.
+template <int NT>
+__device__ void spline_series(SplineLds<NT>& S, int series, int K, const double* __restrict__ t,
+                              const double* __restrict__ y0, const double* __restrict__ y1,
+                              const double* __restrict__ y2, const double* __restrict__ y3,
+                              const double* __restrict__ A, double* __restrict__ tcoef, double* __restrict__ acoef,
+                              int32_t* __restrict__ env) {
+  double* sa = S.sa;
+  double* sb = S.sb;
+  double* sc = S.sc;
+  double* sr = S.sr;
+  double* si = S.si;
+  double* sy_re = S.sy_re;
+  double* sy_im = S.sy_im;
+  double* sh = S.sh;
   const int i = threadIdx.x;
-  const int series = blockIdx.x;  // 0..3 trajectory (real), 4.. amplitude modes (complex)
   const bool cplx = series >= 4;
   const int mode = series - 4;
   const int n = K - 1;  // segments
@@ -56,6 +70,7 @@ __global__ __launch_bounds__(NT) void spline_pcr_kernel(
   }
   if (i < n) sh[i] = t[i + 1] - t[i];
   __syncthreads();
+  if (K > NT) return;  // the host never launches this; keeps every index below in bounds
 
   // assemble row i
   double a = 0.0, b = 1.0, c = 0.0, rr = 0.0, ri = 0.0;
@@ -175,6 +190,35 @@ __global__ __launch_bounds__(NT) void spline_pcr_kernel(
   }
 }
 
+template <int NT>
+__global__ __launch_bounds__(NT) void spline_pcr_kernel(int K, const double* __restrict__ t,
+                                                        const double* __restrict__ y0, const double* __restrict__ y1,
+                                                        const double* __restrict__ y2, const double* __restrict__ y3,
+                                                        const double* __restrict__ A, int Nm, double* __restrict__ tcoef,
+                                                        double* __restrict__ acoef, int32_t* __restrict__ env) {
+  __shared__ SplineLds<NT> S;
+  spline_series<NT>(S, blockIdx.x, K, t, y0, y1, y2, y3, A, tcoef, acoef, env);
+}
+
+// Batched: block -> (waveform, series) through the prefix of 4 + Nm_b.
+template <int NT>
+__global__ __launch_bounds__(NT) void spline_batch_kernel(const WaveItem* __restrict__ items, int B,
+                                                          const int32_t* __restrict__ series_prefix) {
+  __shared__ SplineLds<NT> S;
+  const int g = blockIdx.x;
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (series_prefix[mid] <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const WaveItem& w = items[lo];
+  spline_series<NT>(S, g - series_prefix[lo], w.K, w.t, w.Fphi, w.Fr, w.Phiphi, w.Phir, w.A, w.tcoef, w.acoef,
+                    w.env);
+}
+
 // Host launcher: coefficients of the four trajectory series and of Nm
 // complex amplitude series, all on knots t[K].
 hipError_t launch_spline(int K, const double* t, const double* Fphi, const double* Fr, const double* Phiphi,
@@ -189,6 +233,20 @@ hipError_t launch_spline(int K, const double* t, const double* Fphi, const doubl
     spline_pcr_kernel<256><<<grid, 256, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, Nm, tcoef, acoef, env);
   else
     spline_pcr_kernel<512><<<grid, 512, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, Nm, tcoef, acoef, env);
+  return hipGetLastError();
+}
+
+hipError_t launch_spline_batch(const WaveItem* items, int B, const int32_t* series_prefix, int total_series, int Kmax,
+                               hipStream_t stream) {
+  dim3 grid(total_series);
+  if (Kmax <= 64)
+    spline_batch_kernel<64><<<grid, 64, 0, stream>>>(items, B, series_prefix);
+  else if (Kmax <= 128)
+    spline_batch_kernel<128><<<grid, 128, 0, stream>>>(items, B, series_prefix);
+  else if (Kmax <= 256)
+    spline_batch_kernel<256><<<grid, 256, 0, stream>>>(items, B, series_prefix);
+  else
+    spline_batch_kernel<512><<<grid, 512, 0, stream>>>(items, B, series_prefix);
   return hipGetLastError();
 }
 
