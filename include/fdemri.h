@@ -105,7 +105,12 @@ typedef struct {
   uint32_t flags;
 } fdemri_waveform_desc;
 
-/* Create a context on HIP device `hip_device` (0-based).  flags: reserved, 0.
+/* Context flags */
+#define FDEMRI_CTX_BATCH_GRAPHS 0x1u  /* capture each distinct batch (same descriptors,
+                                         pointers and precision) into a hipGraph on first
+                                         use and replay it on later calls */
+
+/* Create a context on HIP device `hip_device` (0-based) with FDEMRI_CTX_* flags.
  * On success *out receives the context. */
 fdemri_status fdemri_create(fdemri_ctx **out, int hip_device, uint32_t flags);
 
@@ -133,7 +138,11 @@ fdemri_status fdemri_waveform(fdemri_ctx *ctx, const fdemri_waveform_desc *desc,
  * evaluate many parameter draws; the batch amortises launches).
  * descs : HOST array of B descriptors (device pointers inside).
  * hp, hc : HOST arrays of B device output pointers.
- * Results equal B calls of fdemri_waveform with the same precision.
+ * Results equal B calls of fdemri_waveform with the same precision, bit for
+ * bit.  With FDEMRI_CTX_BATCH_GRAPHS the whole sequence (record upload,
+ * batched preparation kernels, persistent gather) is captured once per
+ * distinct batch and replayed; the caller must keep the input contents it
+ * wants evaluated in the same buffers (the graph reads them at replay).
  */
 fdemri_status fdemri_waveform_batch(fdemri_ctx *ctx, int32_t B, const fdemri_waveform_desc *descs,
                                     fdemri_prec prec, void *const *hp, void *const *hc,
@@ -164,6 +173,20 @@ fdemri_status fdemri_vjp(fdemri_ctx *ctx, const fdemri_waveform_desc *desc, fdem
                          const void *g_hp, const void *g_hc, double *gA, double *gPhi,
                          double *gA_knots, double *gPhi_knots, double *g_scalars,
                          hipStream_t stream);
+
+/*
+ * Autotuner of the gather's bin tile (bins per lane: 1, 2 or 4, i.e. tiles of
+ * 64, 128 or 256 contiguous bins per wavefront).  Runs the given batch (B = 1:
+ * a single waveform) once per candidate, timed with HIP events on `stream`,
+ * keeps the fastest for this precision and workload class (log2 of the
+ * total bin count; single or batch) on the context, and, if the environment
+ * variable FDEMRI_TUNE_CACHE names a file, appends the choice there
+ * (keyed by device name and architecture; read back by fdemri_create).
+ * Outputs hp/hc are overwritten.  *bpl_out (host) receives the choice.
+ */
+fdemri_status fdemri_autotune(fdemri_ctx *ctx, int32_t B, const fdemri_waveform_desc *descs,
+                              fdemri_prec prec, void *const *hp, void *const *hc,
+                              hipStream_t stream, int32_t *bpl_out);
 
 /*
  * Count of mode-bin evaluations of the last fdemri_waveform call on this

@@ -23,13 +23,14 @@ LIB_PATH = os.path.join(_HERE, "libfdemri.so")
 FDEMRI_OK, FDEMRI_EINVAL, FDEMRI_ENOMEM, FDEMRI_EDEVICE, FDEMRI_ENOTSUP = range(5)
 FDEMRI_FP64, FDEMRI_MIXED = 0, 1
 FDEMRI_NO_PARTNERS = 0x1
+FDEMRI_CTX_BATCH_GRAPHS = 0x1
 FDEMRI_FLAG_PIECE_OVERFLOW = 0x1
 PRECISIONS = {"fp64": FDEMRI_FP64, "mixed": FDEMRI_MIXED}
 
 EXPORTED = [
     "fdemri_create", "fdemri_destroy", "fdemri_last_error", "fdemri_sync_flags",
     "fdemri_waveform", "fdemri_waveform_batch", "fdemri_vjp", "fdemri_last_eval_count",
-    "fdemri_profile_enable", "fdemri_profile_read",
+    "fdemri_profile_enable", "fdemri_profile_read", "fdemri_autotune",
 ]
 KERNEL_CLASSES = ["spline", "pieces", "gather", "vjp"]
 
@@ -84,6 +85,9 @@ def lib():
         L.fdemri_vjp.restype = ctypes.c_int
         L.fdemri_last_eval_count.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
         L.fdemri_last_eval_count.restype = ctypes.c_int
+        L.fdemri_autotune.argtypes = [vp, i32, ctypes.POINTER(WaveformDesc), ctypes.c_int,
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.POINTER(i32)]
+        L.fdemri_autotune.restype = ctypes.c_int
         L.fdemri_profile_enable.argtypes = [vp, ctypes.c_int]
         L.fdemri_profile_enable.restype = ctypes.c_int
         L.fdemri_profile_read.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -156,14 +160,14 @@ class DeviceWaveform:
 class Context:
     """An fdemri context on one HIP device."""
 
-    def __init__(self, device=None):
+    def __init__(self, device=None, graphs=False):
         if device is None:
             device = torch.cuda.current_device()
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         idx = self.device.index if self.device.index is not None else torch.cuda.current_device()
         self._lib = lib()
         h = ctypes.c_void_p()
-        st = self._lib.fdemri_create(ctypes.byref(h), idx, 0)
+        st = self._lib.fdemri_create(ctypes.byref(h), idx, FDEMRI_CTX_BATCH_GRAPHS if graphs else 0)
         if st != FDEMRI_OK:
             raise FdemriError(st, "fdemri_create failed")
         self._h = h
@@ -254,6 +258,23 @@ class Context:
         if knots:
             out["gA_knots"] = torch.view_as_complex(out["gA_knots"])
         return out
+
+    def autotune(self, dws, prec="fp64", outs=None) -> int:
+        """Pick the gather's bins-per-lane for this workload class (see
+        fdemri_autotune); returns the choice."""
+        p = PRECISIONS[prec]
+        ctype = torch.complex128 if p == FDEMRI_FP64 else torch.complex64
+        B = len(dws)
+        if outs is None:
+            outs = [(torch.empty(d.Nf, dtype=ctype, device=d.device),
+                     torch.empty(d.Nf, dtype=ctype, device=d.device)) for d in dws]
+        descs = (WaveformDesc * B)(*[d.desc() for d in dws])
+        hp = (ctypes.c_void_p * B)(*[o[0].data_ptr() for o in outs])
+        hc = (ctypes.c_void_p * B)(*[o[1].data_ptr() for o in outs])
+        bpl = ctypes.c_int32()
+        self._check(self._lib.fdemri_autotune(self._h, B, descs, p, hp, hc, _stream(self.device),
+                                              ctypes.byref(bpl)))
+        return int(bpl.value)
 
     def waveform_batch(self, dws, prec="fp64", outs=None):
         """Several waveforms in one call; returns a list of (h_+, h_x)."""

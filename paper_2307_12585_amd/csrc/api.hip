@@ -6,6 +6,11 @@
 #include <cstring>
 #include <string>
 #include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
 #include <vector>
 
 #include "fdemri_internal.hpp"
@@ -55,6 +60,22 @@ struct fdemri_ctx {
   size_t stage_bytes = 0;
   hipEvent_t stage_ev = nullptr;
   bool stage_pending = false;
+  // batch graphs
+  uint32_t flags = 0;
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec;
+    hipGraph_t graph;
+    char* records;  // pinned copy of the batch records read by the graph
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t ws_generation = 0;
+  // autotuned bins-per-lane by (precision, batch?, log2 of total bins)
+  std::string device_key;
+  std::vector<std::array<int, 4>> tuned;  // {prec, batch, cls, bpl}
+  bool tuning = false;                     // the autotuner fixes bpl itself
   int bpl = 4;
   // profiling: event pairs per launch, by kernel class
   bool prof = false;
@@ -129,6 +150,7 @@ fdemri_status ensure_ws(fdemri_ctx* c, size_t bytes) {
     c->ws_bytes = 0;
   }
   size_t want = align_up(bytes + bytes / 4, 1 << 20);
+  c->ws_generation++;
   hipError_t e = hipMalloc((void**)&c->ws, want);
   if (e != hipSuccess) {
     c->ws = nullptr;
@@ -136,6 +158,32 @@ fdemri_status ensure_ws(fdemri_ctx* c, size_t bytes) {
   }
   c->ws_bytes = want;
   return FDEMRI_OK;
+}
+
+int size_class(int64_t bins) { return bins <= 1 ? 0 : (int)std::floor(std::log2((double)bins)); }
+
+// Bins per lane for this call: the autotuned choice for (precision, batch,
+// size class) if there is one, else the default.
+int choose_bpl(const fdemri_ctx* c, int prec, bool batch, int64_t bins) {
+  const int cls = size_class(bins);
+  for (const auto& t : c->tuned)
+    if (t[0] == prec && t[1] == (int)batch && t[2] == cls) return t[3];
+  return 4;
+}
+
+void load_tune_cache(fdemri_ctx* c) {
+  const char* path = std::getenv("FDEMRI_TUNE_CACHE");
+  if (!path) return;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    std::istringstream ss(line);
+    std::string dev;
+    int prec, batch, cls, bpl;
+    if (!(ss >> dev >> prec >> batch >> cls >> bpl)) continue;  // malformed lines are ignored
+    if (dev != c->device_key || (bpl != 1 && bpl != 2 && bpl != 4)) continue;
+    c->tuned.push_back({prec, batch, cls, bpl});
+  }
 }
 
 fdemri_status validate(fdemri_ctx* c, const fdemri_waveform_desc* d) {
@@ -195,12 +243,13 @@ extern "C" {
 fdemri_status fdemri_create(fdemri_ctx** out, int hip_device, uint32_t flags) {
   if (!out) return FDEMRI_EINVAL;
   *out = nullptr;
-  if (flags != 0) return FDEMRI_EINVAL;
+  if (flags & ~(uint32_t)FDEMRI_CTX_BATCH_GRAPHS) return FDEMRI_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return FDEMRI_EDEVICE;
   fdemri_ctx* c = new (std::nothrow) fdemri_ctx();
   if (!c) return FDEMRI_ENOMEM;
   c->device = hip_device;
+  c->flags = flags;
   hipError_t e = hipSetDevice(hip_device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->flag_word, sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemset(c->flag_word, 0, sizeof(uint32_t));
@@ -209,6 +258,18 @@ fdemri_status fdemri_create(fdemri_ctx** out, int hip_device, uint32_t flags) {
     delete c;
     return e == hipErrorOutOfMemory ? FDEMRI_ENOMEM : FDEMRI_EDEVICE;
   }
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) {
+      std::string name = std::string(prop.name) + "|" + prop.gcnArchName;
+      for (auto& ch : name)
+        if (ch == ' ') ch = '_';
+      c->device_key = name;
+    } else {
+      c->device_key = "unknown";
+    }
+  }
+  load_tune_cache(c);
   *out = c;
   return FDEMRI_OK;
 }
@@ -226,6 +287,14 @@ void fdemri_destroy(fdemri_ctx* c) {
   for (auto ev : c->pool) (void)hipEventDestroy(ev);
   if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
   if (c->stage) (void)hipHostFree(c->stage);
+  for (auto& g : c->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+    (void)hipHostFree(g.records);
+  }
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   delete c;
 }
 
@@ -315,6 +384,7 @@ fdemri_status fdemri_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, fdem
   float* acoef32 = nullptr;
   st = prepare(c, d, mixed, L, p, acoef32, stream);
   if (st != FDEMRI_OK) return st;
+  if (!c->tuning) c->bpl = choose_bpl(c, (int)prec, false, d->Nf);
   {
     ProfScope ps(c, FDEMRI_KERNEL_GATHER, stream);
     e = launch_gather_flat(p, acoef32, hp, hc, mixed, c->bpl, stream);
@@ -374,75 +444,67 @@ fdemri_status fdemri_last_eval_count(fdemri_ctx* c, hipStream_t stream, int64_t*
   return FDEMRI_OK;
 }
 
-fdemri_status fdemri_waveform_batch(fdemri_ctx* c, int32_t B, const fdemri_waveform_desc* descs, fdemri_prec prec,
-                                    void* const* hp, void* const* hc, hipStream_t stream) {
-  if (!c) return FDEMRI_EINVAL;
-  c->err.clear();
-  if (B < 0 || (B > 0 && (!descs || !hp || !hc))) return fail(c, FDEMRI_EINVAL, "invalid batch arguments");
-  if (B == 0) return FDEMRI_OK;
-  if (prec != FDEMRI_FP64 && prec != FDEMRI_MIXED) return fail(c, FDEMRI_EINVAL, "unknown precision %d", (int)prec);
-  const bool mixed = prec == FDEMRI_MIXED;
-  int Kmax = 0;
+}  // extern "C"
+
+namespace {
+
+// Host-side plan of one batch: per-waveform scratch layouts in the workspace
+// and the offsets of the device records, prefixes and work counter.
+struct BatchPlan {
+  bool mixed = false;
+  int B = 0, Kmax = 0;
   int64_t n_series = 0, n_modes = 0, n_amp = 0, n_items = 0;
-  std::vector<Layout> Ls(B);
-  std::vector<size_t> base(B);
+  std::vector<Layout> Ls;
+  std::vector<size_t> base;
+  size_t items_off = 0, pref_off = 0, pref_bytes = 0, counter_off = 0, total = 0, record_bytes = 0;
+};
+
+fdemri_status plan_batch(fdemri_ctx* c, int B, const fdemri_waveform_desc* descs, bool mixed, void* const* hp,
+                         void* const* hc, BatchPlan& P) {
+  P.mixed = mixed;
+  P.B = B;
+  P.Ls.resize(B);
+  P.base.resize(B);
   size_t off = 0;
   for (int b = 0; b < B; ++b) {
     fdemri_status st = validate(c, &descs[b]);
     if (st != FDEMRI_OK) return fail(c, st, "waveform %d: %s", b, c->err.c_str());
     if (!hp[b] || !hc[b]) return fail(c, FDEMRI_EINVAL, "waveform %d: NULL output pointer", b);
-    Ls[b] = layout_for(descs[b].K, descs[b].Nm, mixed);
-    base[b] = off;
-    off = align_up(off + Ls[b].total, 256);
-    Kmax = std::max(Kmax, (int)descs[b].K);
-    n_series += 4 + descs[b].Nm;
-    n_modes += descs[b].Nm;
-    n_amp += (int64_t)descs[b].Nm * (descs[b].K - 1);
-    n_items += gather_items_per_waveform(descs[b].Nf, c->bpl);
+    P.Ls[b] = layout_for(descs[b].K, descs[b].Nm, mixed);
+    P.base[b] = off;
+    off = align_up(off + P.Ls[b].total, 256);
+    P.Kmax = std::max(P.Kmax, (int)descs[b].K);
+    P.n_series += 4 + descs[b].Nm;
+    P.n_modes += descs[b].Nm;
+    P.n_amp += (int64_t)descs[b].Nm * (descs[b].K - 1);
+    P.n_items += gather_items_per_waveform(descs[b].Nf, c->bpl);
   }
-  if (n_amp > 0x7fffffff || n_items > 0x7fffffff || n_series > 0x7fffffff)
+  if (P.n_amp > 0x7fffffff || P.n_items > 0x7fffffff || P.n_series > 0x7fffffff)
     return fail(c, FDEMRI_ENOTSUP, "batch too large for 32-bit work indices");
-  // device records and prefixes after the per-waveform scratch
-  const size_t items_off = off;
-  const size_t items_bytes = (size_t)B * sizeof(WaveItem);
-  const size_t pref_off = align_up(items_off + items_bytes, 256);
-  const size_t pref_bytes = 4 * (size_t)(B + 1) * sizeof(int32_t);
-  const size_t counter_off = align_up(pref_off + pref_bytes, 256);
-  const size_t total = counter_off + 256;
-  hipError_t e = hipSetDevice(c->device);
-  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-  fdemri_status st = ensure_ws(c, total);
-  if (st != FDEMRI_OK) return st;
-  // pinned staging of the records (wait for the previous upload to finish first)
-  const size_t stage_need = (pref_off - items_off) + pref_bytes;
-  if (c->stage_pending) {
-    e = hipEventSynchronize(c->stage_ev);
-    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
-    c->stage_pending = false;
-  }
-  if (stage_need > c->stage_bytes) {
-    if (c->stage) (void)hipHostFree(c->stage);
-    c->stage = nullptr;
-    c->stage_bytes = 0;
-    e = hipHostMalloc((void**)&c->stage, stage_need);
-    if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc(staging)");
-    c->stage_bytes = stage_need;
-  }
-  if (!c->stage_ev) {
-    e = hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
-  }
+  P.items_off = off;
+  P.pref_off = align_up(P.items_off + (size_t)B * sizeof(WaveItem), 256);
+  P.pref_bytes = 4 * (size_t)(B + 1) * sizeof(int32_t);
+  P.counter_off = align_up(P.pref_off + P.pref_bytes, 256);
+  P.total = P.counter_off + 256;
+  P.record_bytes = (P.pref_off - P.items_off) + P.pref_bytes;
+  return FDEMRI_OK;
+}
+
+// Fill the device records of the batch into host memory `rec` (record_bytes).
+void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc* descs, void* const* hp,
+                  void* const* hc, char* rec) {
+  const int B = P.B;
   char* w = c->ws;
-  WaveItem* hitems = (WaveItem*)c->stage;
-  int32_t* hpref = (int32_t*)(c->stage + (pref_off - items_off));
+  WaveItem* hitems = (WaveItem*)rec;
+  int32_t* hpref = (int32_t*)(rec + (P.pref_off - P.items_off));
   int32_t *series_prefix = hpref, *mode_prefix = hpref + (B + 1), *amp_prefix = hpref + 2 * (B + 1),
           *item_prefix = hpref + 3 * (B + 1);
   series_prefix[0] = mode_prefix[0] = amp_prefix[0] = item_prefix[0] = 0;
   c->last_evals.clear();
   for (int b = 0; b < B; ++b) {
     const fdemri_waveform_desc& d = descs[b];
-    const Layout& L = Ls[b];
-    char* wb = w + base[b];
+    const Layout& L = P.Ls[b];
+    char* wb = w + P.base[b];
     WaveItem it;
     it.K = d.K;
     it.Nm = d.Nm;
@@ -463,7 +525,7 @@ fdemri_status fdemri_waveform_batch(fdemri_ctx* c, int32_t B, const fdemri_wavef
     it.scale = d.scale;
     it.tcoef = (double*)(wb + L.tcoef);
     it.acoef = (double*)(wb + L.acoef);
-    it.acoef32 = mixed ? (float*)(wb + L.acoef32) : nullptr;
+    it.acoef32 = P.mixed ? (float*)(wb + L.acoef32) : nullptr;
     it.modes = (ModeConst*)(wb + L.modes);
     it.mode_kr = (int2*)(wb + L.mode_kr);
     it.pieces = (Piece*)(wb + L.pieces);
@@ -478,29 +540,227 @@ fdemri_status fdemri_waveform_batch(fdemri_ctx* c, int32_t B, const fdemri_wavef
     item_prefix[b + 1] = item_prefix[b] + gather_items_per_waveform(d.Nf, c->bpl);
     c->last_evals.push_back({it.evals, d.Nm});
   }
-  const WaveItem* ditems = (const WaveItem*)(w + items_off);
-  int32_t* dpref = (int32_t*)(w + pref_off);
-  e = hipMemcpyAsync(w + items_off, c->stage, stage_need, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipEventRecord(c->stage_ev, stream);
-  if (e != hipSuccess) return hip_fail(c, e, "batch record upload");
-  c->stage_pending = true;
+}
+
+// Enqueue record upload and the four batched launches on `stream`.
+hipError_t enqueue_batch(fdemri_ctx* c, const BatchPlan& P, const char* rec, hipStream_t stream) {
+  char* w = c->ws;
+  const int B = P.B;
+  const WaveItem* ditems = (const WaveItem*)(w + P.items_off);
+  int32_t* dpref = (int32_t*)(w + P.pref_off);
+  hipError_t e = hipMemcpyAsync(w + P.items_off, rec, P.record_bytes, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return e;
   {
     ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream);
-    e = launch_spline_batch(ditems, B, dpref, (int)n_series, Kmax, stream);
+    e = launch_spline_batch(ditems, B, dpref, (int)P.n_series, P.Kmax, stream);
   }
-  if (e != hipSuccess) return hip_fail(c, e, "batched spline launch");
+  if (e != hipSuccess) return e;
   {
     ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream);
-    e = launch_pieces_batch(ditems, B, dpref + (B + 1), (int)n_modes, c->flag_word, stream);
-    if (e == hipSuccess && mixed) e = launch_amp32_batch(ditems, B, dpref + 2 * (B + 1), (int)n_amp, stream);
+    e = launch_pieces_batch(ditems, B, dpref + (B + 1), (int)P.n_modes, c->flag_word, stream);
+    if (e == hipSuccess && P.mixed) e = launch_amp32_batch(ditems, B, dpref + 2 * (B + 1), (int)P.n_amp, stream);
   }
-  if (e != hipSuccess) return hip_fail(c, e, "batched piece launch");
-  {
-    ProfScope ps(c, FDEMRI_KERNEL_GATHER, stream);
-    e = launch_gather_batch(ditems, B, dpref + 3 * (B + 1), (int)n_items, (int*)(w + counter_off), Kmax, mixed,
-                            c->bpl, stream);
+  if (e != hipSuccess) return e;
+  ProfScope ps(c, FDEMRI_KERNEL_GATHER, stream);
+  return launch_gather_batch(ditems, B, dpref + 3 * (B + 1), (int)P.n_items, (int*)(w + P.counter_off), P.Kmax,
+                             P.mixed, c->bpl, stream);
+}
+
+std::vector<uint64_t> batch_key(const fdemri_ctx* c, int B, const fdemri_waveform_desc* descs, int prec,
+                                void* const* hp, void* const* hc) {
+  std::vector<uint64_t> k;
+  k.reserve(4 + (size_t)B * 20);
+  k.push_back((uint64_t)prec);
+  k.push_back((uint64_t)B);
+  k.push_back((uint64_t)c->bpl);
+  auto bits = [](double x) {
+    uint64_t u;
+    std::memcpy(&u, &x, sizeof u);
+    return u;
+  };
+  for (int b = 0; b < B; ++b) {
+    const fdemri_waveform_desc& d = descs[b];
+    k.push_back(((uint64_t)(uint32_t)d.K << 32) | (uint32_t)d.Nm);
+    k.push_back(((uint64_t)(uint32_t)d.Nf << 32) | d.flags);
+    for (const void* ptr : {(const void*)d.t, (const void*)d.Fphi, (const void*)d.Fr, (const void*)d.Phiphi,
+                            (const void*)d.Phir, (const void*)d.l, (const void*)d.m, (const void*)d.n,
+                            (const void*)d.A, (const void*)d.f, (const void*)hp[b], (const void*)hc[b]})
+      k.push_back((uint64_t)(uintptr_t)ptr);
+    k.push_back(bits(d.theta));
+    k.push_back(bits(d.phi));
+    k.push_back(bits(d.scale));
   }
-  if (e != hipSuccess) return hip_fail(c, e, "batched gather launch");
+  return k;
+}
+
+void drop_graphs(fdemri_ctx* c) {
+  for (auto& g : c->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+    (void)hipHostFree(g.records);
+  }
+  c->graphs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+fdemri_status fdemri_waveform_batch(fdemri_ctx* c, int32_t B, const fdemri_waveform_desc* descs, fdemri_prec prec,
+                                    void* const* hp, void* const* hc, hipStream_t stream) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  if (B < 0 || (B > 0 && (!descs || !hp || !hc))) return fail(c, FDEMRI_EINVAL, "invalid batch arguments");
+  if (B == 0) return FDEMRI_OK;
+  if (prec != FDEMRI_FP64 && prec != FDEMRI_MIXED) return fail(c, FDEMRI_EINVAL, "unknown precision %d", (int)prec);
+  if (!c->tuning) {
+    int64_t bins = 0;
+    for (int b = 0; b < B; ++b) bins += descs[b].Nf;
+    c->bpl = choose_bpl(c, (int)prec, true, bins);
+  }
+  BatchPlan P;
+  fdemri_status st = plan_batch(c, B, descs, prec == FDEMRI_MIXED, hp, hc, P);
+  if (st != FDEMRI_OK) return st;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const uint64_t gen0 = c->ws_generation;
+  st = ensure_ws(c, P.total);
+  if (st != FDEMRI_OK) return st;
+  if (c->ws_generation != gen0) drop_graphs(c);  // recorded graphs point into the old workspace
+
+  if (!(c->flags & FDEMRI_CTX_BATCH_GRAPHS)) {
+    // eager: records through the shared pinned staging buffer
+    if (c->stage_pending) {
+      e = hipEventSynchronize(c->stage_ev);
+      if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+      c->stage_pending = false;
+    }
+    if (P.record_bytes > c->stage_bytes) {
+      if (c->stage) (void)hipHostFree(c->stage);
+      c->stage = nullptr;
+      c->stage_bytes = 0;
+      e = hipHostMalloc((void**)&c->stage, P.record_bytes);
+      if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc(staging)");
+      c->stage_bytes = P.record_bytes;
+    }
+    if (!c->stage_ev) {
+      e = hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+    }
+    fill_records(c, P, descs, hp, hc, c->stage);
+    e = enqueue_batch(c, P, c->stage, stream);
+    if (e == hipSuccess) e = hipEventRecord(c->stage_ev, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "batch launch");
+    c->stage_pending = true;
+    return FDEMRI_OK;
+  }
+
+  // graph mode: capture once per distinct batch on the context's own stream
+  if (!c->gstream) {
+    e = hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(c, e, "graph stream set-up");
+  }
+  const std::vector<uint64_t> key = batch_key(c, B, descs, (int)prec, hp, hc);
+  fdemri_ctx::GraphEntry* G = nullptr;
+  for (auto& g : c->graphs)
+    if (g.key == key) G = &g;
+  if (!G) {
+    fdemri_ctx::GraphEntry ne{};
+    ne.key = key;
+    e = hipHostMalloc((void**)&ne.records, P.record_bytes);
+    if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc(graph records)");
+    fill_records(c, P, descs, hp, hc, ne.records);
+    const bool prof = c->prof;
+    c->prof = false;
+    e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+    hipError_t e2 = hipSuccess;
+    if (e == hipSuccess) e2 = enqueue_batch(c, P, ne.records, c->gstream);
+    hipGraph_t graph = nullptr;
+    if (e == hipSuccess) e = hipStreamEndCapture(c->gstream, &graph);
+    c->prof = prof;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ne.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipHostFree(ne.records);
+      return hip_fail(c, e, "batch graph capture");
+    }
+    ne.graph = graph;
+    c->graphs.push_back(ne);
+    G = &c->graphs.back();
+  } else {
+    c->last_evals.clear();
+    for (int b = 0; b < B; ++b)
+      c->last_evals.push_back({(int64_t*)(c->ws + P.base[b] + P.Ls[b].evals), descs[b].Nm});
+  }
+  e = hipEventRecord(c->ev_in, stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c->gstream, c->ev_in, 0);
+  if (e == hipSuccess) {
+    ProfScope ps(c, FDEMRI_KERNEL_GATHER, c->gstream);
+    e = hipGraphLaunch(G->exec, c->gstream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(c->ev_out, c->gstream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(stream, c->ev_out, 0);
+  if (e != hipSuccess) return hip_fail(c, e, "batch graph launch");
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_autotune(fdemri_ctx* c, int32_t B, const fdemri_waveform_desc* descs, fdemri_prec prec,
+                              void* const* hp, void* const* hc, hipStream_t stream, int32_t* bpl_out) {
+  if (!c || B < 1 || !descs || !hp || !hc) return fail(c, FDEMRI_EINVAL, "invalid autotune arguments");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(c, FDEMRI_EDEVICE, "hipEventCreate failed");
+  }
+  const int cand[3] = {1, 2, 4};
+  float best_ms = 1e30f;
+  int best = 4;
+  c->tuning = true;
+  fdemri_status st = FDEMRI_OK;
+  for (int ci = 0; ci < 3 && st == FDEMRI_OK; ++ci) {
+    c->bpl = cand[ci];
+    auto run = [&]() {
+      return B == 1 ? fdemri_waveform(c, descs, prec, hp[0], hc[0], stream)
+                    : fdemri_waveform_batch(c, B, descs, prec, hp, hc, stream);
+    };
+    st = run();  // warm-up
+    float tot = 0.f;
+    for (int r = 0; r < 3 && st == FDEMRI_OK; ++r) {
+      (void)hipEventRecord(e0, stream);
+      st = run();
+      (void)hipEventRecord(e1, stream);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      tot += ms;
+    }
+    if (st == FDEMRI_OK && tot < best_ms) {
+      best_ms = tot;
+      best = cand[ci];
+    }
+  }
+  c->tuning = false;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != FDEMRI_OK) return st;
+  int64_t bins = 0;
+  for (int b = 0; b < B; ++b) bins += descs[b].Nf;
+  const int batch = B > 1 ? 1 : 0, cls = size_class(bins);
+  c->tuned.erase(std::remove_if(c->tuned.begin(), c->tuned.end(),
+                                [&](const std::array<int, 4>& t) {
+                                  return t[0] == (int)prec && t[1] == batch && t[2] == cls;
+                                }),
+                 c->tuned.end());
+  c->tuned.push_back({(int)prec, batch, cls, best});
+  c->bpl = best;
+  if (const char* path = std::getenv("FDEMRI_TUNE_CACHE")) {
+    std::ofstream out(path, std::ios::app);
+    if (out) out << c->device_key << " " << (int)prec << " " << batch << " " << cls << " " << best << "\n";
+  }
+  if (bpl_out) *bpl_out = best;
   return FDEMRI_OK;
 }
 

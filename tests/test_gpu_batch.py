@@ -52,3 +52,55 @@ def test_batch_repeat_deterministic(ctx):
     torch.cuda.synchronize()
     for (ap, ac), (bp, bc) in zip(a, b):
         assert torch.equal(ap, bp) and torch.equal(ac, bc)
+
+
+def test_batch_graph_replays_match_eager(ctx):
+    """A captured batch replayed several times, with eager work and
+    synchronisations in between, equals the eager batch every time."""
+    ws = batch_members()
+    dws = [fd.DeviceWaveform.from_workload(w, device=ctx.device) for w in ws]
+    ref = ctx.waveform_batch(dws, "fp64")
+    torch.cuda.synchronize()
+    gctx = fd.Context(0, graphs=True)
+    outs = [(torch.empty_like(a), torch.empty_like(b)) for a, b in ref]
+    x = torch.randn(512, 512, device=ctx.device)
+    for rep in range(4):
+        for o in outs:
+            o[0].fill_(float("nan"))
+            o[1].fill_(float("nan"))
+        gctx.waveform_batch(dws, "fp64", outs=outs)
+        y = x @ x                      # unrelated eager work on the same stream
+        ctx.waveform_dev(dws[0], "fp64")
+        torch.cuda.synchronize()
+        assert torch.isfinite(y).all()
+        for (gp, gc), (rp, rc) in zip(outs, ref):
+            assert torch.equal(gp, rp) and torch.equal(gc, rc), rep
+    assert gctx.last_eval_count() > 0
+    gctx.close()
+
+
+def test_autotune_choice_and_invariance(ctx, tmp_path, monkeypatch):
+    """The autotuner picks one of the tile sizes, records it in the cache
+    file, and results do not depend on the tile size."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("FDEMRI_TUNE_CACHE", str(cache))
+    ws = batch_members()[:4]
+    dws = [fd.DeviceWaveform.from_workload(w, device=ctx.device) for w in ws]
+    before = ctx.waveform_batch(dws, "fp64")
+    torch.cuda.synchronize()
+    tctx = fd.Context(0)
+    bpl = tctx.autotune(dws, "fp64")
+    assert bpl in (1, 2, 4)
+    after = tctx.waveform_batch(dws, "fp64")
+    torch.cuda.synchronize()
+    for (a, b), (c, d) in zip(before, after):
+        assert torch.equal(a, c) and torch.equal(b, d)
+    lines = cache.read_text().split("\n")
+    assert any(line.endswith(f" {bpl}") for line in lines if line)
+    tctx.close()
+    # a new context reads the cache back
+    c2 = fd.Context(0)
+    again = c2.waveform_batch(dws, "fp64")
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, c) for (a, _), (c, _) in zip(before, again))
+    c2.close()
