@@ -68,17 +68,11 @@ struct Lds {
   const double* cP;  // [K-1][6]: Phiphi c1..c3, Phir c1..c3
 };
 
-// One (bin, piece) evaluation.
-template <bool MIXED>
-__device__ __forceinline__ void eval_bin(const double f, const Piece& P, const double m, const double n,
-                                         const double cpr, const double cpi, const double cxr, const double cxi,
-                                         const double* __restrict__ ac, const float* __restrict__ ac32,
-                                         const Lds& L, Acc<MIXED>& acc) {
-  const int s = P.s, d = P.d;
-  const double sd = (double)s;
-  const double dd_ = (double)d;
-  // spline segment holding f: largest i in [seg_a, seg_b] whose start value
-  // precedes f in the direction of the piece (ties go to the lower segment)
+// Largest segment i in [seg_a, seg_b] whose start value precedes f in the
+// direction of the piece (i == seg_a or d g_i < d f; ties go to the lower
+// segment).  Used wave-uniformly for the first bin of a sub-tile.
+__device__ __forceinline__ int segment_of(double f, const Piece& P, double m, double n, double sd, double dd_,
+                                          const Lds& L) {
   int lo = P.seg_a, hi = P.seg_b;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -88,6 +82,22 @@ __device__ __forceinline__ void eval_bin(const double f, const Piece& P, const d
     else
       hi = mid - 1;
   }
+  return lo;
+}
+
+// One (bin, piece) evaluation.  i0 is the segment of the sub-tile's bin that
+// comes first along the piece; the lane's own segment is found by scanning
+// forward from there with the same predicate.
+template <bool MIXED>
+__device__ __forceinline__ void eval_bin(const double f, const Piece& P, const int i0, const double m, const double n,
+                                         const double cpr, const double cpi, const double cxr, const double cxi,
+                                         const double* __restrict__ ac, const float* __restrict__ ac32,
+                                         const Lds& L, Acc<MIXED>& acc) {
+  const int s = P.s, d = P.d;
+  const double sd = (double)s;
+  const double dd_ = (double)d;
+  int lo = i0;
+  while (lo < P.seg_b && dd_ * (sd * knot_freq(m, L.Fp[lo + 1], n, L.Fr[lo + 1])) < dd_ * f) ++lo;
   const int i = lo;
   SegData S;
   S.ti = L.t[i];
@@ -222,11 +232,17 @@ __device__ __forceinline__ void process_tile(const Prepared& p, const float* __r
       for (int q = 0; q < md.npieces; ++q) {
         const Piece P = pcs[q];
         if (P.k_lo > k1 || P.k_hi < k0) continue;
+        const double sd = (double)P.s, dd_ = (double)P.d;
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
+          // bins of this piece in sub-tile j (wave-uniform)
+          const long ka = max(k0 + j * 64, (long)P.k_lo);
+          const long kz = min(min(k0 + j * 64 + 63, (long)Nf - 1), (long)P.k_hi);
+          if (ka > kz) continue;
+          const int i0 = segment_of(p.f[P.d > 0 ? ka : kz], P, md.m, md.n, sd, dd_, L);
           const long k = k0 + j * 64 + lane;
-          if (k >= P.k_lo && k <= P.k_hi)
-            eval_bin<MIXED>(fk[j], P, md.m, md.n, md.cp_re, md.cp_im, md.cx_re, md.cx_im, ac, ac32, L, acc[j]);
+          if (k >= ka && k <= kz)
+            eval_bin<MIXED>(fk[j], P, i0, md.m, md.n, md.cp_re, md.cp_im, md.cx_re, md.cx_im, ac, ac32, L, acc[j]);
         }
       }
     }
