@@ -36,6 +36,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-bins", type=int, default=6000)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the secondary measurements (used for counter runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one device-to-device copy of 256 MiB, whose HBM byte counters "
+                         "calibrate the gather kernel's")
     return ap.parse_args()
 
 
@@ -91,6 +97,10 @@ def main():
     hc = torch.empty_like(hp)
     out = (hp, hc)
 
+    bpl = None
+    if not args.no_autotune:
+        bpl = ctx.autotune([dw], "fp64", outs=[out])
+        ctx.autotune([dw], "mixed")
     for _ in range(args.warmup):
         ctx.waveform_dev(dw, "fp64", out=out)
     torch.cuda.synchronize()
@@ -115,6 +125,17 @@ def main():
     # secondary measurements (not the headline): mixed precision on the same
     # workload and the latency of the small and sparse-grid workloads
     secondary = {}
+    if args.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        secondary["copy_calibration_bytes"] = src.numel() * 8
+    if args.headline_only:
+        line = headline(args, w, evals, sec, prof, achieved, bpl, secondary)
+        print(json.dumps(line), flush=True)
+        ctx.close()
+        return
     hpm = torch.empty(dw.Nf, dtype=torch.complex64, device=dev)
     hcm = torch.empty_like(hpm)
     for _ in range(3):
@@ -143,7 +164,20 @@ def main():
         torch.cuda.synchronize()
         secondary[name] = {"us_per_waveform": (time.perf_counter() - ts) / 20 * 1e6}
 
-    line = {
+    line = headline(args, w, evals, sec, prof, achieved, bpl, secondary)
+    if not args.no_cpu_baseline:
+        def count_sample(fs):
+            ds = fd.DeviceWaveform.from_workload(w, device=dev, f=fs)
+            ctx.waveform_dev(ds, "fp64")
+            return ctx.last_eval_count()
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_bins, hp.cpu().numpy(), hc.cpu().numpy(), evals,
+                                            count_sample)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def headline(args, w, evals, sec, prof, achieved, bpl, secondary):
+    return {
         "metric": METRIC,
         "value": 1.0 / sec,
         "unit": "waveforms/s",
@@ -159,7 +193,8 @@ def main():
         "config": {"workload": ("config2: FP64 single waveform, Peters-type toy inspiral M=2e6 mu=20 "
                                 "p0=13 e0=0.45, T=2 yr, dt=10 s; l=2..10, m=0..l, n=-30..30 at 1e-5 "
                                 "power: 3842 modes, K=200 knots, 3155816 bins"),
-                   "modes": w.Nm, "knots": w.K, "bins": w.Nf, "evals": evals},
+                   "modes": w.Nm, "knots": w.K, "bins": w.Nf, "evals": evals,
+                   "bins_per_lane": bpl},
         "evals_per_s": evals / sec,
         "kernel_ms": {k: (v[0] / max(v[1], 1)) for k, v in prof.items() if v[1]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
@@ -167,15 +202,6 @@ def main():
                      "kernel": "gather_kernel<fp64>", "flops_per_eval": FLOPS_PER_EVAL},
         "secondary": secondary,
     }
-    if not args.no_cpu_baseline:
-        def count_sample(fs):
-            ds = fd.DeviceWaveform.from_workload(w, device=dev, f=fs)
-            ctx.waveform_dev(ds, "fp64")
-            return ctx.last_eval_count()
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_bins, hp.cpu().numpy(), hc.cpu().numpy(), evals,
-                                            count_sample)
-    print(json.dumps(line), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -177,11 +177,11 @@ __device__ __forceinline__ Lds stage_lds(const Prepared& p, double* lds) {
   return Lds{s_t, s_Fp, s_Fr, s_Pp, s_Pr, s_cF, s_cP};
 }
 
-template <bool MIXED, int BPL>
-__device__ __forceinline__ void zero_tile(void* hp, void* hc, int Nf, long k0, int lane) {
-#pragma unroll
-  for (int j = 0; j < BPL; ++j) {
-    const long k = k0 + j * 64 + lane;
+// Zeros for the tile [k0, k0 + 64 BPL) (blocks outside every voice's range).
+template <bool MIXED, int BPL, int WAVES>
+__device__ __forceinline__ void zero_tile(void* hp, void* hc, int Nf, long k0) {
+  for (int t = threadIdx.x; t < 64 * BPL; t += 64 * WAVES) {
+    const long k = k0 + t;
     if (k < Nf) {
       if constexpr (MIXED) {
         ((float2*)hp)[k] = make_float2(0.f, 0.f);
@@ -194,13 +194,19 @@ __device__ __forceinline__ void zero_tile(void* hp, void* hc, int Nf, long k0, i
   }
 }
 
-// One wavefront's tile of 64 * BPL contiguous bins starting at k0.
-template <bool MIXED, int BPL>
+// One workgroup's tile of 64 * BPL contiguous bins starting at k0.  Every
+// wave enumerates the (mode, piece) pairs active in the tile and evaluates
+// those with (mode + piece) % WAVES == its index; each lane accumulates its
+// bins in registers, and the partial sums are added in LDS in a fixed wave
+// order.  The grouping and the order within a group depend only on the
+// (mode, piece) pair, so the result is independent of scheduling and of the
+// tile size.  red: LDS scratch of WAVES * BPL * 64 * 4 doubles.
+template <bool MIXED, int BPL, int WAVES>
 __device__ __forceinline__ void process_tile(const Prepared& p, const float* __restrict__ acoef32, void* hp, void* hc,
-                                             long k0, int lane, const Lds& L) {
+                                             long k0, const Lds& L, double* red) {
   constexpr int TILE = 64 * BPL;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int Nf = p.Nf, nseg = p.K - 1;
-  if (k0 >= Nf) return;
   const long k1 = (k0 + TILE - 1 < Nf - 1) ? k0 + TILE - 1 : Nf - 1;
 
   double fk[BPL];
@@ -232,6 +238,7 @@ __device__ __forceinline__ void process_tile(const Prepared& p, const float* __r
       for (int q = 0; q < md.npieces; ++q) {
         const Piece P = pcs[q];
         if (P.k_lo > k1 || P.k_hi < k0) continue;
+        if ((mode + q) % WAVES != wave) continue;
         const double sd = (double)P.s, dd_ = (double)P.d;
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
@@ -248,20 +255,44 @@ __device__ __forceinline__ void process_tile(const Prepared& p, const float* __r
     }
   }
 
-  // coalesced store
+  // partial sums of the waves, added in wave order
 #pragma unroll
   for (int j = 0; j < BPL; ++j) {
-    const long k = k0 + j * 64 + lane;
+    double* r = red + ((size_t)(wave * BPL + j) * 64 + lane) * 4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if constexpr (MIXED)
+        r[c] = (double)acc[j].v[c] - (double)acc[j].c[c];
+      else
+        r[c] = acc[j].v[c];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < TILE; t += 64 * WAVES) {
+    const int j = t >> 6, ln = t & 63;
+    const long k = k0 + t;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+      const double* r = red + ((size_t)(w * BPL + j) * 64 + ln) * 4;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] += r[c];
+    }
     if (k < Nf) {
       if constexpr (MIXED) {
-        ((float2*)hp)[k] = make_float2(acc[j].v[0], acc[j].v[1]);
-        ((float2*)hc)[k] = make_float2(acc[j].v[2], acc[j].v[3]);
+        ((float2*)hp)[k] = make_float2((float)v[0], (float)v[1]);
+        ((float2*)hc)[k] = make_float2((float)v[2], (float)v[3]);
       } else {
-        ((double2*)hp)[k] = make_double2(acc[j].v[0], acc[j].v[1]);
-        ((double2*)hc)[k] = make_double2(acc[j].v[2], acc[j].v[3]);
+        ((double2*)hp)[k] = make_double2(v[0], v[1]);
+        ((double2*)hc)[k] = make_double2(v[2], v[3]);
       }
     }
   }
+}
+
+template <int BPL, int WAVES>
+constexpr size_t red_doubles() {
+  return (size_t)WAVES * BPL * 64 * 4;
 }
 
 template <bool MIXED, int BPL, int WAVES>
@@ -269,27 +300,26 @@ __global__ __launch_bounds__(64 * WAVES) void gather_kernel(GatherArgs a) {
   extern __shared__ double lds[];
   const Prepared& p = a.p;
   constexpr int TILE = 64 * BPL;
-  const long kb0 = (long)blockIdx.x * (TILE * WAVES);
-  const long kb1 = kb0 + TILE * WAVES - 1;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long k0 = kb0 + (long)wave * TILE;
-  // blocks outside the bin envelope of all modes only write zeros
-  if (kb1 < p.env[0] || kb0 > p.env[1]) {
-    zero_tile<MIXED, BPL>(a.hp, a.hc, p.Nf, k0, lane);
+  const long k0 = (long)blockIdx.x * TILE;
+  const long k1 = k0 + TILE - 1;
+  // tiles outside the bin envelope of all modes only write zeros
+  if (k1 < p.env[0] || k0 > p.env[1]) {
+    zero_tile<MIXED, BPL, WAVES>(a.hp, a.hc, p.Nf, k0);
     return;
   }
-  const Lds L = stage_lds(p, lds);
+  double* red = lds;
+  const Lds L = stage_lds(p, lds + red_doubles<BPL, WAVES>());
   __syncthreads();
-  process_tile<MIXED, BPL>(p, a.acoef32, a.hp, a.hc, k0, lane, L);
+  process_tile<MIXED, BPL, WAVES>(p, a.acoef32, a.hp, a.hc, k0, L, red);
 }
 
 // Persistent gather over a batch: every workgroup repeatedly takes the next
-// block-tile (waveform b, bins [j * TILE * WAVES, ...)) from a device counter
+// tile (waveform b, bins [j * 64 BPL, (j + 1) * 64 BPL)) from a device counter
 // and evaluates it exactly as the single-waveform kernel would, restaging the
 // LDS tables when the waveform changes.  The counter only schedules; every
-// output element is still computed by one lane in a fixed order, so results
-// do not depend on the schedule.  Every workgroup leaves the loop once the
-// counter passes the last item.
+// output element is computed in a fixed order, so results do not depend on
+// the schedule.  Every workgroup leaves the loop once the counter passes the
+// last tile.
 template <bool MIXED, int BPL, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void gather_batch_kernel(const WaveItem* __restrict__ items, int B,
                                                                   const int32_t* __restrict__ item_prefix,
@@ -297,7 +327,8 @@ __global__ __launch_bounds__(64 * WAVES) void gather_batch_kernel(const WaveItem
   extern __shared__ double lds[];
   __shared__ int s_item;
   constexpr int TILE = 64 * BPL;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* red = lds;
+  double* tables = lds + red_doubles<BPL, WAVES>();
   int cached = -1;
   Lds L{};
   for (;;) {
@@ -316,19 +347,18 @@ __global__ __launch_bounds__(64 * WAVES) void gather_batch_kernel(const WaveItem
     }
     const WaveItem& w = items[lo];
     const Prepared p = prepared_of(w);
-    const long kb0 = (long)(it - item_prefix[lo]) * (TILE * WAVES);
-    const long kb1 = kb0 + TILE * WAVES - 1;
-    const long k0 = kb0 + (long)wave * TILE;
-    if (kb1 < p.env[0] || kb0 > p.env[1]) {
-      zero_tile<MIXED, BPL>(w.hp, w.hc, p.Nf, k0, lane);
+    const long k0 = (long)(it - item_prefix[lo]) * TILE;
+    const long k1 = k0 + TILE - 1;
+    if (k1 < p.env[0] || k0 > p.env[1]) {
+      zero_tile<MIXED, BPL, WAVES>(w.hp, w.hc, p.Nf, k0);
       continue;
     }
     if (lo != cached) {
-      L = stage_lds(p, lds);
+      L = stage_lds(p, tables);
       __syncthreads();
       cached = lo;
     }
-    process_tile<MIXED, BPL>(p, w.acoef32, w.hp, w.hc, k0, lane, L);
+    process_tile<MIXED, BPL, WAVES>(p, w.acoef32, w.hp, w.hc, k0, L, red);
   }
 }
 
@@ -387,13 +417,14 @@ size_t gather_lds_bytes(int K) { return (size_t)(5 * K + 12 * (K - 1)) * sizeof(
 
 template <bool MIXED, int BPL, int WAVES>
 static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t stream) {
-  constexpr int per_block = 64 * BPL * WAVES;
+  constexpr int per_block = 64 * BPL;
   const long blocks = ((long)a.p.Nf + per_block - 1) / per_block;
-  const size_t lds = gather_lds_bytes(a.p.K);
+  const size_t red = red_doubles<BPL, WAVES>() * sizeof(double);
+  const size_t lds = gather_lds_bytes(a.p.K) + red;
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)gather_kernel<MIXED, BPL, WAVES>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)gather_lds_bytes(kMaxKnots));
+                              (int)(gather_lds_bytes(kMaxKnots) + red));
     attr_set = true;
   }
   gather_kernel<MIXED, BPL, WAVES><<<dim3((unsigned)blocks), dim3(64 * WAVES), lds, stream>>>(a);
@@ -424,11 +455,12 @@ hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp,
 template <bool MIXED, int BPL, int WAVES>
 static hipError_t launch_gather_batch_t(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
                                         int* counter, int Kmax, int grid, hipStream_t stream) {
-  const size_t lds = gather_lds_bytes(Kmax);
+  const size_t red = red_doubles<BPL, WAVES>() * sizeof(double);
+  const size_t lds = gather_lds_bytes(Kmax) + red;
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)gather_batch_kernel<MIXED, BPL, WAVES>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)gather_lds_bytes(kMaxKnots));
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(gather_lds_bytes(kMaxKnots) + red));
     attr_set = true;
   }
   reset_counter_kernel<<<1, 1, 0, stream>>>(counter);
@@ -444,15 +476,16 @@ static int persistent_grid(int Kmax) {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)gather_batch_kernel<MIXED, BPL, WAVES>,
-                                                     64 * WAVES, gather_lds_bytes(Kmax));
+                                                     64 * WAVES,
+                                                     gather_lds_bytes(Kmax) + red_doubles<BPL, WAVES>() * sizeof(double));
   if (ncu <= 0) ncu = 256;
   if (per_cu <= 0) per_cu = 1;
   return ncu * per_cu;
 }
 
 int gather_items_per_waveform(int Nf, int bpl) {
-  const int per_block = 64 * bpl * 4;
-  return (Nf + per_block - 1) / per_block;
+  const int per_tile = 64 * bpl;
+  return (Nf + per_tile - 1) / per_tile;
 }
 
 hipError_t launch_gather_batch(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,

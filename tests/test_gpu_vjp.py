@@ -166,7 +166,9 @@ def test_autograd_whittle_backward(ctx):
     S = torch.as_tensor(W.psd_closed_form(w.f), device=dev)
     wts = torch.full_like(S, float(w.f[1] - w.f[0]))
     wts[0] = 0
-    dp, dc = (1.1 * hp).detach(), (0.9 * hc).detach()
+    # data with a phase offset, so that the phase gradients do not cancel
+    dp = (1.1 * hp * np.exp(0.3j)).detach()
+    dc = (0.9 * hc * np.exp(-0.2j)).detach()
     L = whittle_loglike(hp, hc, dp, dc, S, wts)
     L.backward()
     g_p = (4 * wts * (dp - hp) / S).detach()
