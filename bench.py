@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-bins", type=int, default=6000)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--batch", type=int, default=8,
+                    help="waveforms in the secondary batched mixed-precision measurement")
+    ap.add_argument("--adjoint", type=int, default=4,
+                    help="waveforms in the secondary forward+adjoint measurement")
     ap.add_argument("--headline-only", action="store_true",
                     help="skip the secondary measurements (used for counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -75,6 +79,75 @@ def cpu_baseline(w, n_sample_bins, gpu_hp, gpu_hc, evals_full, count_sample):
         "evals_per_s": ev_sample / max(t_sample - t_fixed, 1e-9),
         "gpu_rel_l2_vs_oracle_on_sample": err,
     }
+
+
+def batch_measure(ctx, W, fd, dev, B):
+    """Mixed-precision batch of B draws from the batched distribution (M
+    log-U[1e5,1e7], mu U[1,100], e0 U[0.05,0.5], p0 U[10,16], T U[0.5,4] yr,
+    dt = 10 s, full DFT grids), one persistent launch per call; error of each
+    waveform against the FP64 batch."""
+    import torch
+    ws = [W.batch_workload(prm) for prm in W.batch_params(B, 4)]
+    dws = [fd.DeviceWaveform.from_workload(w, device=dev) for w in ws]
+    bins = sum(w.Nf for w in ws)
+    ref = ctx.waveform_batch(dws, "fp64")
+    torch.cuda.synchronize()
+    evals = ctx.last_eval_count()
+    outs = ctx.waveform_batch(dws, "mixed")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 2
+    for _ in range(reps):
+        ctx.waveform_batch(dws, "mixed", outs=outs)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    errs = []
+    for (mp, mc), (rp, rc) in zip(outs, ref):
+        for a, b in ((mp, rp), (mc, rc)):
+            nb = float(torch.linalg.vector_norm(b))
+            if nb > 0:
+                errs.append(float(torch.linalg.vector_norm(a.to(torch.complex128) - b)) / nb)
+    del ref, outs
+    return {"waveforms": B, "bins": bins, "evals": evals, "seconds_per_batch": sec,
+            "waveforms_per_s": B / sec, "evals_per_s": evals / sec,
+            "rel_l2_vs_fp64_max": max(errs), "rel_l2_vs_fp64_median": sorted(errs)[len(errs) // 2]}
+
+
+def adjoint_measure(ctx, W, fd, dev, B):
+    """Forward plus adjoint of the Whittle log-likelihood (noise with the
+    closed-form PSD) for B draws of the batched distribution, mixed precision;
+    the gradient error against the FP64 adjoint is reported."""
+    import numpy as np
+    import torch
+    ws = [W.batch_workload(prm) for prm in W.batch_params(B, 1)]
+    tot = 0.0
+    evals = 0
+    errs = []
+    for w in ws:
+        dw = fd.DeviceWaveform.from_workload(w, device=dev)
+        S = torch.as_tensor(W.psd_closed_form(w.f), device=dev)
+        wts = torch.full_like(S, float(w.f[1] - w.f[0]))
+        wts[0] = 0
+        n1, n2 = W.noise_draw(w.f, float(w.f[1] - w.f[0]), 7)
+        hp, hc = ctx.waveform_dev(dw, "fp64")
+        dp = hp + torch.as_tensor(n1, device=dev)
+        dc = hc + torch.as_tensor(n2, device=dev)
+        ref = ctx.vjp_dev(dw, 4 * wts * (dp - hp) / S, 4 * wts * (dc - hc) / S, "fp64", coef=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mp, mc = ctx.waveform_dev(dw, "mixed")
+        evals += ctx.last_eval_count()
+        gp = (4 * wts * (dp - mp.to(torch.complex128)) / S).to(torch.complex64)
+        gc = (4 * wts * (dc - mc.to(torch.complex128)) / S).to(torch.complex64)
+        g = ctx.vjp_dev(dw, gp, gc, "mixed", coef=False)
+        torch.cuda.synchronize()
+        tot += time.perf_counter() - t0
+        for key in ("gA_knots", "gPhi_knots", "g_scalars"):
+            nb = float(torch.linalg.vector_norm(ref[key]))
+            if nb > 0:
+                errs.append(float(torch.linalg.vector_norm(g[key] - ref[key])) / nb)
+    return {"waveforms": B, "evals_forward": evals, "seconds": tot, "waveforms_per_s": B / tot,
+            "evals_per_s_forward_plus_adjoint": evals / tot, "grad_rel_l2_vs_fp64_max": max(errs)}
 
 
 def main():
@@ -151,6 +224,8 @@ def main():
                   float(torch.linalg.vector_norm(hcm.to(torch.complex128) - hc) / torch.linalg.vector_norm(hc)))
     secondary["mixed_same_workload"] = {"waveforms_per_s": 1.0 / smix, "ms": smix * 1e3,
                                         "rel_l2_vs_fp64": mix_err}
+    secondary["batch_mixed"] = batch_measure(ctx, W, fd, dev, args.batch)
+    secondary["forward_adjoint"] = adjoint_measure(ctx, W, fd, dev, args.adjoint)
     for name, wl in (("config1_fp64", W.config1()), ("config3_fp64_sparse_grid", W.config3())):
         d2 = fd.DeviceWaveform.from_workload(wl, device=dev)
         o2 = (torch.empty(d2.Nf, dtype=torch.complex128, device=dev),

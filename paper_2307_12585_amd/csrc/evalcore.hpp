@@ -45,7 +45,7 @@ __device__ __forceinline__ Bracket make_bracket(const Piece& P, int i, double sd
 __device__ __forceinline__ double solve_root(double f, double sd, double dd, const SegData& S, const Bracket& B) {
   double tau = B.tl;
   const double dg = B.gh - B.gl;
-  if (dg != 0.0) tau = B.tl + (f - B.gl) / dg * (B.th - B.tl);
+  if (dg != 0.0) tau = B.tl + (f - B.gl) * (B.th - B.tl) * rcp_nr1(dg);
   tau = fmin(fmax(tau, B.tl), B.th);
   double blo = B.tl, bhi = B.th;
   const double tol = 4e-16 * fmax(S.h, 1.0);
@@ -57,7 +57,7 @@ __device__ __forceinline__ double solve_root(double f, double sd, double dd, con
       blo = tau;
     else
       bhi = tau;
-    double tn = tau - r / gp;
+    double tn = tau - r * rcp_nr1(gp);
     if (!(tn > blo && tn < bhi)) tn = 0.5 * (blo + bhi);
     const double step = fabs(tn - tau);
     tau = tn;
@@ -86,6 +86,47 @@ __device__ __forceinline__ double phase_psi(double f, double tau, double sd, dou
   return red + small;
 }
 
+// sin and cos of x in double precision: Cody-Waite reduction by pi/2 split
+// into three parts (33 + 33 + 53 bits, each product subtracted with one
+// fused multiply-add), then the Taylor series of sin and cos on
+// [-pi/4, pi/4] (terms up to r^17 and r^18; the first omitted terms are
+// below 1e-19) and a quadrant rotation.
+__device__ __forceinline__ void sincos_cw(double x, double* sn, double* cs) {
+  constexpr double kPio2A = 1.5707963267341256;
+  constexpr double kPio2B = 6.077100506303966e-11;
+  constexpr double kPio2C = 2.0222662487959506e-21;
+  constexpr double k2OverPi = 0.6366197723675814;
+  const double k = rint(x * k2OverPi);
+  double r = __builtin_fma(-k, kPio2A, x);
+  r = __builtin_fma(-k, kPio2B, r);
+  r = __builtin_fma(-k, kPio2C, r);
+  const double z = r * r;
+  double ps = 2.8114572543455206e-15;
+  ps = __builtin_fma(ps, z, -7.647163731819816e-13);
+  ps = __builtin_fma(ps, z, 1.6059043836821613e-10);
+  ps = __builtin_fma(ps, z, -2.505210838544172e-08);
+  ps = __builtin_fma(ps, z, 2.7557319223985893e-06);
+  ps = __builtin_fma(ps, z, -0.0001984126984126984);
+  ps = __builtin_fma(ps, z, 0.008333333333333333);
+  ps = __builtin_fma(ps, z, -0.16666666666666666);
+  const double s_r = __builtin_fma(r * z, ps, r);
+  double pc = -1.5619206968586225e-16;
+  pc = __builtin_fma(pc, z, 4.779477332387385e-14);
+  pc = __builtin_fma(pc, z, -1.1470745597729725e-11);
+  pc = __builtin_fma(pc, z, 2.08767569878681e-09);
+  pc = __builtin_fma(pc, z, -2.755731922398589e-07);
+  pc = __builtin_fma(pc, z, 2.48015873015873e-05);
+  pc = __builtin_fma(pc, z, -0.001388888888888889);
+  pc = __builtin_fma(pc, z, 0.041666666666666664);
+  pc = __builtin_fma(pc, z, -0.5);
+  const double c_r = __builtin_fma(z, pc, 1.0);
+  const int q = ((int)(long long)k) & 3;
+  const double s1 = (q & 1) ? c_r : s_r;
+  const double c1 = (q & 1) ? s_r : c_r;
+  *sn = (q & 2) ? -s1 : s1;
+  *cs = ((q + 1) & 2) ? -c1 : c1;
+}
+
 // E = e^{i psi} G and the amplitude spline value A at the root (FP64).
 __device__ __forceinline__ void root_terms64(double f, double tau, double sd, int d, double m, double n,
                                              const SegData& S, const double* __restrict__ ac_seg, double2& E,
@@ -95,7 +136,7 @@ __device__ __forceinline__ void root_terms64(double f, double tau, double sd, in
   const double psi = phase_psi(f, tau, sd, m, n, S);
   const double2 G = spa_factor64(gd, gdd, d);
   double sn, cs;
-  sincos(psi, &sn, &cs);
+  sincos_cw(psi, &sn, &cs);
   E = make_double2(cs * G.x - sn * G.y, cs * G.y + sn * G.x);
   const double* c = ac_seg;
   A = make_double2(c[0] + tau * (c[2] + tau * (c[4] + tau * c[6])), c[1] + tau * (c[3] + tau * (c[5] + tau * c[7])));

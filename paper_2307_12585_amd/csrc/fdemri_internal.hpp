@@ -25,13 +25,16 @@ constexpr double kPi = 3.141592653589793116;
 // direction d in t.  It starts at tau_a inside spline segment seg_a and ends
 // at tau_b inside segment seg_b; g_a, g_b are |F_V| at the two ends, and
 // [k_lo, k_hi] the bins whose frequency lies in [min, max](g_a, g_b).
+// rate = (seg_b - seg_a + 1) / (g_b - g_a) gives a first guess of the
+// segment holding a frequency (the search that follows does not depend on it).
 struct alignas(64) Piece {
   double tau_a, tau_b;
   double g_a, g_b;
   int32_t seg_a, seg_b;
   int32_t k_lo, k_hi;
   int32_t s, d;
-  int32_t pad0, pad1;
+  float rate;
+  int32_t pad1;
 };
 static_assert(sizeof(Piece) == 64, "Piece layout");
 
@@ -129,6 +132,26 @@ __device__ __forceinline__ double knot_freq(double m, double fphi, double n, dou
   double a = m * fphi;
   double b = n * fr;
   return a + b;
+}
+
+// Reciprocal and reciprocal square root from the hardware estimates refined
+// by Newton-Raphson steps (one step: for iterations that correct themselves;
+// two steps: full double precision).
+__device__ __forceinline__ double rcp_nr1(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+}
+
+__device__ __forceinline__ double rcp_nr2(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+  return __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+}
+
+__device__ __forceinline__ double rsq_nr2(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = __builtin_fma(0.5 * y, __builtin_fma(-x * y, y, 1.0), y);
+  return __builtin_fma(0.5 * y, __builtin_fma(-x * y, y, 1.0), y);
 }
 
 }  // namespace fdemri

@@ -68,37 +68,23 @@ struct Lds {
   const double* cP;  // [K-1][6]: Phiphi c1..c3, Phir c1..c3
 };
 
-// Largest segment i in [seg_a, seg_b] whose start value precedes f in the
-// direction of the piece (i == seg_a or d g_i < d f; ties go to the lower
-// segment).  Used wave-uniformly for the first bin of a sub-tile.
-__device__ __forceinline__ int segment_of(double f, const Piece& P, double m, double n, double sd, double dd_,
-                                          const Lds& L) {
-  int lo = P.seg_a, hi = P.seg_b;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    const double gm = sd * knot_freq(m, L.Fp[mid], n, L.Fr[mid]);
-    if (dd_ * gm < dd_ * f)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
-// One (bin, piece) evaluation.  i0 is the segment of the sub-tile's bin that
-// comes first along the piece; the lane's own segment is found by scanning
-// forward from there with the same predicate.
+// One (bin, piece) evaluation.  The spline segment holding f is the largest i
+// in [seg_a, seg_b] whose start value precedes f in the direction of the
+// piece (i == seg_a or d g_i < d f; ties go to the lower segment); it is found
+// from the piece's rate guess and a short correction in either direction.
 template <bool MIXED>
-__device__ __forceinline__ void eval_bin(const double f, const Piece& P, const int i0, const double m, const double n,
+__device__ __forceinline__ void eval_bin(const double f, const Piece& P, const double m, const double n,
                                          const double cpr, const double cpi, const double cxr, const double cxi,
                                          const double* __restrict__ ac, const float* __restrict__ ac32,
                                          const Lds& L, Acc<MIXED>& acc) {
   const int s = P.s, d = P.d;
   const double sd = (double)s;
   const double dd_ = (double)d;
-  int lo = i0;
-  while (lo < P.seg_b && dd_ * (sd * knot_freq(m, L.Fp[lo + 1], n, L.Fr[lo + 1])) < dd_ * f) ++lo;
-  const int i = lo;
+  const double span = (double)(P.seg_b - P.seg_a);
+  const double est = fmin(fmax((f - P.g_a) * (double)P.rate, 0.0), span);
+  int i = P.seg_a + (int)est;
+  while (i > P.seg_a && !(dd_ * (sd * knot_freq(m, L.Fp[i], n, L.Fr[i])) < dd_ * f)) --i;
+  while (i < P.seg_b && dd_ * (sd * knot_freq(m, L.Fp[i + 1], n, L.Fr[i + 1])) < dd_ * f) ++i;
   SegData S;
   S.ti = L.t[i];
   S.h = L.t[i + 1] - S.ti;
@@ -239,17 +225,15 @@ __device__ __forceinline__ void process_tile(const Prepared& p, const float* __r
         const Piece P = pcs[q];
         if (P.k_lo > k1 || P.k_hi < k0) continue;
         if ((mode + q) % WAVES != wave) continue;
-        const double sd = (double)P.s, dd_ = (double)P.d;
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
           // bins of this piece in sub-tile j (wave-uniform)
           const long ka = max(k0 + j * 64, (long)P.k_lo);
           const long kz = min(min(k0 + j * 64 + 63, (long)Nf - 1), (long)P.k_hi);
           if (ka > kz) continue;
-          const int i0 = segment_of(p.f[P.d > 0 ? ka : kz], P, md.m, md.n, sd, dd_, L);
           const long k = k0 + j * 64 + lane;
           if (k >= ka && k <= kz)
-            eval_bin<MIXED>(fk[j], P, i0, md.m, md.n, md.cp_re, md.cp_im, md.cx_re, md.cx_im, ac, ac32, L, acc[j]);
+            eval_bin<MIXED>(fk[j], P, md.m, md.n, md.cp_re, md.cp_im, md.cx_re, md.cx_im, ac, ac32, L, acc[j]);
         }
       }
     }

@@ -247,7 +247,8 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
       P.g_b = s * eb.F;
       P.s = s;
       P.d = s * dV;
-      P.pad0 = P.pad1 = 0;
+      P.rate = (float)((double)(P.seg_b - P.seg_a + 1) / (P.g_b - P.g_a));
+      P.pad1 = 0;
       const double glo = fmin(P.g_a, P.g_b), ghi = fmax(P.g_a, P.g_b);
       int klo = lower_bound(a.f, a.Nf, glo);
       if (klo < kpos) klo = kpos;

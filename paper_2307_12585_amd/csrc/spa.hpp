@@ -68,22 +68,24 @@ __device__ __forceinline__ float2 q_cheb32(float y) {
 }
 
 // G in FP64.  dir = direction of the piece (used only when gd == 0).
+// u = 1/X = 3 gdd^2 / (2 pi gd^3) is formed with one reciprocal; |u| <= 1/X_B
+// selects the large-argument expansion (u = +-inf at gd = 0 selects the Airy
+// form, NaN falls into the expansion branch and stays NaN).
 __device__ __forceinline__ double2 spa_factor64(double gd, double gdd, int dir) {
   constexpr double kRsqrt2 = 0.70710678118654752440;
+  constexpr double k3Over2Pi = 0.47746482927568600730;
   if (gdd == 0.0) {
     if (gd == 0.0) return make_double2(0.0, 0.0);
-    const double c = kRsqrt2 / sqrt(fabs(gd));
+    const double c = kRsqrt2 * rsq_nr2(fabs(gd));
     return make_double2(c, gd > 0.0 ? -c : c);
   }
-  const double rr = gd / gdd;
-  const double X = (2.0 * kPi / 3.0) * gd * rr * rr;
-  const double ax = fabs(X);
+  const double u = k3Over2Pi * gdd * gdd * rcp_nr2(gd * gd * gd);
+  const double au = fabs(u);
   const int sg = gd > 0.0 ? 1 : (gd < 0.0 ? -1 : dir);
-  if (!(ax < FDW_X_B)) {
-    const double u = 1.0 / X;
+  if (!(au > 1.0 / FDW_X_B)) {
     const double v = u * u;
     double re = 0.0, im = 0.0;
-    if (__all(ax >= 1e3)) {
+    if (__all(au <= 1e-3)) {
       // |X| >= 1e3 on every active lane: 8 terms (first omitted term < 1e-23)
 #pragma unroll
       for (int j = 3; j >= 0; --j) {
@@ -100,11 +102,12 @@ __device__ __forceinline__ double2 spa_factor64(double gd, double gdd, int dir) 
       }
     }
     im *= u;
-    const double c = kRsqrt2 / sqrt(fabs(gd));
+    const double c = kRsqrt2 * rsq_nr2(fabs(gd));
     // (c - i sg c) (re + i im)
     const double br = c, bi = -sg * c;
     return make_double2(br * re - bi * im, br * im + bi * re);
   }
+  const double ax = rcp_nr2(au);  // |X| (0 when gd == 0)
   const double y = cbrt(1.5 * ax);
   double2 q = q_cheb64(y);
   if (sg < 0) q.y = -q.y;
@@ -116,18 +119,18 @@ __device__ __forceinline__ double2 spa_factor64(double gd, double gdd, int dir) 
 // FP64 and evaluates the special function in FP32).
 __device__ __forceinline__ float2 spa_factor32(double gd, double gdd, int dir) {
   constexpr float kRsqrt2 = 0.70710678118654752440f;
+  constexpr double k3Over2Pi = 0.47746482927568600730;
   if (gdd == 0.0) {
     if (gd == 0.0) return make_float2(0.f, 0.f);
     const float c = kRsqrt2 * rsqrtf((float)fabs(gd));
     return make_float2(c, gd > 0.0 ? -c : c);
   }
-  const double rr = gd / gdd;
-  const double X = (2.0 * kPi / 3.0) * gd * rr * rr;
-  const double ax = fabs(X);
+  const double u = k3Over2Pi * gdd * gdd * rcp_nr1(gd * gd * gd);
+  const double au = fabs(u);
   const int sg = gd > 0.0 ? 1 : (gd < 0.0 ? -1 : dir);
-  if (!(ax < FDW_X_B)) {
-    const float u = (float)(1.0 / X);
-    const float v = u * u;
+  if (!(au > 1.0 / FDW_X_B)) {
+    const float uf = (float)u;
+    const float v = uf * uf;
     float re = 0.f, im = 0.f;
 #pragma unroll
     for (int j = (FDW_NASYM32 - 1) / 2; j >= 0; --j) {
@@ -135,12 +138,12 @@ __device__ __forceinline__ float2 spa_factor32(double gd, double gdd, int dir) {
       re = re * v + sgn * fdw_asym32[2 * j];
       if (2 * j + 1 < FDW_NASYM32) im = im * v + sgn * fdw_asym32[2 * j + 1];
     }
-    im *= u;
+    im *= uf;
     const float c = kRsqrt2 * rsqrtf((float)fabs(gd));
     const float br = c, bi = -sg * c;
     return make_float2(br * re - bi * im, br * im + bi * re);
   }
-  const float y = cbrtf((float)(1.5 * ax));
+  const float y = cbrtf((float)(1.5 * rcp_nr2(au)));
   float2 q = q_cheb32(y);
   if (sg < 0) q.y = -q.y;
   const float pref = (float)(kPi / cbrt(kPi * fabs(gdd)));
