@@ -4,11 +4,12 @@
 //
 // For a voice (m, n) on a monotonic piece with sign s and direction d, and a
 // bin f whose root lies in spline segment i (Eq. cubic_equation):
-//   |F_V|(t_i + tau) = s (F0 + a1 tau + a2 tau^2 + a3 tau^3),
-//   s Phi_V(t_i + tau) = s (Phi_V,i + b1 tau + b2 tau^2 + b3 tau^3),
-// with F0 = m F_phi,i + n F_r,i from the knot data and a_k, b_k the
-// mode-weighted spline coefficients of the fundamental frequencies and
-// phases.
+//   |F_V|(t_i + tau) = G0 + q1 tau + q2 tau^2 + q3 tau^3,
+//   s Phi_V(t_i + tau) = s Phi_V,i + r1 tau + r2 tau^2 + r3 tau^3,
+// with G0 = (s m) F_phi,i + (s n) F_r,i from the knot data and q_k, r_k the
+// spline coefficients of the fundamental frequencies and phases weighted by
+// s m and s n (the sign is folded into the mode numbers, which is exact).
+
 #pragma once
 
 #include "spa.hpp"
@@ -16,9 +17,9 @@
 namespace fdemri {
 
 struct SegData {
-  double ti, h, F0, F1;   // knot time, segment length, voice frequency at both knots
-  double a1, a2, a3;      // frequency spline coefficients (mode-weighted)
-  double b1, b2, b3;      // phase spline coefficients (mode-weighted)
+  double ti, h, G0, G1;   // knot time, segment length, |F_V| at both knots
+  double q1, q2, q3;      // |F_V| spline coefficients
+  double r1, r2, r3;      // s Phi_V spline coefficients
   double Ppi, Pri;        // Phi_phi, Phi_r knot values at t_i
 };
 
@@ -29,60 +30,80 @@ struct Bracket {
   double tl, th, gl, gh;
 };
 
-__device__ __forceinline__ Bracket make_bracket(const Piece& P, int i, double sd, const SegData& S) {
+__device__ __forceinline__ Bracket make_bracket(const Piece& P, int i, const SegData& S) {
   const bool first = (i == P.seg_a), last = (i == P.seg_b);
   Bracket B;
   B.tl = first ? P.tau_a : 0.0;
   B.th = last ? P.tau_b : S.h;
-  B.gl = first ? P.g_a : sd * S.F0;
-  B.gh = last ? P.g_b : sd * S.F1;
+  B.gl = first ? P.g_a : S.G0;
+  B.gh = last ? P.g_b : S.G1;
   return B;
 }
 
-// Root of s (F0 + a1 tau + a2 tau^2 + a3 tau^3) = f on [tl, th] (|F_V|
-// monotonic there with direction d): secant start, Newton steps safeguarded
-// by bisection of the shrinking bracket.
-__device__ __forceinline__ double solve_root(double f, double sd, double dd, const SegData& S, const Bracket& B) {
+// Root of G0 + q1 tau + q2 tau^2 + q3 tau^3 = f on [tl, th] (|F_V|
+// monotonic there with direction d).  Secant start from the bracket ends,
+// then Halley steps on p(tau) = |F_V|(t_i + tau) - f, each kept inside the
+// shrinking bracket (bisection when a step leaves it).  After a Halley step
+// of length x the error is about (p2^2 / (4 p1^2) - p3 / (6 p1)) x^3, with
+// p1, p2, p3 the first three derivatives of p; once the iterate lies where
+// that holds (|p p2| <= p1^2 / 2) and the predicted error is below the
+// tolerance, the new iterate is returned.  On smooth trajectories one step
+// from the secant start reaches the rounding floor of p.
+__device__ __forceinline__ double solve_root(double f, double dd, const SegData& S, const Bracket& B) {
   double tau = B.tl;
   const double dg = B.gh - B.gl;
   if (dg != 0.0) tau = B.tl + (f - B.gl) * (B.th - B.tl) * rcp_nr1(dg);
   tau = fmin(fmax(tau, B.tl), B.th);
   double blo = B.tl, bhi = B.th;
   const double tol = 4e-16 * fmax(S.h, 1.0);
+  const double c0 = S.G0 - f;
+  const double q1 = S.q1, q2 = S.q2, q3 = S.q3;
+  const double q2x2 = 2.0 * q2, q3x3 = 3.0 * q3, q3x6 = 6.0 * q3, aq3 = fabs(q3);
   for (int it = 0; it < 100; ++it) {
-    const double r = sd * (S.F0 + tau * (S.a1 + tau * (S.a2 + tau * S.a3))) - f;
+    const double r = c0 + tau * (q1 + tau * (q2 + tau * q3));
     if (r == 0.0) break;
-    const double gp = sd * (S.a1 + tau * (2.0 * S.a2 + 3.0 * S.a3 * tau));
+    const double p1 = q1 + tau * (q2x2 + q3x3 * tau);
+    const double p2 = q2x2 + q3x6 * tau;
     if (dd * r < 0.0)
       blo = tau;
     else
       bhi = tau;
-    double tn = tau - r * rcp_nr1(gp);
-    if (!(tn > blo && tn < bhi)) tn = 0.5 * (blo + bhi);
+    const double p1s = p1 * p1, rp2 = r * p2;
+    double tn = tau - 2.0 * r * p1 * rcp_nr1(2.0 * p1s - rp2);
+    const bool inside = (tn > blo && tn < bhi);
+    if (!inside) tn = 0.5 * (blo + bhi);
     const double step = fabs(tn - tau);
     tau = tn;
     if (step <= tol || !(bhi - blo > tol)) break;
+    if (inside && fabs(rp2) <= 0.5 * p1s && step * step * step * (0.25 * p2 * p2 + aq3 * fabs(p1)) <= tol * p1s)
+      break;
   }
   return tau;
 }
 
-// psi = 2 pi f (t_i + tau) - s Phi_V(t_i + tau): the large part
-// 2 pi f t_i - s Phi_V,i in double-double, reduced modulo 2 pi, plus the
-// segment-local part in double.
-__device__ __forceinline__ double phase_psi(double f, double tau, double sd, double m, double n, const SegData& S) {
-  const dd ft = two_prod(f, S.ti);
-  dd q = two_prod(ft.hi, kTwoPiHi);
-  q.lo = __builtin_fma(ft.hi, kTwoPiLo, __builtin_fma(ft.lo, kTwoPiHi, q.lo));
-  const dd pm = two_prod(m, S.Ppi);
-  const dd pn = two_prod(n, S.Pri);
+// 2 pi f as an unevaluated double-double (formed once per bin).
+__device__ __forceinline__ dd two_pi_f(double f) {
+  dd w = two_prod(f, kTwoPiHi);
+  w.lo = __builtin_fma(f, kTwoPiLo, w.lo);
+  return w;
+}
+
+// psi = 2 pi f (t_i + tau) - s Phi_V(t_i + tau), with w = 2 pi f and
+// (ms, ns) = (s m, s n): the large part 2 pi f t_i - s Phi_V,i in
+// double-double, reduced modulo 2 pi, plus the segment-local part in double.
+__device__ __forceinline__ double phase_psi(const dd w, double tau, double ms, double ns, const SegData& S) {
+  dd q = two_prod(w.hi, S.ti);
+  q.lo = __builtin_fma(w.lo, S.ti, q.lo);
+  const dd pm = two_prod(ms, S.Ppi);
+  const dd pn = two_prod(ns, S.Pri);
   dd z = two_sum(pm.hi, pn.hi);
   z.lo += pm.lo + pn.lo;
-  dd b = two_sum(q.hi, -sd * z.hi);
-  b.lo += q.lo - sd * z.lo;
+  dd b = two_sum(q.hi, -z.hi);
+  b.lo += q.lo - z.lo;
   const double kk = rint(b.hi * kInvTwoPi);
   const dd kc = two_prod(kk, kTwoPiHi);
   const double red = (b.hi - kc.hi) + ((b.lo - kc.lo) - kk * kTwoPiLo);
-  const double small = tau * (kTwoPiHi * f - sd * (S.b1 + tau * (S.b2 + tau * S.b3)));
+  const double small = tau * (w.hi - (S.r1 + tau * (S.r2 + tau * S.r3)));
   return red + small;
 }
 
@@ -90,7 +111,9 @@ __device__ __forceinline__ double phase_psi(double f, double tau, double sd, dou
 // into three parts (33 + 33 + 53 bits, each product subtracted with one
 // fused multiply-add), then the Taylor series of sin and cos on
 // [-pi/4, pi/4] (terms up to r^17 and r^18; the first omitted terms are
-// below 1e-19) and a quadrant rotation.
+// below 1e-19) and a quadrant rotation.  The phases passed here are reduced
+// modulo 2 pi up to the segment-local part, a few thousand radians at most,
+// so the quadrant count fits an int.
 __device__ __forceinline__ void sincos_cw(double x, double* sn, double* cs) {
   constexpr double kPio2A = 1.5707963267341256;
   constexpr double kPio2B = 6.077100506303966e-11;
@@ -120,20 +143,20 @@ __device__ __forceinline__ void sincos_cw(double x, double* sn, double* cs) {
   pc = __builtin_fma(pc, z, 0.041666666666666664);
   pc = __builtin_fma(pc, z, -0.5);
   const double c_r = __builtin_fma(z, pc, 1.0);
-  const int q = ((int)(long long)k) & 3;
+  const int q = ((int)k) & 3;
   const double s1 = (q & 1) ? c_r : s_r;
   const double c1 = (q & 1) ? s_r : c_r;
   *sn = (q & 2) ? -s1 : s1;
   *cs = ((q + 1) & 2) ? -c1 : c1;
 }
 
-// E = e^{i psi} G and the amplitude spline value A at the root (FP64).
-__device__ __forceinline__ void root_terms64(double f, double tau, double sd, int d, double m, double n,
-                                             const SegData& S, const double* __restrict__ ac_seg, double2& E,
-                                             double2& A) {
-  const double gd = sd * (S.a1 + tau * (2.0 * S.a2 + 3.0 * S.a3 * tau));
-  const double gdd = sd * (2.0 * S.a2 + 6.0 * S.a3 * tau);
-  const double psi = phase_psi(f, tau, sd, m, n, S);
+// E = e^{i psi} G and the amplitude spline value A at the root (FP64);
+// w = 2 pi f as double-double, (ms, ns) = (s m, s n).
+__device__ __forceinline__ void root_terms64(const dd w, double tau, int d, double ms, double ns, const SegData& S,
+                                             const double* __restrict__ ac_seg, double2& E, double2& A) {
+  const double gd = S.q1 + tau * (2.0 * S.q2 + 3.0 * S.q3 * tau);
+  const double gdd = 2.0 * S.q2 + 6.0 * S.q3 * tau;
+  const double psi = phase_psi(w, tau, ms, ns, S);
   const double2 G = spa_factor64(gd, gdd, d);
   double sn, cs;
   sincos_cw(psi, &sn, &cs);
@@ -144,12 +167,11 @@ __device__ __forceinline__ void root_terms64(double f, double tau, double sd, in
 
 // Mixed precision: root, derivatives, phase and its reduction in FP64; the
 // factor, sincos and the (normalised) amplitude spline in FP32.
-__device__ __forceinline__ void root_terms32(double f, double tau, double sd, int d, double m, double n,
-                                             const SegData& S, const float* __restrict__ ac32_seg, float2& E,
-                                             float2& A) {
-  const double gd = sd * (S.a1 + tau * (2.0 * S.a2 + 3.0 * S.a3 * tau));
-  const double gdd = sd * (2.0 * S.a2 + 6.0 * S.a3 * tau);
-  const double psi = phase_psi(f, tau, sd, m, n, S);
+__device__ __forceinline__ void root_terms32(const dd w, double tau, int d, double ms, double ns, const SegData& S,
+                                             const float* __restrict__ ac32_seg, float2& E, float2& A) {
+  const double gd = S.q1 + tau * (2.0 * S.q2 + 3.0 * S.q3 * tau);
+  const double gdd = 2.0 * S.q2 + 6.0 * S.q3 * tau;
+  const double psi = phase_psi(w, tau, ms, ns, S);
   const double psr = psi - kTwoPiHi * rint(psi * kInvTwoPi);
   const float2 G = spa_factor32(gd, gdd, d);
   float sn, cs;

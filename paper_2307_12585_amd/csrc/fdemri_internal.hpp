@@ -105,6 +105,15 @@ __host__ __device__ inline Prepared prepared_of(const WaveItem& w) {
   return p;
 }
 
+// Qualifier of read-only device tables read through the constant address
+// space (wave-uniform loads from it become scalar loads).  The host pass,
+// which only checks device code, has no such address space.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define kconst __attribute__((address_space(4)))
+#else
+#define kconst
+#endif
+
 // ---------------------------------------------------------------- helpers
 
 struct dd {
@@ -133,6 +142,10 @@ __device__ __forceinline__ double knot_freq(double m, double fphi, double n, dou
   double b = n * fr;
   return a + b;
 }
+
+// m x + n y with one fused multiply-add in a fixed order, so that the
+// forward and adjoint kernels form identical mode-weighted coefficients.
+__device__ __forceinline__ double wsum(double m, double x, double n, double y) { return __builtin_fma(m, x, n * y); }
 
 // Reciprocal and reciprocal square root from the hardware estimates refined
 // by Newton-Raphson steps (one step: for iterations that correct themselves;

@@ -3,22 +3,21 @@
 //
 // The paper's GPU kernel places one block per (voice, spline segment) and
 // adds every contribution atomically into the output vector.  Here each
-// wavefront owns a tile of contiguous frequency bins instead and gathers all
-// contributions to its bins in registers, so every output element is written
-// once, coalesced, in a fixed order of voices and pieces (deterministic, no
-// atomics):
+// wavefront owns tiles of 64 contiguous frequency bins instead and gathers
+// all contributions to its bins in registers, so every output element is
+// written once, coalesced, in a fixed order of voices and pieces
+// (deterministic, no atomics):
 //   1. the workgroup stages the shared trajectory tables (knots and spline
-//      coefficients of F_phi, F_r, Phi_phi, Phi_r) in LDS;
-//   2. the wave scans the per-mode bin ranges 64 modes at a time and keeps,
-//      by ballot, the modes whose range meets its tile;
-//   3. for each active piece of an active mode, each lane with a bin inside
-//      the piece's range finds the spline segment holding f (binary search
-//      over the knot frequencies), solves the cubic of Eq. cubic_equation for
-//      the root by safeguarded Newton iteration, evaluates dF/dt, d2F/dt2,
-//      the factor G of Eq. extendedspa1, the phase 2 pi f t - Phi_V(t) (large
-//      part in double-double, reduced modulo 2 pi) and the amplitude spline,
-//      and accumulates h_+ and h_x;
-//   4. the wave stores its tile.
+//      coefficients of F_phi, F_r, Phi_phi, Phi_r) in LDS and lists, in LDS,
+//      the modes whose bin range meets its block of bins;
+//   2. for each listed mode and each of its monotonic pieces with bins in the
+//      tile, each lane with a bin inside the piece's range finds the spline
+//      segment holding f, solves the cubic of Eq. cubic_equation for the root
+//      (secant start, safeguarded Halley steps), evaluates d|F|/dt,
+//      d2|F|/dt2, the factor G of Eq. extendedspa1, the phase
+//      2 pi f t - Phi_V(t) (large part in double-double, reduced modulo 2 pi)
+//      and the amplitude spline, and accumulates h_+ and h_x;
+//   3. the wave stores its tile.
 // FP64 path: everything in double.  Mixed path: root, derivatives, phase and
 // its reduction in double; the special function, sincos, amplitude spline and
 // products in float with compensated (Kahan) accumulation.
@@ -70,66 +69,79 @@ struct Lds {
 
 // One (bin, piece) evaluation.  The spline segment holding f is the largest i
 // in [seg_a, seg_b] whose start value precedes f in the direction of the
-// piece (i == seg_a or d g_i < d f; ties go to the lower segment); it is found
-// from the piece's rate guess and a short correction in either direction.
+// piece (i == seg_a or d g_i < d f; ties go to the lower segment).  It is
+// guessed from the piece's rate, refined by one secant step on the segment
+// index through the knot frequencies at the guess, and checked against the
+// definition; the rare misses walk to the right segment.
+//   f, w: the bin frequency and 2 pi f (double-double);
+//   ms, ns: s m and s n of the piece, so that |F_V| = ms F_phi + ns F_r;
+//   dd_, span, rate: d, seg_b - seg_a and the rate of the piece;
+//   cP, cX: c_+ and c_x, conjugated when s < 0, so that the contribution is
+//   cP (A^(s) E) and cX (A^(s) E), A^(s) being A conjugated when s < 0.
 template <bool MIXED>
-__device__ __forceinline__ void eval_bin(const double f, const Piece& P, const double m, const double n,
-                                         const double cpr, const double cpi, const double cxr, const double cxi,
-                                         const double* __restrict__ ac, const float* __restrict__ ac32,
-                                         const Lds& L, Acc<MIXED>& acc) {
-  const int s = P.s, d = P.d;
-  const double sd = (double)s;
-  const double dd_ = (double)d;
-  const double span = (double)(P.seg_b - P.seg_a);
-  const double est = fmin(fmax((f - P.g_a) * (double)P.rate, 0.0), span);
-  int i = P.seg_a + (int)est;
-  while (i > P.seg_a && !(dd_ * (sd * knot_freq(m, L.Fp[i], n, L.Fr[i])) < dd_ * f)) --i;
-  while (i < P.seg_b && dd_ * (sd * knot_freq(m, L.Fp[i + 1], n, L.Fr[i + 1])) < dd_ * f) ++i;
+__device__ __forceinline__ void eval_bin(const double f, const dd w, const Piece& P, const double ms, const double ns,
+                                         const double dd_, const double span, const double rate, const double2 cP,
+                                         const double2 cX, const double* __restrict__ ac,
+                                         const float* __restrict__ ac32, const Lds& L, Acc<MIXED>& acc) {
+  const double fd = dd_ * f;
+  int i = P.seg_a + (int)fmin(fmax((f - P.g_a) * rate, 0.0), span);
+  double G0 = knot_freq(ms, L.Fp[i], ns, L.Fr[i]);
+  double G1 = knot_freq(ms, L.Fp[i + 1], ns, L.Fr[i + 1]);
+  {
+    const float num = (float)(f - G0);
+    const float den = (float)(G1 - G0);
+    float di = 0.f;
+    if (den != 0.f) di = fminf(fmaxf(floorf(num * __builtin_amdgcn_rcpf(den)), -(float)span), (float)span);
+    const int j = min(max(i + (int)di, P.seg_a), P.seg_b);
+    if (j != i) {
+      i = j;
+      G0 = knot_freq(ms, L.Fp[i], ns, L.Fr[i]);
+      G1 = knot_freq(ms, L.Fp[i + 1], ns, L.Fr[i + 1]);
+    }
+  }
+  if ((i > P.seg_a && !(dd_ * G0 < fd)) || (i < P.seg_b && dd_ * G1 < fd)) {
+    while (i > P.seg_a && !(dd_ * knot_freq(ms, L.Fp[i], ns, L.Fr[i]) < fd)) --i;
+    while (i < P.seg_b && dd_ * knot_freq(ms, L.Fp[i + 1], ns, L.Fr[i + 1]) < fd) ++i;
+    G0 = knot_freq(ms, L.Fp[i], ns, L.Fr[i]);
+    G1 = knot_freq(ms, L.Fp[i + 1], ns, L.Fr[i + 1]);
+  }
   SegData S;
   S.ti = L.t[i];
   S.h = L.t[i + 1] - S.ti;
-  S.F0 = knot_freq(m, L.Fp[i], n, L.Fr[i]);
-  S.F1 = knot_freq(m, L.Fp[i + 1], n, L.Fr[i + 1]);
+  S.G0 = G0;
+  S.G1 = G1;
   const double* cf = L.cF + i * 6;
-  S.a1 = m * cf[0] + n * cf[3];
-  S.a2 = m * cf[1] + n * cf[4];
-  S.a3 = m * cf[2] + n * cf[5];
+  S.q1 = wsum(ms, cf[0], ns, cf[3]);
+  S.q2 = wsum(ms, cf[1], ns, cf[4]);
+  S.q3 = wsum(ms, cf[2], ns, cf[5]);
   const double* cp = L.cP + i * 6;
-  S.b1 = m * cp[0] + n * cp[3];
-  S.b2 = m * cp[1] + n * cp[4];
-  S.b3 = m * cp[2] + n * cp[5];
+  S.r1 = wsum(ms, cp[0], ns, cp[3]);
+  S.r2 = wsum(ms, cp[1], ns, cp[4]);
+  S.r3 = wsum(ms, cp[2], ns, cp[5]);
   S.Ppi = L.Pp[i];
   S.Pri = L.Pr[i];
-  const Bracket B = make_bracket(P, i, sd, S);
-  const double tau = solve_root(f, sd, dd_, S, B);
+  const Bracket B = make_bracket(P, i, S);
+  const double tau = solve_root(f, dd_, S, B);
 
   if constexpr (!MIXED) {
     double2 E, A;
-    root_terms64(f, tau, sd, d, m, n, S, ac + (size_t)i * 8, E, A);
-    double pr = A.x * cpr - A.y * cpi, pi = A.x * cpi + A.y * cpr;
-    double xr = A.x * cxr - A.y * cxi, xi = A.x * cxi + A.y * cxr;
-    if (s < 0) {
-      pi = -pi;
-      xi = -xi;
-    }
-    acc.v[0] += pr * E.x - pi * E.y;
-    acc.v[1] += pr * E.y + pi * E.x;
-    acc.v[2] += xr * E.x - xi * E.y;
-    acc.v[3] += xr * E.y + xi * E.x;
+    root_terms64(w, tau, P.d, ms, ns, S, ac + (size_t)i * 8, E, A);
+    const double ay = P.s < 0 ? -A.y : A.y;
+    const double Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
+    acc.v[0] += cP.x * Wr - cP.y * Wi;
+    acc.v[1] += cP.x * Wi + cP.y * Wr;
+    acc.v[2] += cX.x * Wr - cX.y * Wi;
+    acc.v[3] += cX.x * Wi + cX.y * Wr;
   } else {
     float2 E, A;
-    root_terms32(f, tau, sd, d, m, n, S, ac32 + (size_t)i * 8, E, A);
-    const float fcpr = (float)cpr, fcpi = (float)cpi, fcxr = (float)cxr, fcxi = (float)cxi;
-    float pr = A.x * fcpr - A.y * fcpi, pi = A.x * fcpi + A.y * fcpr;
-    float xr = A.x * fcxr - A.y * fcxi, xi = A.x * fcxi + A.y * fcxr;
-    if (s < 0) {
-      pi = -pi;
-      xi = -xi;
-    }
-    acc.add(0, pr * E.x - pi * E.y);
-    acc.add(1, pr * E.y + pi * E.x);
-    acc.add(2, xr * E.x - xi * E.y);
-    acc.add(3, xr * E.y + xi * E.x);
+    root_terms32(w, tau, P.d, ms, ns, S, ac32 + (size_t)i * 8, E, A);
+    const float ay = P.s < 0 ? -A.y : A.y;
+    const float Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
+    const float pr = (float)cP.x, pi = (float)cP.y, xr = (float)cX.x, xi = (float)cX.y;
+    acc.add(0, pr * Wr - pi * Wi);
+    acc.add(1, pr * Wi + pi * Wr);
+    acc.add(2, xr * Wr - xi * Wi);
+    acc.add(3, xr * Wi + xi * Wr);
   }
 }
 
@@ -163,11 +175,25 @@ __device__ __forceinline__ Lds stage_lds(const Prepared& p, double* lds) {
   return Lds{s_t, s_Fp, s_Fr, s_Pp, s_Pr, s_cF, s_cP};
 }
 
-// Zeros for the tile [k0, k0 + 64 BPL) (blocks outside every voice's range).
+// Active-mode list of a block: at most kListCap mode indices at a time, in
+// LDS in front of the trajectory tables, followed by the per-wave counts of
+// the scan.
+constexpr int kListCap = 512;
+// Modes examined per lane and round of the active-mode scan.
+constexpr int kModesPerLane = 16;
+constexpr size_t kHeadDoubles = (kListCap + 8) / 2;
+
+// Bins of one block: WAVES waves, each owning BPL consecutive 64-bin tiles.
+template <int BPL, int WAVES>
+constexpr int block_bins() {
+  return 64 * BPL * WAVES;
+}
+
+// Zeros for the bins of a block outside every voice's range.
 template <bool MIXED, int BPL, int WAVES>
-__device__ __forceinline__ void zero_tile(void* hp, void* hc, int Nf, long k0) {
-  for (int t = threadIdx.x; t < 64 * BPL; t += 64 * WAVES) {
-    const long k = k0 + t;
+__device__ __forceinline__ void zero_block(void* hp, void* hc, int Nf, long kb) {
+  for (int t = threadIdx.x; t < block_bins<BPL, WAVES>(); t += 64 * WAVES) {
+    const long k = kb + t;
     if (k < Nf) {
       if constexpr (MIXED) {
         ((float2*)hp)[k] = make_float2(0.f, 0.f);
@@ -180,139 +206,207 @@ __device__ __forceinline__ void zero_tile(void* hp, void* hc, int Nf, long k0) {
   }
 }
 
-// One workgroup's tile of 64 * BPL contiguous bins starting at k0.  Every
-// wave enumerates the (mode, piece) pairs active in the tile and evaluates
-// those with (mode + piece) % WAVES == its index; each lane accumulates its
-// bins in registers, and the partial sums are added in LDS in a fixed wave
-// order.  The grouping and the order within a group depend only on the
-// (mode, piece) pair, so the result is independent of scheduling and of the
-// tile size.  red: LDS scratch of WAVES * BPL * 64 * 4 doubles.
-template <bool MIXED, int BPL, int WAVES>
-__device__ __forceinline__ void process_tile(const Prepared& p, const float* __restrict__ acoef32, void* hp, void* hc,
-                                             long k0, const Lds& L, double* red) {
-  constexpr int TILE = 64 * BPL;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int Nf = p.Nf, nseg = p.K - 1;
-  const long k1 = (k0 + TILE - 1 < Nf - 1) ? k0 + TILE - 1 : Nf - 1;
-
-  double fk[BPL];
-  Acc<MIXED> acc[BPL];
+// Writes the active modes of round `base` with list position in
+// [c0, c0 + kListCap) (hits: bit j <=> mode wbase + 64 j + lane is active;
+// off: list position of the wave's first hit).
+__device__ __forceinline__ void write_list(int* list, uint32_t hits, int wbase, int off, int c0) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lanes_below = (1ull << lane) - 1ull;
+  int pos = off;
 #pragma unroll
-  for (int j = 0; j < BPL; ++j) {
-    const long k = k0 + j * 64 + lane;
-    fk[j] = (k < Nf) ? p.f[k] : 0.0;
-    acc[j].zero();
+  for (int j = 0; j < kModesPerLane; ++j) {
+    const unsigned long long bm = __ballot((hits >> j) & 1u);
+    if ((hits >> j) & 1u) {
+      const int e = pos + __popcll(bm & lanes_below) - c0;
+      if (e >= 0 && e < kListCap) list[e] = wbase + j * 64 + lane;
+    }
+    pos += __popcll(bm);
+  }
+}
+
+// One wave's pass over list entries [0, n) for its 64-bin tile [ks, ke]:
+// every piece of every listed mode that has bins in the tile is evaluated by
+// the lanes whose bin lies in the piece's range, in list (mode) order and
+// piece order.  The mode, range and piece tables are read-only here and are
+// read through the constant address space, so that their wave-uniform
+// records come in by scalar loads.
+template <bool MIXED>
+__device__ __forceinline__ void walk_list(const Prepared& p, const float* __restrict__ acoef32, const int* list, int n,
+                                          long ks, long ke, double f, const dd w, const Lds& L, Acc<MIXED>& acc) {
+  const int lane = threadIdx.x & 63;
+  const long k = ks + lane;
+  const int nseg = p.K - 1;
+  const kconst int2* kr = (const kconst int2*)p.mode_kr;
+  for (int e = 0; e < n; ++e) {
+    const int mode = __builtin_amdgcn_readfirstlane(list[e]);
+    const int2 r = kr[mode];
+    if (r.x > ke || r.y < ks) continue;
+    const ModeConst md = ((const kconst ModeConst*)p.modes)[mode];
+    const kconst Piece* pcs = (const kconst Piece*)p.pieces + (size_t)mode * kMaxPieces;
+    for (int q = 0; q < md.npieces; ++q) {
+      const Piece P = pcs[q];
+      // bins of this piece in the tile (wave-uniform)
+      const long ka = max(ks, (long)P.k_lo);
+      const long kz = min(ke, (long)P.k_hi);
+      if (ka > kz) continue;
+      if (k >= ka && k <= kz) {
+        const bool neg = P.s < 0;
+        const double ms = neg ? -md.m : md.m, ns = neg ? -md.n : md.n;
+        const double2 cP = make_double2(md.cp_re, neg ? -md.cp_im : md.cp_im);
+        const double2 cX = make_double2(md.cx_re, neg ? -md.cx_im : md.cx_im);
+        const double* ac = p.acoef + (size_t)mode * nseg * 8;
+        const float* ac32 = MIXED ? acoef32 + (size_t)mode * nseg * 8 : nullptr;
+        eval_bin<MIXED>(f, w, P, ms, ns, (double)P.d, (double)(P.seg_b - P.seg_a), (double)P.rate, cP, cX, ac, ac32,
+                        L, acc);
+      }
+    }
+  }
+}
+
+// One workgroup's block of WAVES * BPL * 64 contiguous bins starting at kb;
+// wave w owns the BPL tiles [kb + 64 (w BPL + j), + 64).
+//  1. The workgroup lists the modes whose bin range meets the block: wave w
+//     scans a contiguous run of 64 * kModesPerLane modes per round with
+//     coalesced loads of the range table, compacts the hits by ballot and
+//     writes them, after the hits of lower waves, into an LDS list in
+//     increasing mode order.
+//  2. Each wave walks the list for each of its tiles; every lane sums all
+//     contributions to its bin in one register accumulator, in mode and
+//     piece order, and stores the bin.
+// The sum of every bin is taken by one lane in a fixed order, so the result
+// does not depend on scheduling, on the block shape or on the tile size.
+// list: LDS of kListCap + 8 ints.
+template <bool MIXED, int BPL, int WAVES>
+__device__ __forceinline__ void process_block(const Prepared& p, const float* __restrict__ acoef32, void* hp,
+                                              void* hc, long kb, const Lds& L, int* list) {
+  constexpr int CHUNK = 64 * kModesPerLane;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int Nf = p.Nf;
+  const long kbe = min(kb + block_bins<BPL, WAVES>() - 1, (long)Nf - 1);
+  int* wcount = list + kListCap;
+
+  // 1. scan, in rounds of WAVES * CHUNK modes
+  const int rounds = (p.Nm + WAVES * CHUNK - 1) / (WAVES * CHUNK);
+  bool single = false;  // one round whose hits fit the list: built once, walked for every tile
+  int total = 0, off = 0, wbase = 0;
+  uint32_t hits = 0;
+  auto scan = [&](int base) {
+    wbase = base + wave * CHUNK;
+    hits = 0;
+    const kconst int2* kr = (const kconst int2*)p.mode_kr + wbase + lane;
+    const int lim = p.Nm - wbase - lane;
+#pragma unroll 4
+    for (int j = 0; j < kModesPerLane; ++j) {
+      if (j * 64 < lim) {
+        const int2 r = kr[j * 64];
+        if (r.x <= kbe && r.y >= kb) hits |= 1u << j;
+      }
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kModesPerLane; ++j) cnt += __popcll(__ballot((hits >> j) & 1u));
+    __syncthreads();  // the previous list has been consumed
+    if (lane == 0) wcount[wave] = cnt;
+    __syncthreads();
+    off = 0;
+    total = 0;
+#pragma unroll
+    for (int v = 0; v < WAVES; ++v) {
+      const int c = wcount[v];
+      off += v < wave ? c : 0;
+      total += c;
+    }
+  };
+  if (rounds == 1) {
+    scan(0);
+    if (total <= kListCap) {
+      single = true;
+      if (total > 0) {
+        write_list(list, hits, wbase, off, 0);
+        __syncthreads();
+      }
+    }
   }
 
-  // modes whose bin range meets the tile, 64 at a time, by ballot
-  for (int mc = 0; mc < p.Nm; mc += 64) {
-    const int mu = mc + lane;
-    bool act = false;
-    if (mu < p.Nm) {
-      const int2 r = p.mode_kr[mu];
-      act = (r.x <= k1) && (r.y >= k0);
-    }
-    unsigned long long mask = __ballot(act);
-    while (mask) {
-      const int bit = __ffsll((long long)mask) - 1;
-      mask &= mask - 1;
-      const int mode = mc + bit;
-      const ModeConst md = p.modes[mode];
-      const Piece* pcs = p.pieces + (size_t)mode * kMaxPieces;
-      const double* ac = p.acoef + (size_t)mode * nseg * 8;
-      const float* ac32 = MIXED ? acoef32 + (size_t)mode * nseg * 8 : nullptr;
-      for (int q = 0; q < md.npieces; ++q) {
-        const Piece P = pcs[q];
-        if (P.k_lo > k1 || P.k_hi < k0) continue;
-        if ((mode + q) % WAVES != wave) continue;
-#pragma unroll
-        for (int j = 0; j < BPL; ++j) {
-          // bins of this piece in sub-tile j (wave-uniform)
-          const long ka = max(k0 + j * 64, (long)P.k_lo);
-          const long kz = min(min(k0 + j * 64 + 63, (long)Nf - 1), (long)P.k_hi);
-          if (ka > kz) continue;
-          const long k = k0 + j * 64 + lane;
-          if (k >= ka && k <= kz)
-            eval_bin<MIXED>(fk[j], P, md.m, md.n, md.cp_re, md.cp_im, md.cx_re, md.cx_im, ac, ac32, L, acc[j]);
+  // 2. evaluate, tile by tile
+#pragma unroll 1
+  for (int j = 0; j < BPL; ++j) {
+    const long ks = kb + (long)(wave * BPL + j) * 64;
+    const long ke = min(ks + 63, (long)Nf - 1);
+    const long k = ks + lane;
+    const double f = (k < Nf) ? p.f[k] : 0.0;
+    const dd w = two_pi_f(f);
+    Acc<MIXED> acc;
+    acc.zero();
+    if (single) {
+      if (ks <= ke) walk_list<MIXED>(p, acoef32, list, total, ks, ke, f, w, L, acc);
+    } else {
+      // many active modes: rebuild the list window by window (every wave
+      // takes part in every rebuild)
+      for (int r = 0; r < rounds; ++r) {
+        scan(r * WAVES * CHUNK);
+        for (int c0 = 0; c0 < total; c0 += kListCap) {
+          if (c0 > 0) __syncthreads();  // the previous window has been consumed
+          write_list(list, hits, wbase, off, c0);
+          __syncthreads();
+          if (ks <= ke) walk_list<MIXED>(p, acoef32, list, min(kListCap, total - c0), ks, ke, f, w, L, acc);
         }
       }
     }
-  }
-
-  // partial sums of the waves, added in wave order
-#pragma unroll
-  for (int j = 0; j < BPL; ++j) {
-    double* r = red + ((size_t)(wave * BPL + j) * 64 + lane) * 4;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if constexpr (MIXED)
-        r[c] = (double)acc[j].v[c] - (double)acc[j].c[c];
-      else
-        r[c] = acc[j].v[c];
-    }
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < TILE; t += 64 * WAVES) {
-    const int j = t >> 6, ln = t & 63;
-    const long k = k0 + t;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) {
-      const double* r = red + ((size_t)(w * BPL + j) * 64 + ln) * 4;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] += r[c];
-    }
     if (k < Nf) {
       if constexpr (MIXED) {
-        ((float2*)hp)[k] = make_float2((float)v[0], (float)v[1]);
-        ((float2*)hc)[k] = make_float2((float)v[2], (float)v[3]);
+        float v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = (float)((double)acc.v[c] - (double)acc.c[c]);
+        ((float2*)hp)[k] = make_float2(v[0], v[1]);
+        ((float2*)hc)[k] = make_float2(v[2], v[3]);
       } else {
-        ((double2*)hp)[k] = make_double2(v[0], v[1]);
-        ((double2*)hc)[k] = make_double2(v[2], v[3]);
+        ((double2*)hp)[k] = make_double2(acc.v[0], acc.v[1]);
+        ((double2*)hc)[k] = make_double2(acc.v[2], acc.v[3]);
       }
     }
   }
 }
 
-template <int BPL, int WAVES>
-constexpr size_t red_doubles() {
-  return (size_t)WAVES * BPL * 64 * 4;
+// Occupancy target of the gather kernels, in waves per SIMD: the register
+// budget of the FP64 evaluation fits 3 (168 VGPRs), that of the mixed one 4.
+template <bool MIXED>
+constexpr int gather_min_waves() {
+  return MIXED ? 4 : 3;
 }
 
 template <bool MIXED, int BPL, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void gather_kernel(GatherArgs a) {
+__global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_kernel(GatherArgs a) {
   extern __shared__ double lds[];
   const Prepared& p = a.p;
-  constexpr int TILE = 64 * BPL;
-  const long k0 = (long)blockIdx.x * TILE;
-  const long k1 = k0 + TILE - 1;
-  // tiles outside the bin envelope of all modes only write zeros
-  if (k1 < p.env[0] || k0 > p.env[1]) {
-    zero_tile<MIXED, BPL, WAVES>(a.hp, a.hc, p.Nf, k0);
+  const long kb = (long)blockIdx.x * block_bins<BPL, WAVES>();
+  const long kbe = kb + block_bins<BPL, WAVES>() - 1;
+  // blocks outside the bin envelope of all modes only write zeros
+  if (kbe < p.env[0] || kb > p.env[1]) {
+    zero_block<MIXED, BPL, WAVES>(a.hp, a.hc, p.Nf, kb);
     return;
   }
-  double* red = lds;
-  const Lds L = stage_lds(p, lds + red_doubles<BPL, WAVES>());
+  int* list = (int*)lds;
+  const Lds L = stage_lds(p, lds + kHeadDoubles);
   __syncthreads();
-  process_tile<MIXED, BPL, WAVES>(p, a.acoef32, a.hp, a.hc, k0, L, red);
+  process_block<MIXED, BPL, WAVES>(p, a.acoef32, a.hp, a.hc, kb, L, list);
 }
 
 // Persistent gather over a batch: every workgroup repeatedly takes the next
-// tile (waveform b, bins [j * 64 BPL, (j + 1) * 64 BPL)) from a device counter
-// and evaluates it exactly as the single-waveform kernel would, restaging the
-// LDS tables when the waveform changes.  The counter only schedules; every
-// output element is computed in a fixed order, so results do not depend on
-// the schedule.  Every workgroup leaves the loop once the counter passes the
-// last tile.
+// block (waveform b, bins [j B, (j + 1) B) with B = 64 BPL WAVES) from a
+// device counter and evaluates it exactly as the single-waveform kernel
+// would, restaging the LDS tables when the waveform changes.  The counter
+// only schedules; every output element is computed in a fixed order, so
+// results do not depend on the schedule.  Every workgroup leaves the loop
+// once the counter passes the last block.
 template <bool MIXED, int BPL, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void gather_batch_kernel(const WaveItem* __restrict__ items, int B,
-                                                                  const int32_t* __restrict__ item_prefix,
-                                                                  int total_items, int* __restrict__ counter) {
+__global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_batch_kernel(const WaveItem* __restrict__ items, int B,
+                                                                const int32_t* __restrict__ item_prefix,
+                                                                int total_items, int* __restrict__ counter) {
   extern __shared__ double lds[];
   __shared__ int s_item;
-  constexpr int TILE = 64 * BPL;
-  double* red = lds;
-  double* tables = lds + red_doubles<BPL, WAVES>();
+  int* list = (int*)lds;
+  double* tables = lds + kHeadDoubles;
   int cached = -1;
   Lds L{};
   for (;;) {
@@ -321,20 +415,22 @@ __global__ __launch_bounds__(64 * WAVES) void gather_batch_kernel(const WaveItem
     __syncthreads();
     const int it = s_item;
     if (it >= total_items) break;
+    // the records are read-only here (constant address space: scalar loads)
+    const kconst int32_t* pre = (const kconst int32_t*)item_prefix;
     int lo = 0, hi = B - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (item_prefix[mid] <= it)
+      if (pre[mid] <= it)
         lo = mid;
       else
         hi = mid - 1;
     }
-    const WaveItem& w = items[lo];
+    const WaveItem w = ((const kconst WaveItem*)items)[lo];
     const Prepared p = prepared_of(w);
-    const long k0 = (long)(it - item_prefix[lo]) * TILE;
-    const long k1 = k0 + TILE - 1;
-    if (k1 < p.env[0] || k0 > p.env[1]) {
-      zero_tile<MIXED, BPL, WAVES>(w.hp, w.hc, p.Nf, k0);
+    const long kb = (long)(it - pre[lo]) * block_bins<BPL, WAVES>();
+    const long kbe = kb + block_bins<BPL, WAVES>() - 1;
+    if (kbe < p.env[0] || kb > p.env[1]) {
+      zero_block<MIXED, BPL, WAVES>(w.hp, w.hc, p.Nf, kb);
       continue;
     }
     if (lo != cached) {
@@ -342,7 +438,7 @@ __global__ __launch_bounds__(64 * WAVES) void gather_batch_kernel(const WaveItem
       __syncthreads();
       cached = lo;
     }
-    process_tile<MIXED, BPL, WAVES>(p, w.acoef32, w.hp, w.hc, k0, L, red);
+    process_block<MIXED, BPL, WAVES>(p, w.acoef32, w.hp, w.hc, kb, L, list);
   }
 }
 
@@ -401,9 +497,9 @@ size_t gather_lds_bytes(int K) { return (size_t)(5 * K + 12 * (K - 1)) * sizeof(
 
 template <bool MIXED, int BPL, int WAVES>
 static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t stream) {
-  constexpr int per_block = 64 * BPL;
+  constexpr int per_block = block_bins<BPL, WAVES>();
   const long blocks = ((long)a.p.Nf + per_block - 1) / per_block;
-  const size_t red = red_doubles<BPL, WAVES>() * sizeof(double);
+  const size_t red = kHeadDoubles * sizeof(double);
   const size_t lds = gather_lds_bytes(a.p.K) + red;
   static bool attr_set = false;
   if (!attr_set) {
@@ -439,7 +535,7 @@ hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp,
 template <bool MIXED, int BPL, int WAVES>
 static hipError_t launch_gather_batch_t(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
                                         int* counter, int Kmax, int grid, hipStream_t stream) {
-  const size_t red = red_doubles<BPL, WAVES>() * sizeof(double);
+  const size_t red = kHeadDoubles * sizeof(double);
   const size_t lds = gather_lds_bytes(Kmax) + red;
   static bool attr_set = false;
   if (!attr_set) {
@@ -461,15 +557,15 @@ static int persistent_grid(int Kmax) {
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)gather_batch_kernel<MIXED, BPL, WAVES>,
                                                      64 * WAVES,
-                                                     gather_lds_bytes(Kmax) + red_doubles<BPL, WAVES>() * sizeof(double));
+                                                     gather_lds_bytes(Kmax) + kHeadDoubles * sizeof(double));
   if (ncu <= 0) ncu = 256;
   if (per_cu <= 0) per_cu = 1;
   return ncu * per_cu;
 }
 
 int gather_items_per_waveform(int Nf, int bpl) {
-  const int per_tile = 64 * bpl;
-  return (Nf + per_tile - 1) / per_tile;
+  const int per_block = 64 * bpl * 4;  // WAVES = 4 in every launch below
+  return (Nf + per_block - 1) / per_block;
 }
 
 hipError_t launch_gather_batch(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,

@@ -34,7 +34,9 @@ __device__ __forceinline__ double2 q_cheb64(double y) {
   const double* ci = fdw_q64_im + j * (FDW_DEG64 + 1);
   double b1r = 0.0, b2r = 0.0, b1i = 0.0, b2i = 0.0;
   const double x2 = 2.0 * x;
-#pragma unroll
+  // kept rolled: the branch is rare, and unrolling would hold every
+  // coefficient in registers at once
+#pragma unroll 1
   for (int k = FDW_DEG64; k >= 1; --k) {
     const double tr = x2 * b1r - b2r + cr[k];
     const double ti = x2 * b1i - b2i + ci[k];
@@ -55,7 +57,7 @@ __device__ __forceinline__ float2 q_cheb32(float y) {
   const float* ci = fdw_q32_im + j * (FDW_DEG32 + 1);
   float b1r = 0.f, b2r = 0.f, b1i = 0.f, b2i = 0.f;
   const float x2 = 2.0f * x;
-#pragma unroll
+#pragma unroll 1
   for (int k = FDW_DEG32; k >= 1; --k) {
     const float tr = x2 * b1r - b2r + cr[k];
     const float ti = x2 * b1i - b2i + ci[k];
@@ -68,25 +70,35 @@ __device__ __forceinline__ float2 q_cheb32(float y) {
 }
 
 // G in FP64.  dir = direction of the piece (used only when gd == 0).
-// u = 1/X = 3 gdd^2 / (2 pi gd^3) is formed with one reciprocal; |u| <= 1/X_B
-// selects the large-argument expansion (u = +-inf at gd = 0 selects the Airy
-// form, NaN falls into the expansion branch and stays NaN).
+// |gd|^{-1/2} is formed once (refined hardware estimate) and also gives
+// |u| = |1/X| = 3 gdd^2 / (2 pi |gd|^3) through its sixth power.  |u| <= 1/X_B
+// selects the large-argument expansion, whose length is chosen per wave from
+// the largest |u| among the active lanes (|u| <= 1e-5: terms to u^3, first
+// omitted below 1e-21; |u| <= 1e-3: terms to u^7, below 1e-23; otherwise the
+// full table).  gd == 0 (a root on a turning point) has no finite |u| and
+// takes the Airy form, which is finite there.
 __device__ __forceinline__ double2 spa_factor64(double gd, double gdd, int dir) {
   constexpr double kRsqrt2 = 0.70710678118654752440;
   constexpr double k3Over2Pi = 0.47746482927568600730;
-  if (gdd == 0.0) {
-    if (gd == 0.0) return make_double2(0.0, 0.0);
-    const double c = kRsqrt2 * rsq_nr2(fabs(gd));
-    return make_double2(c, gd > 0.0 ? -c : c);
-  }
-  const double u = k3Over2Pi * gdd * gdd * rcp_nr2(gd * gd * gd);
-  const double au = fabs(u);
+  constexpr double k2PiOver3 = 2.0943951023931954923;
+  if (gd == 0.0 && gdd == 0.0) return make_double2(0.0, 0.0);
+  const double agd = fabs(gd);
   const int sg = gd > 0.0 ? 1 : (gd < 0.0 ? -1 : dir);
-  if (!(au > 1.0 / FDW_X_B)) {
+  const double rs = rsq_nr2(agd);
+  const double rs2 = rs * rs;
+  const double au = (gdd == 0.0) ? 0.0 : k3Over2Pi * gdd * gdd * (rs2 * rs2 * rs2);
+  if (gd != 0.0 && au <= 1.0 / FDW_X_B) {
+    const double u = sg > 0 ? au : -au;
     const double v = u * u;
     double re = 0.0, im = 0.0;
-    if (__all(au <= 1e-3)) {
-      // |X| >= 1e3 on every active lane: 8 terms (first omitted term < 1e-23)
+    if (__all(au <= 1e-5)) {
+#pragma unroll
+      for (int j = 1; j >= 0; --j) {
+        const double sgn = (j & 1) ? -1.0 : 1.0;
+        re = re * v + sgn * fdw_asym64[2 * j];
+        im = im * v + sgn * fdw_asym64[2 * j + 1];
+      }
+    } else if (__all(au <= 1e-3)) {
 #pragma unroll
       for (int j = 3; j >= 0; --j) {
         const double sgn = (j & 1) ? -1.0 : 1.0;
@@ -102,12 +114,12 @@ __device__ __forceinline__ double2 spa_factor64(double gd, double gdd, int dir) 
       }
     }
     im *= u;
-    const double c = kRsqrt2 * rsq_nr2(fabs(gd));
+    const double c = kRsqrt2 * rs;
     // (c - i sg c) (re + i im)
-    const double br = c, bi = -sg * c;
-    return make_double2(br * re - bi * im, br * im + bi * re);
+    const double bi = sg > 0 ? -c : c;
+    return make_double2(c * re - bi * im, c * im + bi * re);
   }
-  const double ax = rcp_nr2(au);  // |X| (0 when gd == 0)
+  const double ax = k2PiOver3 * agd * agd * agd * rcp_nr2(gdd * gdd);  // |X|
   const double y = cbrt(1.5 * ax);
   double2 q = q_cheb64(y);
   if (sg < 0) q.y = -q.y;
@@ -116,20 +128,18 @@ __device__ __forceinline__ double2 spa_factor64(double gd, double gdd, int dir) 
 }
 
 // G in FP32 from FP64 derivatives (the mixed-precision path keeps gd, gdd in
-// FP64 and evaluates the special function in FP32).
+// FP64 and evaluates the special function in FP32); same branches as the
+// FP64 factor.
 __device__ __forceinline__ float2 spa_factor32(double gd, double gdd, int dir) {
   constexpr float kRsqrt2 = 0.70710678118654752440f;
   constexpr double k3Over2Pi = 0.47746482927568600730;
-  if (gdd == 0.0) {
-    if (gd == 0.0) return make_float2(0.f, 0.f);
-    const float c = kRsqrt2 * rsqrtf((float)fabs(gd));
-    return make_float2(c, gd > 0.0 ? -c : c);
-  }
-  const double u = k3Over2Pi * gdd * gdd * rcp_nr1(gd * gd * gd);
-  const double au = fabs(u);
+  constexpr double k2PiOver3 = 2.0943951023931954923;
+  if (gd == 0.0 && gdd == 0.0) return make_float2(0.f, 0.f);
+  const double agd = fabs(gd);
   const int sg = gd > 0.0 ? 1 : (gd < 0.0 ? -1 : dir);
-  if (!(au > 1.0 / FDW_X_B)) {
-    const float uf = (float)u;
+  const double au = (gdd == 0.0) ? 0.0 : k3Over2Pi * gdd * gdd * rcp_nr1(agd * agd * agd);
+  if (gd != 0.0 && au <= 1.0 / FDW_X_B) {
+    const float uf = (float)(sg > 0 ? au : -au);
     const float v = uf * uf;
     float re = 0.f, im = 0.f;
 #pragma unroll
@@ -139,11 +149,11 @@ __device__ __forceinline__ float2 spa_factor32(double gd, double gdd, int dir) {
       if (2 * j + 1 < FDW_NASYM32) im = im * v + sgn * fdw_asym32[2 * j + 1];
     }
     im *= uf;
-    const float c = kRsqrt2 * rsqrtf((float)fabs(gd));
-    const float br = c, bi = -sg * c;
-    return make_float2(br * re - bi * im, br * im + bi * re);
+    const float c = kRsqrt2 * rsqrtf((float)agd);
+    const float bi = sg > 0 ? -c : c;
+    return make_float2(c * re - bi * im, c * im + bi * re);
   }
-  const float y = cbrtf((float)(1.5 * rcp_nr2(au)));
+  const float y = cbrtf((float)(1.5 * k2PiOver3 * agd * agd * agd * rcp_nr2(gdd * gdd)));
   float2 q = q_cheb32(y);
   if (sg < 0) q.y = -q.y;
   const float pref = (float)(kPi / cbrt(kPi * fabs(gdd)));

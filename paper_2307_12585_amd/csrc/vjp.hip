@@ -76,25 +76,13 @@ __global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
 
   // segment data of this unit (wave-uniform)
-  SegData S;
-  S.ti = p.t[i];
-  S.h = p.t[i + 1] - S.ti;
-  S.F0 = knot_freq(m, p.Fphi[i], n, p.Fr[i]);
-  S.F1 = knot_freq(m, p.Fphi[i + 1], n, p.Fr[i + 1]);
-  {
-    const double* cFp = p.tcoef + ((size_t)0 * nseg + i) * 4;
-    const double* cFr = p.tcoef + ((size_t)1 * nseg + i) * 4;
-    const double* cPp = p.tcoef + ((size_t)2 * nseg + i) * 4;
-    const double* cPr = p.tcoef + ((size_t)3 * nseg + i) * 4;
-    S.a1 = m * cFp[1] + n * cFr[1];
-    S.a2 = m * cFp[2] + n * cFr[2];
-    S.a3 = m * cFp[3] + n * cFr[3];
-    S.b1 = m * cPp[1] + n * cPr[1];
-    S.b2 = m * cPp[2] + n * cPr[2];
-    S.b3 = m * cPp[3] + n * cPr[3];
-  }
-  S.Ppi = p.Phiphi[i];
-  S.Pri = p.Phir[i];
+  const double ti = p.t[i], h = p.t[i + 1] - ti;
+  const double F0 = knot_freq(m, p.Fphi[i], n, p.Fr[i]);
+  const double F1 = knot_freq(m, p.Fphi[i + 1], n, p.Fr[i + 1]);
+  const double* cFp = p.tcoef + ((size_t)0 * nseg + i) * 4;
+  const double* cFr = p.tcoef + ((size_t)1 * nseg + i) * 4;
+  const double* cPp = p.tcoef + ((size_t)2 * nseg + i) * 4;
+  const double* cPr = p.tcoef + ((size_t)3 * nseg + i) * 4;
   const double* acs = p.acoef + ((size_t)mu * nseg + i) * 8;
   const float* acs32 = MIXED ? a.acoef32 + ((size_t)mu * nseg + i) * 8 : nullptr;
 
@@ -103,10 +91,25 @@ __global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
     if (i < P.seg_a || i > P.seg_b || P.k_lo > P.k_hi) continue;
     const int s = P.s, d = P.d;
     const double sd = (double)s, dd_ = (double)d;
+    // |F_V| and s Phi_V of this piece on segment i (sign folded into the mode numbers)
+    const double ms = s < 0 ? -m : m, ns = s < 0 ? -n : n;
+    SegData S;
+    S.ti = ti;
+    S.h = h;
+    S.G0 = s < 0 ? -F0 : F0;
+    S.G1 = s < 0 ? -F1 : F1;
+    S.q1 = wsum(ms, cFp[1], ns, cFr[1]);
+    S.q2 = wsum(ms, cFp[2], ns, cFr[2]);
+    S.q3 = wsum(ms, cFp[3], ns, cFr[3]);
+    S.r1 = wsum(ms, cPp[1], ns, cPr[1]);
+    S.r2 = wsum(ms, cPp[2], ns, cPr[2]);
+    S.r3 = wsum(ms, cPp[3], ns, cPr[3]);
+    S.Ppi = p.Phiphi[i];
+    S.Pri = p.Phir[i];
     // bins whose root the forward search places in segment i of this piece:
     // the largest segment j in [seg_a, seg_b] with j == seg_a or d g_j < d f
     int kA = P.k_lo, kB = P.k_hi;
-    const double gi = sd * S.F0, gi1 = sd * S.F1;
+    const double gi = S.G0, gi1 = S.G1;
     if (d > 0) {
       if (i > P.seg_a) kA = max(kA, first_gt(p.f, p.Nf, gi));
       if (i < P.seg_b) kB = min(kB, first_gt(p.f, p.Nf, gi1) - 1);
@@ -115,14 +118,15 @@ __global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
       if (i < P.seg_b) kA = max(kA, first_ge(p.f, p.Nf, gi1));
     }
     if (kA > kB) continue;
-    const Bracket B = make_bracket(P, i, sd, S);
+    const Bracket B = make_bracket(P, i, S);
     for (int k = kA + lane; k <= kB; k += 64) {
       const double f = p.f[k];
-      const double tau = solve_root(f, sd, dd_, S, B);
+      const dd w = two_pi_f(f);
+      const double tau = solve_root(f, dd_, S, B);
       double Er, Ei, Ar, Ai, gpr, gpi, gcr, gci;
       if constexpr (MIXED) {
         float2 E, A;
-        root_terms32(f, tau, sd, d, m, n, S, acs32, E, A);
+        root_terms32(w, tau, d, ms, ns, S, acs32, E, A);
         Er = E.x;
         Ei = E.y;
         // the FP32 amplitude is in the normalised variable u = tau / h
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
         gci = gc.y;
       } else {
         double2 E, A;
-        root_terms64(f, tau, sd, d, m, n, S, acs, E, A);
+        root_terms64(w, tau, d, ms, ns, S, acs, E, A);
         Er = E.x;
         Ei = E.y;
         Ar = A.x;
