@@ -17,7 +17,7 @@
 
 namespace fdemri {
 hipError_t launch_spline(int K, const double* t, const double* Fphi, const double* Fr, const double* Phiphi,
-                         const double* Phir, const double* A, int Nm, double* tcoef, double* acoef, int32_t* env,
+                         const double* Phir, const double* A, int Nm, double* tcoef, double* acoef,
                          hipStream_t stream);
 struct PieceArgs;
 hipError_t launch_pieces_flat(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
@@ -333,7 +333,7 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   hipError_t e;
   {
     ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream);
-    e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, d->Nm, tcoef, acoef, env, stream);
+    e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, d->Nm, tcoef, acoef, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "spline kernel launch");
   {

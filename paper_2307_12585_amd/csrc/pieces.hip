@@ -23,6 +23,7 @@
 
 #include "fdemri_internal.hpp"
 #include "harmonics.hpp"
+#include "search.hpp"
 
 namespace fdemri {
 
@@ -42,53 +43,32 @@ struct PieceArgs {
   int2* mode_kr;
   Piece* pieces;
   int64_t* evals;  // [Nm]
-  int32_t* env;    // [2]
   uint32_t* flag_word;
 };
 
-// first index k with f[k] >= x (f ascending), in [0, Nf]
-__device__ __forceinline__ int lower_bound(const double* f, int Nf, double x) {
-  int lo = 0, hi = Nf;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (f[mid] < x)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// first index k with f[k] > x
-__device__ __forceinline__ int upper_bound(const double* f, int Nf, double x) {
-  int lo = 0, hi = Nf;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (f[mid] <= x)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// Segment-local part of the piece walk for spline segment i of one voice:
-// the monotonic sub-intervals between the interior turning points, and the
-// piece-closing events in order.  A piece closes where the direction of F_V
-// changes (at a sub-interval start, which may be a knot), where F_V changes
-// sign inside a sub-interval (bisection to full precision), and where F_V is
-// exactly 0 at an interior knot.  `cur_dir` is the last non-zero direction
-// before the segment.  With emit == false only the events are counted; with
-// emit == true they are written to ev[base + ...] (bounded by cap).  Returns
-// the number of events and, in last_dir, the last non-zero direction inside
-// the segment (0 if F_V is flat on it).
+// Segment-local part of the piece walk for spline segment i of one voice,
+// computed once: the monotonic sub-intervals between the interior turning
+// points of F_V (at most three), the direction of F_V on each, the zero
+// crossing inside each (bisection to full precision) and whether F_V is
+// exactly 0 at an interior knot ending the segment.  Which of these become
+// piece-closing events depends only on the direction before the segment
+// (segment_events below).
 struct Event {
   double tau, F;
   int seg;
 };
 
-__device__ int segment_events(const PieceArgs& a, int i, double m, double n, int cur_dir, bool emit, Event* ev,
-                              int base, int cap, int& last_dir) {
+struct SegScan {
+  double u0[3], F0[3];  // start of each sub-interval and F_V there
+  double zc[3];         // zero crossing inside sub-interval j (bit j of zc_mask)
+  int dir[3];           // direction of F_V on sub-interval j (0: flat)
+  int nsub, zc_mask;
+  bool zero_end;        // F_V == 0 exactly at the interior knot ending the segment
+  int last_dir;         // last non-zero direction inside the segment (0 if flat)
+  double h;             // segment length
+};
+
+__device__ __forceinline__ void scan_segment(const PieceArgs& a, int i, double m, double n, SegScan& S) {
   const int nseg = a.K - 1;
   const double h = a.t[i + 1] - a.t[i];
   const double* cp_ = a.tcoef + (size_t)i * 4;
@@ -99,70 +79,115 @@ __device__ int segment_events(const PieceArgs& a, int i, double m, double n, int
   const double a2 = m * cp_[2] + n * cr_[2];
   const double a3 = m * cp_[3] + n * cr_[3];
   auto poly = [&](double u) { return F0 + u * (a1 + u * (a2 + u * a3)); };
-  // turning points: sign changes of a1 + 2 a2 u + 3 a3 u^2 inside (0, h)
-  double tp[2];
+  // turning points: sign changes of a1 + 2 a2 u + 3 a3 u^2 inside (0, h), ascending
+  double t0 = 0.0, t1 = 0.0;
   int ntp = 0;
   {
     const double A2 = 3.0 * a3, B2 = 2.0 * a2, C2 = a1;
+    double r0 = 0.0, r1 = 0.0;
+    int nr = 0;
     if (A2 == 0.0) {
-      if (B2 != 0.0) tp[ntp++] = -C2 / B2;
+      if (B2 != 0.0) {
+        r0 = -C2 / B2;
+        nr = 1;
+      }
     } else {
       const double disc = B2 * B2 - 4.0 * A2 * C2;
       if (disc > 0.0) {
         const double sq = sqrt(disc);
         const double q = -0.5 * (B2 + (B2 >= 0.0 ? sq : -sq));
-        tp[ntp++] = q / A2;
-        if (q != 0.0) tp[ntp++] = C2 / q;
+        r0 = q / A2;
+        nr = 1;
+        if (q != 0.0) {
+          r1 = C2 / q;
+          nr = 2;
+        }
       }
     }
-    int keep = 0;
-    for (int j = 0; j < ntp; ++j)
-      if (tp[j] > 0.0 && tp[j] < h) tp[keep++] = tp[j];
-    ntp = keep;
-    if (ntp == 2 && tp[1] < tp[0]) {
-      const double x = tp[0];
-      tp[0] = tp[1];
-      tp[1] = x;
+    const bool k0 = nr >= 1 && r0 > 0.0 && r0 < h;
+    const bool k1 = nr >= 2 && r1 > 0.0 && r1 < h;
+    if (k0 && k1) {
+      t0 = fmin(r0, r1);
+      t1 = fmax(r0, r1);
+      ntp = 2;
+    } else if (k0 || k1) {
+      t0 = k0 ? r0 : r1;
+      ntp = 1;
     }
   }
+  S.h = h;
+  S.nsub = ntp + 1;
+  S.zc_mask = 0;
+  S.last_dir = 0;
+  double u0 = 0.0, Fu0 = F0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    S.u0[j] = u0;
+    S.F0[j] = Fu0;
+    S.dir[j] = 0;
+    S.zc[j] = 0.0;
+    if (j <= ntp) {
+      const bool last = (j == ntp);
+      const double u = last ? h : (j == 0 ? t0 : t1);
+      const double Fu = last ? F1 : poly(u);
+      const int dir = (Fu > Fu0) ? 1 : ((Fu < Fu0) ? -1 : 0);
+      S.dir[j] = dir;
+      if ((Fu0 < 0.0 && Fu > 0.0) || (Fu0 > 0.0 && Fu < 0.0)) {
+        // zero crossing inside the monotonic sub-interval (u0, u): bisection
+        double lo = u0, hi = u, flo = Fu0;
+        for (int it = 0; it < 200; ++it) {
+          const double mid = 0.5 * (lo + hi);
+          if (mid <= lo || mid >= hi) break;
+          const double fm = poly(mid);
+          if ((fm < 0.0) == (flo < 0.0)) {
+            lo = mid;
+            flo = fm;
+          } else {
+            hi = mid;
+          }
+        }
+        S.zc[j] = 0.5 * (lo + hi);
+        S.zc_mask |= 1 << j;
+      }
+      if (dir != 0) S.last_dir = dir;
+      u0 = u;
+      Fu0 = Fu;
+    }
+  }
+  S.zero_end = (F1 == 0.0 && i + 1 < nseg);
+}
+
+// Piece-closing events of a scanned segment, in order, given the last
+// non-zero direction before it: a change of direction at a sub-interval
+// start (which may be a knot), a zero crossing inside a sub-interval, and
+// F_V = 0 exactly at an interior knot.  With emit == false only the events
+// are counted; with emit == true they are written to ev[base + ...] (bounded
+// by cap).
+__device__ __forceinline__ int segment_events(const SegScan& S, int i, int cur_dir, bool emit, Event* ev, int base,
+                                              int cap) {
   int cnt = 0;
-  last_dir = 0;
   auto push = [&](double tau, double F) {
     if (emit && base + cnt < cap) ev[base + cnt] = Event{tau, F, i};
     ++cnt;
   };
-  double u0 = 0.0, Fu0 = F0;
-  for (int j = 0; j <= ntp; ++j) {
-    const bool last = (j == ntp);
-    const double u = last ? h : tp[j];
-    const double Fu = last ? F1 : poly(u);
-    const int dir = (Fu > Fu0) ? 1 : ((Fu < Fu0) ? -1 : 0);
-    if (dir != 0 && cur_dir != 0 && dir != cur_dir) push(u0, Fu0);
-    if ((Fu0 < 0.0 && Fu > 0.0) || (Fu0 > 0.0 && Fu < 0.0)) {
-      // zero crossing inside the monotonic sub-interval (u0, u): bisection
-      double lo = u0, hi = u, flo = Fu0;
-      for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (mid <= lo || mid >= hi) break;
-        const double fm = poly(mid);
-        if ((fm < 0.0) == (flo < 0.0)) {
-          lo = mid;
-          flo = fm;
-        } else {
-          hi = mid;
-        }
-      }
-      push(0.5 * (lo + hi), 0.0);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    if (j < S.nsub) {
+      const int dir = S.dir[j];
+      if (dir != 0 && cur_dir != 0 && dir != cur_dir) push(S.u0[j], S.F0[j]);
+      if ((S.zc_mask >> j) & 1) push(S.zc[j], 0.0);
+      if (dir != 0) cur_dir = dir;
     }
-    if (dir != 0) {
-      cur_dir = dir;
-      last_dir = dir;
-    }
-    if (last && Fu == 0.0 && i + 1 < nseg) push(u, 0.0);  // F_V = 0 exactly at an interior knot
-    u0 = u;
-    Fu0 = Fu;
   }
+  if (S.zero_end) push(S.h, 0.0);  // the end of the last sub-interval is the knot t_{i+1}
   return cnt;
+}
+
+// Orders a wavefront's LDS writes before its later LDS reads when lanes
+// exchange data through LDS (each wave owns its event buffer).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 // Mode constants and monotonic pieces of one voice, computed by one full
@@ -187,21 +212,20 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
   if (!flat_voice) {
     for (int c0 = 0; c0 < nseg; c0 += 64) {
       const int i = c0 + lane;
-      int own_last = 0, cnt = 0;
-      // pass 1: own last direction (independent of the incoming direction)
-      if (i < nseg) {
-        int ld;
-        segment_events(a, i, m, n, 0, false, ev, 0, 0, ld);
-        own_last = ld;
-      }
+      SegScan S;
+      S.nsub = 0;
+      S.zc_mask = 0;
+      S.zero_end = false;
+      S.last_dir = 0;
+      if (i < nseg) scan_segment(a, i, m, n, S);
+      const int own_last = S.last_dir;
       const unsigned long long nz = __ballot(own_last != 0);
       const unsigned long long below = nz & ((1ull << lane) - 1ull);
       const int src = below ? 63 - __clzll((long long)below) : 0;
       const int from_below = __shfl(own_last, src, 64);
       const int incoming = below ? from_below : carry_dir;
-      // pass 2: events with the true incoming direction (count, then place)
-      int ld = 0;
-      if (i < nseg) cnt = segment_events(a, i, m, n, incoming, false, ev, 0, 0, ld);
+      // events with the true incoming direction (count, then place)
+      const int cnt = (i < nseg) ? segment_events(S, i, incoming, false, ev, 0, 0) : 0;
       int pre = cnt;  // inclusive prefix sum over lanes
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
@@ -209,22 +233,22 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
         if (lane >= off) pre += v;
       }
       const int total = __shfl(pre, 63, 64);
-      if (i < nseg && cnt > 0) segment_events(a, i, m, n, incoming, true, ev, n_ev + pre - cnt, kMaxEvents, ld);
+      if (i < nseg && cnt > 0) segment_events(S, i, incoming, true, ev, n_ev + pre - cnt, kMaxEvents);
       n_ev += total;
       if (nz) carry_dir = __shfl(own_last, 63 - __clzll((long long)nz), 64);
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   // final event: the end of the trajectory
   const double Fend = knot_freq(m, a.Fphi[nseg], n, a.Fr[nseg]);
   const double hend = a.t[nseg] - a.t[nseg - 1];
   const bool ev_overflow = (n_ev + 1 > kMaxEvents);
   const int n_all = ev_overflow ? kMaxEvents : n_ev + 1;
   if (lane == 0) ev[min(n_ev, kMaxEvents - 1)] = Event{hend, Fend, nseg - 1};
-  __syncthreads();
+  wave_lds_sync();
 
   // ---- pieces between consecutive events, one per lane
-  const int kpos = upper_bound(a.f, a.Nf, 0.0);  // first bin with f > 0 (wave-uniform)
+  const int kpos = first_gt(a.f, a.Nf, 0.0);  // first bin with f > 0 (wave-uniform)
   const int n_cand = flat_voice ? 0 : n_all;
   bool valid = false;
   Piece P{};
@@ -250,10 +274,10 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
       P.rate = (float)((double)(P.seg_b - P.seg_a + 1) / (P.g_b - P.g_a));
       P.pad1 = 0;
       const double glo = fmin(P.g_a, P.g_b), ghi = fmax(P.g_a, P.g_b);
-      int klo = lower_bound(a.f, a.Nf, glo);
+      int klo = first_ge(a.f, a.Nf, glo);
       if (klo < kpos) klo = kpos;
       P.k_lo = klo;
-      P.k_hi = upper_bound(a.f, a.Nf, ghi) - 1;
+      P.k_hi = first_gt(a.f, a.Nf, ghi) - 1;
     }
   }
   const unsigned long long vmask = __ballot(valid);
@@ -277,17 +301,17 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
     kr_hi = max(kr_hi, __shfl_xor(kr_hi, off, 64));
   }
 
+  // ---- fused polarization factors (harmonics by the whole wave)
+  const double4 yy = swsh_m2_pair_wave(li, mi, a.theta, a.phi);
   if (lane == 0) {
-    // ---- fused polarization factors
     ModeConst mc;
     mc.m = m;
     mc.n = n;
-    const double2 y = swsh_m2(li, mi, a.theta, a.phi);
+    const double2 y = make_double2(yy.x, yy.y);
     double2 yp = make_double2(0.0, 0.0);  // (-1)^l conj Y_{l,-m}
     if (mi > 0 && !(a.flags & FDEMRI_NO_PARTNERS)) {
-      const double2 ym = swsh_m2(li, -mi, a.theta, a.phi);
       const double sg = (li & 1) ? -1.0 : 1.0;
-      yp = make_double2(sg * ym.x, -sg * ym.y);
+      yp = make_double2(sg * yy.z, -sg * yy.w);
     }
     const double hs = 0.5 * a.scale;
     mc.cp_re = hs * (y.x + yp.x);
@@ -302,18 +326,60 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
     a.modes[mu] = mc;
     a.mode_kr[mu] = make_int2(kr_lo, kr_hi);
     a.evals[mu] = evals;
-    if (kr_lo <= kr_hi) {
-      atomicMin(&a.env[0], kr_lo);
-      atomicMax(&a.env[1], kr_hi);
-    }
     if (n_valid > kMaxPieces || ev_overflow) atomicOr(a.flag_word, (uint32_t)FDEMRI_FLAG_PIECE_OVERFLOW);
   }
 }
 
-// One wavefront per mode.
-__global__ __launch_bounds__(64) void pieces_kernel(PieceArgs a) {
-  __shared__ Event ev[kMaxEvents];
-  piece_mode_wave(a, blockIdx.x, ev);
+// Bin envelope [env[0], env[1]] of one waveform's modes (min and max over
+// the non-empty per-mode ranges; {INT_MAX, -1} when all are empty), by one
+// workgroup in a fixed reduction order.
+__device__ __forceinline__ void envelope_block(const int2* __restrict__ mode_kr, int Nm, int32_t* __restrict__ env) {
+  __shared__ int s_lo[4], s_hi[4];
+  int lo = INT_MAX, hi = -1;
+  for (int mu = threadIdx.x; mu < Nm; mu += 256) {
+    const int2 r = mode_kr[mu];
+    if (r.x <= r.y) {
+      lo = min(lo, r.x);
+      hi = max(hi, r.y);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    lo = min(lo, __shfl_xor(lo, off, 64));
+    hi = max(hi, __shfl_xor(hi, off, 64));
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_lo[wave] = lo;
+    s_hi[wave] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    env[0] = min(min(s_lo[0], s_lo[1]), min(s_lo[2], s_lo[3]));
+    env[1] = max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3]));
+  }
+}
+
+__global__ __launch_bounds__(256) void envelope_kernel(const int2* __restrict__ mode_kr, int Nm,
+                                                       int32_t* __restrict__ env) {
+  envelope_block(mode_kr, Nm, env);
+}
+
+// Batched: one workgroup per waveform.
+__global__ __launch_bounds__(256) void envelope_batch_kernel(const WaveItem* __restrict__ items) {
+  const WaveItem& w = items[blockIdx.x];
+  envelope_block(w.mode_kr, w.Nm, w.env);
+}
+
+// One wavefront per mode, kPieceWaves modes per workgroup.
+constexpr int kPieceWaves = 4;
+
+__global__ __launch_bounds__(64 * kPieceWaves) void pieces_kernel(PieceArgs a) {
+  __shared__ Event ev[kPieceWaves][kMaxEvents];
+  const int wave = threadIdx.x >> 6;
+  const int mu = blockIdx.x * kPieceWaves + wave;
+  if (mu >= a.Nm) return;
+  piece_mode_wave(a, mu, ev[wave]);
 }
 
 __device__ PieceArgs piece_args_of(const WaveItem& w, uint32_t* flag_word) {
@@ -337,17 +403,18 @@ __device__ PieceArgs piece_args_of(const WaveItem& w, uint32_t* flag_word) {
   a.mode_kr = w.mode_kr;
   a.pieces = w.pieces;
   a.evals = w.evals;
-  a.env = w.env;
   a.flag_word = flag_word;
   return a;
 }
 
 // Batched: one wavefront per (waveform, mode) through the prefix of Nm_b.
-__global__ __launch_bounds__(64) void pieces_batch_kernel(const WaveItem* __restrict__ items, int B,
-                                                          const int32_t* __restrict__ mode_prefix, int total,
-                                                          uint32_t* flag_word) {
-  __shared__ Event ev[kMaxEvents];
-  const int g = blockIdx.x;
+__global__ __launch_bounds__(64 * kPieceWaves) void pieces_batch_kernel(const WaveItem* __restrict__ items, int B,
+                                                                        const int32_t* __restrict__ mode_prefix,
+                                                                        int total, uint32_t* flag_word) {
+  __shared__ Event ev[kPieceWaves][kMaxEvents];
+  const int wave = threadIdx.x >> 6;
+  const int g = blockIdx.x * kPieceWaves + wave;
+  if (g >= total) return;
   int lo = 0, hi = B - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -357,12 +424,14 @@ __global__ __launch_bounds__(64) void pieces_batch_kernel(const WaveItem* __rest
       hi = mid - 1;
   }
   const PieceArgs a = piece_args_of(items[lo], flag_word);
-  piece_mode_wave(a, g - mode_prefix[lo], ev);
+  piece_mode_wave(a, g - mode_prefix[lo], ev[wave]);
 }
 
 hipError_t launch_pieces_batch(const WaveItem* items, int B, const int32_t* mode_prefix, int total_modes,
                                uint32_t* flag_word, hipStream_t stream) {
-  pieces_batch_kernel<<<total_modes, 64, 0, stream>>>(items, B, mode_prefix, total_modes, flag_word);
+  const int blocks = (total_modes + kPieceWaves - 1) / kPieceWaves;
+  pieces_batch_kernel<<<blocks, 64 * kPieceWaves, 0, stream>>>(items, B, mode_prefix, total_modes, flag_word);
+  envelope_batch_kernel<<<B, 256, 0, stream>>>(items);
   return hipGetLastError();
 }
 
@@ -391,9 +460,9 @@ hipError_t launch_pieces_flat(int K, int Nm, int Nf, const double* t, const doub
   a.mode_kr = mode_kr;
   a.pieces = pieces;
   a.evals = evals;
-  a.env = env;
   a.flag_word = flag_word;
-  pieces_kernel<<<Nm, 64, 0, stream>>>(a);
+  pieces_kernel<<<(Nm + kPieceWaves - 1) / kPieceWaves, 64 * kPieceWaves, 0, stream>>>(a);
+  envelope_kernel<<<1, 256, 0, stream>>>(mode_kr, Nm, env);
   return hipGetLastError();
 }
 

@@ -34,8 +34,7 @@ template <int NT>
 __device__ void spline_series(SplineLds<NT>& S, int series, int K, const double* __restrict__ t,
                               const double* __restrict__ y0, const double* __restrict__ y1,
                               const double* __restrict__ y2, const double* __restrict__ y3,
-                              const double* __restrict__ A, double* __restrict__ tcoef, double* __restrict__ acoef,
-                              int32_t* __restrict__ env) {
+                              const double* __restrict__ A, double* __restrict__ tcoef, double* __restrict__ acoef) {
   double* sa = S.sa;
   double* sb = S.sb;
   double* sc = S.sc;
@@ -48,11 +47,6 @@ __device__ void spline_series(SplineLds<NT>& S, int series, int K, const double*
   const bool cplx = series >= 4;
   const int mode = series - 4;
   const int n = K - 1;  // segments
-
-  if (series == 0 && i == 0 && env != nullptr) {
-    env[0] = 0x7fffffff;
-    env[1] = -1;
-  }
 
   // load knots
   if (i < K) {
@@ -195,9 +189,9 @@ __global__ __launch_bounds__(NT) void spline_pcr_kernel(int K, const double* __r
                                                         const double* __restrict__ y0, const double* __restrict__ y1,
                                                         const double* __restrict__ y2, const double* __restrict__ y3,
                                                         const double* __restrict__ A, int Nm, double* __restrict__ tcoef,
-                                                        double* __restrict__ acoef, int32_t* __restrict__ env) {
+                                                        double* __restrict__ acoef) {
   __shared__ SplineLds<NT> S;
-  spline_series<NT>(S, blockIdx.x, K, t, y0, y1, y2, y3, A, tcoef, acoef, env);
+  spline_series<NT>(S, blockIdx.x, K, t, y0, y1, y2, y3, A, tcoef, acoef);
 }
 
 // Batched: block -> (waveform, series) through the prefix of 4 + Nm_b.
@@ -215,24 +209,23 @@ __global__ __launch_bounds__(NT) void spline_batch_kernel(const WaveItem* __rest
       hi = mid - 1;
   }
   const WaveItem& w = items[lo];
-  spline_series<NT>(S, g - series_prefix[lo], w.K, w.t, w.Fphi, w.Fr, w.Phiphi, w.Phir, w.A, w.tcoef, w.acoef,
-                    w.env);
+  spline_series<NT>(S, g - series_prefix[lo], w.K, w.t, w.Fphi, w.Fr, w.Phiphi, w.Phir, w.A, w.tcoef, w.acoef);
 }
 
 // Host launcher: coefficients of the four trajectory series and of Nm
 // complex amplitude series, all on knots t[K].
 hipError_t launch_spline(int K, const double* t, const double* Fphi, const double* Fr, const double* Phiphi,
-                         const double* Phir, const double* A, int Nm, double* tcoef, double* acoef, int32_t* env,
+                         const double* Phir, const double* A, int Nm, double* tcoef, double* acoef,
                          hipStream_t stream) {
   dim3 grid(4 + Nm);
   if (K <= 64)
-    spline_pcr_kernel<64><<<grid, 64, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, Nm, tcoef, acoef, env);
+    spline_pcr_kernel<64><<<grid, 64, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, Nm, tcoef, acoef);
   else if (K <= 128)
-    spline_pcr_kernel<128><<<grid, 128, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, Nm, tcoef, acoef, env);
+    spline_pcr_kernel<128><<<grid, 128, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, Nm, tcoef, acoef);
   else if (K <= 256)
-    spline_pcr_kernel<256><<<grid, 256, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, Nm, tcoef, acoef, env);
+    spline_pcr_kernel<256><<<grid, 256, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, Nm, tcoef, acoef);
   else
-    spline_pcr_kernel<512><<<grid, 512, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, Nm, tcoef, acoef, env);
+    spline_pcr_kernel<512><<<grid, 512, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, Nm, tcoef, acoef);
   return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@
 // and no atomics are used.
 #include "evalcore.hpp"
 #include "harmonics.hpp"
+#include "search.hpp"
 
 namespace fdemri {
 
@@ -35,30 +36,6 @@ struct VjpArgs {
   double* PZ;     // [Nm][nseg][4]  sum s tau^k Im Z
   double* Upart;  // [Nm][nseg][4]  partial U_+ (re, im), U_x (re, im)
 };
-
-__device__ __forceinline__ int first_gt(const double* f, int Nf, double x) {
-  int lo = 0, hi = Nf;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (f[mid] <= x)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ int first_ge(const double* f, int Nf, double x) {
-  int lo = 0, hi = Nf;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (f[mid] < x)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
 
 template <bool MIXED>
 __global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
