@@ -175,8 +175,10 @@ fdemri_status fdemri_vjp(fdemri_ctx *ctx, const fdemri_waveform_desc *desc, fdem
                          hipStream_t stream);
 
 /*
- * Autotuner of the gather's bin tile (bins per lane: 1, 2 or 4, i.e. tiles of
- * 64, 128 or 256 contiguous bins per wavefront).  Runs the given batch (B = 1:
+ * Autotuner of the gather's block shape (1, 2 or 4 consecutive 64-bin tiles
+ * per wavefront, i.e. 256, 512 or 1024 contiguous bins per 4-wave workgroup
+ * sharing one active-mode list; the result does not depend on the choice,
+ * only the time does).  Runs the given batch (B = 1:
  * a single waveform) once per candidate, timed with HIP events on `stream`,
  * keeps the fastest for this precision and workload class (log2 of the
  * total bin count; single or batch) on the context, and, if the environment

@@ -168,7 +168,7 @@ int choose_bpl(const fdemri_ctx* c, int prec, bool batch, int64_t bins) {
   const int cls = size_class(bins);
   for (const auto& t : c->tuned)
     if (t[0] == prec && t[1] == (int)batch && t[2] == cls) return t[3];
-  return prec == FDEMRI_MIXED ? 1 : 2;  // measured best on the 3842-mode workload
+  return 1;  // measured best for both precisions on the 3842-mode workload
 }
 
 void load_tune_cache(fdemri_ctx* c) {

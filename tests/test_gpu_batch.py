@@ -18,7 +18,7 @@ def ctx():
 
 
 def batch_members():
-    ws = [W.config1(), W.config3(), W.linear_chirp_workload(f0=1e-4, fdot=1e-9, T=1e5, Nf=3001)]
+    ws = [W.inspiral_20_modes(), W.inspiral_20_modes_log_grid(), W.linear_chirp_workload(f0=1e-4, fdot=1e-9, T=1e5, Nf=3001)]
     for prm in W.batch_params(4, 123):
         prm["T"] = min(prm["T"], 0.6 * W.YRSID_SI)
         w = W.batch_workload(prm, K=60 + 10 * len(ws))

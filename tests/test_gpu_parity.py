@@ -38,21 +38,21 @@ def _check64(hg, ho, what):
         assert err <= TOL64, (what, name, err)
 
 
-def test_config1_full_grid(ctx):
-    w = W.config1()
+def test_20_modes_full_grid(ctx):
+    w = W.inspiral_20_modes()
     hg = gpu_waveform(ctx, w)
     ho = oracle.waveform(w)
-    _check64(hg, ho, "config1")
+    _check64(hg, ho, "inspiral_20_modes")
     assert ctx.last_eval_count() == count_evals(w) == 8724
 
 
-def test_config3_log_grid(ctx):
-    w = W.config3()
-    _check64(gpu_waveform(ctx, w), oracle.waveform(w), "config3")
+def test_20_modes_log_grid(ctx):
+    w = W.inspiral_20_modes_log_grid()
+    _check64(gpu_waveform(ctx, w), oracle.waveform(w), "inspiral_20_modes_log_grid")
 
 
-def test_config1_ragged_and_offset_grids(ctx):
-    w = W.config1()
+def test_20_modes_ragged_and_offset_grids(ctx):
+    w = W.inspiral_20_modes()
     for lo, hi in [(0, 1), (0, 255), (3, 1000), (12345, 12345 + 777), (100001, 100001 + 65 * 64 + 3)]:
         f = w.f[lo:hi]
         hg = gpu_waveform(ctx, w, f=f)
@@ -63,17 +63,17 @@ def test_config1_ragged_and_offset_grids(ctx):
                 assert rel_l2(g, o) <= TOL64
 
 
-def test_config2_sampled_bins(ctx):
-    """Full-size config 2 on the GPU; the oracle evaluates a sample of bins
+def test_3842_modes_sampled_bins(ctx):
+    """The full-size 3842-mode waveform on the GPU; the oracle evaluates a sample of bins
     (each bin is independent) drawn across the active band and the tail."""
-    w = W.config2()
+    w = W.inspiral_3842_modes()
     hp, hc = gpu_waveform(ctx, w)
     rng = np.random.default_rng(11)
     act = np.nonzero(w.f < 9e-3)[0]
     idx = np.unique(np.concatenate([rng.choice(act, 1500, replace=False),
                                     rng.choice(w.Nf, 200, replace=False), [0, 1, w.Nf - 1]]))
     op, oc = oracle.waveform(w, f=w.f[idx])
-    _check64((hp[idx], hc[idx]), (op, oc), "config2-sampled")
+    _check64((hp[idx], hc[idx]), (op, oc), "inspiral_3842_modes-sampled")
     assert np.all(hp[w.f > 1.2e-2] == 0)
 
 
@@ -89,7 +89,7 @@ def test_linear_chirp_and_turnover(ctx):
 def test_explicit_voices_no_partners(ctx):
     """FDEMRI_NO_PARTNERS with rows of both signs of m equals the oracle's
     explicit voice list."""
-    w = W.config1()
+    w = W.inspiral_20_modes()
     w.m = np.where(np.arange(w.Nm) % 2 == 0, w.m, -w.m).astype(np.int32)
     f = w.f[::3]
     hg = gpu_waveform(ctx, w, partners=False, f=f)
@@ -101,7 +101,7 @@ def test_explicit_voices_no_partners(ctx):
 
 
 def test_mixed_precision_against_fp64(ctx):
-    for w in [W.config1(), W.config2()]:
+    for w in [W.inspiral_20_modes(), W.inspiral_3842_modes()]:
         h64 = gpu_waveform(ctx, w, "fp64")
         hmx = gpu_waveform(ctx, w, "mixed")
         for g, o in zip(hmx, h64):
@@ -111,14 +111,14 @@ def test_mixed_precision_against_fp64(ctx):
 
 
 def test_deterministic_bitwise(ctx):
-    w = W.config1()
+    w = W.inspiral_20_modes()
     a = gpu_waveform(ctx, w)
     b = gpu_waveform(ctx, w)
     assert all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
 def test_outputs_fully_overwritten(ctx):
-    w = W.config1()
+    w = W.inspiral_20_modes()
     dw = fd.DeviceWaveform.from_workload(w, device=ctx.device)
     hp = torch.full((dw.Nf,), complex(float("nan"), float("nan")), dtype=torch.complex128, device=ctx.device)
     hc = hp.clone()
@@ -129,7 +129,7 @@ def test_outputs_fully_overwritten(ctx):
 
 
 def test_degenerate_inputs(ctx):
-    w = W.config1()
+    w = W.inspiral_20_modes()
     # all frequencies outside every voice
     f = np.linspace(0.2, 0.3, 1000)
     hp, hc = gpu_waveform(ctx, w, f=f)
@@ -138,7 +138,7 @@ def test_degenerate_inputs(ctx):
     hp, hc = gpu_waveform(ctx, w, f=np.zeros(1))
     assert hp[0] == 0 and hc[0] == 0
     # minimal trajectory (K = 4) and an (l,0,0) mode with F = 0
-    w4 = W.config1(K=4)
+    w4 = W.inspiral_20_modes(K=4)
     w4.l = np.array([2, 3], np.int32)
     w4.m = np.array([2, 0], np.int32)
     w4.n = np.array([1, 0], np.int32)
@@ -148,7 +148,7 @@ def test_degenerate_inputs(ctx):
 
 
 def test_invalid_arguments_leave_outputs(ctx):
-    w = W.config1()
+    w = W.inspiral_20_modes()
     dw = fd.DeviceWaveform.from_workload(w, device=ctx.device)
     hp = torch.full((dw.Nf,), 7 + 7j, dtype=torch.complex128, device=ctx.device)
     hc = hp.clone()

@@ -20,7 +20,7 @@ def ctx():
 
 
 def small_workload(stride=9):
-    w = W.config1()
+    w = W.inspiral_20_modes()
     sel = np.array([2, 6, 9, 13])
     w.l, w.m, w.n, w.A = w.l[sel], w.m[sel], w.n[sel], w.A[sel]
     w.f = w.f[::stride]
@@ -133,7 +133,7 @@ def test_autograd_gradcheck(ctx):
     """torch.autograd.gradcheck of the waveform through FDEmriFn (FP64) on a
     tiny input: 12 knots, 2 modes, ~60 bins."""
     from paper_2307_12585_amd.autograd import WaveformStatic, fdemri_waveform
-    w = W.config1(K=12)
+    w = W.inspiral_20_modes(K=12)
     w.l, w.m, w.n, w.A = w.l[[6, 9]], w.m[[6, 9]], w.n[[6, 9]], w.A[[6, 9]]
     sel = np.nonzero((w.f > 0) & (np.arange(w.Nf) % 97 == 0))[0]
     dev = ctx.device

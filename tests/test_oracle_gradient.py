@@ -13,7 +13,7 @@ from oracle.waveform import splines, voices_from_modes, waveform_voices
 
 
 def small_workload():
-    w = W.config1()
+    w = W.inspiral_20_modes()
     sel = np.array([2, 6, 9, 13])          # n = -3, 1, 4, 8
     w.l, w.m, w.n, w.A = w.l[sel], w.m[sel], w.n[sel], w.A[sel]
     w.f = w.f[::9]

@@ -86,7 +86,7 @@ def test_partner_identity():
     """h_{l,-m,-n}(-f) = conj( h_{l,m,n}(f) with H -> conj H' ), where
     H' = scale (-1)^l conj(A) Y_{l,-m}: the negative-frequency branch of the
     explicit partner equals the conjugate of the positive branch."""
-    w = W.config1()
+    w = W.inspiral_20_modes()
     sp = splines(w.traj, w.A)
     f = w.f[::7]
     for mu in [0, 4, 11]:
@@ -105,7 +105,7 @@ def test_partner_identity():
 
 def test_polarization_ratio_single_22_mode():
     """For one (2,2,n) mode with F > 0 throughout, h_x/h_+ = 2i cos(theta)/(1+cos^2 theta)."""
-    w = W.config1()
+    w = W.inspiral_20_modes()
     sel = np.nonzero(w.n == 3)[0]
     w.l, w.m, w.n, w.A = w.l[sel], w.m[sel], w.n[sel], w.A[sel]
     hp, hc = oracle.waveform(w)
@@ -119,7 +119,7 @@ def test_polarization_ratio_single_22_mode():
 # --- P6: invariants -----------------------------------------------------------
 
 def _small_cfg1():
-    w = W.config1()
+    w = W.inspiral_20_modes()
     w.f = w.f[::3]
     return w
 
@@ -168,7 +168,7 @@ def test_phase_offset_invariant():
 
 
 def test_dc_bin_zero_and_evals_count():
-    w = W.config1()
+    w = W.inspiral_20_modes()
     hp, hc = oracle.waveform(w, f=w.f[:2000])
     assert hp[0] == 0 and hc[0] == 0
     assert oracle.waveform.__module__ == "oracle.waveform"

@@ -30,22 +30,22 @@ def test_paper_full_grid_size():
     assert f.size == int(g["N_f_full"])
 
 
-def test_config1_shapes():
-    w = W.config1()
+def test_20_mode_workload_shapes():
+    w = W.inspiral_20_modes()
     assert (w.K, w.Nm, w.Nf) == (100, 20, 394478)
     assert abs(w.traj.p[0] - 12.0) < 1e-12 and 11.8 < w.traj.p[-1] < 11.9
     assert np.all(np.diff(w.traj.t) > 0) and np.all(np.diff(w.f) > 0)
 
 
-def test_config2_shapes():
-    w = W.config2()
+def test_3842_mode_workload_shapes():
+    w = W.inspiral_3842_modes()
     assert w.K == 200 and w.Nf == 3155816
     assert 3800 <= w.Nm <= W.count_total_modes() == 3843
     assert np.all(w.m >= 0) and np.all(w.m <= w.l)
 
 
-def test_config3_grid():
-    w = W.config3()
+def test_log_grid_workload():
+    w = W.inspiral_20_modes_log_grid()
     assert w.Nf == 10000 and abs(w.f[0] - 1e-4) < 1e-18 and abs(w.f[-1] - 0.1) < 1e-15
 
 

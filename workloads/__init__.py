@@ -35,7 +35,7 @@ YRSID_SI = 31558149.763545603        # sidereal year [s]
 __all__ = [
     "MTSUN_SI", "MRSUN_SI", "GPC_SI", "YRSID_SI",
     "Trajectory", "Workload", "peters_trajectory", "mode_table",
-    "rfft_grid", "log_grid", "config1", "config2", "config3",
+    "rfft_grid", "log_grid", "inspiral_20_modes", "inspiral_3842_modes", "inspiral_20_modes_log_grid",
     "batch_params", "batch_workload", "psd_closed_form", "noise_draw",
     "linear_chirp_workload", "count_total_modes",
 ]
@@ -158,7 +158,7 @@ def _select(power: np.ndarray, eps: float) -> np.ndarray:
     return power > eps * power.sum()
 
 
-def config1(seed: int = 0, K: int = 100) -> Workload:
+def inspiral_20_modes(seed: int = 0, K: int = 100) -> Workload:
     """Small single waveform: M=1e6, mu=10, p0=12, e0=0.3, T=0.25 yr at
     dt=10 s on the full rfft grid; 20 modes l=2, m=2, n=-5..14 with
     A = a_n (p/p0)^-1 e^{i phi_n}, a_n = e0^|n| LN(0, 0.3), phi_n ~ U[0, 2pi)."""
@@ -175,7 +175,7 @@ def config1(seed: int = 0, K: int = 100) -> Workload:
     A = (a * np.exp(1j * ph))[:, None] * (traj.p / p0)[None, :] ** -1
     return Workload(traj=traj, l=l, m=m, n=n, A=A, theta=math.pi / 3, phi=math.pi / 4,
                     scale=_scale(mu), f=rfft_grid(T, dt),
-                    meta=dict(name="config1", M=M, mu=mu, p0=p0, e0=e0, T=T, dt=dt, seed=seed))
+                    meta=dict(name="inspiral_20_modes", M=M, mu=mu, p0=p0, e0=e0, T=T, dt=dt, seed=seed))
 
 
 def _law_amplitudes(rng, e0: float, l, m, n, p, p0):
@@ -187,7 +187,7 @@ def _law_amplitudes(rng, e0: float, l, m, n, p, p0):
     return a * np.exp(1j * ph), a * a
 
 
-def config2(seed: int = 0, K: int = 200, eps: float = 1e-5) -> Workload:
+def inspiral_3842_modes(seed: int = 0, K: int = 200, eps: float = 1e-5) -> Workload:
     """Realistic single waveform: M=2e6, mu=20, p0=13, e0=0.45, T=2 yr at
     dt=10 s, K=200 knots, l=2..10, m=0..l, n=-30..30 selected at 1e-5 of the
     total power."""
@@ -202,14 +202,14 @@ def config2(seed: int = 0, K: int = 200, eps: float = 1e-5) -> Workload:
     A = a[keep][:, None] * (traj.p / p0)[None, :] ** -1
     return Workload(traj=traj, l=l[keep], m=m[keep], n=n[keep], A=A,
                     theta=math.pi / 3, phi=math.pi / 4, scale=_scale(mu), f=rfft_grid(T, dt),
-                    meta=dict(name="config2", M=M, mu=mu, p0=p0, e0=e0, T=T, dt=dt, seed=seed))
+                    meta=dict(name="inspiral_3842_modes", M=M, mu=mu, p0=p0, e0=e0, T=T, dt=dt, seed=seed))
 
 
-def config3(seed: int = 0) -> Workload:
+def inspiral_20_modes_log_grid(seed: int = 0) -> Workload:
     """Config 1 evaluated on 1e4 log-spaced frequencies in [1e-4, 1e-1] Hz."""
-    w = config1(seed)
+    w = inspiral_20_modes(seed)
     w.f = log_grid(1e-4, 1e-1, 10_000)
-    w.meta["name"] = "config3"
+    w.meta["name"] = "inspiral_20_modes_log_grid"
     return w
 
 
