@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-bins", type=int, default=6000)
+    ap.add_argument("--cpu-sample-bins", type=int, default=20000)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batch", type=int, default=8,
                     help="waveforms in the secondary batched mixed-precision measurement")

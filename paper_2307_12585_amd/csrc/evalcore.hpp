@@ -42,23 +42,39 @@ __device__ __forceinline__ Bracket make_bracket(const Piece& P, int i, const Seg
 
 // Root of G0 + q1 tau + q2 tau^2 + q3 tau^3 = f on [tl, th] (|F_V|
 // monotonic there with direction d).  Secant start from the bracket ends,
-// then Halley steps on p(tau) = |F_V|(t_i + tau) - f, each kept inside the
-// shrinking bracket (bisection when a step leaves it).  After a Halley step
+// then Halley steps on p(tau) = |F_V|(t_i + tau) - f.  After a Halley step
 // of length x the error is about (p2^2 / (4 p1^2) - p3 / (6 p1)) x^3, with
-// p1, p2, p3 the first three derivatives of p; once the iterate lies where
-// that holds (|p p2| <= p1^2 / 2) and the predicted error is below the
-// tolerance, the new iterate is returned.  On smooth trajectories one step
-// from the secant start reaches the rounding floor of p.
+// p1, p2, p3 the first three derivatives of p; a step is accepted as the
+// root once the iterate lies where that holds (|p p2| <= p1^2 / 2) and the
+// predicted error is below the tolerance.  On smooth trajectories the first
+// step from the secant start is accepted; otherwise the iteration restarts
+// from the secant start with every step kept inside the shrinking bracket
+// (bisection when a step leaves it).
 __device__ __forceinline__ double solve_root(double f, double dd, const SegData& S, const Bracket& B) {
-  double tau = B.tl;
+  double tau0 = B.tl;
   const double dg = B.gh - B.gl;
-  if (dg != 0.0) tau = B.tl + (f - B.gl) * (B.th - B.tl) * rcp_nr1(dg);
-  tau = fmin(fmax(tau, B.tl), B.th);
-  double blo = B.tl, bhi = B.th;
+  if (dg != 0.0) tau0 = B.tl + (f - B.gl) * (B.th - B.tl) * rcp_nr1(dg);
+  tau0 = fmin(fmax(tau0, B.tl), B.th);
   const double tol = 4e-16 * fmax(S.h, 1.0);
   const double c0 = S.G0 - f;
   const double q1 = S.q1, q2 = S.q2, q3 = S.q3;
   const double q2x2 = 2.0 * q2, q3x3 = 3.0 * q3, q3x6 = 6.0 * q3, aq3 = fabs(q3);
+  // first Halley step, accepted when the error estimate allows
+  {
+    const double r = c0 + tau0 * (q1 + tau0 * (q2 + tau0 * q3));
+    const double p1 = q1 + tau0 * (q2x2 + q3x3 * tau0);
+    const double p2 = q2x2 + q3x6 * tau0;
+    const double p1s = p1 * p1, rp2 = r * p2;
+    const double tn = tau0 - 2.0 * r * p1 * rcp_nr1(2.0 * p1s - rp2);
+    const double step = fabs(tn - tau0);
+    if (r == 0.0) return tau0;
+    if (tn >= B.tl && tn <= B.th &&
+        (step <= tol ||
+         (fabs(rp2) <= 0.5 * p1s && step * step * step * (0.25 * p2 * p2 + aq3 * fabs(p1)) <= tol * p1s)))
+      return tn;
+  }
+  double tau = tau0;
+  double blo = B.tl, bhi = B.th;
   for (int it = 0; it < 100; ++it) {
     const double r = c0 + tau * (q1 + tau * (q2 + tau * q3));
     if (r == 0.0) break;

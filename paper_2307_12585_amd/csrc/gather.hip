@@ -191,9 +191,9 @@ constexpr int block_bins() {
 
 // Zeros for the bins of a block outside every voice's range.
 template <bool MIXED, int BPL, int WAVES>
-__device__ __forceinline__ void zero_block(void* hp, void* hc, int Nf, long kb) {
+__device__ __forceinline__ void zero_block(void* hp, void* hc, int Nf, int kb) {
   for (int t = threadIdx.x; t < block_bins<BPL, WAVES>(); t += 64 * WAVES) {
-    const long k = kb + t;
+    const int k = kb + t;
     if (k < Nf) {
       if constexpr (MIXED) {
         ((float2*)hp)[k] = make_float2(0.f, 0.f);
@@ -232,9 +232,9 @@ __device__ __forceinline__ void write_list(int* list, uint32_t hits, int wbase, 
 // records come in by scalar loads.
 template <bool MIXED>
 __device__ __forceinline__ void walk_list(const Prepared& p, const float* __restrict__ acoef32, const int* list, int n,
-                                          long ks, long ke, double f, const dd w, const Lds& L, Acc<MIXED>& acc) {
+                                          int ks, int ke, double f, const dd w, const Lds& L, Acc<MIXED>& acc) {
   const int lane = threadIdx.x & 63;
-  const long k = ks + lane;
+  const int k = ks + lane;
   const int nseg = p.K - 1;
   const kconst int2* kr = (const kconst int2*)p.mode_kr;
   for (int e = 0; e < n; ++e) {
@@ -246,8 +246,8 @@ __device__ __forceinline__ void walk_list(const Prepared& p, const float* __rest
     for (int q = 0; q < md.npieces; ++q) {
       const Piece P = pcs[q];
       // bins of this piece in the tile (wave-uniform)
-      const long ka = max(ks, (long)P.k_lo);
-      const long kz = min(ke, (long)P.k_hi);
+      const int ka = max(ks, P.k_lo);
+      const int kz = min(ke, P.k_hi);
       if (ka > kz) continue;
       if (k >= ka && k <= kz) {
         const bool neg = P.s < 0;
@@ -278,11 +278,11 @@ __device__ __forceinline__ void walk_list(const Prepared& p, const float* __rest
 // list: LDS of kListCap + 8 ints.
 template <bool MIXED, int BPL, int WAVES>
 __device__ __forceinline__ void process_block(const Prepared& p, const float* __restrict__ acoef32, void* hp,
-                                              void* hc, long kb, const Lds& L, int* list) {
+                                              void* hc, int kb, const Lds& L, int* list) {
   constexpr int CHUNK = 64 * kModesPerLane;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int Nf = p.Nf;
-  const long kbe = min(kb + block_bins<BPL, WAVES>() - 1, (long)Nf - 1);
+  const int kbe = min(kb + block_bins<BPL, WAVES>() - 1, Nf - 1);
   int* wcount = list + kListCap;
 
   // 1. scan, in rounds of WAVES * CHUNK modes
@@ -331,9 +331,9 @@ __device__ __forceinline__ void process_block(const Prepared& p, const float* __
   // 2. evaluate, tile by tile
 #pragma unroll 1
   for (int j = 0; j < BPL; ++j) {
-    const long ks = kb + (long)(wave * BPL + j) * 64;
-    const long ke = min(ks + 63, (long)Nf - 1);
-    const long k = ks + lane;
+    const int ks = kb + (wave * BPL + j) * 64;
+    const int ke = min(ks + 63, Nf - 1);
+    const int k = ks + lane;
     const double f = (k < Nf) ? p.f[k] : 0.0;
     const dd w = two_pi_f(f);
     Acc<MIXED> acc;
@@ -379,8 +379,8 @@ template <bool MIXED, int BPL, int WAVES>
 __global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_kernel(GatherArgs a) {
   extern __shared__ double lds[];
   const Prepared& p = a.p;
-  const long kb = (long)blockIdx.x * block_bins<BPL, WAVES>();
-  const long kbe = kb + block_bins<BPL, WAVES>() - 1;
+  const int kb = (int)blockIdx.x * block_bins<BPL, WAVES>();
+  const int kbe = kb + block_bins<BPL, WAVES>() - 1;
   // blocks outside the bin envelope of all modes only write zeros
   if (kbe < p.env[0] || kb > p.env[1]) {
     zero_block<MIXED, BPL, WAVES>(a.hp, a.hc, p.Nf, kb);
@@ -427,8 +427,8 @@ __global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_
     }
     const WaveItem w = ((const kconst WaveItem*)items)[lo];
     const Prepared p = prepared_of(w);
-    const long kb = (long)(it - pre[lo]) * block_bins<BPL, WAVES>();
-    const long kbe = kb + block_bins<BPL, WAVES>() - 1;
+    const int kb = (it - pre[lo]) * block_bins<BPL, WAVES>();
+    const int kbe = kb + block_bins<BPL, WAVES>() - 1;
     if (kbe < p.env[0] || kb > p.env[1]) {
       zero_block<MIXED, BPL, WAVES>(w.hp, w.hc, p.Nf, kb);
       continue;
