@@ -132,6 +132,7 @@ def adjoint_measure(ctx, W, fd, dev, B):
     e2e = {k: 0.0 for k in keys}
     vjp_only = {k: 0.0 for k in keys}
     fwd_err = 0.0
+    kms = {}
 
     def rel(a, b):
         nb = float(torch.linalg.vector_norm(b))
@@ -156,6 +157,8 @@ def adjoint_measure(ctx, W, fd, dev, B):
         ref = ctx.vjp_dev(dw, g64p, g64c, "fp64", coef=False)
         only = ctx.vjp_dev(dw, g64p.to(torch.complex64), g64c.to(torch.complex64), "mixed", coef=False)
         torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read()
         t0 = time.perf_counter()
         mp, mc = ctx.waveform_dev(dw, "mixed")
         evals += ctx.last_eval_count()
@@ -164,6 +167,9 @@ def adjoint_measure(ctx, W, fd, dev, B):
         g = ctx.vjp_dev(dw, gp, gc, "mixed", coef=False)
         torch.cuda.synchronize()
         tot += time.perf_counter() - t0
+        for k, (ms, n) in ctx.profile_read().items():
+            kms[k] = kms.get(k, 0.0) + ms / B
+        ctx.profile(False)
         fwd_err = max(fwd_err, rel(mp, hp), rel(mc, hc))
         for k in keys:
             e2e[k] = max(e2e[k], rel(g[k], ref[k]))
@@ -171,6 +177,7 @@ def adjoint_measure(ctx, W, fd, dev, B):
     return {"waveforms": B, "evals_forward": evals, "seconds": tot, "waveforms_per_s": B / tot,
             "evals_per_s_forward_plus_adjoint": evals / tot,
             "forward_rel_l2_vs_fp64_max": fwd_err,
+            "kernel_ms_per_waveform": kms,
             "grad_rel_l2_vs_fp64_max": e2e, "adjoint_only_rel_l2_vs_fp64_max": vjp_only}
 
 

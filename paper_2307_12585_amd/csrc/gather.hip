@@ -368,10 +368,18 @@ __device__ __forceinline__ void process_block(const Prepared& p, const float* __
   }
 }
 
-// Occupancy target of the gather kernels, in waves per SIMD: the register
-// budget of the FP64 evaluation fits 3 (168 VGPRs), that of the mixed one 4.
+// Occupancy target of the gather kernels, in waves per SIMD (register
+// budget 512 / waves VGPRs).  The mixed evaluation fits 4 waves; the FP64
+// one needs about 160 VGPRs, and bounding it to 4 waves (a few spills) still
+// runs faster than 3 waves without spills in the single-waveform kernel.  The
+// persistent batch kernel holds more state and stays at 3 in FP64.
 template <bool MIXED>
 constexpr int gather_min_waves() {
+  return 4;
+}
+
+template <bool MIXED>
+constexpr int gather_batch_min_waves() {
   return MIXED ? 4 : 3;
 }
 
@@ -400,7 +408,7 @@ __global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_
 // results do not depend on the schedule.  Every workgroup leaves the loop
 // once the counter passes the last block.
 template <bool MIXED, int BPL, int WAVES>
-__global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_batch_kernel(const WaveItem* __restrict__ items, int B,
+__global__ __launch_bounds__(64 * WAVES, gather_batch_min_waves<MIXED>()) void gather_batch_kernel(const WaveItem* __restrict__ items, int B,
                                                                 const int32_t* __restrict__ item_prefix,
                                                                 int total_items, int* __restrict__ counter) {
   extern __shared__ double lds[];
