@@ -57,14 +57,21 @@ struct Acc<true> {
   }
 };
 
+// LDS copy of one waveform's trajectory tables, interleaved so that one base
+// address per index reaches every field by immediate offsets: per knot i
+// {F_phi, F_r, t, Phi_phi, Phi_r} (48 B, 16-B aligned pairs), per segment i
+// the c1..c3 spline coefficients of F_phi, F_r, Phi_phi, Phi_r (96 B).
+struct alignas(16) KnotRec {
+  double Fp, Fr, t, Pp, Pr, pad;
+};
+struct alignas(16) SegCoef {
+  double cFp[3], cFr[3], cPp[3], cPr[3];
+};
+static_assert(sizeof(KnotRec) == 48 && sizeof(SegCoef) == 96, "LDS record layout");
+
 struct Lds {
-  const double* t;
-  const double* Fp;
-  const double* Fr;
-  const double* Pp;
-  const double* Pr;
-  const double* cF;  // [K-1][6]: Fphi c1..c3, Fr c1..c3
-  const double* cP;  // [K-1][6]: Phiphi c1..c3, Phir c1..c3
+  const KnotRec* kn;  // [K]
+  const SegCoef* sc;  // [K-1]
 };
 
 // One (bin, piece) evaluation.  The spline segment holding f is the largest i
@@ -85,8 +92,8 @@ __device__ __forceinline__ void eval_bin(const double f, const dd w, const Piece
                                          const float* __restrict__ ac32, const Lds& L, Acc<MIXED>& acc) {
   const double fd = dd_ * f;
   int i = P.seg_a + (int)fmin(fmax((f - P.g_a) * rate, 0.0), span);
-  double G0 = knot_freq(ms, L.Fp[i], ns, L.Fr[i]);
-  double G1 = knot_freq(ms, L.Fp[i + 1], ns, L.Fr[i + 1]);
+  double G0 = knot_freq(ms, L.kn[i].Fp, ns, L.kn[i].Fr);
+  double G1 = knot_freq(ms, L.kn[i + 1].Fp, ns, L.kn[i + 1].Fr);
   {
     const float num = (float)(f - G0);
     const float den = (float)(G1 - G0);
@@ -95,31 +102,30 @@ __device__ __forceinline__ void eval_bin(const double f, const dd w, const Piece
     const int j = min(max(i + (int)di, P.seg_a), P.seg_b);
     if (j != i) {
       i = j;
-      G0 = knot_freq(ms, L.Fp[i], ns, L.Fr[i]);
-      G1 = knot_freq(ms, L.Fp[i + 1], ns, L.Fr[i + 1]);
+      G0 = knot_freq(ms, L.kn[i].Fp, ns, L.kn[i].Fr);
+      G1 = knot_freq(ms, L.kn[i + 1].Fp, ns, L.kn[i + 1].Fr);
     }
   }
   if ((i > P.seg_a && !(dd_ * G0 < fd)) || (i < P.seg_b && dd_ * G1 < fd)) {
-    while (i > P.seg_a && !(dd_ * knot_freq(ms, L.Fp[i], ns, L.Fr[i]) < fd)) --i;
-    while (i < P.seg_b && dd_ * knot_freq(ms, L.Fp[i + 1], ns, L.Fr[i + 1]) < fd) ++i;
-    G0 = knot_freq(ms, L.Fp[i], ns, L.Fr[i]);
-    G1 = knot_freq(ms, L.Fp[i + 1], ns, L.Fr[i + 1]);
+    while (i > P.seg_a && !(dd_ * knot_freq(ms, L.kn[i].Fp, ns, L.kn[i].Fr) < fd)) --i;
+    while (i < P.seg_b && dd_ * knot_freq(ms, L.kn[i + 1].Fp, ns, L.kn[i + 1].Fr) < fd) ++i;
+    G0 = knot_freq(ms, L.kn[i].Fp, ns, L.kn[i].Fr);
+    G1 = knot_freq(ms, L.kn[i + 1].Fp, ns, L.kn[i + 1].Fr);
   }
   SegData S;
-  S.ti = L.t[i];
-  S.h = L.t[i + 1] - S.ti;
+  S.ti = L.kn[i].t;
+  S.h = L.kn[i + 1].t - S.ti;
   S.G0 = G0;
   S.G1 = G1;
-  const double* cf = L.cF + i * 6;
-  S.q1 = wsum(ms, cf[0], ns, cf[3]);
-  S.q2 = wsum(ms, cf[1], ns, cf[4]);
-  S.q3 = wsum(ms, cf[2], ns, cf[5]);
-  const double* cp = L.cP + i * 6;
-  S.r1 = wsum(ms, cp[0], ns, cp[3]);
-  S.r2 = wsum(ms, cp[1], ns, cp[4]);
-  S.r3 = wsum(ms, cp[2], ns, cp[5]);
-  S.Ppi = L.Pp[i];
-  S.Pri = L.Pr[i];
+  const SegCoef& cs = L.sc[i];
+  S.q1 = wsum(ms, cs.cFp[0], ns, cs.cFr[0]);
+  S.q2 = wsum(ms, cs.cFp[1], ns, cs.cFr[1]);
+  S.q3 = wsum(ms, cs.cFp[2], ns, cs.cFr[2]);
+  S.r1 = wsum(ms, cs.cPp[0], ns, cs.cPr[0]);
+  S.r2 = wsum(ms, cs.cPp[1], ns, cs.cPr[1]);
+  S.r3 = wsum(ms, cs.cPp[2], ns, cs.cPr[2]);
+  S.Ppi = L.kn[i].Pp;
+  S.Pri = L.kn[i].Pr;
   const Bracket B = make_bracket(P, i, S);
   const double tau = solve_root(f, dd_, S, B);
 
@@ -149,30 +155,30 @@ __device__ __forceinline__ void eval_bin(const double f, const dd w, const Piece
 // (caller synchronises).
 __device__ __forceinline__ Lds stage_lds(const Prepared& p, double* lds) {
   const int K = p.K, nseg = K - 1;
-  double* s_t = lds;
-  double* s_Fp = s_t + K;
-  double* s_Fr = s_Fp + K;
-  double* s_Pp = s_Fr + K;
-  double* s_Pr = s_Pp + K;
-  double* s_cF = s_Pr + K;
-  double* s_cP = s_cF + 6 * nseg;
+  KnotRec* kn = (KnotRec*)lds;
+  SegCoef* sc = (SegCoef*)(lds + 6 * (size_t)K);
   for (int i = threadIdx.x; i < K; i += blockDim.x) {
-    s_t[i] = p.t[i];
-    s_Fp[i] = p.Fphi[i];
-    s_Fr[i] = p.Fr[i];
-    s_Pp[i] = p.Phiphi[i];
-    s_Pr[i] = p.Phir[i];
+    KnotRec r;
+    r.Fp = p.Fphi[i];
+    r.Fr = p.Fr[i];
+    r.t = p.t[i];
+    r.Pp = p.Phiphi[i];
+    r.Pr = p.Phir[i];
+    r.pad = 0.0;
+    kn[i] = r;
   }
   for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
+    SegCoef c;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      s_cF[i * 6 + c] = p.tcoef[((size_t)0 * nseg + i) * 4 + 1 + c];
-      s_cF[i * 6 + 3 + c] = p.tcoef[((size_t)1 * nseg + i) * 4 + 1 + c];
-      s_cP[i * 6 + c] = p.tcoef[((size_t)2 * nseg + i) * 4 + 1 + c];
-      s_cP[i * 6 + 3 + c] = p.tcoef[((size_t)3 * nseg + i) * 4 + 1 + c];
+    for (int k = 0; k < 3; ++k) {
+      c.cFp[k] = p.tcoef[((size_t)0 * nseg + i) * 4 + 1 + k];
+      c.cFr[k] = p.tcoef[((size_t)1 * nseg + i) * 4 + 1 + k];
+      c.cPp[k] = p.tcoef[((size_t)2 * nseg + i) * 4 + 1 + k];
+      c.cPr[k] = p.tcoef[((size_t)3 * nseg + i) * 4 + 1 + k];
     }
+    sc[i] = c;
   }
-  return Lds{s_t, s_Fp, s_Fr, s_Pp, s_Pr, s_cF, s_cP};
+  return Lds{kn, sc};
 }
 
 // Active-mode list of a block: at most kListCap mode indices at a time, in
@@ -385,7 +391,7 @@ constexpr int gather_batch_min_waves() {
 
 template <bool MIXED, int BPL, int WAVES>
 __global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_kernel(GatherArgs a) {
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) double lds[];
   const Prepared& p = a.p;
   const int kb = (int)blockIdx.x * block_bins<BPL, WAVES>();
   const int kbe = kb + block_bins<BPL, WAVES>() - 1;
@@ -411,7 +417,7 @@ template <bool MIXED, int BPL, int WAVES>
 __global__ __launch_bounds__(64 * WAVES, gather_batch_min_waves<MIXED>()) void gather_batch_kernel(const WaveItem* __restrict__ items, int B,
                                                                 const int32_t* __restrict__ item_prefix,
                                                                 int total_items, int* __restrict__ counter) {
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) double lds[];
   __shared__ int s_item;
   int* list = (int*)lds;
   double* tables = lds + kHeadDoubles;
@@ -501,7 +507,7 @@ __global__ void amp32_batch_kernel(const WaveItem* __restrict__ items, int B, co
   }
 }
 
-size_t gather_lds_bytes(int K) { return (size_t)(5 * K + 12 * (K - 1)) * sizeof(double); }
+size_t gather_lds_bytes(int K) { return (size_t)K * sizeof(KnotRec) + (size_t)(K - 1) * sizeof(SegCoef); }
 
 template <bool MIXED, int BPL, int WAVES>
 static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t stream) {
