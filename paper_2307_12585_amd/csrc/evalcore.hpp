@@ -20,8 +20,17 @@ struct SegData {
   double ti, h, G0, G1;   // knot time, segment length, |F_V| at both knots
   double q1, q2, q3;      // |F_V| spline coefficients
   double r1, r2, r3;      // s Phi_V spline coefficients
-  double Ppi, Pri;        // Phi_phi, Phi_r knot values at t_i
+  double Ppi, Pri;        // Phi_phi, Phi_r at t_i reduced modulo 2 pi (reduce_2pi)
 };
+
+// x modulo 2 pi, in [-pi, pi]: the multiple k of 2 pi is removed with 2 pi
+// split into hi + lo parts and k * hi formed exactly, so the result carries
+// the rounding error of x only.
+__device__ __forceinline__ double reduce_2pi(double x) {
+  const double k = rint(x * kInvTwoPi);
+  const dd kc = two_prod(k, kTwoPiHi);
+  return ((x - kc.hi) - kc.lo) - k * kTwoPiLo;
+}
 
 // Bracket of the root inside segment i of piece P: [tl, th] in tau, with
 // |F_V| = gl, gh at its ends (piece end values at the piece's first/last
@@ -97,30 +106,19 @@ __device__ __forceinline__ double solve_root(double f, double dd, const SegData&
   return tau;
 }
 
-// 2 pi f as an unevaluated double-double (formed once per bin).
-__device__ __forceinline__ dd two_pi_f(double f) {
-  dd w = two_prod(f, kTwoPiHi);
-  w.lo = __builtin_fma(f, kTwoPiLo, w.lo);
-  return w;
-}
-
-// psi = 2 pi f (t_i + tau) - s Phi_V(t_i + tau), with w = 2 pi f and
-// (ms, ns) = (s m, s n): the large part 2 pi f t_i - s Phi_V,i in
-// double-double, reduced modulo 2 pi, plus the segment-local part in double.
-__device__ __forceinline__ double phase_psi(const dd w, double tau, double ms, double ns, const SegData& S) {
-  dd q = two_prod(w.hi, S.ti);
-  q.lo = __builtin_fma(w.lo, S.ti, q.lo);
-  const dd pm = two_prod(ms, S.Ppi);
-  const dd pn = two_prod(ns, S.Pri);
-  dd z = two_sum(pm.hi, pn.hi);
-  z.lo += pm.lo + pn.lo;
-  dd b = two_sum(q.hi, -z.hi);
-  b.lo += q.lo - z.lo;
-  const double kk = rint(b.hi * kInvTwoPi);
-  const dd kc = two_prod(kk, kTwoPiHi);
-  const double red = (b.hi - kc.hi) + ((b.lo - kc.lo) - kk * kTwoPiLo);
-  const double small = tau * (w.hi - (S.r1 + tau * (S.r2 + tau * S.r3)));
-  return red + small;
+// psi = 2 pi f (t_i + tau) - s Phi_V(t_i + tau) up to a multiple of 2 pi,
+// with w = 2 pi f and (ms, ns) = (s m, s n).  The large part is taken modulo
+// 2 pi without double-double products of the phases: f t_i is formed exactly
+// as a two-product and only its fractional part is kept, and since ms and
+// ns are integers, ms Phi_phi,i + ns Phi_r,i equals (mod 2 pi) the same
+// combination of the knot phases reduced modulo 2 pi, at most a few hundred
+// radians here.  The segment-local part is added in double.
+__device__ __forceinline__ double phase_psi(double f, double w, double tau, double ms, double ns, const SegData& S) {
+  const dd ft = two_prod(f, S.ti);
+  const double fr = (ft.hi - rint(ft.hi)) + ft.lo;
+  const double big = kTwoPiHi * fr - __builtin_fma(ms, S.Ppi, ns * S.Pri);
+  const double small = tau * (w - (S.r1 + tau * (S.r2 + tau * S.r3)));
+  return big + small;
 }
 
 // sin and cos of x in double precision: Cody-Waite reduction by pi/2 split
@@ -128,8 +126,8 @@ __device__ __forceinline__ double phase_psi(const dd w, double tau, double ms, d
 // fused multiply-add), then the Taylor series of sin and cos on
 // [-pi/4, pi/4] (terms up to r^17 and r^18; the first omitted terms are
 // below 1e-19) and a quadrant rotation.  The phases passed here are reduced
-// modulo 2 pi up to the segment-local part, a few thousand radians at most,
-// so the quadrant count fits an int.
+// modulo 2 pi up to a few hundred radians and the segment-local part, a few
+// thousand radians at most, so the quadrant count fits an int.
 __device__ __forceinline__ void sincos_cw(double x, double* sn, double* cs) {
   constexpr double kPio2A = 1.5707963267341256;
   constexpr double kPio2B = 6.077100506303966e-11;
@@ -167,12 +165,13 @@ __device__ __forceinline__ void sincos_cw(double x, double* sn, double* cs) {
 }
 
 // E = e^{i psi} G and the amplitude spline value A at the root (FP64);
-// w = 2 pi f as double-double, (ms, ns) = (s m, s n).
-__device__ __forceinline__ void root_terms64(const dd w, double tau, int d, double ms, double ns, const SegData& S,
-                                             const double* __restrict__ ac_seg, double2& E, double2& A) {
+// w = 2 pi f, (ms, ns) = (s m, s n).
+__device__ __forceinline__ void root_terms64(double f, double w, double tau, int d, double ms, double ns,
+                                             const SegData& S, const double* __restrict__ ac_seg, double2& E,
+                                             double2& A) {
   const double gd = S.q1 + tau * (2.0 * S.q2 + 3.0 * S.q3 * tau);
   const double gdd = 2.0 * S.q2 + 6.0 * S.q3 * tau;
-  const double psi = phase_psi(w, tau, ms, ns, S);
+  const double psi = phase_psi(f, w, tau, ms, ns, S);
   const double2 G = spa_factor64(gd, gdd, d);
   double sn, cs;
   sincos_cw(psi, &sn, &cs);
@@ -183,11 +182,12 @@ __device__ __forceinline__ void root_terms64(const dd w, double tau, int d, doub
 
 // Mixed precision: root, derivatives, phase and its reduction in FP64; the
 // factor, sincos and the (normalised) amplitude spline in FP32.
-__device__ __forceinline__ void root_terms32(const dd w, double tau, int d, double ms, double ns, const SegData& S,
-                                             const float* __restrict__ ac32_seg, float2& E, float2& A) {
+__device__ __forceinline__ void root_terms32(double f, double w, double tau, int d, double ms, double ns,
+                                             const SegData& S, const float* __restrict__ ac32_seg, float2& E,
+                                             float2& A) {
   const double gd = S.q1 + tau * (2.0 * S.q2 + 3.0 * S.q3 * tau);
   const double gdd = 2.0 * S.q2 + 6.0 * S.q3 * tau;
-  const double psi = phase_psi(w, tau, ms, ns, S);
+  const double psi = phase_psi(f, w, tau, ms, ns, S);
   const double psr = psi - kTwoPiHi * rint(psi * kInvTwoPi);
   const float2 G = spa_factor32(gd, gdd, d);
   float sn, cs;

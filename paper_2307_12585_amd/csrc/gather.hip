@@ -59,8 +59,9 @@ struct Acc<true> {
 
 // LDS copy of one waveform's trajectory tables, interleaved so that one base
 // address per index reaches every field by immediate offsets: per knot i
-// {F_phi, F_r, t, Phi_phi, Phi_r} (48 B, 16-B aligned pairs), per segment i
-// the c1..c3 spline coefficients of F_phi, F_r, Phi_phi, Phi_r (96 B).
+// {F_phi, F_r, t, Phi_phi mod 2 pi, Phi_r mod 2 pi} (48 B, 16-B aligned
+// pairs), per segment i the c1..c3 spline coefficients of F_phi, F_r,
+// Phi_phi, Phi_r (96 B).
 struct alignas(16) KnotRec {
   double Fp, Fr, t, Pp, Pr, pad;
 };
@@ -80,13 +81,13 @@ struct Lds {
 // guessed from the piece's rate, refined by one secant step on the segment
 // index through the knot frequencies at the guess, and checked against the
 // definition; the rare misses walk to the right segment.
-//   f, w: the bin frequency and 2 pi f (double-double);
+//   f, w: the bin frequency and 2 pi f;
 //   ms, ns: s m and s n of the piece, so that |F_V| = ms F_phi + ns F_r;
 //   dd_, span, rate: d, seg_b - seg_a and the rate of the piece;
 //   cP, cX: c_+ and c_x, conjugated when s < 0, so that the contribution is
 //   cP (A^(s) E) and cX (A^(s) E), A^(s) being A conjugated when s < 0.
 template <bool MIXED>
-__device__ __forceinline__ void eval_bin(const double f, const dd w, const Piece& P, const double ms, const double ns,
+__device__ __forceinline__ void eval_bin(const double f, const double w, const Piece& P, const double ms, const double ns,
                                          const double dd_, const double span, const double rate, const double2 cP,
                                          const double2 cX, const double* __restrict__ ac,
                                          const float* __restrict__ ac32, const Lds& L, Acc<MIXED>& acc) {
@@ -131,7 +132,7 @@ __device__ __forceinline__ void eval_bin(const double f, const dd w, const Piece
 
   if constexpr (!MIXED) {
     double2 E, A;
-    root_terms64(w, tau, P.d, ms, ns, S, ac + (size_t)i * 8, E, A);
+    root_terms64(f, w, tau, P.d, ms, ns, S, ac + (size_t)i * 8, E, A);
     const double ay = P.s < 0 ? -A.y : A.y;
     const double Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
     acc.v[0] += cP.x * Wr - cP.y * Wi;
@@ -140,7 +141,7 @@ __device__ __forceinline__ void eval_bin(const double f, const dd w, const Piece
     acc.v[3] += cX.x * Wi + cX.y * Wr;
   } else {
     float2 E, A;
-    root_terms32(w, tau, P.d, ms, ns, S, ac32 + (size_t)i * 8, E, A);
+    root_terms32(f, w, tau, P.d, ms, ns, S, ac32 + (size_t)i * 8, E, A);
     const float ay = P.s < 0 ? -A.y : A.y;
     const float Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
     const float pr = (float)cP.x, pi = (float)cP.y, xr = (float)cX.x, xi = (float)cX.y;
@@ -162,8 +163,8 @@ __device__ __forceinline__ Lds stage_lds(const Prepared& p, double* lds) {
     r.Fp = p.Fphi[i];
     r.Fr = p.Fr[i];
     r.t = p.t[i];
-    r.Pp = p.Phiphi[i];
-    r.Pr = p.Phir[i];
+    r.Pp = reduce_2pi(p.Phiphi[i]);
+    r.Pr = reduce_2pi(p.Phir[i]);
     r.pad = 0.0;
     kn[i] = r;
   }
@@ -238,7 +239,7 @@ __device__ __forceinline__ void write_list(int* list, uint32_t hits, int wbase, 
 // records come in by scalar loads.
 template <bool MIXED>
 __device__ __forceinline__ void walk_list(const Prepared& p, const float* __restrict__ acoef32, const int* list, int n,
-                                          int ks, int ke, double f, const dd w, const Lds& L, Acc<MIXED>& acc) {
+                                          int ks, int ke, double f, double w, const Lds& L, Acc<MIXED>& acc) {
   const int lane = threadIdx.x & 63;
   const int k = ks + lane;
   const int nseg = p.K - 1;
@@ -341,7 +342,7 @@ __device__ __forceinline__ void process_block(const Prepared& p, const float* __
     const int ke = min(ks + 63, Nf - 1);
     const int k = ks + lane;
     const double f = (k < Nf) ? p.f[k] : 0.0;
-    const dd w = two_pi_f(f);
+    const double w = kTwoPiHi * f;
     Acc<MIXED> acc;
     acc.zero();
     if (single) {

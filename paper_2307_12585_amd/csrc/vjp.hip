@@ -62,6 +62,7 @@ __global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
   const double* cPr = p.tcoef + ((size_t)3 * nseg + i) * 4;
   const double* acs = p.acoef + ((size_t)mu * nseg + i) * 8;
   const float* acs32 = MIXED ? a.acoef32 + ((size_t)mu * nseg + i) * 8 : nullptr;
+  const double Ppr = reduce_2pi(p.Phiphi[i]), Prr = reduce_2pi(p.Phir[i]);
 
   for (int q = 0; q < md.npieces; ++q) {
     const Piece P = p.pieces[(size_t)mu * kMaxPieces + q];
@@ -81,8 +82,8 @@ __global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
     S.r1 = wsum(ms, cPp[1], ns, cPr[1]);
     S.r2 = wsum(ms, cPp[2], ns, cPr[2]);
     S.r3 = wsum(ms, cPp[3], ns, cPr[3]);
-    S.Ppi = p.Phiphi[i];
-    S.Pri = p.Phir[i];
+    S.Ppi = Ppr;
+    S.Pri = Prr;
     // bins whose root the forward search places in segment i of this piece:
     // the largest segment j in [seg_a, seg_b] with j == seg_a or d g_j < d f
     int kA = P.k_lo, kB = P.k_hi;
@@ -98,12 +99,12 @@ __global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
     const Bracket B = make_bracket(P, i, S);
     for (int k = kA + lane; k <= kB; k += 64) {
       const double f = p.f[k];
-      const dd w = two_pi_f(f);
+      const double w = kTwoPiHi * f;
       const double tau = solve_root(f, dd_, S, B);
       double Er, Ei, Ar, Ai, gpr, gpi, gcr, gci;
       if constexpr (MIXED) {
         float2 E, A;
-        root_terms32(w, tau, d, ms, ns, S, acs32, E, A);
+        root_terms32(f, w, tau, d, ms, ns, S, acs32, E, A);
         Er = E.x;
         Ei = E.y;
         // the FP32 amplitude is in the normalised variable u = tau / h
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
         gci = gc.y;
       } else {
         double2 E, A;
-        root_terms64(w, tau, d, ms, ns, S, acs, E, A);
+        root_terms64(f, w, tau, d, ms, ns, S, acs, E, A);
         Er = E.x;
         Ei = E.y;
         Ar = A.x;
