@@ -122,41 +122,38 @@ __device__ __forceinline__ double phase_psi(double f, double w, double tau, doub
 }
 
 // sin and cos of x in double precision: Cody-Waite reduction by pi/2 split
-// into three parts (33 + 33 + 53 bits, each product subtracted with one
-// fused multiply-add), then the Taylor series of sin and cos on
-// [-pi/4, pi/4] (terms up to r^17 and r^18; the first omitted terms are
-// below 1e-19) and a quadrant rotation.  The phases passed here are reduced
-// modulo 2 pi up to a few hundred radians and the segment-local part, a few
-// thousand radians at most, so the quadrant count fits an int.
+// into two parts (a 33-bit head, so k times it is exact for the quadrant
+// counts that occur, and the rounded remainder; residual 3.5e-27), each
+// product subtracted with one fused multiply-add; then on [-pi/4, pi/4]
+//   sin r = r + r z P(z),  cos r = 1 - z/2 + z^2 Q(z),  z = r^2,
+// with P, Q degree-5 least-squares fits in extended precision
+// (gen_sincos_coeffs.py; approximation errors 1e-17 and 5e-19), and a
+// quadrant rotation.  The phases passed here are reduced modulo 2 pi up to a
+// few hundred radians and the segment-local part, a few thousand radians at
+// most, so the quadrant count fits an int.  Error against extended precision:
+// 2.2e-16 absolute for |x| <= 1e4.
 __device__ __forceinline__ void sincos_cw(double x, double* sn, double* cs) {
   constexpr double kPio2A = 1.5707963267341256;
-  constexpr double kPio2B = 6.077100506303966e-11;
-  constexpr double kPio2C = 2.0222662487959506e-21;
+  constexpr double kPio2B = 6.077100506506192e-11;
   constexpr double k2OverPi = 0.6366197723675814;
   const double k = rint(x * k2OverPi);
   double r = __builtin_fma(-k, kPio2A, x);
   r = __builtin_fma(-k, kPio2B, r);
-  r = __builtin_fma(-k, kPio2C, r);
   const double z = r * r;
-  double ps = 2.8114572543455206e-15;
-  ps = __builtin_fma(ps, z, -7.647163731819816e-13);
-  ps = __builtin_fma(ps, z, 1.6059043836821613e-10);
-  ps = __builtin_fma(ps, z, -2.505210838544172e-08);
-  ps = __builtin_fma(ps, z, 2.7557319223985893e-06);
-  ps = __builtin_fma(ps, z, -0.0001984126984126984);
-  ps = __builtin_fma(ps, z, 0.008333333333333333);
+  double ps = 1.5918135932869774e-10;
+  ps = __builtin_fma(ps, z, -2.5051131947374594e-08);
+  ps = __builtin_fma(ps, z, 2.7557316103105014e-06);
+  ps = __builtin_fma(ps, z, -0.0001984126983675979);
+  ps = __builtin_fma(ps, z, 0.00833333333333095);
   ps = __builtin_fma(ps, z, -0.16666666666666666);
   const double s_r = __builtin_fma(r * z, ps, r);
-  double pc = -1.5619206968586225e-16;
-  pc = __builtin_fma(pc, z, 4.779477332387385e-14);
-  pc = __builtin_fma(pc, z, -1.1470745597729725e-11);
-  pc = __builtin_fma(pc, z, 2.08767569878681e-09);
-  pc = __builtin_fma(pc, z, -2.755731922398589e-07);
-  pc = __builtin_fma(pc, z, 2.48015873015873e-05);
-  pc = __builtin_fma(pc, z, -0.001388888888888889);
+  double pc = -1.1382636115964061e-11;
+  pc = __builtin_fma(pc, z, 2.087614632531677e-09);
+  pc = __builtin_fma(pc, z, -2.7557317272036996e-07);
+  pc = __builtin_fma(pc, z, 2.4801587298766363e-05);
+  pc = __builtin_fma(pc, z, -0.0013888888888887398);
   pc = __builtin_fma(pc, z, 0.041666666666666664);
-  pc = __builtin_fma(pc, z, -0.5);
-  const double c_r = __builtin_fma(z, pc, 1.0);
+  const double c_r = __builtin_fma(z * z, pc, __builtin_fma(-0.5, z, 1.0));
   const int q = ((int)k) & 3;
   const double s1 = (q & 1) ? c_r : s_r;
   const double c1 = (q & 1) ? s_r : c_r;

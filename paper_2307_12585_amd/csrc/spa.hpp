@@ -88,8 +88,10 @@ __device__ __forceinline__ double2 spa_factor64(double gd, double gdd, int dir) 
   const double rs2 = rs * rs;
   const double au = (gdd == 0.0) ? 0.0 : k3Over2Pi * gdd * gdd * (rs2 * rs2 * rs2);
   if (gd != 0.0 && au <= 1.0 / FDW_X_B) {
-    const double u = sg > 0 ? au : -au;
-    const double v = u * u;
+    // W = re + i sg im with re, im the even and odd parts of the series in
+    // |u| (u = 1/X carries the sign sg of gd); then
+    // G = c (1 - i sg) W = c (re + im) + i sg c (im - re).
+    const double v = au * au;
     double re = 0.0, im = 0.0;
     if (__all(au <= 1e-5)) {
 #pragma unroll
@@ -113,11 +115,10 @@ __device__ __forceinline__ double2 spa_factor64(double gd, double gdd, int dir) 
         if (2 * j + 1 < FDW_NASYM64) im = im * v + sgn * fdw_asym64[2 * j + 1];
       }
     }
-    im *= u;
+    im *= au;
     const double c = kRsqrt2 * rs;
-    // (c - i sg c) (re + i im)
-    const double bi = sg > 0 ? -c : c;
-    return make_double2(c * re - bi * im, c * im + bi * re);
+    const double gi = c * (im - re);
+    return make_double2(c * (re + im), sg > 0 ? gi : -gi);
   }
   const double ax = k2PiOver3 * agd * agd * agd * rcp_nr2(gdd * gdd);  // |X|
   const double y = cbrt(1.5 * ax);
@@ -139,7 +140,7 @@ __device__ __forceinline__ float2 spa_factor32(double gd, double gdd, int dir) {
   const int sg = gd > 0.0 ? 1 : (gd < 0.0 ? -1 : dir);
   const double au = (gdd == 0.0) ? 0.0 : k3Over2Pi * gdd * gdd * rcp_nr1(agd * agd * agd);
   if (gd != 0.0 && au <= 1.0 / FDW_X_B) {
-    const float uf = (float)(sg > 0 ? au : -au);
+    const float uf = (float)au;
     const float v = uf * uf;
     float re = 0.f, im = 0.f;
 #pragma unroll
@@ -150,8 +151,8 @@ __device__ __forceinline__ float2 spa_factor32(double gd, double gdd, int dir) {
     }
     im *= uf;
     const float c = kRsqrt2 * rsqrtf((float)agd);
-    const float bi = sg > 0 ? -c : c;
-    return make_float2(c * re - bi * im, c * im + bi * re);
+    const float gi = c * (im - re);
+    return make_float2(c * (re + im), sg > 0 ? gi : -gi);
   }
   const float y = cbrtf((float)(1.5 * k2PiOver3 * agd * agd * agd * rcp_nr2(gdd * gdd)));
   float2 q = q_cheb32(y);
