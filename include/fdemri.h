@@ -59,6 +59,9 @@ typedef enum {
 /* flags of fdemri_waveform_desc.flags */
 #define FDEMRI_NO_PARTNERS 0x1u  /* treat every row as a single voice (l,m,n) with any
                                     sign of m; do not add the (l,-m,-n) partner */
+#define FDEMRI_COEFFS_GIVEN 0x2u /* A holds the amplitude spline coefficients of every
+                                    segment instead of knot values (layout below); they
+                                    are used as given, without a spline solve */
 
 /* Flag bits reported by fdemri_sync_flags */
 #define FDEMRI_FLAG_PIECE_OVERFLOW 0x1u  /* a voice had more monotonic pieces than
@@ -84,7 +87,9 @@ typedef enum {
  *       the voices (l,m,n) and (l,-m,-n), the latter with amplitude
  *       (-1)^l conj(A) (the equatorial-symmetry relation of the Schwarzschild
  *       amplitudes); m = 0 rows are single voices.
- *   A : [Nm][K][2] double, complex amplitude knot values (re, im).
+ *   A : [Nm][K][2] double, complex amplitude knot values (re, im); with
+ *       FDEMRI_COEFFS_GIVEN instead [Nm][K-1][4][2] double, the coefficients
+ *       a_k of A(t_i + tau) = sum_k a_k tau^k on segment i (ascending k, re, im).
  *   f : [Nf] double, ascending, f >= 0 (Hz).  Bins with f == 0 are set to 0.
  * Host scalars: theta, phi (source-frame polar/azimuthal viewing angles),
  *   scale = mu/d_L (dimensionless strain scale of Eq. main_wave).
@@ -163,7 +168,9 @@ fdemri_status fdemri_waveform_batch(fdemri_ctx *ctx, int32_t B, const fdemri_wav
  *   gPhi      : [2][K-1][4] double, dL/d(Phi_phi and Phi_r spline coefficients),
  *               ascending powers of tau.
  *   gA_knots  : [Nm][K][2] double, dL/d(amplitude knot values A of the desc),
- *               through the transposed not-a-knot spline.
+ *               through the transposed not-a-knot spline (must be NULL with
+ *               FDEMRI_COEFFS_GIVEN: the amplitudes then have no knots;
+ *               FDEMRI_EINVAL otherwise).
  *   gPhi_knots: [2][K] double, dL/d(Phi_phi and Phi_r knot values).
  *   g_scalars : [5] double: dL/dtheta, dL/dphi, dL/dscale, dL/dPhi_phi0,
  *               dL/dPhi_r0 (the last two: a common offset of all Phi knots).

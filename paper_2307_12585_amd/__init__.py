@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libfdemri.so")
 FDEMRI_OK, FDEMRI_EINVAL, FDEMRI_ENOMEM, FDEMRI_EDEVICE, FDEMRI_ENOTSUP = range(5)
 FDEMRI_FP64, FDEMRI_MIXED = 0, 1
 FDEMRI_NO_PARTNERS = 0x1
+FDEMRI_COEFFS_GIVEN = 0x2
 FDEMRI_CTX_BATCH_GRAPHS = 0x1
 FDEMRI_FLAG_PIECE_OVERFLOW = 0x1
 PRECISIONS = {"fp64": FDEMRI_FP64, "mixed": FDEMRI_MIXED}
@@ -106,10 +107,12 @@ def _stream(device):
 
 class DeviceWaveform:
     """Device-resident inputs of one waveform, in the layouts of
-    fdemri_waveform_desc (float64 / int32 contiguous tensors; A as [Nm, K, 2])."""
+    fdemri_waveform_desc (float64 / int32 contiguous tensors; A as [Nm, K, 2]
+    knot values, or with coeffs_given=True as [Nm, K-1, 4, 2] spline
+    coefficients in ascending powers of t - t_i)."""
 
     def __init__(self, t, Fphi, Fr, Phiphi, Phir, l, m, n, A, theta, phi, scale, f,
-                 partners=True, device="cuda"):
+                 partners=True, device="cuda", coeffs_given=False):
         dev = torch.device(device)
         d64 = dict(dtype=torch.float64, device=dev)
         self.t = torch.as_tensor(t, **d64).contiguous()
@@ -127,6 +130,7 @@ class DeviceWaveform:
         self.f = torch.as_tensor(f, **d64).contiguous()
         self.theta, self.phi, self.scale = float(theta), float(phi), float(scale)
         self.partners = bool(partners)
+        self.coeffs_given = bool(coeffs_given)
         self.device = dev
 
     @property
@@ -147,7 +151,8 @@ class DeviceWaveform:
             Phiphi=_ptr(self.Phiphi).value, Phir=_ptr(self.Phir).value, Nm=self.Nm,
             l=_ptr(self.l).value, m=_ptr(self.m).value, n=_ptr(self.n).value, A=_ptr(self.A).value,
             theta=self.theta, phi=self.phi, scale=self.scale, Nf=self.Nf, f=_ptr(self.f).value,
-            flags=0 if self.partners else FDEMRI_NO_PARTNERS)
+            flags=(0 if self.partners else FDEMRI_NO_PARTNERS)
+            | (FDEMRI_COEFFS_GIVEN if self.coeffs_given else 0))
 
     @classmethod
     def from_workload(cls, w, device="cuda", partners=True, f=None):
@@ -247,7 +252,8 @@ class Context:
             out["gA"] = torch.empty(Nm, K - 1, 4, 2, dtype=torch.float64, device=dev)
             out["gPhi"] = torch.empty(2, K - 1, 4, dtype=torch.float64, device=dev)
         if knots:
-            out["gA_knots"] = torch.empty(Nm, K, 2, dtype=torch.float64, device=dev)
+            if not dw.coeffs_given:  # given coefficients have no amplitude knots
+                out["gA_knots"] = torch.empty(Nm, K, 2, dtype=torch.float64, device=dev)
             out["gPhi_knots"] = torch.empty(2, K, dtype=torch.float64, device=dev)
         d = dw.desc()
         self._check(self._lib.fdemri_vjp(
@@ -255,7 +261,7 @@ class Context:
             _ptr(out.get("gA_knots")), _ptr(out.get("gPhi_knots")), _ptr(out["g_scalars"]), _stream(self.device)))
         if coef:
             out["gA"] = torch.view_as_complex(out["gA"])
-        if knots:
+        if "gA_knots" in out:
             out["gA_knots"] = torch.view_as_complex(out["gA_knots"])
         return out
 

@@ -42,6 +42,7 @@ class WaveformStatic:
         dw.A = torch.view_as_real(A.detach().to(torch.complex128)).contiguous()
         dw.theta, dw.phi, dw.scale = float(theta), float(phi), float(scale)
         dw.partners, dw.device = self.partners, self.device
+        dw.coeffs_given = False
         return dw
 
 

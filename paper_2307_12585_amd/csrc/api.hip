@@ -196,7 +196,8 @@ fdemri_status validate(fdemri_ctx* c, const fdemri_waveform_desc* d) {
     return fail(c, FDEMRI_EINVAL, "NULL input pointer in desc");
   if (!(d->theta == d->theta) || !(d->phi == d->phi) || !(d->scale == d->scale))
     return fail(c, FDEMRI_EINVAL, "theta, phi and scale must not be NaN");
-  if (d->flags & ~(uint32_t)FDEMRI_NO_PARTNERS) return fail(c, FDEMRI_EINVAL, "unknown flags 0x%x", d->flags);
+  if (d->flags & ~(uint32_t)(FDEMRI_NO_PARTNERS | FDEMRI_COEFFS_GIVEN))
+    return fail(c, FDEMRI_EINVAL, "unknown flags 0x%x", d->flags);
   return FDEMRI_OK;
 }
 
@@ -323,7 +324,9 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
                       float*& acoef32, hipStream_t stream) {
   char* w = c->ws;
   double* tcoef = (double*)(w + L.tcoef);
-  double* acoef = (double*)(w + L.acoef);
+  // with FDEMRI_COEFFS_GIVEN the caller's coefficients (same layout) are read in place
+  const bool given = (d->flags & FDEMRI_COEFFS_GIVEN) != 0;
+  double* acoef = given ? const_cast<double*>(d->A) : (double*)(w + L.acoef);
   acoef32 = mixed ? (float*)(w + L.acoef32) : nullptr;
   ModeConst* modes = (ModeConst*)(w + L.modes);
   int2* mode_kr = (int2*)(w + L.mode_kr);
@@ -333,7 +336,7 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   hipError_t e;
   {
     ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream);
-    e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, d->Nm, tcoef, acoef, stream);
+    e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, given ? 0 : d->Nm, tcoef, acoef, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "spline kernel launch");
   {
@@ -401,6 +404,8 @@ fdemri_status fdemri_vjp(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemri_pr
   fdemri_status st = validate(c, d);
   if (st != FDEMRI_OK) return st;
   if (prec != FDEMRI_FP64 && prec != FDEMRI_MIXED) return fail(c, FDEMRI_EINVAL, "unknown precision %d", (int)prec);
+  if (gA_knots && (d->flags & FDEMRI_COEFFS_GIVEN))
+    return fail(c, FDEMRI_EINVAL, "gA_knots requested but the amplitudes are given as coefficients");
   if (!g_hp || !g_hc) return fail(c, FDEMRI_EINVAL, "NULL cotangent pointer");
   const bool mixed = prec == FDEMRI_MIXED;
   hipError_t e = hipSetDevice(c->device);
@@ -474,7 +479,7 @@ fdemri_status plan_batch(fdemri_ctx* c, int B, const fdemri_waveform_desc* descs
     P.base[b] = off;
     off = align_up(off + P.Ls[b].total, 256);
     P.Kmax = std::max(P.Kmax, (int)descs[b].K);
-    P.n_series += 4 + descs[b].Nm;
+    P.n_series += 4 + ((descs[b].flags & FDEMRI_COEFFS_GIVEN) ? 0 : descs[b].Nm);
     P.n_modes += descs[b].Nm;
     P.n_amp += (int64_t)descs[b].Nm * (descs[b].K - 1);
     P.n_items += gather_items_per_waveform(descs[b].Nf, c->bpl);
@@ -524,7 +529,7 @@ void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc*
     it.phi = d.phi;
     it.scale = d.scale;
     it.tcoef = (double*)(wb + L.tcoef);
-    it.acoef = (double*)(wb + L.acoef);
+    it.acoef = (d.flags & FDEMRI_COEFFS_GIVEN) ? const_cast<double*>(d.A) : (double*)(wb + L.acoef);
     it.acoef32 = P.mixed ? (float*)(wb + L.acoef32) : nullptr;
     it.modes = (ModeConst*)(wb + L.modes);
     it.mode_kr = (int2*)(wb + L.mode_kr);
@@ -534,7 +539,7 @@ void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc*
     it.hp = hp[b];
     it.hc = hc[b];
     hitems[b] = it;
-    series_prefix[b + 1] = series_prefix[b] + 4 + d.Nm;
+    series_prefix[b + 1] = series_prefix[b] + 4 + ((d.flags & FDEMRI_COEFFS_GIVEN) ? 0 : d.Nm);
     mode_prefix[b + 1] = mode_prefix[b] + d.Nm;
     amp_prefix[b + 1] = amp_prefix[b] + d.Nm * (d.K - 1);
     item_prefix[b + 1] = item_prefix[b] + gather_items_per_waveform(d.Nf, c->bpl);

@@ -160,3 +160,55 @@ def test_invalid_arguments_leave_outputs(ctx):
     assert b"K=3" in ctx._lib.fdemri_last_error(ctx._h)
     torch.cuda.synchronize()
     assert torch.all(hp == 7 + 7j)
+
+
+def _amplitude_coefficients(w):
+    """Not-a-knot spline coefficients of every amplitude series, [Nm, K-1, 4, 2]
+    in ascending powers of t - t_i (SciPy, on the test side)."""
+    from scipy.interpolate import CubicSpline
+    t = w.traj.t
+    coef = np.empty((w.A.shape[0], t.size - 1, 4, 2))
+    for mu in range(w.A.shape[0]):
+        for part, comp in ((0, w.A[mu].real), (1, w.A[mu].imag)):
+            coef[mu, :, :, part] = CubicSpline(t, comp, bc_type="not-a-knot").c[::-1].T
+    return coef
+
+
+def test_amplitude_coefficients_given(ctx):
+    """FDEMRI_COEFFS_GIVEN: the amplitude splines passed as coefficients give
+    the oracle's waveform (which splines the same knots), and the coefficient
+    gradient of the adjoint does not depend on how the coefficients arrived;
+    amplitude knot gradients are refused."""
+    w = W.inspiral_20_modes()
+    tr = w.traj
+    coef = _amplitude_coefficients(w)
+    dwc = fd.DeviceWaveform(tr.t, tr.Fphi, tr.Fr, tr.Phiphi, tr.Phir, w.l, w.m, w.n, coef, w.theta, w.phi,
+                            w.scale, w.f, device=ctx.device, coeffs_given=True)
+    dwk = fd.DeviceWaveform.from_workload(w, device=ctx.device)
+    hp, hc = ctx.waveform_dev(dwc, "fp64")
+    kp, kc = ctx.waveform_dev(dwk, "fp64")
+    torch.cuda.synchronize()
+    hg = (hp.cpu().numpy(), hc.cpu().numpy())
+    _check64(hg, oracle.waveform(w), "coefficients given")
+    for a, b in zip(hg, (kp.cpu().numpy(), kc.cpu().numpy())):
+        assert rel_l2(a, b) <= 1e-12
+    mp, mc = ctx.waveform_dev(dwc, "mixed")
+    torch.cuda.synchronize()
+    for a, b in zip((mp.cpu().numpy(), mc.cpu().numpy()), hg):
+        assert rel_l2(a.astype(np.complex128), b) <= TOLMIX
+    rng = np.random.default_rng(3)
+    g = [torch.as_tensor(rng.standard_normal(w.f.size) + 1j * rng.standard_normal(w.f.size), device=ctx.device)
+         for _ in range(2)]
+    gc = ctx.vjp_dev(dwc, g[0], g[1], "fp64")
+    gk = ctx.vjp_dev(dwk, g[0], g[1], "fp64")
+    assert "gA_knots" not in gc
+    for key in ("gA", "gPhi", "gPhi_knots", "g_scalars"):
+        a, b = gc[key].cpu().numpy(), gk[key].cpu().numpy()
+        assert rel_l2(a, b) <= 1e-11, key
+    d = dwc.desc()
+    import ctypes
+    buf = torch.empty(w.Nm * tr.t.size * 2, dtype=torch.float64, device=ctx.device)
+    st = ctx._lib.fdemri_vjp(ctx._h, ctypes.byref(d), 0, ctypes.c_void_p(g[0].data_ptr()),
+                             ctypes.c_void_p(g[1].data_ptr()), None, None, ctypes.c_void_p(buf.data_ptr()), None,
+                             ctypes.c_void_p(buf.data_ptr()), None)
+    assert st == 1  # FDEMRI_EINVAL: no amplitude knots to differentiate
