@@ -23,8 +23,9 @@
  *    last error is per context (fdemri_last_error).
  *  - Device-side conditions that the host cannot see without a
  *    synchronisation (more monotonic pieces in one voice than the table
- *    holds) are recorded in a per-context flag word; fdemri_sync_flags
- *    synchronises the stream and returns it.
+ *    holds, mode rows outside the supported range) are recorded in a
+ *    per-context flag word; fdemri_sync_flags synchronises the stream,
+ *    returns the word and clears it.
  *  - One context per host thread (contexts are not internally locked).
  *  - Transform convention of Eq. singlevoiceFT: h(f) = int h(t) e^{+2 pi i f t} dt,
  *    with h = h_+ - i h_x (Eq. main_wave).
@@ -66,6 +67,9 @@ typedef enum {
 /* Flag bits reported by fdemri_sync_flags */
 #define FDEMRI_FLAG_PIECE_OVERFLOW 0x1u  /* a voice had more monotonic pieces than
                                             FDEMRI_MAX_PIECES; extra pieces dropped */
+#define FDEMRI_FLAG_BAD_MODE 0x2u        /* a row had l outside [2, FDEMRI_MAX_L], |m| > l,
+                                            or m < 0 without FDEMRI_NO_PARTNERS; such rows
+                                            contribute nothing */
 #define FDEMRI_MAX_PIECES 16
 #define FDEMRI_MAX_KNOTS 512
 #define FDEMRI_MAX_L 40

@@ -26,6 +26,7 @@ FDEMRI_NO_PARTNERS = 0x1
 FDEMRI_COEFFS_GIVEN = 0x2
 FDEMRI_CTX_BATCH_GRAPHS = 0x1
 FDEMRI_FLAG_PIECE_OVERFLOW = 0x1
+FDEMRI_FLAG_BAD_MODE = 0x2
 PRECISIONS = {"fp64": FDEMRI_FP64, "mixed": FDEMRI_MIXED}
 
 EXPORTED = [

@@ -41,6 +41,7 @@ __device__ __forceinline__ double ipow(double x, int e) {
 // (-1)^m sqrt[(l+m)!(l-m)!(2l+1) / (4 pi (l+s)!(l-s)!)] for s = -2.
 __device__ __forceinline__ double goldberg_pref(int l, int m) {
   const int s = -2;
+  if (l < 2 || l > kMaxL || m > l || m < -l) return 0.0;  // no harmonic (such rows are flagged)
   double ratio = 1.0;
   int a = l + m, b = l - s;
   if (a >= b)
@@ -61,6 +62,7 @@ __device__ __forceinline__ double goldberg_term(int l, int m, int r, double sh, 
   const int s = -2;
   const int b2 = r + s - m;
   if (dterm) *dterm = 0.0;
+  if (l < 2 || l > kMaxL) return 0.0;  // outside the binomial table (such rows are flagged)
   if (r < 0 || r > l - s || b2 < 0 || b2 > l + s) return 0.0;
   const int k = 2 * r + s - m;
   const int ea = 2 * l - k;

@@ -208,7 +208,9 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
   // ---- ordered events over all segments
   int n_ev = 0;           // events found so far (may exceed kMaxEvents)
   int carry_dir = 0;      // last non-zero direction before the current chunk
-  const bool flat_voice = (mi == 0 && ni == 0);
+  // rows outside the harmonics' range contribute nothing and are flagged
+  const bool bad_mode = li < 2 || li > kMaxL || mi > li || mi < -li || (mi < 0 && !(a.flags & FDEMRI_NO_PARTNERS));
+  const bool flat_voice = (mi == 0 && ni == 0) || bad_mode;
   if (!flat_voice) {
     for (int c0 = 0; c0 < nseg; c0 += 64) {
       const int i = c0 + lane;
@@ -327,6 +329,7 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
     a.mode_kr[mu] = make_int2(kr_lo, kr_hi);
     a.evals[mu] = evals;
     if (n_valid > kMaxPieces || ev_overflow) atomicOr(a.flag_word, (uint32_t)FDEMRI_FLAG_PIECE_OVERFLOW);
+    if (bad_mode) atomicOr(a.flag_word, (uint32_t)FDEMRI_FLAG_BAD_MODE);
   }
 }
 

@@ -212,3 +212,27 @@ def test_amplitude_coefficients_given(ctx):
                              ctypes.c_void_p(g[1].data_ptr()), None, None, ctypes.c_void_p(buf.data_ptr()), None,
                              ctypes.c_void_p(buf.data_ptr()), None)
     assert st == 1  # FDEMRI_EINVAL: no amplitude knots to differentiate
+
+
+def test_out_of_range_mode_rows_are_flagged_and_skipped(ctx):
+    """Rows with l above FDEMRI_MAX_L or |m| > l contribute nothing, set
+    FDEMRI_FLAG_BAD_MODE, and leave the other rows' sum unchanged; the
+    adjoint stays finite."""
+    w = W.inspiral_20_modes()
+    hp0, hc0 = gpu_waveform(ctx, w)
+    import copy
+    wb = copy.deepcopy(w)
+    wb.l = np.concatenate([w.l, [50, 2]]).astype(w.l.dtype)
+    wb.m = np.concatenate([w.m, [2, 3]]).astype(w.m.dtype)
+    wb.n = np.concatenate([w.n, [0, 0]]).astype(w.n.dtype)
+    wb.A = np.concatenate([w.A, w.A[:2]])
+    hp, hc = gpu_waveform(ctx, wb, check_flags=False)
+    assert ctx.sync_flags() == fd.FDEMRI_FLAG_BAD_MODE
+    assert np.array_equal(hp, hp0) and np.array_equal(hc, hc0)
+    dw = fd.DeviceWaveform.from_workload(wb, device=ctx.device)
+    rng = np.random.default_rng(4)
+    g = [torch.as_tensor(rng.standard_normal(w.f.size) + 1j * rng.standard_normal(w.f.size), device=ctx.device)
+         for _ in range(2)]
+    out = ctx.vjp_dev(dw, g[0], g[1], "fp64")
+    assert all(bool(torch.isfinite(torch.view_as_real(v) if v.is_complex() else v).all()) for v in out.values())
+    ctx.sync_flags()
