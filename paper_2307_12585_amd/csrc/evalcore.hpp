@@ -34,18 +34,27 @@ __device__ __forceinline__ double reduce_2pi(double x) {
 
 // Bracket of the root inside segment i of piece P: [tl, th] in tau, with
 // |F_V| = gl, gh at its ends (piece end values at the piece's first/last
-// segment, knot values elsewhere).
+// segment, knot values elsewhere).  A piece over the whole trajectory has
+// knot values at both ends, so its bracket is the segment's (a wave-uniform
+// test that saves the per-lane selects).
 struct Bracket {
   double tl, th, gl, gh;
 };
 
 __device__ __forceinline__ Bracket make_bracket(const Piece& P, int i, const SegData& S) {
-  const bool first = (i == P.seg_a), last = (i == P.seg_b);
   Bracket B;
-  B.tl = first ? P.tau_a : 0.0;
-  B.th = last ? P.tau_b : S.h;
-  B.gl = first ? P.g_a : S.G0;
-  B.gh = last ? P.g_b : S.G1;
+  if (P.whole) {
+    B = Bracket{0.0, S.h, S.G0, S.G1};
+  } else {
+    // an empty volatile statement keeps this a branch: if-converted, both
+    // sides would be computed with per-lane selects for every piece
+    asm volatile("");
+    const bool first = (i == P.seg_a), last = (i == P.seg_b);
+    B.tl = first ? P.tau_a : 0.0;
+    B.th = last ? P.tau_b : S.h;
+    B.gl = first ? P.g_a : S.G0;
+    B.gh = last ? P.g_b : S.G1;
+  }
   return B;
 }
 
@@ -140,19 +149,17 @@ __device__ __forceinline__ void sincos_cw(double x, double* sn, double* cs) {
   double r = __builtin_fma(-k, kPio2A, x);
   r = __builtin_fma(-k, kPio2B, r);
   const double z = r * r;
-  double ps = 1.5918135932869774e-10;
-  ps = __builtin_fma(ps, z, -2.5051131947374594e-08);
-  ps = __builtin_fma(ps, z, 2.7557316103105014e-06);
-  ps = __builtin_fma(ps, z, -0.0001984126983675979);
-  ps = __builtin_fma(ps, z, 0.00833333333333095);
-  ps = __builtin_fma(ps, z, -0.16666666666666666);
+  double ps = __builtin_fma(1.5918135932869774e-10, z, -2.5051131947374594e-08);
+  ps = fma_sc(ps, z, 2.7557316103105014e-06);
+  ps = fma_sc(ps, z, -0.0001984126983675979);
+  ps = fma_sc(ps, z, 0.00833333333333095);
+  ps = fma_sc(ps, z, -0.16666666666666666);
   const double s_r = __builtin_fma(r * z, ps, r);
-  double pc = -1.1382636115964061e-11;
-  pc = __builtin_fma(pc, z, 2.087614632531677e-09);
-  pc = __builtin_fma(pc, z, -2.7557317272036996e-07);
-  pc = __builtin_fma(pc, z, 2.4801587298766363e-05);
-  pc = __builtin_fma(pc, z, -0.0013888888888887398);
-  pc = __builtin_fma(pc, z, 0.041666666666666664);
+  double pc = __builtin_fma(-1.1382636115964061e-11, z, 2.087614632531677e-09);
+  pc = fma_sc(pc, z, -2.7557317272036996e-07);
+  pc = fma_sc(pc, z, 2.4801587298766363e-05);
+  pc = fma_sc(pc, z, -0.0013888888888887398);
+  pc = fma_sc(pc, z, 0.041666666666666664);
   const double c_r = __builtin_fma(z * z, pc, __builtin_fma(-0.5, z, 1.0));
   const int q = ((int)k) & 3;
   const double s1 = (q & 1) ? c_r : s_r;

@@ -27,6 +27,9 @@ constexpr double kPi = 3.141592653589793116;
 // [k_lo, k_hi] the bins whose frequency lies in [min, max](g_a, g_b).
 // rate = (seg_b - seg_a + 1) / (g_b - g_a) gives a first guess of the
 // segment holding a frequency (the search that follows does not depend on it).
+// whole = 1 when the piece runs from the first knot of the trajectory to the
+// last (no turning point or zero crossing): then its end values are the knot
+// values, bit for bit.
 struct alignas(64) Piece {
   double tau_a, tau_b;
   double g_a, g_b;
@@ -34,7 +37,7 @@ struct alignas(64) Piece {
   int32_t k_lo, k_hi;
   int32_t s, d;
   float rate;
-  int32_t pad1;
+  int32_t whole;
 };
 static_assert(sizeof(Piece) == 64, "Piece layout");
 
@@ -146,6 +149,22 @@ __device__ __forceinline__ double knot_freq(double m, double fphi, double n, dou
 // m x + n y with one fused multiply-add in a fixed order, so that the
 // forward and adjoint kernels form identical mode-weighted coefficients.
 __device__ __forceinline__ double wsum(double m, double x, double n, double y) { return __builtin_fma(m, x, n * y); }
+
+// a b + c for a constant c, as one three-operand FP64 fused multiply-add
+// reading c from a scalar register pair.  Written out because the compiler
+// otherwise keeps such constants in vector registers, hoisted out of the
+// loops, and copies one into the destination before every two-operand
+// multiply-add of a Horner step: an extra vector instruction per step and
+// two vector registers held per constant.
+__device__ __forceinline__ double fma_sc(double a, double b, double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+#else
+  return __builtin_fma(a, b, c);
+#endif
+}
 
 // Reciprocal and reciprocal square root from the hardware estimates refined
 // by Newton-Raphson steps (one step: for iterations that correct themselves;

@@ -287,7 +287,9 @@ template <bool MIXED, int BPL, int WAVES>
 __device__ __forceinline__ void process_block(const Prepared& p, const float* __restrict__ acoef32, void* hp,
                                               void* hc, int kb, const Lds& L, int* list) {
   constexpr int CHUNK = 64 * kModesPerLane;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index is uniform: taken into a scalar register, it makes the
+  // tile bounds and every test against them scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int Nf = p.Nf;
   const int kbe = min(kb + block_bins<BPL, WAVES>() - 1, Nf - 1);
   int* wcount = list + kListCap;

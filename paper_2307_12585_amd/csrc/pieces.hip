@@ -274,7 +274,7 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
       P.s = s;
       P.d = s * dV;
       P.rate = (float)((double)(P.seg_b - P.seg_a + 1) / (P.g_b - P.g_a));
-      P.pad1 = 0;
+      P.whole = (n_all == 1) ? 1 : 0;  // lane 0 from the first knot to the final event
       const double glo = fmin(P.g_a, P.g_b), ghi = fmax(P.g_a, P.g_b);
       int klo = first_ge(a.f, a.Nf, glo);
       if (klo < kpos) klo = kpos;

@@ -69,6 +69,25 @@ __device__ __forceinline__ float2 q_cheb32(float y) {
   return make_float2(x * b1r - b2r + cr[0], x * b1i - b2i + ci[0]);
 }
 
+// Even and odd parts of the large-argument series in v = u^2: the sums over
+// j <= J of (-1)^j a_{2j} v^j and (-1)^j a_{2j+1} v^j (Horner, highest term
+// first).
+template <int J>
+__device__ __forceinline__ double asym_even(double v) {
+  double s = (J & 1) ? -fdw_asym64[2 * J] : fdw_asym64[2 * J];
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j) s = fma_sc(s, v, (j & 1) ? -fdw_asym64[2 * j] : fdw_asym64[2 * j]);
+  return s;
+}
+
+template <int J>
+__device__ __forceinline__ double asym_odd(double v) {
+  double s = (J & 1) ? -fdw_asym64[2 * J + 1] : fdw_asym64[2 * J + 1];
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j) s = fma_sc(s, v, (j & 1) ? -fdw_asym64[2 * j + 1] : fdw_asym64[2 * j + 1]);
+  return s;
+}
+
 // G in FP64.  dir = direction of the piece (used only when gd == 0).
 // |gd|^{-1/2} is formed once (refined hardware estimate) and also gives
 // |u| = |1/X| = 3 gdd^2 / (2 pi |gd|^3) through its sixth power.  |u| <= 1/X_B
@@ -92,28 +111,16 @@ __device__ __forceinline__ double2 spa_factor64(double gd, double gdd, int dir) 
     // |u| (u = 1/X carries the sign sg of gd); then
     // G = c (1 - i sg) W = c (re + im) + i sg c (im - re).
     const double v = au * au;
-    double re = 0.0, im = 0.0;
+    double re, im;
     if (__all(au <= 1e-5)) {
-#pragma unroll
-      for (int j = 1; j >= 0; --j) {
-        const double sgn = (j & 1) ? -1.0 : 1.0;
-        re = re * v + sgn * fdw_asym64[2 * j];
-        im = im * v + sgn * fdw_asym64[2 * j + 1];
-      }
+      re = asym_even<1>(v);
+      im = asym_odd<1>(v);
     } else if (__all(au <= 1e-3)) {
-#pragma unroll
-      for (int j = 3; j >= 0; --j) {
-        const double sgn = (j & 1) ? -1.0 : 1.0;
-        re = re * v + sgn * fdw_asym64[2 * j];
-        im = im * v + sgn * fdw_asym64[2 * j + 1];
-      }
+      re = asym_even<3>(v);
+      im = asym_odd<3>(v);
     } else {
-#pragma unroll
-      for (int j = (FDW_NASYM64 - 1) / 2; j >= 0; --j) {
-        const double sgn = (j & 1) ? -1.0 : 1.0;
-        re = re * v + sgn * fdw_asym64[2 * j];
-        if (2 * j + 1 < FDW_NASYM64) im = im * v + sgn * fdw_asym64[2 * j + 1];
-      }
+      re = asym_even<(FDW_NASYM64 - 1) / 2>(v);
+      im = asym_odd<(FDW_NASYM64 - 2) / 2>(v);
     }
     im *= au;
     const double c = kRsqrt2 * rs;
