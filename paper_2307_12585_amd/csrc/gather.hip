@@ -25,9 +25,13 @@
 
 namespace fdemri {
 
+// amp: the amplitude spline coefficients the path reads, [Nm][K-1][8]: the
+// FP64 ones (p.acoef) or, on the mixed path, the FP32 normalised-u ones.  A
+// field of its own, so that the kernel does not keep the whole table of
+// trajectory pointers in registers for it.
 struct GatherArgs {
   Prepared p;
-  const float* acoef32;  // [Nm][K-1][8] normalised-u amplitude coefficients (mixed path)
+  const void* amp;
   void* hp;
   void* hc;
 };
@@ -238,7 +242,7 @@ __device__ __forceinline__ void write_list(int* list, uint32_t hits, int wbase, 
 // read through the constant address space, so that their wave-uniform
 // records come in by scalar loads.
 template <bool MIXED>
-__device__ __forceinline__ void walk_list(const Prepared& p, const float* __restrict__ acoef32, const int* list, int n,
+__device__ __forceinline__ void walk_list(const Prepared& p, const void* __restrict__ amp, const int* list, int n,
                                           int ks, int ke, double f, double w, const Lds& L, Acc<MIXED>& acc) {
   const int lane = threadIdx.x & 63;
   const int k = ks + lane;
@@ -261,8 +265,8 @@ __device__ __forceinline__ void walk_list(const Prepared& p, const float* __rest
         const double ms = neg ? -md.m : md.m, ns = neg ? -md.n : md.n;
         const double2 cP = make_double2(md.cp_re, neg ? -md.cp_im : md.cp_im);
         const double2 cX = make_double2(md.cx_re, neg ? -md.cx_im : md.cx_im);
-        const double* ac = p.acoef + (size_t)mode * nseg * 8;
-        const float* ac32 = MIXED ? acoef32 + (size_t)mode * nseg * 8 : nullptr;
+        const double* ac = MIXED ? nullptr : (const double*)amp + (size_t)mode * nseg * 8;
+        const float* ac32 = MIXED ? (const float*)amp + (size_t)mode * nseg * 8 : nullptr;
         eval_bin<MIXED>(f, w, P, ms, ns, (double)P.d, (double)(P.seg_b - P.seg_a), (double)P.rate, cP, cX, ac, ac32,
                         L, acc);
       }
@@ -284,7 +288,7 @@ __device__ __forceinline__ void walk_list(const Prepared& p, const float* __rest
 // does not depend on scheduling, on the block shape or on the tile size.
 // list: LDS of kListCap + 8 ints.
 template <bool MIXED, int BPL, int WAVES>
-__device__ __forceinline__ void process_block(const Prepared& p, const float* __restrict__ acoef32, void* hp,
+__device__ __forceinline__ void process_block(const Prepared& p, const void* __restrict__ amp, void* hp,
                                               void* hc, int kb, const Lds& L, int* list) {
   constexpr int CHUNK = 64 * kModesPerLane;
   // the wave index is uniform: taken into a scalar register, it makes the
@@ -348,7 +352,7 @@ __device__ __forceinline__ void process_block(const Prepared& p, const float* __
     Acc<MIXED> acc;
     acc.zero();
     if (single) {
-      if (ks <= ke) walk_list<MIXED>(p, acoef32, list, total, ks, ke, f, w, L, acc);
+      if (ks <= ke) walk_list<MIXED>(p, amp, list, total, ks, ke, f, w, L, acc);
     } else {
       // many active modes: rebuild the list window by window (every wave
       // takes part in every rebuild)
@@ -358,7 +362,7 @@ __device__ __forceinline__ void process_block(const Prepared& p, const float* __
           if (c0 > 0) __syncthreads();  // the previous window has been consumed
           write_list(list, hits, wbase, off, c0);
           __syncthreads();
-          if (ks <= ke) walk_list<MIXED>(p, acoef32, list, min(kListCap, total - c0), ks, ke, f, w, L, acc);
+          if (ks <= ke) walk_list<MIXED>(p, amp, list, min(kListCap, total - c0), ks, ke, f, w, L, acc);
         }
       }
     }
@@ -406,7 +410,7 @@ __global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_
   int* list = (int*)lds;
   const Lds L = stage_lds(p, lds + kHeadDoubles);
   __syncthreads();
-  process_block<MIXED, BPL, WAVES>(p, a.acoef32, a.hp, a.hc, kb, L, list);
+  process_block<MIXED, BPL, WAVES>(p, a.amp, a.hp, a.hc, kb, L, list);
 }
 
 // Persistent gather over a batch: every workgroup repeatedly takes the next
@@ -455,7 +459,7 @@ __global__ __launch_bounds__(64 * WAVES, gather_batch_min_waves<MIXED>()) void g
       __syncthreads();
       cached = lo;
     }
-    process_block<MIXED, BPL, WAVES>(p, w.acoef32, w.hp, w.hc, kb, L, list);
+    process_block<MIXED, BPL, WAVES>(p, MIXED ? (const void*)w.acoef32 : (const void*)w.acoef, w.hp, w.hc, kb, L, list);
   }
 }
 
@@ -543,7 +547,7 @@ hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp,
                               hipStream_t stream) {
   GatherArgs a;
   a.p = p;
-  a.acoef32 = acoef32;
+  a.amp = mixed ? (const void*)acoef32 : (const void*)p.acoef;
   a.hp = hp;
   a.hc = hc;
   return launch_gather(a, mixed, bpl, stream);
