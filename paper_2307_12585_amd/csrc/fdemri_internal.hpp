@@ -25,21 +25,23 @@ constexpr double kPi = 3.141592653589793116;
 // direction d in t.  It starts at tau_a inside spline segment seg_a and ends
 // at tau_b inside segment seg_b; g_a, g_b are |F_V| at the two ends, and
 // [k_lo, k_hi] the bins whose frequency lies in [min, max](g_a, g_b).
-// rate = (seg_b - seg_a + 1) / (g_b - g_a) gives a first guess of the
-// segment holding a frequency (the search that follows does not depend on it).
-// whole = 1 when the piece runs from the first knot of the trajectory to the
-// last (no turning point or zero crossing): then its end values are the knot
-// values, bit for bit.
-struct alignas(64) Piece {
+// rate f + rate0, with rate = (seg_b - seg_a + 1) / (g_b - g_a) and
+// rate0 = seg_a - rate g_a, gives a first guess of the segment holding a
+// frequency f (the search that follows does not depend on it); dd and sd are
+// d and s as doubles.  whole = 1 when the piece runs from the first knot of the
+// trajectory to the last (no turning point or zero crossing): then its end
+// values are the knot values, bit for bit.
+struct alignas(32) Piece {
   double tau_a, tau_b;
   double g_a, g_b;
+  double rate, rate0;
+  double dd, sd;
   int32_t seg_a, seg_b;
   int32_t k_lo, k_hi;
   int32_t s, d;
-  float rate;
-  int32_t whole;
+  int32_t whole, pad;
 };
-static_assert(sizeof(Piece) == 64, "Piece layout");
+static_assert(sizeof(Piece) == 96, "Piece layout");
 
 // Per-mode constants: mode numbers as doubles and the fused polarization
 // factors c_+ and c_x (scale and spin-weighted harmonics folded in).
@@ -163,6 +165,19 @@ __device__ __forceinline__ double fma_sc(double a, double b, double c) {
   return r;
 #else
   return __builtin_fma(a, b, c);
+#endif
+}
+
+// x converted to int32 with the hardware's saturating conversion (out-of-range
+// values go to the nearest end of the range, NaN to 0), without the undefined
+// behaviour of a C++ conversion of such values.
+__device__ __forceinline__ int cvt_i32_sat(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  int r;
+  asm("v_cvt_i32_f64 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+#else
+  return (int)x;
 #endif
 }
 

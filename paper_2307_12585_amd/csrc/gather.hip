@@ -63,20 +63,36 @@ struct Acc<true> {
 
 // LDS copy of one waveform's trajectory tables, interleaved so that one base
 // address per index reaches every field by immediate offsets: per knot i
-// {F_phi, F_r, t, Phi_phi mod 2 pi, Phi_r mod 2 pi} (48 B, 16-B aligned
-// pairs), per segment i the c1..c3 spline coefficients of F_phi, F_r,
-// Phi_phi, Phi_r (96 B).
+// {F_phi, F_r, t, Phi_phi mod 2 pi, Phi_r mod 2 pi, h = t_{i+1} - t_i}
+// (48 B, 16-B aligned pairs), per segment i the c1..c3 spline coefficients of
+// F_phi, F_r, Phi_phi, Phi_r (96 B).
 struct alignas(16) KnotRec {
-  double Fp, Fr, t, Pp, Pr, pad;
+  double Fp, Fr, t, Pp, Pr, h;
 };
 struct alignas(16) SegCoef {
   double cFp[3], cFr[3], cPp[3], cPr[3];
 };
 static_assert(sizeof(KnotRec) == 48 && sizeof(SegCoef) == 96, "LDS record layout");
 
+// LDS address space for the device pass (the host pass has none).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define klds __attribute__((address_space(3)))
+#else
+#define klds
+#endif
+
+// The tables as LDS pointers, so that addresses are 32-bit; a record's
+// address is formed with a 24-bit multiply-add (indices stay below 2^24),
+// which runs at full rate where a 32- or 64-bit integer multiply does not.
 struct Lds {
-  const KnotRec* kn;  // [K]
-  const SegCoef* sc;  // [K-1]
+  const klds KnotRec* kn;  // [K]
+  const klds SegCoef* sc;  // [K-1]
+  __device__ __forceinline__ const klds KnotRec& knot(int i) const {
+    return *(const klds KnotRec*)((const klds char*)kn + __umul24(i, (int)sizeof(KnotRec)));
+  }
+  __device__ __forceinline__ const klds SegCoef& seg(int i) const {
+    return *(const klds SegCoef*)((const klds char*)sc + __umul24(i, (int)sizeof(SegCoef)));
+  }
 };
 
 // One (bin, piece) evaluation.  The spline segment holding f is the largest i
@@ -87,57 +103,64 @@ struct Lds {
 // definition; the rare misses walk to the right segment.
 //   f, w: the bin frequency and 2 pi f;
 //   ms, ns: s m and s n of the piece, so that |F_V| = ms F_phi + ns F_r;
-//   dd_, span, rate: d, seg_b - seg_a and the rate of the piece;
 //   cP, cX: c_+ and c_x, conjugated when s < 0, so that the contribution is
 //   cP (A^(s) E) and cX (A^(s) E), A^(s) being A conjugated when s < 0.
 template <bool MIXED>
 __device__ __forceinline__ void eval_bin(const double f, const double w, const Piece& P, const double ms, const double ns,
-                                         const double dd_, const double span, const double rate, const double2 cP,
-                                         const double2 cX, const double* __restrict__ ac,
+                                         const double2 cP, const double2 cX, const double* __restrict__ ac,
                                          const float* __restrict__ ac32, const Lds& L, Acc<MIXED>& acc) {
+  const double dd_ = P.dd;
   const double fd = dd_ * f;
-  int i = P.seg_a + (int)fmin(fmax((f - P.g_a) * rate, 0.0), span);
-  double G0 = knot_freq(ms, L.kn[i].Fp, ns, L.kn[i].Fr);
-  double G1 = knot_freq(ms, L.kn[i + 1].Fp, ns, L.kn[i + 1].Fr);
+  // the conversion saturates (and takes NaN to 0); the clamp keeps the guess
+  // inside the piece
+  int i = min(max(cvt_i32_sat(__builtin_fma(f, P.rate, P.rate0)), P.seg_a), P.seg_b);
+  double G0 = knot_freq(ms, L.knot(i).Fp, ns, L.knot(i).Fr);
+  double G1 = knot_freq(ms, L.knot(i + 1).Fp, ns, L.knot(i + 1).Fr);
   {
     const float num = (float)(f - G0);
     const float den = (float)(G1 - G0);
     float di = 0.f;
-    if (den != 0.f) di = fminf(fmaxf(floorf(num * __builtin_amdgcn_rcpf(den)), -(float)span), (float)span);
+    // the step is bounded by the largest segment count, which keeps i + di
+    // inside the int range
+    constexpr float kStepMax = (float)kMaxKnots;
+    if (den != 0.f) di = fminf(fmaxf(floorf(num * __builtin_amdgcn_rcpf(den)), -kStepMax), kStepMax);
     const int j = min(max(i + (int)di, P.seg_a), P.seg_b);
     if (j != i) {
       i = j;
-      G0 = knot_freq(ms, L.kn[i].Fp, ns, L.kn[i].Fr);
-      G1 = knot_freq(ms, L.kn[i + 1].Fp, ns, L.kn[i + 1].Fr);
+      G0 = knot_freq(ms, L.knot(i).Fp, ns, L.knot(i).Fr);
+      G1 = knot_freq(ms, L.knot(i + 1).Fp, ns, L.knot(i + 1).Fr);
     }
   }
   if ((i > P.seg_a && !(dd_ * G0 < fd)) || (i < P.seg_b && dd_ * G1 < fd)) {
-    while (i > P.seg_a && !(dd_ * knot_freq(ms, L.kn[i].Fp, ns, L.kn[i].Fr) < fd)) --i;
-    while (i < P.seg_b && dd_ * knot_freq(ms, L.kn[i + 1].Fp, ns, L.kn[i + 1].Fr) < fd) ++i;
-    G0 = knot_freq(ms, L.kn[i].Fp, ns, L.kn[i].Fr);
-    G1 = knot_freq(ms, L.kn[i + 1].Fp, ns, L.kn[i + 1].Fr);
+    while (i > P.seg_a && !(dd_ * knot_freq(ms, L.knot(i).Fp, ns, L.knot(i).Fr) < fd)) --i;
+    while (i < P.seg_b && dd_ * knot_freq(ms, L.knot(i + 1).Fp, ns, L.knot(i + 1).Fr) < fd) ++i;
+    G0 = knot_freq(ms, L.knot(i).Fp, ns, L.knot(i).Fr);
+    G1 = knot_freq(ms, L.knot(i + 1).Fp, ns, L.knot(i + 1).Fr);
   }
   SegData S;
-  S.ti = L.kn[i].t;
-  S.h = L.kn[i + 1].t - S.ti;
+  const klds KnotRec& kr = L.knot(i);
+  S.ti = kr.t;
+  S.h = kr.h;
   S.G0 = G0;
   S.G1 = G1;
-  const SegCoef& cs = L.sc[i];
+  const klds SegCoef& cs = L.seg(i);
   S.q1 = wsum(ms, cs.cFp[0], ns, cs.cFr[0]);
   S.q2 = wsum(ms, cs.cFp[1], ns, cs.cFr[1]);
   S.q3 = wsum(ms, cs.cFp[2], ns, cs.cFr[2]);
   S.r1 = wsum(ms, cs.cPp[0], ns, cs.cPr[0]);
   S.r2 = wsum(ms, cs.cPp[1], ns, cs.cPr[1]);
   S.r3 = wsum(ms, cs.cPp[2], ns, cs.cPr[2]);
-  S.Ppi = L.kn[i].Pp;
-  S.Pri = L.kn[i].Pr;
+  S.Ppi = kr.Pp;
+  S.Pri = kr.Pr;
   const Bracket B = make_bracket(P, i, S);
   const double tau = solve_root(f, dd_, S, B);
 
   if constexpr (!MIXED) {
     double2 E, A;
-    root_terms64(f, w, tau, P.d, ms, ns, S, ac + (size_t)i * 8, E, A);
-    const double ay = P.s < 0 ? -A.y : A.y;
+    // 32-bit byte offset from the mode's (wave-uniform) base: one shift
+    const double* acs = (const double*)((const char*)ac + ((uint32_t)i << 6));
+    root_terms64(f, w, tau, P.d, ms, ns, S, acs, E, A);
+    const double ay = A.y * P.sd;  // A conjugated on s < 0 pieces
     const double Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
     acc.v[0] += cP.x * Wr - cP.y * Wi;
     acc.v[1] += cP.x * Wi + cP.y * Wr;
@@ -145,8 +168,9 @@ __device__ __forceinline__ void eval_bin(const double f, const double w, const P
     acc.v[3] += cX.x * Wi + cX.y * Wr;
   } else {
     float2 E, A;
-    root_terms32(f, w, tau, P.d, ms, ns, S, ac32 + (size_t)i * 8, E, A);
-    const float ay = P.s < 0 ? -A.y : A.y;
+    const float* acs = (const float*)((const char*)ac32 + ((uint32_t)i << 5));
+    root_terms32(f, w, tau, P.d, ms, ns, S, acs, E, A);
+    const float ay = A.y * (float)P.sd;
     const float Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
     const float pr = (float)cP.x, pi = (float)cP.y, xr = (float)cX.x, xi = (float)cX.y;
     acc.add(0, pr * Wr - pi * Wi);
@@ -169,7 +193,7 @@ __device__ __forceinline__ Lds stage_lds(const Prepared& p, double* lds) {
     r.t = p.t[i];
     r.Pp = reduce_2pi(p.Phiphi[i]);
     r.Pr = reduce_2pi(p.Phir[i]);
-    r.pad = 0.0;
+    r.h = (i + 1 < K) ? p.t[i + 1] - p.t[i] : 0.0;
     kn[i] = r;
   }
   for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
@@ -183,7 +207,7 @@ __device__ __forceinline__ Lds stage_lds(const Prepared& p, double* lds) {
     }
     sc[i] = c;
   }
-  return Lds{kn, sc};
+  return Lds{(const klds KnotRec*)kn, (const klds SegCoef*)sc};
 }
 
 // Active-mode list of a block: at most kListCap mode indices at a time, in
@@ -267,8 +291,7 @@ __device__ __forceinline__ void walk_list(const Prepared& p, const void* __restr
         const double2 cX = make_double2(md.cx_re, neg ? -md.cx_im : md.cx_im);
         const double* ac = MIXED ? nullptr : (const double*)amp + (size_t)mode * nseg * 8;
         const float* ac32 = MIXED ? (const float*)amp + (size_t)mode * nseg * 8 : nullptr;
-        eval_bin<MIXED>(f, w, P, ms, ns, (double)P.d, (double)(P.seg_b - P.seg_a), (double)P.rate, cP, cX, ac, ac32,
-                        L, acc);
+        eval_bin<MIXED>(f, w, P, ms, ns, cP, cX, ac, ac32, L, acc);
       }
     }
   }

@@ -273,8 +273,12 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
       P.g_b = s * eb.F;
       P.s = s;
       P.d = s * dV;
-      P.rate = (float)((double)(P.seg_b - P.seg_a + 1) / (P.g_b - P.g_a));
+      P.rate = (double)(P.seg_b - P.seg_a + 1) / (P.g_b - P.g_a);
+      P.rate0 = (double)P.seg_a - P.rate * P.g_a;
+      P.dd = (double)P.d;
+      P.sd = (double)P.s;
       P.whole = (n_all == 1) ? 1 : 0;  // lane 0 from the first knot to the final event
+      P.pad = 0;
       const double glo = fmin(P.g_a, P.g_b), ghi = fmax(P.g_a, P.g_b);
       int klo = first_ge(a.f, a.Nf, glo);
       if (klo < kpos) klo = kpos;

@@ -100,16 +100,17 @@ __device__ __forceinline__ double2 spa_factor64(double gd, double gdd, int dir) 
   constexpr double kRsqrt2 = 0.70710678118654752440;
   constexpr double k3Over2Pi = 0.47746482927568600730;
   constexpr double k2PiOver3 = 2.0943951023931954923;
-  if (gd == 0.0 && gdd == 0.0) return make_double2(0.0, 0.0);
   const double agd = fabs(gd);
-  const int sg = gd > 0.0 ? 1 : (gd < 0.0 ? -1 : dir);
   const double rs = rsq_nr2(agd);
   const double rs2 = rs * rs;
-  const double au = (gdd == 0.0) ? 0.0 : k3Over2Pi * gdd * gdd * (rs2 * rs2 * rs2);
+  // gdd = 0 gives |u| = 0, the standard SPA, with no special case; gd = 0
+  // leaves no finite |u| and takes the Airy form
+  const double au = k3Over2Pi * gdd * gdd * (rs2 * rs2 * rs2);
   if (gd != 0.0 && au <= 1.0 / FDW_X_B) {
     // W = re + i sg im with re, im the even and odd parts of the series in
     // |u| (u = 1/X carries the sign sg of gd); then
-    // G = c (1 - i sg) W = c (re + im) + i sg c (im - re).
+    // G = c (1 - i sg) W = c (re + im) + i sg c (im - re), the factor sg
+    // applied by giving c the sign of gd.
     const double v = au * au;
     double re, im;
     if (__all(au <= 1e-5)) {
@@ -124,9 +125,16 @@ __device__ __forceinline__ double2 spa_factor64(double gd, double gdd, int dir) 
     }
     im *= au;
     const double c = kRsqrt2 * rs;
-    const double gi = c * (im - re);
-    return make_double2(c * (re + im), sg > 0 ? gi : -gi);
+    return make_double2(c * (re + im), __builtin_copysign(c, gd) * (im - re));
   }
+  if (gdd == 0.0) {
+    // reached only when |u| above could not be formed (gd = 0, or |gd| so
+    // small that rs^6 overflows): W = 1, or no contribution when gd = 0 too
+    if (gd == 0.0) return make_double2(0.0, 0.0);
+    const double c = kRsqrt2 * rs;
+    return make_double2(c, -__builtin_copysign(c, gd));
+  }
+  const int sg = gd > 0.0 ? 1 : (gd < 0.0 ? -1 : dir);
   const double ax = k2PiOver3 * agd * agd * agd * rcp_nr2(gdd * gdd);  // |X|
   const double y = cbrt(1.5 * ax);
   double2 q = q_cheb64(y);
@@ -142,10 +150,8 @@ __device__ __forceinline__ float2 spa_factor32(double gd, double gdd, int dir) {
   constexpr float kRsqrt2 = 0.70710678118654752440f;
   constexpr double k3Over2Pi = 0.47746482927568600730;
   constexpr double k2PiOver3 = 2.0943951023931954923;
-  if (gd == 0.0 && gdd == 0.0) return make_float2(0.f, 0.f);
   const double agd = fabs(gd);
-  const int sg = gd > 0.0 ? 1 : (gd < 0.0 ? -1 : dir);
-  const double au = (gdd == 0.0) ? 0.0 : k3Over2Pi * gdd * gdd * rcp_nr1(agd * agd * agd);
+  const double au = k3Over2Pi * gdd * gdd * rcp_nr1(agd * agd * agd);
   if (gd != 0.0 && au <= 1.0 / FDW_X_B) {
     const float uf = (float)au;
     const float v = uf * uf;
@@ -158,9 +164,15 @@ __device__ __forceinline__ float2 spa_factor32(double gd, double gdd, int dir) {
     }
     im *= uf;
     const float c = kRsqrt2 * rsqrtf((float)agd);
-    const float gi = c * (im - re);
-    return make_float2(c * (re + im), sg > 0 ? gi : -gi);
+    return make_float2(c * (re + im), __builtin_copysignf(c, (float)gd) * (im - re));
   }
+  if (gdd == 0.0) {
+    // as in the FP64 factor: W = 1, or nothing when gd = 0 too
+    if (gd == 0.0) return make_float2(0.f, 0.f);
+    const float c = (float)(kRsqrt2 * rsq_nr2(agd));
+    return make_float2(c, -__builtin_copysignf(c, (float)gd));
+  }
+  const int sg = gd > 0.0 ? 1 : (gd < 0.0 ? -1 : dir);
   const float y = cbrtf((float)(1.5 * k2PiOver3 * agd * agd * agd * rcp_nr2(gdd * gdd)));
   float2 q = q_cheb32(y);
   if (sg < 0) q.y = -q.y;
