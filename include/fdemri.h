@@ -53,7 +53,7 @@ typedef enum {
 typedef enum {
   FDEMRI_FP64 = 0,     /* everything in FP64; output complex128 (2 x double per bin) */
   FDEMRI_MIXED = 1     /* FP64 root, phase and range reduction; FP32 special function,
-                          sincos, amplitude spline and compensated accumulation;
+                          sincos and amplitude spline, contributions summed in FP64;
                           output complex64 (2 x float per bin) */
 } fdemri_prec;
 

@@ -197,7 +197,7 @@ __device__ __forceinline__ void root_terms32(double f, double w, double tau, int
   float sn, cs;
   sincosf((float)psr, &sn, &cs);
   E = make_float2(cs * G.x - sn * G.y, cs * G.y + sn * G.x);
-  const float u = (float)(tau / S.h);
+  const float u = (float)tau * __builtin_amdgcn_rcpf((float)S.h);  // tau / h to FP32 accuracy
   const float* c = ac32_seg;
   A = make_float2(c[0] + u * (c[2] + u * (c[4] + u * c[6])), c[1] + u * (c[3] + u * (c[5] + u * c[7])));
 }

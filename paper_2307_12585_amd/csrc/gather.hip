@@ -20,7 +20,8 @@
 //   3. the wave stores its tile.
 // FP64 path: everything in double.  Mixed path: root, derivatives, phase and
 // its reduction in double; the special function, sincos, amplitude spline and
-// products in float with compensated (Kahan) accumulation.
+// products in float, each contribution added to a double accumulator (fewer
+// instructions than compensated float sums, at least as accurate).
 #include "evalcore.hpp"
 
 namespace fdemri {
@@ -47,18 +48,9 @@ struct Acc<false> {
 
 template <>
 struct Acc<true> {
-  float v[4], c[4];
-  __device__ __forceinline__ void zero() {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = c[q] = 0.f;
-  }
-  __device__ __forceinline__ void add(int q, float y) {
-    // compensated (Kahan) summation
-    const float yy = y - c[q];
-    const float tt = v[q] + yy;
-    c[q] = (tt - v[q]) - yy;
-    v[q] = tt;
-  }
+  double v[4];
+  __device__ __forceinline__ void zero() { v[0] = v[1] = v[2] = v[3] = 0.0; }
+  __device__ __forceinline__ void add(int q, float y) { v[q] += (double)y; }
 };
 
 // LDS copy of one waveform's trajectory tables, interleaved so that one base
@@ -393,7 +385,7 @@ __device__ __forceinline__ void process_block(const Prepared& p, const void* __r
       if constexpr (MIXED) {
         float v[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] = (float)((double)acc.v[c] - (double)acc.c[c]);
+        for (int c = 0; c < 4; ++c) v[c] = (float)acc.v[c];
         ((float2*)hp)[k] = make_float2(v[0], v[1]);
         ((float2*)hc)[k] = make_float2(v[2], v[3]);
       } else {
