@@ -185,6 +185,36 @@ fdemri_status fdemri_vjp(fdemri_ctx *ctx, const fdemri_waveform_desc *desc, fdem
                          double *gA_knots, double *gPhi_knots, double *g_scalars,
                          hipStream_t stream);
 
+/* flags of fdemri_loglike */
+#define FDEMRI_LL_HANN 0x1u  /* compare the data with the model convolved with the
+                                3-tap Hann kernel h_w(f_k) = h(f_k)/2 - h(f_{k+1})/4
+                                - h(f_{k-1})/4 (the frequency-domain form of a Hann
+                                window on the DFT grid; h = 0 past the last bin and
+                                h(f_{-1}) = conj h(f_1) before the first) */
+
+/*
+ * Whittle log-likelihood of data against the waveform of `desc` (Eq. likelihood
+ * with the inner product of Eq. innerprod), with the mode sum fused: the
+ * model is reduced bin by bin where it is formed and never written to memory.
+ *   d_p, d_c : [Nf] complex data per channel (interleaved re, im) of the
+ *              precision's type (double for FDEMRI_FP64, float for FDEMRI_MIXED).
+ *   wS       : [Nf] double, the weight of each bin in the inner product,
+ *              4 w_k / S_n(f_k) with w_k the quadrature weight of the grid
+ *              (1/T on the DFT grid); 0 excludes a bin (the DC bin, f = 0,
+ *              is outside the sum of Eq. innerprod).
+ *   ll_flags : FDEMRI_LL_* flags.
+ *   out      : [3] double, DEVICE: out[0] = log L = -1/2 sum_{+,x} sum_k wS_k
+ *              |d_k - h_k|^2, out[1] = sum wS |h|^2 (<h|h> summed over the two
+ *              channels), out[2] = sum wS Re(conj(d) h) (<d|h>), with h the
+ *              (windowed) model; on the mixed path the model is rounded to FP32
+ *              first, as fdemri_waveform would store it, and the sums are FP64.
+ * The result is deterministic (fixed reduction order, no atomics).  Errors as
+ * fdemri_waveform; FDEMRI_EINVAL for NULL data, weights or output.
+ */
+fdemri_status fdemri_loglike(fdemri_ctx *ctx, const fdemri_waveform_desc *desc, fdemri_prec prec,
+                             const void *d_p, const void *d_c, const double *wS, uint32_t ll_flags,
+                             double *out, hipStream_t stream);
+
 /*
  * Autotuner of the gather's block shape (1, 2 or 4 consecutive 64-bin tiles
  * per wavefront, i.e. 256, 512 or 1024 contiguous bins per 4-wave workgroup

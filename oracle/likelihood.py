@@ -6,6 +6,10 @@ trapezoid weights of the grid are used (the continuous integral of
 Eq. innerprod).  The DC bin (f = 0) is excluded.
 
 Eq. likelihood:  log p = -1/2 sum_{alpha=+,x} <d - h | d - h>_alpha.
+
+fused_sums gives the three sums of the fused likelihood (fdemri_loglike) by
+their definitions, with the per-bin weight wS_k = 4 w_k / S(f_k) taken as an
+input.
 """
 from __future__ import annotations
 
@@ -39,3 +43,23 @@ def inner_product(a, b, S, w):
 def whittle_loglike(d, h, S, w):
     """d, h: (h_plus, h_cross) pairs."""
     return -0.5 * sum(inner_product(di - hi, di - hi, S, w) for di, hi in zip(d, h))
+
+
+def fused_sums(d, h, wS, hann=False):
+    """(log L, <h|h>, <d|h>) over the two channels for data d = (d_+, d_x) and
+    model h = (h_+, h_x), each bin weighted by wS:
+        log L = -1/2 sum_alpha sum_k wS_k |d_k - g_k|^2,
+        <h|h> = sum_alpha sum_k wS_k |g_k|^2,
+        <d|h> = sum_alpha sum_k wS_k Re(conj(d_k) g_k),
+    with g = fd_hann(h) (the frequency-domain Hann window of the DFT grid)
+    when hann, else g = h."""
+    from .td import fd_hann
+    wS = np.asarray(wS, np.float64)
+    ll = hh = dh = 0.0
+    for da, ha in zip(d, h):
+        g = fd_hann(np.asarray(ha, np.complex128)) if hann else np.asarray(ha, np.complex128)
+        da = np.asarray(da, np.complex128)
+        ll += -0.5 * float(np.sum(wS * np.abs(da - g) ** 2))
+        hh += float(np.sum(wS * np.abs(g) ** 2))
+        dh += float(np.sum(wS * np.real(np.conj(da) * g)))
+    return ll, hh, dh

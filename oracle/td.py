@@ -55,7 +55,8 @@ def fd_hann(h):
     out = 0.5 * h.copy()
     out[:-1] -= 0.25 * h[1:]
     out[1:] -= 0.25 * h[:-1]
-    out[0] -= 0.25 * np.conj(h[1])
+    if h.size > 1:  # a one-bin grid: its missing neighbour is zero, as at the last bin
+        out[0] -= 0.25 * np.conj(h[1])
     return out
 
 

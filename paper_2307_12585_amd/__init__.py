@@ -27,12 +27,13 @@ FDEMRI_COEFFS_GIVEN = 0x2
 FDEMRI_CTX_BATCH_GRAPHS = 0x1
 FDEMRI_FLAG_PIECE_OVERFLOW = 0x1
 FDEMRI_FLAG_BAD_MODE = 0x2
+FDEMRI_LL_HANN = 0x1
 PRECISIONS = {"fp64": FDEMRI_FP64, "mixed": FDEMRI_MIXED}
 
 EXPORTED = [
     "fdemri_create", "fdemri_destroy", "fdemri_last_error", "fdemri_sync_flags",
     "fdemri_waveform", "fdemri_waveform_batch", "fdemri_vjp", "fdemri_last_eval_count",
-    "fdemri_profile_enable", "fdemri_profile_read", "fdemri_autotune",
+    "fdemri_profile_enable", "fdemri_profile_read", "fdemri_autotune", "fdemri_loglike",
 ]
 KERNEL_CLASSES = ["spline", "pieces", "gather", "vjp"]
 
@@ -85,6 +86,8 @@ def lib():
         L.fdemri_waveform_batch.restype = ctypes.c_int
         L.fdemri_vjp.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
         L.fdemri_vjp.restype = ctypes.c_int
+        L.fdemri_loglike.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_int, vp, vp, vp, u32, vp, vp]
+        L.fdemri_loglike.restype = ctypes.c_int
         L.fdemri_last_eval_count.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
         L.fdemri_last_eval_count.restype = ctypes.c_int
         L.fdemri_autotune.argtypes = [vp, i32, ctypes.POINTER(WaveformDesc), ctypes.c_int,
@@ -236,6 +239,23 @@ class Context:
         dw = DeviceWaveform(t, Fphi, Fr, Phiphi, Phir, l, m, n, A, theta, phi, scale, f,
                             partners=partners, device=self.device)
         return self.waveform_dev(dw, prec)
+
+    def loglike_dev(self, dw: DeviceWaveform, d_p, d_c, wS, prec="fp64", hann=False, out=None):
+        """Whittle log-likelihood with the mode sum fused (fdemri_loglike):
+        returns a float64 device tensor (log L, <h|h>, <d|h>) for data d_p, d_c
+        ([Nf] complex of the precision's type) and per-bin weights
+        wS = 4 w_k / S_n(f_k) ([Nf] float64)."""
+        p = PRECISIONS[prec]
+        ctype = torch.complex128 if p == FDEMRI_FP64 else torch.complex64
+        assert d_p.dtype == ctype and d_c.dtype == ctype and wS.dtype == torch.float64
+        assert d_p.numel() == dw.Nf and d_c.numel() == dw.Nf and wS.numel() == dw.Nf
+        assert d_p.is_contiguous() and d_c.is_contiguous() and wS.is_contiguous()
+        if out is None:
+            out = torch.empty(3, dtype=torch.float64, device=dw.device)
+        d = dw.desc()
+        self._check(self._lib.fdemri_loglike(self._h, ctypes.byref(d), p, _ptr(d_p), _ptr(d_c), _ptr(wS),
+                                             FDEMRI_LL_HANN if hann else 0, _ptr(out), _stream(self.device)))
+        return out
 
     def vjp_dev(self, dw: DeviceWaveform, g_hp, g_hc, prec="fp64", coef=True, knots=True):
         """Gradients of a real loss from the cotangents g = dL/dRe h + i dL/dIm h.

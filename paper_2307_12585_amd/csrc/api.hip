@@ -37,6 +37,11 @@ hipError_t launch_amp32_batch(const WaveItem* items, int B, const int32_t* amp_p
 hipError_t launch_gather_batch(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
                                int* counter, int Kmax, bool mixed, int bpl, hipStream_t stream);
 int gather_items_per_waveform(int Nf, int bpl);
+int loglike_tiles(int Nf, int bpl);
+size_t loglike_partial_doubles(int Nf, int bpl);
+hipError_t launch_loglike(const Prepared& p, const float* acoef32, bool mixed, int bpl, const void* d_p,
+                          const void* d_c, const double* wS, int hann, double* partial, double* edge, double* out,
+                          hipStream_t stream);
 hipError_t launch_vjp(const Prepared& p, const float* acoef32, bool mixed, const void* g_hp, const void* g_hc,
                       double* gA_coef, double* PZ, double* Upart, double* T3, double* gPhi_coef,
                       double* g_scalars, const int32_t* l, const int32_t* m, double theta, double phi, double scale,
@@ -109,10 +114,13 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
   size_t tcoef, acoef, acoef32, modes, mode_kr, pieces, evals, env;
   size_t gA, PZ, Upart, T3, gPhi, gsc;  // adjoint scratch (0 bytes unless requested)
+  size_t ll_partial, ll_edge;           // likelihood scratch (0 bytes unless requested)
   size_t total;
 };
 
-Layout layout_for(int K, int Nm, bool mixed, bool vjp = false) {
+// ll_tiles, ll_partial: tiles of the likelihood gather and doubles of its
+// partial sums (0: no likelihood scratch).
+Layout layout_for(int K, int Nm, bool mixed, bool vjp = false, int ll_tiles = 0, size_t ll_partial = 0) {
   Layout L{};
   size_t off = 0;
   const size_t nseg = (size_t)K - 1;
@@ -136,6 +144,8 @@ Layout layout_for(int K, int Nm, bool mixed, bool vjp = false) {
   L.T3 = take(vjp ? (size_t)Nm * 4 * sizeof(double) : 0);
   L.gPhi = take(vjp ? 2 * nseg * 4 * sizeof(double) : 0);
   L.gsc = take(vjp ? 8 * sizeof(double) : 0);
+  L.ll_partial = take(ll_partial * sizeof(double));
+  L.ll_edge = take((size_t)ll_tiles * 16 * sizeof(double));
   L.total = off;
   return L;
 }
@@ -393,6 +403,36 @@ fdemri_status fdemri_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, fdem
     e = launch_gather_flat(p, acoef32, hp, hc, mixed, c->bpl, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "gather kernel launch");
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_loglike(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemri_prec prec, const void* d_p,
+                             const void* d_c, const double* wS, uint32_t ll_flags, double* out, hipStream_t stream) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  fdemri_status st = validate(c, d);
+  if (st != FDEMRI_OK) return st;
+  if (prec != FDEMRI_FP64 && prec != FDEMRI_MIXED) return fail(c, FDEMRI_EINVAL, "unknown precision %d", (int)prec);
+  if (!d_p || !d_c || !wS || !out) return fail(c, FDEMRI_EINVAL, "NULL data, weight or output pointer");
+  if (ll_flags & ~FDEMRI_LL_HANN) return fail(c, FDEMRI_EINVAL, "unknown likelihood flags 0x%x", ll_flags);
+  const bool mixed = prec == FDEMRI_MIXED;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const int bpl = c->tuning ? c->bpl : choose_bpl(c, (int)prec, false, d->Nf);
+  const Layout L = layout_for(d->K, d->Nm, mixed, false, loglike_tiles(d->Nf, bpl), loglike_partial_doubles(d->Nf, bpl));
+  st = ensure_ws(c, L.total);
+  if (st != FDEMRI_OK) return st;
+  Prepared p;
+  float* acoef32 = nullptr;
+  st = prepare(c, d, mixed, L, p, acoef32, stream);
+  if (st != FDEMRI_OK) return st;
+  char* w = c->ws;
+  {
+    ProfScope ps(c, FDEMRI_KERNEL_GATHER, stream);
+    e = launch_loglike(p, acoef32, mixed, bpl, d_p, d_c, wS, (ll_flags & FDEMRI_LL_HANN) ? 1 : 0,
+                       (double*)(w + L.ll_partial), (double*)(w + L.ll_edge), out, stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "likelihood kernel launch");
   return FDEMRI_OK;
 }
 

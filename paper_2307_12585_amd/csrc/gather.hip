@@ -26,6 +26,25 @@
 
 namespace fdemri {
 
+// Destination of the sums of a tile: the waveform (h_+, h_x per bin, complex128
+// or complex64) or the partial sums of the Whittle log-likelihood
+// (Eqs. likelihood and innerprod) against data d_p, d_c (same element type as
+// the waveform) with per-bin weights wS = 4 w_k / S_n(f_k): per tile,
+// partial[3] = (sum wS |d - h|^2, sum wS |h|^2, sum wS Re(conj(d) h)) over
+// both channels and, with the 3-tap Hann kernel (hann != 0), the model at
+// lanes 0, 1, 62 and 63 in edge[4][4], from which the terms of each tile's
+// first and last bin are completed afterwards.
+struct Sink {
+  void* hp;
+  void* hc;
+  const void* d_p;
+  const void* d_c;
+  const double* wS;
+  double* partial;
+  double* edge;
+  int hann;
+};
+
 // amp: the amplitude spline coefficients the path reads, [Nm][K-1][8]: the
 // FP64 ones (p.acoef) or, on the mixed path, the FP32 normalised-u ones.  A
 // field of its own, so that the kernel does not keep the whole table of
@@ -33,8 +52,7 @@ namespace fdemri {
 struct GatherArgs {
   Prepared p;
   const void* amp;
-  void* hp;
-  void* hc;
+  Sink out;
 };
 
 template <bool MIXED>
@@ -289,6 +307,99 @@ __device__ __forceinline__ void walk_list(const Prepared& p, const void* __restr
   }
 }
 
+// Likelihood terms of bin k for the model values hw (h_+ re, im, h_x re, im)
+// added to t: wS |d - hw|^2, wS |hw|^2 and wS Re(conj(d) hw), summed over the
+// two channels.
+template <bool MIXED>
+__device__ __forceinline__ void ll_terms(const Sink& o, int k, const double hw[4], double t[3]) {
+  double d[4];
+  if constexpr (MIXED) {
+    const float2 a = ((const float2*)o.d_p)[k], b = ((const float2*)o.d_c)[k];
+    d[0] = a.x;
+    d[1] = a.y;
+    d[2] = b.x;
+    d[3] = b.y;
+  } else {
+    const double2 a = ((const double2*)o.d_p)[k], b = ((const double2*)o.d_c)[k];
+    d[0] = a.x;
+    d[1] = a.y;
+    d[2] = b.x;
+    d[3] = b.y;
+  }
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double e = d[c] - hw[c];
+    s1 = __builtin_fma(e, e, s1);
+    s2 = __builtin_fma(hw[c], hw[c], s2);
+    s3 = __builtin_fma(d[c], hw[c], s3);
+  }
+  const double ws = o.wS[k];
+  t[0] = __builtin_fma(ws, s1, t[0]);
+  t[1] = __builtin_fma(ws, s2, t[1]);
+  t[2] = __builtin_fma(ws, s3, t[2]);
+}
+
+// Hands the sums of one 64-bin tile (global tile index `tile`, this lane's
+// bin k) to the sink: stores them, or forms the lane's likelihood terms, sums
+// them over the wave (fixed butterfly order) and writes the tile's partials.
+// With the Hann kernel, h_w(f_k) = h_k / 2 - (h_{k-1} + h_{k+1}) / 4 takes
+// the neighbours from the adjacent lanes; lanes 0 and 63 leave their terms to
+// the finishing kernel, which has the neighbouring tiles' edge records.  On
+// the mixed path the model is rounded to FP32 first, as the stored waveform
+// would be.
+template <bool MIXED, bool LL>
+__device__ __forceinline__ void emit(const Sink& o, int tile, int k, int Nf, const Acc<MIXED>& acc) {
+  if constexpr (!LL) {
+    if (k < Nf) {
+      if constexpr (MIXED) {
+        float v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = (float)acc.v[c];
+        ((float2*)o.hp)[k] = make_float2(v[0], v[1]);
+        ((float2*)o.hc)[k] = make_float2(v[2], v[3]);
+      } else {
+        ((double2*)o.hp)[k] = make_double2(acc.v[0], acc.v[1]);
+        ((double2*)o.hc)[k] = make_double2(acc.v[2], acc.v[3]);
+      }
+    }
+  } else {
+    const int lane = threadIdx.x & 63;
+    const bool in = k < Nf;
+    double h[4], hw[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) h[c] = in ? (MIXED ? (double)(float)acc.v[c] : (double)acc.v[c]) : 0.0;
+    if (o.hann) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double lft = __shfl_up(h[c], 1, 64), rgt = __shfl_down(h[c], 1, 64);
+        hw[c] = 0.5 * h[c] - 0.25 * (lft + rgt);
+      }
+      if (lane < 2 || lane >= 62) {
+        double* e = o.edge + ((size_t)tile * 4 + (lane < 2 ? lane : lane - 60)) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) e[c] = h[c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) hw[c] = h[c];
+    }
+    double t[3] = {0.0, 0.0, 0.0};
+    if (in && !(o.hann && (lane == 0 || lane == 63))) ll_terms<MIXED>(o, k, hw, t);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) t[q] += __shfl_xor(t[q], off, 64);
+    }
+    if (lane == 0) {
+      double* q = o.partial + (size_t)tile * 3;
+      q[0] = t[0];
+      q[1] = t[1];
+      q[2] = t[2];
+    }
+  }
+}
+
 // One workgroup's block of WAVES * BPL * 64 contiguous bins starting at kb;
 // wave w owns the BPL tiles [kb + 64 (w BPL + j), + 64).
 //  1. The workgroup lists the modes whose bin range meets the block: wave w
@@ -302,9 +413,9 @@ __device__ __forceinline__ void walk_list(const Prepared& p, const void* __restr
 // The sum of every bin is taken by one lane in a fixed order, so the result
 // does not depend on scheduling, on the block shape or on the tile size.
 // list: LDS of kListCap + 8 ints.
-template <bool MIXED, int BPL, int WAVES>
-__device__ __forceinline__ void process_block(const Prepared& p, const void* __restrict__ amp, void* hp,
-                                              void* hc, int kb, const Lds& L, int* list) {
+template <bool MIXED, int BPL, int WAVES, bool LL>
+__device__ __forceinline__ void process_block(const Prepared& p, const void* __restrict__ amp, const Sink& out,
+                                              int kb, const Lds& L, int* list) {
   constexpr int CHUNK = 64 * kModesPerLane;
   // the wave index is uniform: taken into a scalar register, it makes the
   // tile bounds and every test against them scalar
@@ -381,18 +492,7 @@ __device__ __forceinline__ void process_block(const Prepared& p, const void* __r
         }
       }
     }
-    if (k < Nf) {
-      if constexpr (MIXED) {
-        float v[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] = (float)acc.v[c];
-        ((float2*)hp)[k] = make_float2(v[0], v[1]);
-        ((float2*)hc)[k] = make_float2(v[2], v[3]);
-      } else {
-        ((double2*)hp)[k] = make_double2(acc.v[0], acc.v[1]);
-        ((double2*)hc)[k] = make_double2(acc.v[2], acc.v[3]);
-      }
-    }
+    emit<MIXED, LL>(out, ks >> 6, k, Nf, acc);
   }
 }
 
@@ -411,21 +511,117 @@ constexpr int gather_batch_min_waves() {
   return MIXED ? 4 : 3;
 }
 
-template <bool MIXED, int BPL, int WAVES>
+// LL = false: the waveform; LL = true: the likelihood partials (Sink).
+template <bool MIXED, int BPL, int WAVES, bool LL>
 __global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_kernel(GatherArgs a) {
   extern __shared__ __align__(16) double lds[];
   const Prepared& p = a.p;
   const int kb = (int)blockIdx.x * block_bins<BPL, WAVES>();
   const int kbe = kb + block_bins<BPL, WAVES>() - 1;
-  // blocks outside the bin envelope of all modes only write zeros
+  // blocks outside the bin envelope of all modes hold a zero model
   if (kbe < p.env[0] || kb > p.env[1]) {
-    zero_block<MIXED, BPL, WAVES>(a.hp, a.hc, p.Nf, kb);
+    if constexpr (LL) {
+      const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+      Acc<MIXED> z;
+      z.zero();
+#pragma unroll 1
+      for (int j = 0; j < BPL; ++j) {
+        const int ks = kb + (wave * BPL + j) * 64;
+        emit<MIXED, true>(a.out, ks >> 6, ks + (int)(threadIdx.x & 63), p.Nf, z);
+      }
+    } else {
+      zero_block<MIXED, BPL, WAVES>(a.out.hp, a.out.hc, p.Nf, kb);
+    }
     return;
   }
   int* list = (int*)lds;
   const Lds L = stage_lds(p, lds + kHeadDoubles);
   __syncthreads();
-  process_block<MIXED, BPL, WAVES>(p, a.amp, a.hp, a.hc, kb, L, list);
+  process_block<MIXED, BPL, WAVES, LL>(p, a.amp, a.out, kb, L, list);
+}
+
+// Completes the likelihood of one waveform from the gather's per-tile
+// partials, in two fixed-order stages.  Stage 1, one thread per tile: the
+// tile's partials and, with the Hann kernel, the terms of its first and last
+// bin, whose neighbours come from the edge records of the tile and of the
+// tiles beside it (outside the grid the model is zero; below the first bin of
+// the grid h(-f_1) = conj h(f_1), the transform of a real series); then a
+// tree over the workgroup, one triple per workgroup in block_sums.  Stage 2
+// (one workgroup) adds the workgroups' triples in order:
+// out = (-1/2 sum wS |d - h_w|^2, sum wS |h_w|^2, sum wS Re(conj(d) h_w)).
+constexpr int kLLThreads = 256;
+
+template <bool MIXED>
+__global__ __launch_bounds__(kLLThreads) void loglike_tiles_kernel(Sink o, int Nf, double* block_sums) {
+  __shared__ double red[3][kLLThreads];
+  const int ntiles = (Nf + 63) / 64;
+  const int i = (int)blockIdx.x * kLLThreads + (int)threadIdx.x;
+  double t[3] = {0.0, 0.0, 0.0};
+  if (i < ntiles) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) t[q] = o.partial[(size_t)i * 3 + q];
+    if (o.hann) {
+      const double* e = o.edge + (size_t)i * 16;  // lanes 0, 1, 62, 63 of tile i
+      double hw[4];
+      const int k0 = 64 * i;
+      const double* prv = o.edge + (size_t)(i > 0 ? i - 1 : 0) * 16 + 12;  // lane 63 of tile i - 1
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double hm = (i > 0) ? prv[c] : ((c & 1) ? -e[4 + c] : e[4 + c]);
+        hw[c] = 0.5 * e[c] - 0.25 * (hm + e[4 + c]);
+      }
+      ll_terms<MIXED>(o, k0, hw, t);
+      const int k1 = 64 * i + 63;
+      if (k1 < Nf) {
+        const double* nxt = o.edge + (size_t)(i + 1 < ntiles ? i + 1 : i) * 16;  // lane 0 of tile i + 1
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double hp1 = (i + 1 < ntiles) ? nxt[c] : 0.0;
+          hw[c] = 0.5 * e[12 + c] - 0.25 * (e[8 + c] + hp1);
+        }
+        ll_terms<MIXED>(o, k1, hw, t);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = t[q];
+  __syncthreads();
+  for (int w = kLLThreads / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) block_sums[(size_t)blockIdx.x * 3 + q] = red[q][0];
+  }
+}
+
+__global__ __launch_bounds__(kLLThreads) void loglike_total_kernel(const double* block_sums, int nblocks,
+                                                                   double* out) {
+  __shared__ double red[3][kLLThreads];
+  double t[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += kLLThreads) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) t[q] += block_sums[(size_t)b * 3 + q];
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = t[q];
+  __syncthreads();
+  for (int w = kLLThreads / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = -0.5 * red[0][0];
+    out[1] = red[1][0];
+    out[2] = red[2][0];
+  }
 }
 
 // Persistent gather over a batch: every workgroup repeatedly takes the next
@@ -469,12 +665,16 @@ __global__ __launch_bounds__(64 * WAVES, gather_batch_min_waves<MIXED>()) void g
       zero_block<MIXED, BPL, WAVES>(w.hp, w.hc, p.Nf, kb);
       continue;
     }
+    Sink out{};
+    out.hp = w.hp;
+    out.hc = w.hc;
     if (lo != cached) {
       L = stage_lds(p, tables);
       __syncthreads();
       cached = lo;
     }
-    process_block<MIXED, BPL, WAVES>(p, MIXED ? (const void*)w.acoef32 : (const void*)w.acoef, w.hp, w.hc, kb, L, list);
+    process_block<MIXED, BPL, WAVES, false>(p, MIXED ? (const void*)w.acoef32 : (const void*)w.acoef, out, kb, L,
+                                           list);
   }
 }
 
@@ -531,7 +731,7 @@ __global__ void amp32_batch_kernel(const WaveItem* __restrict__ items, int B, co
 
 size_t gather_lds_bytes(int K) { return (size_t)K * sizeof(KnotRec) + (size_t)(K - 1) * sizeof(SegCoef); }
 
-template <bool MIXED, int BPL, int WAVES>
+template <bool MIXED, int BPL, int WAVES, bool LL>
 static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t stream) {
   constexpr int per_block = block_bins<BPL, WAVES>();
   const long blocks = ((long)a.p.Nf + per_block - 1) / per_block;
@@ -539,33 +739,74 @@ static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t stream) {
   const size_t lds = gather_lds_bytes(a.p.K) + red;
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)gather_kernel<MIXED, BPL, WAVES>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(gather_lds_bytes(kMaxKnots) + red));
+    (void)hipFuncSetAttribute((const void*)gather_kernel<MIXED, BPL, WAVES, LL>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(gather_lds_bytes(kMaxKnots) + red));
     attr_set = true;
   }
-  gather_kernel<MIXED, BPL, WAVES><<<dim3((unsigned)blocks), dim3(64 * WAVES), lds, stream>>>(a);
+  gather_kernel<MIXED, BPL, WAVES, LL><<<dim3((unsigned)blocks), dim3(64 * WAVES), lds, stream>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const GatherArgs& a, bool mixed, int bpl, hipStream_t stream) {
+template <bool LL>
+static hipError_t launch_gather(const GatherArgs& a, bool mixed, int bpl, hipStream_t stream) {
   if (mixed) {
-    if (bpl == 1) return launch_gather_t<true, 1, 4>(a, stream);
-    if (bpl == 2) return launch_gather_t<true, 2, 4>(a, stream);
-    return launch_gather_t<true, 4, 4>(a, stream);
+    if (bpl == 1) return launch_gather_t<true, 1, 4, LL>(a, stream);
+    if (bpl == 2) return launch_gather_t<true, 2, 4, LL>(a, stream);
+    return launch_gather_t<true, 4, 4, LL>(a, stream);
   }
-  if (bpl == 1) return launch_gather_t<false, 1, 4>(a, stream);
-  if (bpl == 2) return launch_gather_t<false, 2, 4>(a, stream);
-  return launch_gather_t<false, 4, 4>(a, stream);
+  if (bpl == 1) return launch_gather_t<false, 1, 4, LL>(a, stream);
+  if (bpl == 2) return launch_gather_t<false, 2, 4, LL>(a, stream);
+  return launch_gather_t<false, 4, 4, LL>(a, stream);
 }
 
 hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp, void* hc, bool mixed, int bpl,
                               hipStream_t stream) {
-  GatherArgs a;
+  GatherArgs a{};
   a.p = p;
   a.amp = mixed ? (const void*)acoef32 : (const void*)p.acoef;
-  a.hp = hp;
-  a.hc = hc;
-  return launch_gather(a, mixed, bpl, stream);
+  a.out.hp = hp;
+  a.out.hc = hc;
+  return launch_gather<false>(a, mixed, bpl, stream);
+}
+
+// Tiles of the gather grid for Nf bins (every tile of every block, also those
+// past the last bin): the size of the likelihood partial and edge arrays; the
+// workgroup triples of the first reduction stage follow the partials.
+int loglike_tiles(int Nf, int bpl) {
+  const int per_block = 64 * bpl * 4;
+  return (Nf + per_block - 1) / per_block * bpl * 4;
+}
+
+static int loglike_reduce_blocks(int Nf) { return ((Nf + 63) / 64 + kLLThreads - 1) / kLLThreads; }
+
+// Doubles of likelihood scratch before the edge records: partials, then the
+// triples of the first reduction stage.
+size_t loglike_partial_doubles(int Nf, int bpl) {
+  return (size_t)loglike_tiles(Nf, bpl) * 3 + (size_t)loglike_reduce_blocks(Nf) * 3;
+}
+
+hipError_t launch_loglike(const Prepared& p, const float* acoef32, bool mixed, int bpl, const void* d_p,
+                          const void* d_c, const double* wS, int hann, double* partial, double* edge, double* out,
+                          hipStream_t stream) {
+  GatherArgs a{};
+  a.p = p;
+  a.amp = mixed ? (const void*)acoef32 : (const void*)p.acoef;
+  a.out.d_p = d_p;
+  a.out.d_c = d_c;
+  a.out.wS = wS;
+  a.out.partial = partial;
+  a.out.edge = edge;
+  a.out.hann = hann;
+  hipError_t e = launch_gather<true>(a, mixed, bpl, stream);
+  if (e != hipSuccess) return e;
+  const int nb = loglike_reduce_blocks(p.Nf);
+  double* block_sums = partial + (size_t)loglike_tiles(p.Nf, bpl) * 3;
+  if (mixed)
+    loglike_tiles_kernel<true><<<nb, kLLThreads, 0, stream>>>(a.out, p.Nf, block_sums);
+  else
+    loglike_tiles_kernel<false><<<nb, kLLThreads, 0, stream>>>(a.out, p.Nf, block_sums);
+  loglike_total_kernel<<<1, kLLThreads, 0, stream>>>(block_sums, nb, out);
+  return hipGetLastError();
 }
 
 template <bool MIXED, int BPL, int WAVES>
