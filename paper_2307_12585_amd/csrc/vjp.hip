@@ -37,35 +37,82 @@ struct VjpArgs {
   double* Upart;  // [Nm][nseg][4]  partial U_+ (re, im), U_x (re, im)
 };
 
+// Sum over the wave of 16 per-lane values by halving exchanges: at each of the
+// lane offsets 32, 16, 8 and 4 a lane keeps the half of its values selected
+// by that lane bit and adds the partner's copy of the same half, so that lane
+// L ends with a partial of value (L >> 2) over 16 lanes; two butterfly steps
+// complete it.  Returns in every lane the total of value L >> 2 (fixed order:
+// deterministic).  About a third of the exchanges of 16 full butterflies.
+__device__ __forceinline__ double wave_sum16(const double v[16]) {
+  const int lane = threadIdx.x & 63;
+  double a8[8], a4[4], a2[2];
+  {
+    const bool hi = (lane & 32) != 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double keep = hi ? v[j + 8] : v[j], send = hi ? v[j] : v[j + 8];
+      a8[j] = keep + __shfl_xor(send, 32, 64);
+    }
+  }
+  {
+    const bool hi = (lane & 16) != 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double keep = hi ? a8[j + 4] : a8[j], send = hi ? a8[j] : a8[j + 4];
+      a4[j] = keep + __shfl_xor(send, 16, 64);
+    }
+  }
+  {
+    const bool hi = (lane & 8) != 0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double keep = hi ? a4[j + 2] : a4[j], send = hi ? a4[j] : a4[j + 2];
+      a2[j] = keep + __shfl_xor(send, 8, 64);
+    }
+  }
+  const bool hi = (lane & 4) != 0;
+  double a1 = (hi ? a2[1] : a2[0]) + __shfl_xor(hi ? a2[0] : a2[1], 4, 64);
+  a1 += __shfl_xor(a1, 2, 64);
+  a1 += __shfl_xor(a1, 1, 64);
+  return a1;
+}
+
 template <bool MIXED>
 __global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
   const Prepared& p = a.p;
   const int nseg = p.K - 1;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index is uniform; in a scalar register it makes the unit, and
+  // every load indexed by it, scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const long unit = (long)blockIdx.x * 4 + wave;
   if (unit >= (long)p.Nm * nseg) return;
   const int mu = (int)(unit / nseg), i = (int)(unit % nseg);
-  const ModeConst md = p.modes[mu];
+  const ModeConst md = ((const kconst ModeConst*)p.modes)[mu];
   const double m = md.m, n = md.n;
 
   double acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
 
-  // segment data of this unit (wave-uniform)
-  const double ti = p.t[i], h = p.t[i + 1] - ti;
-  const double F0 = knot_freq(m, p.Fphi[i], n, p.Fr[i]);
-  const double F1 = knot_freq(m, p.Fphi[i + 1], n, p.Fr[i + 1]);
-  const double* cFp = p.tcoef + ((size_t)0 * nseg + i) * 4;
-  const double* cFr = p.tcoef + ((size_t)1 * nseg + i) * 4;
-  const double* cPp = p.tcoef + ((size_t)2 * nseg + i) * 4;
-  const double* cPr = p.tcoef + ((size_t)3 * nseg + i) * 4;
+  // segment data of this unit (wave-uniform; read-only tables through the
+  // constant address space, so scalar loads)
+  const kconst double* kt = (const kconst double*)p.t;
+  const kconst double* kFp = (const kconst double*)p.Fphi;
+  const kconst double* kFr = (const kconst double*)p.Fr;
+  const double ti = kt[i], h = kt[i + 1] - ti;
+  const double F0 = knot_freq(m, kFp[i], n, kFr[i]);
+  const double F1 = knot_freq(m, kFp[i + 1], n, kFr[i + 1]);
+  const kconst double* cFp = (const kconst double*)p.tcoef + ((size_t)0 * nseg + i) * 4;
+  const kconst double* cFr = (const kconst double*)p.tcoef + ((size_t)1 * nseg + i) * 4;
+  const kconst double* cPp = (const kconst double*)p.tcoef + ((size_t)2 * nseg + i) * 4;
+  const kconst double* cPr = (const kconst double*)p.tcoef + ((size_t)3 * nseg + i) * 4;
   const double* acs = p.acoef + ((size_t)mu * nseg + i) * 8;
   const float* acs32 = MIXED ? a.acoef32 + ((size_t)mu * nseg + i) * 8 : nullptr;
-  const double Ppr = reduce_2pi(p.Phiphi[i]), Prr = reduce_2pi(p.Phir[i]);
+  const double Ppr = reduce_2pi(((const kconst double*)p.Phiphi)[i]);
+  const double Prr = reduce_2pi(((const kconst double*)p.Phir)[i]);
 
   for (int q = 0; q < md.npieces; ++q) {
-    const Piece P = p.pieces[(size_t)mu * kMaxPieces + q];
+    const Piece P = ((const kconst Piece*)p.pieces)[(size_t)mu * kMaxPieces + q];
     if (i < P.seg_a || i > P.seg_b || P.k_lo > P.k_hi) continue;
     const int s = P.s, d = P.d;
     const double sd = (double)s, dd_ = (double)d;
@@ -189,26 +236,17 @@ __global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
       acc[15] += uxi;
     }
   }
-  // wave reduction (fixed butterfly order)
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    double v = acc[q];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    acc[q] = v;
-  }
-  if (lane == 0) {
-    if (a.gA) {
-      double* o = a.gA + ((size_t)mu * nseg + i) * 8;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) o[q] = acc[q];
-    }
-    double* z = a.PZ + ((size_t)mu * nseg + i) * 4;
-    double* u = a.Upart + ((size_t)mu * nseg + i) * 4;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      z[q] = acc[8 + q];
-      u[q] = acc[12 + q];
+  // wave reduction: lane 4 q holds the total of value q
+  const double tot = wave_sum16(acc);
+  if ((lane & 3) == 0) {
+    const int q = lane >> 2;
+    const size_t u = (size_t)mu * nseg + i;
+    if (q < 8) {
+      if (a.gA) a.gA[u * 8 + q] = tot;
+    } else if (q < 12) {
+      a.PZ[u * 4 + (q - 8)] = tot;
+    } else {
+      a.Upart[u * 4 + (q - 12)] = tot;
     }
   }
 }
