@@ -216,6 +216,22 @@ fdemri_status fdemri_loglike(fdemri_ctx *ctx, const fdemri_waveform_desc *desc, 
                              double *out, hipStream_t stream);
 
 /*
+ * fdemri_loglike for B waveforms in one persistent launch (the batch path of
+ * fdemri_waveform_batch with the model reduced where it is formed, so that
+ * no waveform of the batch is written to memory).
+ *   descs          : HOST array of B descriptors.
+ *   d_p, d_c, wS   : HOST arrays of B device pointers (data and weights per
+ *                    waveform, as for fdemri_loglike).
+ *   out            : [B][3] double, DEVICE.
+ * Each out[b] equals fdemri_loglike of waveform b with the same precision and
+ * flags, bit for bit.  Not captured into graphs (enqueued eagerly).
+ */
+fdemri_status fdemri_loglike_batch(fdemri_ctx *ctx, int32_t B, const fdemri_waveform_desc *descs,
+                                   fdemri_prec prec, const void *const *d_p, const void *const *d_c,
+                                   const double *const *wS, uint32_t ll_flags, double *out,
+                                   hipStream_t stream);
+
+/*
  * Autotuner of the gather's block shape (1, 2 or 4 consecutive 64-bin tiles
  * per wavefront, i.e. 256, 512 or 1024 contiguous bins per 4-wave workgroup
  * sharing one active-mode list; the result does not depend on the choice,

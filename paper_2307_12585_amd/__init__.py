@@ -34,6 +34,7 @@ EXPORTED = [
     "fdemri_create", "fdemri_destroy", "fdemri_last_error", "fdemri_sync_flags",
     "fdemri_waveform", "fdemri_waveform_batch", "fdemri_vjp", "fdemri_last_eval_count",
     "fdemri_profile_enable", "fdemri_profile_read", "fdemri_autotune", "fdemri_loglike",
+    "fdemri_loglike_batch",
 ]
 KERNEL_CLASSES = ["spline", "pieces", "gather", "vjp"]
 
@@ -88,6 +89,9 @@ def lib():
         L.fdemri_vjp.restype = ctypes.c_int
         L.fdemri_loglike.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_int, vp, vp, vp, u32, vp, vp]
         L.fdemri_loglike.restype = ctypes.c_int
+        L.fdemri_loglike_batch.argtypes = [vp, i32, ctypes.POINTER(WaveformDesc), ctypes.c_int,
+                                           ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), u32, vp, vp]
+        L.fdemri_loglike_batch.restype = ctypes.c_int
         L.fdemri_last_eval_count.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
         L.fdemri_last_eval_count.restype = ctypes.c_int
         L.fdemri_autotune.argtypes = [vp, i32, ctypes.POINTER(WaveformDesc), ctypes.c_int,
@@ -255,6 +259,25 @@ class Context:
         d = dw.desc()
         self._check(self._lib.fdemri_loglike(self._h, ctypes.byref(d), p, _ptr(d_p), _ptr(d_c), _ptr(wS),
                                              FDEMRI_LL_HANN if hann else 0, _ptr(out), _stream(self.device)))
+        return out
+
+    def loglike_batch(self, dws, ds_p, ds_c, wSs, prec="fp64", hann=False, out=None):
+        """fdemri_loglike_batch: a [B, 3] float64 device tensor of (log L,
+        <h|h>, <d|h>) per waveform, for lists of data and weight tensors."""
+        p = PRECISIONS[prec]
+        ctype = torch.complex128 if p == FDEMRI_FP64 else torch.complex64
+        B = len(dws)
+        for dw, a, b, w in zip(dws, ds_p, ds_c, wSs):
+            assert a.dtype == ctype and b.dtype == ctype and w.dtype == torch.float64
+            assert a.numel() == dw.Nf and b.numel() == dw.Nf and w.numel() == dw.Nf
+            assert a.is_contiguous() and b.is_contiguous() and w.is_contiguous()
+        if out is None:
+            out = torch.empty(B, 3, dtype=torch.float64, device=dws[0].device)
+        descs = (WaveformDesc * B)(*[d.desc() for d in dws])
+        arr = lambda ts: (ctypes.c_void_p * B)(*[t.data_ptr() for t in ts])
+        self._check(self._lib.fdemri_loglike_batch(self._h, B, descs, p, arr(ds_p), arr(ds_c), arr(wSs),
+                                                   FDEMRI_LL_HANN if hann else 0, _ptr(out),
+                                                   _stream(self.device)))
         return out
 
     def vjp_dev(self, dw: DeviceWaveform, g_hp, g_hc, prec="fp64", coef=True, knots=True):

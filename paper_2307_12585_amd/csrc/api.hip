@@ -39,6 +39,10 @@ hipError_t launch_gather_batch(const WaveItem* items, int B, const int32_t* item
 int gather_items_per_waveform(int Nf, int bpl);
 int loglike_tiles(int Nf, int bpl);
 size_t loglike_partial_doubles(int Nf, int bpl);
+int loglike_batch_reduce_blocks(int Nf_max);
+hipError_t launch_loglike_batch(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
+                                int* counter, int Kmax, bool mixed, int bpl, int hann, int Nf_max,
+                                double* block_sums, double* out, hipStream_t stream);
 hipError_t launch_loglike(const Prepared& p, const float* acoef32, bool mixed, int bpl, const void* d_p,
                           const void* d_c, const double* wS, int hann, double* partial, double* edge, double* out,
                           hipStream_t stream);
@@ -495,18 +499,22 @@ namespace {
 
 // Host-side plan of one batch: per-waveform scratch layouts in the workspace
 // and the offsets of the device records, prefixes and work counter.
+// With ll set the batch computes the fused likelihood: per-waveform partial
+// and edge scratch in the layouts, and the stage-1 triples (B x nbmax x 3
+// doubles) at ll_off.
 struct BatchPlan {
-  bool mixed = false;
-  int B = 0, Kmax = 0;
+  bool mixed = false, ll = false;
+  int B = 0, Kmax = 0, Nf_max = 0, nbmax = 0;
   int64_t n_series = 0, n_modes = 0, n_amp = 0, n_items = 0;
   std::vector<Layout> Ls;
   std::vector<size_t> base;
-  size_t items_off = 0, pref_off = 0, pref_bytes = 0, counter_off = 0, total = 0, record_bytes = 0;
+  size_t items_off = 0, pref_off = 0, pref_bytes = 0, counter_off = 0, ll_off = 0, total = 0, record_bytes = 0;
 };
 
 fdemri_status plan_batch(fdemri_ctx* c, int B, const fdemri_waveform_desc* descs, bool mixed, void* const* hp,
-                         void* const* hc, BatchPlan& P) {
+                         void* const* hc, BatchPlan& P, bool ll = false) {
   P.mixed = mixed;
+  P.ll = ll;
   P.B = B;
   P.Ls.resize(B);
   P.base.resize(B);
@@ -514,8 +522,11 @@ fdemri_status plan_batch(fdemri_ctx* c, int B, const fdemri_waveform_desc* descs
   for (int b = 0; b < B; ++b) {
     fdemri_status st = validate(c, &descs[b]);
     if (st != FDEMRI_OK) return fail(c, st, "waveform %d: %s", b, c->err.c_str());
-    if (!hp[b] || !hc[b]) return fail(c, FDEMRI_EINVAL, "waveform %d: NULL output pointer", b);
-    P.Ls[b] = layout_for(descs[b].K, descs[b].Nm, mixed);
+    if (!ll && (!hp[b] || !hc[b])) return fail(c, FDEMRI_EINVAL, "waveform %d: NULL output pointer", b);
+    P.Ls[b] = ll ? layout_for(descs[b].K, descs[b].Nm, mixed, false, loglike_tiles(descs[b].Nf, c->bpl),
+                              loglike_partial_doubles(descs[b].Nf, c->bpl))
+                 : layout_for(descs[b].K, descs[b].Nm, mixed);
+    P.Nf_max = std::max(P.Nf_max, (int)descs[b].Nf);
     P.base[b] = off;
     off = align_up(off + P.Ls[b].total, 256);
     P.Kmax = std::max(P.Kmax, (int)descs[b].K);
@@ -530,14 +541,18 @@ fdemri_status plan_batch(fdemri_ctx* c, int B, const fdemri_waveform_desc* descs
   P.pref_off = align_up(P.items_off + (size_t)B * sizeof(WaveItem), 256);
   P.pref_bytes = 4 * (size_t)(B + 1) * sizeof(int32_t);
   P.counter_off = align_up(P.pref_off + P.pref_bytes, 256);
-  P.total = P.counter_off + 256;
+  P.ll_off = P.counter_off + 256;
+  P.nbmax = ll ? loglike_batch_reduce_blocks(P.Nf_max) : 0;
+  P.total = align_up(P.ll_off + (size_t)B * P.nbmax * 3 * sizeof(double), 256);
   P.record_bytes = (P.pref_off - P.items_off) + P.pref_bytes;
   return FDEMRI_OK;
 }
 
-// Fill the device records of the batch into host memory `rec` (record_bytes).
+// Fill the device records of the batch into host memory `rec` (record_bytes);
+// for a likelihood batch, ll_d_p, ll_d_c, ll_wS hold the data and weights.
 void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc* descs, void* const* hp,
-                  void* const* hc, char* rec) {
+                  void* const* hc, char* rec, const void* const* ll_d_p = nullptr,
+                  const void* const* ll_d_c = nullptr, const double* const* ll_wS = nullptr) {
   const int B = P.B;
   char* w = c->ws;
   WaveItem* hitems = (WaveItem*)rec;
@@ -576,8 +591,13 @@ void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc*
     it.pieces = (Piece*)(wb + L.pieces);
     it.evals = (int64_t*)(wb + L.evals);
     it.env = (int32_t*)(wb + L.env);
-    it.hp = hp[b];
-    it.hc = hc[b];
+    it.hp = P.ll ? nullptr : hp[b];
+    it.hc = P.ll ? nullptr : hc[b];
+    it.d_p = P.ll ? ll_d_p[b] : nullptr;
+    it.d_c = P.ll ? ll_d_c[b] : nullptr;
+    it.wS = P.ll ? ll_wS[b] : nullptr;
+    it.ll_partial = P.ll ? (double*)(wb + L.ll_partial) : nullptr;
+    it.ll_edge = P.ll ? (double*)(wb + L.ll_edge) : nullptr;
     hitems[b] = it;
     series_prefix[b + 1] = series_prefix[b] + 4 + ((d.flags & FDEMRI_COEFFS_GIVEN) ? 0 : d.Nm);
     mode_prefix[b + 1] = mode_prefix[b] + d.Nm;
@@ -587,8 +607,11 @@ void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc*
   }
 }
 
-// Enqueue record upload and the four batched launches on `stream`.
-hipError_t enqueue_batch(fdemri_ctx* c, const BatchPlan& P, const char* rec, hipStream_t stream) {
+// Enqueue record upload and the four batched launches on `stream` (for a
+// likelihood batch: the fused gather and its two reduction stages into
+// ll_out[B][3], with the Hann kernel when hann is set).
+hipError_t enqueue_batch(fdemri_ctx* c, const BatchPlan& P, const char* rec, hipStream_t stream,
+                         double* ll_out = nullptr, int hann = 0) {
   char* w = c->ws;
   const int B = P.B;
   const WaveItem* ditems = (const WaveItem*)(w + P.items_off);
@@ -607,6 +630,9 @@ hipError_t enqueue_batch(fdemri_ctx* c, const BatchPlan& P, const char* rec, hip
   }
   if (e != hipSuccess) return e;
   ProfScope ps(c, FDEMRI_KERNEL_GATHER, stream);
+  if (P.ll)
+    return launch_loglike_batch(ditems, B, dpref + 3 * (B + 1), (int)P.n_items, (int*)(w + P.counter_off), P.Kmax,
+                                P.mixed, c->bpl, hann, P.Nf_max, (double*)(w + P.ll_off), ll_out, stream);
   return launch_gather_batch(ditems, B, dpref + 3 * (B + 1), (int)P.n_items, (int*)(w + P.counter_off), P.Kmax,
                              P.mixed, c->bpl, stream);
 }
@@ -749,6 +775,58 @@ fdemri_status fdemri_waveform_batch(fdemri_ctx* c, int32_t B, const fdemri_wavef
   if (e == hipSuccess) e = hipEventRecord(c->ev_out, c->gstream);
   if (e == hipSuccess) e = hipStreamWaitEvent(stream, c->ev_out, 0);
   if (e != hipSuccess) return hip_fail(c, e, "batch graph launch");
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_loglike_batch(fdemri_ctx* c, int32_t B, const fdemri_waveform_desc* descs, fdemri_prec prec,
+                                   const void* const* d_p, const void* const* d_c, const double* const* wS,
+                                   uint32_t ll_flags, double* out, hipStream_t stream) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  if (B < 0 || (B > 0 && (!descs || !d_p || !d_c || !wS || !out)))
+    return fail(c, FDEMRI_EINVAL, "invalid batch arguments");
+  if (B == 0) return FDEMRI_OK;
+  if (prec != FDEMRI_FP64 && prec != FDEMRI_MIXED) return fail(c, FDEMRI_EINVAL, "unknown precision %d", (int)prec);
+  if (ll_flags & ~FDEMRI_LL_HANN) return fail(c, FDEMRI_EINVAL, "unknown likelihood flags 0x%x", ll_flags);
+  for (int b = 0; b < B; ++b)
+    if (!d_p[b] || !d_c[b] || !wS[b]) return fail(c, FDEMRI_EINVAL, "waveform %d: NULL data or weight pointer", b);
+  if (!c->tuning) {
+    int64_t bins = 0;
+    for (int b = 0; b < B; ++b) bins += descs[b].Nf;
+    c->bpl = choose_bpl(c, (int)prec, true, bins);
+  }
+  BatchPlan P;
+  fdemri_status st = plan_batch(c, B, descs, prec == FDEMRI_MIXED, nullptr, nullptr, P, true);
+  if (st != FDEMRI_OK) return st;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const uint64_t gen0 = c->ws_generation;
+  st = ensure_ws(c, P.total);
+  if (st != FDEMRI_OK) return st;
+  if (c->ws_generation != gen0) drop_graphs(c);  // recorded graphs point into the old workspace
+  // records through the shared pinned staging buffer (eager; not captured)
+  if (c->stage_pending) {
+    e = hipEventSynchronize(c->stage_ev);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    c->stage_pending = false;
+  }
+  if (P.record_bytes > c->stage_bytes) {
+    if (c->stage) (void)hipHostFree(c->stage);
+    c->stage = nullptr;
+    c->stage_bytes = 0;
+    e = hipHostMalloc((void**)&c->stage, P.record_bytes);
+    if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc(staging)");
+    c->stage_bytes = P.record_bytes;
+  }
+  if (!c->stage_ev) {
+    e = hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+  }
+  fill_records(c, P, descs, nullptr, nullptr, c->stage, d_p, d_c, wS);
+  e = enqueue_batch(c, P, c->stage, stream, out, (ll_flags & FDEMRI_LL_HANN) ? 1 : 0);
+  if (e == hipSuccess) e = hipEventRecord(c->stage_ev, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "likelihood batch launch");
+  c->stage_pending = true;
   return FDEMRI_OK;
 }
 

@@ -88,6 +88,13 @@ struct WaveItem {
   int32_t* env;
   void* hp;
   void* hc;
+  // fused likelihood of the batch: data, per-bin weights and this waveform's
+  // partial-sum and edge-record scratch (unused for a waveform batch)
+  const void* d_p;
+  const void* d_c;
+  const double* wS;
+  double* ll_partial;
+  double* ll_edge;
 };
 
 __host__ __device__ inline Prepared prepared_of(const WaveItem& w) {

@@ -551,11 +551,13 @@ __global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_
 // out = (-1/2 sum wS |d - h_w|^2, sum wS |h_w|^2, sum wS Re(conj(d) h_w)).
 constexpr int kLLThreads = 256;
 
+// One workgroup of stage 1: the triple of tiles [x kLLThreads, (x + 1)
+// kLLThreads) of one waveform into dst[3].
 template <bool MIXED>
-__global__ __launch_bounds__(kLLThreads) void loglike_tiles_kernel(Sink o, int Nf, double* block_sums) {
+__device__ __forceinline__ void loglike_tile_block(const Sink& o, int Nf, int x, double* dst) {
   __shared__ double red[3][kLLThreads];
   const int ntiles = (Nf + 63) / 64;
-  const int i = (int)blockIdx.x * kLLThreads + (int)threadIdx.x;
+  const int i = x * kLLThreads + (int)threadIdx.x;
   double t[3] = {0.0, 0.0, 0.0};
   if (i < ntiles) {
 #pragma unroll
@@ -595,13 +597,38 @@ __global__ __launch_bounds__(kLLThreads) void loglike_tiles_kernel(Sink o, int N
   }
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) block_sums[(size_t)blockIdx.x * 3 + q] = red[q][0];
+    for (int q = 0; q < 3; ++q) dst[q] = red[q][0];
   }
 }
 
+template <bool MIXED>
+__global__ __launch_bounds__(kLLThreads) void loglike_tiles_kernel(Sink o, int Nf, double* block_sums) {
+  loglike_tile_block<MIXED>(o, Nf, (int)blockIdx.x, block_sums + (size_t)blockIdx.x * 3);
+}
+
+// Stage 1 for a batch: blockIdx.y selects the waveform; its workgroups past
+// the waveform's own count leave zeros (stage 2 then adds the same terms in
+// the same order as for a single waveform).
+template <bool MIXED>
+__global__ __launch_bounds__(kLLThreads) void loglike_tiles_batch_kernel(const WaveItem* __restrict__ items, int hann,
+                                                                         int nbmax, double* block_sums) {
+  const WaveItem w = ((const kconst WaveItem*)items)[blockIdx.y];
+  Sink o{};
+  o.d_p = w.d_p;
+  o.d_c = w.d_c;
+  o.wS = w.wS;
+  o.partial = w.ll_partial;
+  o.edge = w.ll_edge;
+  o.hann = hann;
+  loglike_tile_block<MIXED>(o, w.Nf, (int)blockIdx.x, block_sums + ((size_t)blockIdx.y * nbmax + blockIdx.x) * 3);
+}
+
+// Stage 2; workgroup b adds the nblocks triples of waveform b into out[b].
 __global__ __launch_bounds__(kLLThreads) void loglike_total_kernel(const double* block_sums, int nblocks,
                                                                    double* out) {
   __shared__ double red[3][kLLThreads];
+  block_sums += (size_t)blockIdx.x * nblocks * 3;
+  out += (size_t)blockIdx.x * 3;
   double t[3] = {0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblocks; b += kLLThreads) {
 #pragma unroll
@@ -631,10 +658,11 @@ __global__ __launch_bounds__(kLLThreads) void loglike_total_kernel(const double*
 // only schedules; every output element is computed in a fixed order, so
 // results do not depend on the schedule.  Every workgroup leaves the loop
 // once the counter passes the last block.
-template <bool MIXED, int BPL, int WAVES>
+template <bool MIXED, int BPL, int WAVES, bool LL>
 __global__ __launch_bounds__(64 * WAVES, gather_batch_min_waves<MIXED>()) void gather_batch_kernel(const WaveItem* __restrict__ items, int B,
                                                                 const int32_t* __restrict__ item_prefix,
-                                                                int total_items, int* __restrict__ counter) {
+                                                                int total_items, int* __restrict__ counter,
+                                                                int hann) {
   extern __shared__ __align__(16) double lds[];
   __shared__ int s_item;
   int* list = (int*)lds;
@@ -661,20 +689,39 @@ __global__ __launch_bounds__(64 * WAVES, gather_batch_min_waves<MIXED>()) void g
     const Prepared p = prepared_of(w);
     const int kb = (it - pre[lo]) * block_bins<BPL, WAVES>();
     const int kbe = kb + block_bins<BPL, WAVES>() - 1;
-    if (kbe < p.env[0] || kb > p.env[1]) {
-      zero_block<MIXED, BPL, WAVES>(w.hp, w.hc, p.Nf, kb);
-      continue;
-    }
     Sink out{};
     out.hp = w.hp;
     out.hc = w.hc;
+    if constexpr (LL) {
+      out.d_p = w.d_p;
+      out.d_c = w.d_c;
+      out.wS = w.wS;
+      out.partial = w.ll_partial;
+      out.edge = w.ll_edge;
+      out.hann = hann;
+    }
+    if (kbe < p.env[0] || kb > p.env[1]) {
+      if constexpr (LL) {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        Acc<MIXED> z;
+        z.zero();
+#pragma unroll 1
+        for (int j = 0; j < BPL; ++j) {
+          const int ks = kb + (wave * BPL + j) * 64;
+          emit<MIXED, true>(out, ks >> 6, ks + (int)(threadIdx.x & 63), p.Nf, z);
+        }
+      } else {
+        zero_block<MIXED, BPL, WAVES>(w.hp, w.hc, p.Nf, kb);
+      }
+      continue;
+    }
     if (lo != cached) {
       L = stage_lds(p, tables);
       __syncthreads();
       cached = lo;
     }
-    process_block<MIXED, BPL, WAVES, false>(p, MIXED ? (const void*)w.acoef32 : (const void*)w.acoef, out, kb, L,
-                                           list);
+    process_block<MIXED, BPL, WAVES, LL>(p, MIXED ? (const void*)w.acoef32 : (const void*)w.acoef, out, kb, L,
+                                        list);
   }
 }
 
@@ -809,30 +856,30 @@ hipError_t launch_loglike(const Prepared& p, const float* acoef32, bool mixed, i
   return hipGetLastError();
 }
 
-template <bool MIXED, int BPL, int WAVES>
+template <bool MIXED, int BPL, int WAVES, bool LL>
 static hipError_t launch_gather_batch_t(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
-                                        int* counter, int Kmax, int grid, hipStream_t stream) {
+                                        int* counter, int Kmax, int grid, int hann, hipStream_t stream) {
   const size_t red = kHeadDoubles * sizeof(double);
   const size_t lds = gather_lds_bytes(Kmax) + red;
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)gather_batch_kernel<MIXED, BPL, WAVES>,
+    (void)hipFuncSetAttribute((const void*)gather_batch_kernel<MIXED, BPL, WAVES, LL>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)(gather_lds_bytes(kMaxKnots) + red));
     attr_set = true;
   }
   reset_counter_kernel<<<1, 1, 0, stream>>>(counter);
-  gather_batch_kernel<MIXED, BPL, WAVES><<<dim3(grid), dim3(64 * WAVES), lds, stream>>>(items, B, item_prefix,
-                                                                                     total_items, counter);
+  gather_batch_kernel<MIXED, BPL, WAVES, LL><<<dim3(grid), dim3(64 * WAVES), lds, stream>>>(
+      items, B, item_prefix, total_items, counter, hann);
   return hipGetLastError();
 }
 
 // Number of workgroups of the persistent kernel: enough to fill every CU.
-template <bool MIXED, int BPL, int WAVES>
+template <bool MIXED, int BPL, int WAVES, bool LL>
 static int persistent_grid(int Kmax) {
   int dev = 0, ncu = 0, per_cu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)gather_batch_kernel<MIXED, BPL, WAVES>,
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)gather_batch_kernel<MIXED, BPL, WAVES, LL>,
                                                      64 * WAVES,
                                                      gather_lds_bytes(Kmax) + kHeadDoubles * sizeof(double));
   if (ncu <= 0) ncu = 256;
@@ -845,26 +892,47 @@ int gather_items_per_waveform(int Nf, int bpl) {
   return (Nf + per_block - 1) / per_block;
 }
 
+template <bool MIXED, bool LL>
+static hipError_t launch_gather_batch_p(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
+                                        int* counter, int Kmax, int bpl, int hann, hipStream_t stream) {
+  if (bpl == 1)
+    return launch_gather_batch_t<MIXED, 1, 4, LL>(items, B, item_prefix, total_items, counter, Kmax,
+                                                  persistent_grid<MIXED, 1, 4, LL>(Kmax), hann, stream);
+  if (bpl == 2)
+    return launch_gather_batch_t<MIXED, 2, 4, LL>(items, B, item_prefix, total_items, counter, Kmax,
+                                                  persistent_grid<MIXED, 2, 4, LL>(Kmax), hann, stream);
+  return launch_gather_batch_t<MIXED, 4, 4, LL>(items, B, item_prefix, total_items, counter, Kmax,
+                                                persistent_grid<MIXED, 4, 4, LL>(Kmax), hann, stream);
+}
+
 hipError_t launch_gather_batch(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
                                int* counter, int Kmax, bool mixed, int bpl, hipStream_t stream) {
-  if (mixed) {
-    if (bpl == 1)
-      return launch_gather_batch_t<true, 1, 4>(items, B, item_prefix, total_items, counter, Kmax,
-                                               persistent_grid<true, 1, 4>(Kmax), stream);
-    if (bpl == 2)
-      return launch_gather_batch_t<true, 2, 4>(items, B, item_prefix, total_items, counter, Kmax,
-                                               persistent_grid<true, 2, 4>(Kmax), stream);
-    return launch_gather_batch_t<true, 4, 4>(items, B, item_prefix, total_items, counter, Kmax,
-                                             persistent_grid<true, 4, 4>(Kmax), stream);
-  }
-  if (bpl == 1)
-    return launch_gather_batch_t<false, 1, 4>(items, B, item_prefix, total_items, counter, Kmax,
-                                              persistent_grid<false, 1, 4>(Kmax), stream);
-  if (bpl == 2)
-    return launch_gather_batch_t<false, 2, 4>(items, B, item_prefix, total_items, counter, Kmax,
-                                              persistent_grid<false, 2, 4>(Kmax), stream);
-  return launch_gather_batch_t<false, 4, 4>(items, B, item_prefix, total_items, counter, Kmax,
-                                            persistent_grid<false, 4, 4>(Kmax), stream);
+  if (mixed) return launch_gather_batch_p<true, false>(items, B, item_prefix, total_items, counter, Kmax, bpl, 0, stream);
+  return launch_gather_batch_p<false, false>(items, B, item_prefix, total_items, counter, Kmax, bpl, 0, stream);
+}
+
+// Likelihood stage-1 workgroups of the largest waveform of a batch.
+int loglike_batch_reduce_blocks(int Nf_max) { return loglike_reduce_blocks(Nf_max); }
+
+// The fused likelihood of a batch: persistent gather into every waveform's
+// partials, then the two reduction stages, out[b][3] per waveform (same
+// arithmetic and order as a single-waveform call).  block_sums: B x nbmax x 3.
+hipError_t launch_loglike_batch(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
+                                int* counter, int Kmax, bool mixed, int bpl, int hann, int Nf_max,
+                                double* block_sums, double* out, hipStream_t stream) {
+  hipError_t e = mixed
+                     ? launch_gather_batch_p<true, true>(items, B, item_prefix, total_items, counter, Kmax, bpl, hann, stream)
+                     : launch_gather_batch_p<false, true>(items, B, item_prefix, total_items, counter, Kmax, bpl, hann,
+                                                         stream);
+  if (e != hipSuccess) return e;
+  const int nbmax = loglike_reduce_blocks(Nf_max);
+  const dim3 grid((unsigned)nbmax, (unsigned)B);
+  if (mixed)
+    loglike_tiles_batch_kernel<true><<<grid, kLLThreads, 0, stream>>>(items, hann, nbmax, block_sums);
+  else
+    loglike_tiles_batch_kernel<false><<<grid, kLLThreads, 0, stream>>>(items, hann, nbmax, block_sums);
+  loglike_total_kernel<<<B, kLLThreads, 0, stream>>>(block_sums, nbmax, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_amp32_batch(const WaveItem* items, int B, const int32_t* amp_prefix, int total, hipStream_t stream) {

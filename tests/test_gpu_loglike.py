@@ -151,3 +151,34 @@ def test_loglike_deterministic_and_invalid(ctx):
     assert st == 1
     torch.cuda.synchronize()
     assert torch.all(out == 0)
+
+
+@pytest.mark.parametrize("prec,hann", [("fp64", False), ("fp64", True), ("mixed", True)])
+def test_loglike_batch_equals_single_calls(ctx, prec, hann):
+    """fdemri_loglike_batch over waveforms of uneven sizes (ragged grids, a
+    log grid) equals one fdemri_loglike call per waveform, bit for bit."""
+    ws = [W.inspiral_20_modes(), W.inspiral_20_modes_log_grid()]
+    for prm in W.batch_params(3, 321):
+        prm["T"] = min(prm["T"], 0.6 * W.YRSID_SI)
+        w = W.batch_workload(prm, K=70 + 10 * len(ws))
+        w.f = w.f[: 120_000 + 37 * len(ws)]
+        ws.append(w)
+    ctype = torch.complex128 if prec == "fp64" else torch.complex64
+    rng = np.random.default_rng(17)
+    dws, dps, dcs, wss = [], [], [], []
+    for w in ws:
+        dw = fd.DeviceWaveform.from_workload(w, device=ctx.device)
+        hp, hc = ctx.waveform_dev(dw, "fp64")
+        noise = [torch.as_tensor(rng.normal(size=(w.Nf, 2)), device=ctx.device) for _ in range(2)]
+        sc = float(torch.max(torch.abs(hp))) + 1e-30
+        dps.append((1.2 * hp + sc * torch.view_as_complex(noise[0])).to(ctype).contiguous())
+        dcs.append((0.8 * hc + sc * torch.view_as_complex(noise[1])).to(ctype).contiguous())
+        wss.append(torch.as_tensor(rng.uniform(0.5, 2.0, w.Nf), device=ctx.device))
+        dws.append(dw)
+    out = ctx.loglike_batch(dws, dps, dcs, wss, prec=prec, hann=hann)
+    torch.cuda.synchronize()
+    assert ctx.sync_flags() == 0
+    for b, dw in enumerate(dws):
+        single = ctx.loglike_dev(dw, dps[b], dcs[b], wss[b], prec=prec, hann=hann)
+        torch.cuda.synchronize()
+        assert torch.equal(out[b], single), (b, out[b], single)
