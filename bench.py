@@ -394,7 +394,7 @@ def gather_traffic(bpl):
         return None
     if h.hexdigest() != rec.get("kernel_sources_sha256"):
         return None
-    if rec.get("kernel") != f"gather_kernel<false, {bpl}, 4>":
+    if rec.get("kernel") != f"gather_kernel<false, {bpl}, 4, false>":
         return None
     return float(rec["traffic_bytes_per_launch"])
 
@@ -423,7 +423,7 @@ def headline(args, w, evals, sec, prof, achieved, bpl, secondary):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": gather_traffic(bpl),
                      "traffic_unit": "HBM bytes per launch (read + write)",
-                     "kernel": f"gather_kernel<false, {bpl}, 4>", "flops_per_eval": FLOPS_PER_EVAL},
+                     "kernel": f"gather_kernel<false, {bpl}, 4, false>", "flops_per_eval": FLOPS_PER_EVAL},
         "secondary": secondary,
     }
 
