@@ -279,6 +279,17 @@ def main():
     secondary["mixed_same_workload"] = {"waveforms_per_s": 1.0 / smix, "ms": smix * 1e3,
                                         "rel_l2_vs_fp64": mix_err}
     secondary["loglike_fused_fp64"] = loglike_measure(ctx, W, dw, hp, hc, dev, max(5, args.steps // 2))
+    # mode selection on the device: the unselected 3843-row table of the same source
+    full = W.inspiral_3842_modes(eps=0.0)
+    At = torch.as_tensor(full.A, device=dev)
+    ctx.select_modes(At, 1e-5)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(20):
+        kept = ctx.select_modes(At, 1e-5)
+    secondary["mode_selection"] = {"rows": int(full.l.size), "knots": int(full.traj.t.size), "kept": int(kept.numel()),
+                                   "us_per_call": (time.perf_counter() - ts) / 20 * 1e6,
+                                   "note": "includes the device-to-host read of the kept count"}
     secondary["batch_mixed"] = batch_measure(ctx, W, fd, dev, args.batch)
     secondary["forward_adjoint"] = adjoint_measure(ctx, W, fd, dev, args.adjoint)
     for name, wl in (("inspiral_20_modes_fp64", W.inspiral_20_modes()),

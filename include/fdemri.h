@@ -232,6 +232,23 @@ fdemri_status fdemri_loglike_batch(fdemri_ctx *ctx, int32_t B, const fdemri_wave
                                    hipStream_t stream);
 
 /*
+ * Mode selection by power (Sec. 2.1: modes are kept by their share of the
+ * total power; the share is taken at every knot and the union kept):
+ * row mu of A is kept when |A_mu(t_i)|^2 > eps * sum_nu |A_nu(t_i)|^2 at one
+ * knot i at least, |A|^2 = re*re + im*im rounded term by term.
+ *   A      : [Nm][K][2] double, DEVICE, complex amplitude knot values (the
+ *            layout of fdemri_waveform_desc.A).
+ *   eps    : threshold, finite and >= 0.
+ *   idx    : [Nm] int32, DEVICE: the kept rows, in table order, in
+ *            idx[0 .. *n_keep); the rest is left as it was.
+ *   n_keep : int32, DEVICE.
+ * 1 <= K, 0 <= Nm.  Deterministic (fixed summation order).  FDEMRI_EINVAL for
+ * invalid sizes, eps or NULL pointers (nothing enqueued).
+ */
+fdemri_status fdemri_select_modes(fdemri_ctx *ctx, int32_t K, int32_t Nm, const double *A, double eps,
+                                  int32_t *idx, int32_t *n_keep, hipStream_t stream);
+
+/*
  * Autotuner of the gather's block shape (1, 2 or 4 consecutive 64-bin tiles
  * per wavefront, i.e. 256, 512 or 1024 contiguous bins per 4-wave workgroup
  * sharing one active-mode list; the result does not depend on the choice,

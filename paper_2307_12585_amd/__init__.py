@@ -34,7 +34,7 @@ EXPORTED = [
     "fdemri_create", "fdemri_destroy", "fdemri_last_error", "fdemri_sync_flags",
     "fdemri_waveform", "fdemri_waveform_batch", "fdemri_vjp", "fdemri_last_eval_count",
     "fdemri_profile_enable", "fdemri_profile_read", "fdemri_autotune", "fdemri_loglike",
-    "fdemri_loglike_batch",
+    "fdemri_loglike_batch", "fdemri_select_modes",
 ]
 KERNEL_CLASSES = ["spline", "pieces", "gather", "vjp"]
 
@@ -89,6 +89,8 @@ def lib():
         L.fdemri_vjp.restype = ctypes.c_int
         L.fdemri_loglike.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_int, vp, vp, vp, u32, vp, vp]
         L.fdemri_loglike.restype = ctypes.c_int
+        L.fdemri_select_modes.argtypes = [vp, i32, i32, vp, ctypes.c_double, vp, vp, vp]
+        L.fdemri_select_modes.restype = ctypes.c_int
         L.fdemri_loglike_batch.argtypes = [vp, i32, ctypes.POINTER(WaveformDesc), ctypes.c_int,
                                            ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), u32, vp, vp]
         L.fdemri_loglike_batch.restype = ctypes.c_int
@@ -260,6 +262,19 @@ class Context:
         self._check(self._lib.fdemri_loglike(self._h, ctypes.byref(d), p, _ptr(d_p), _ptr(d_c), _ptr(wS),
                                              FDEMRI_LL_HANN if hann else 0, _ptr(out), _stream(self.device)))
         return out
+
+    def select_modes(self, A, eps):
+        """fdemri_select_modes: indices (int32 device tensor, table order) of the
+        rows of A ([Nm, K] complex128 device tensor of amplitude knot values)
+        kept by the power criterion at threshold eps (synchronises to read the
+        count)."""
+        A = A.to(torch.complex128).contiguous()
+        Nm, K = A.shape
+        idx = torch.empty(max(Nm, 1), dtype=torch.int32, device=A.device)
+        cnt = torch.zeros(1, dtype=torch.int32, device=A.device)
+        self._check(self._lib.fdemri_select_modes(self._h, K, Nm, _ptr(A), float(eps), _ptr(idx), _ptr(cnt),
+                                                  _stream(self.device)))
+        return idx[: int(cnt.item())]
 
     def loglike_batch(self, dws, ds_p, ds_c, wSs, prec="fp64", hann=False, out=None):
         """fdemri_loglike_batch: a [B, 3] float64 device tensor of (log L,

@@ -37,6 +37,8 @@ hipError_t launch_amp32_batch(const WaveItem* items, int B, const int32_t* amp_p
 hipError_t launch_gather_batch(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
                                int* counter, int Kmax, bool mixed, int bpl, hipStream_t stream);
 int gather_items_per_waveform(int Nf, int bpl);
+hipError_t launch_select_modes(int K, int Nm, const double* A, double eps, double* P, int32_t* keep, int32_t* idx,
+                               int32_t* n_keep, hipStream_t stream);
 int loglike_tiles(int Nf, int bpl);
 size_t loglike_partial_doubles(int Nf, int bpl);
 int loglike_batch_reduce_blocks(int Nf_max);
@@ -437,6 +439,23 @@ fdemri_status fdemri_loglike(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemr
                        (double*)(w + L.ll_partial), (double*)(w + L.ll_edge), out, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "likelihood kernel launch");
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_select_modes(fdemri_ctx* c, int32_t K, int32_t Nm, const double* A, double eps, int32_t* idx,
+                                  int32_t* n_keep, hipStream_t stream) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  if (K < 1 || Nm < 0) return fail(c, FDEMRI_EINVAL, "invalid sizes K=%d Nm=%d", K, Nm);
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(c, FDEMRI_EINVAL, "eps must be finite and >= 0");
+  if (!n_keep || (Nm > 0 && (!A || !idx))) return fail(c, FDEMRI_EINVAL, "NULL pointer");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const size_t p_bytes = align_up((size_t)K * sizeof(double), 256);
+  fdemri_status st = ensure_ws(c, p_bytes + (size_t)Nm * sizeof(int32_t) + 256);
+  if (st != FDEMRI_OK) return st;
+  e = launch_select_modes(K, Nm, A, eps, (double*)c->ws, (int32_t*)(c->ws + p_bytes), idx, n_keep, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "mode selection launch");
   return FDEMRI_OK;
 }
 
