@@ -279,6 +279,7 @@ def main():
     secondary["mixed_same_workload"] = {"waveforms_per_s": 1.0 / smix, "ms": smix * 1e3,
                                         "rel_l2_vs_fp64": mix_err}
     secondary["loglike_fused_fp64"] = loglike_measure(ctx, W, dw, hp, hc, dev, max(5, args.steps // 2))
+    secondary["td_vs_fd_fp64"] = td_measure(ctx, W, dw, hp, hc, dev, sec)
     # mode selection on the device: the unselected 3843-row table of the same source
     full = W.inspiral_3842_modes(eps=0.0)
     At = torch.as_tensor(full.A, device=dev)
@@ -316,6 +317,61 @@ def main():
                                             count_sample)
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def td_measure(ctx, W, dw, hp, hc, dev, fd_sec):
+    """The paper's FD/TD comparison on the same source: the time-domain voice
+    sum (fdemri_td_waveform) on the full 10 s grid plus the Hann-windowed
+    rfft of both channels, against the FD step; and the mismatch (R12)
+    between the windowed TD transform and the FD sum with the matching
+    three-tap kernel."""
+    import numpy as np
+    import torch
+    w = W.inspiral_3842_modes()
+    dt = w.meta["dt"]
+    Nt = 2 * (w.f.size - 1)
+    out = (torch.empty(Nt, dtype=torch.float64, device=dev), torch.empty(Nt, dtype=torch.float64, device=dev))
+    win = 0.5 - 0.5 * torch.cos(2 * np.pi * torch.arange(Nt, dtype=torch.float64, device=dev) / Nt)
+    ctx.td_waveform_dev(dw, 0.0, dt, Nt, out=out)
+    torch.fft.rfft(out[0] * win)  # FFT plan set up outside the timed region
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(3):
+        torch.fft.rfft(out[0] * win)
+    torch.cuda.synchronize()
+    fft_ms = (time.perf_counter() - ts) / 3 * 1e3
+    ctx.profile(True)
+    ctx.profile_read()
+    reps = 3
+    ts = time.perf_counter()
+    for _ in range(reps):
+        ctx.td_waveform_dev(dw, 0.0, dt, Nt, out=out)
+        tp = dt * torch.conj(torch.fft.rfft(out[0] * win))
+        tc = dt * torch.conj(torch.fft.rfft(out[1] * win))
+    torch.cuda.synchronize()
+    td_sec = (time.perf_counter() - ts) / reps
+    k_ms, k_n = ctx.profile_read()["gather"]
+    ctx.profile(False)
+
+    def hw(h):
+        g = 0.5 * h.clone()
+        g[:-1] -= 0.25 * h[1:]
+        g[1:] -= 0.25 * h[:-1]
+        g[0] -= 0.25 * torch.conj(h[1])
+        return g
+    S = torch.as_tensor(W.psd_closed_form(w.f), device=dev)
+    wts = torch.full_like(S, float(w.f[1] - w.f[0]))
+    good = torch.isfinite(S)
+    wS = torch.where(good, 4.0 * wts / torch.where(good, S, torch.ones_like(S)), torch.zeros_like(S))
+    ip = lambda a, b: float(torch.sum(wS * torch.real(torch.conj(a) * b)))
+    fp, fc = hw(hp), hw(hc)
+    ab = ip(fp, tp) + ip(fc, tc)
+    mm = 1.0 - ab / np.sqrt((ip(fp, fp) + ip(fc, fc)) * (ip(tp, tp) + ip(tc, tc)))
+    k_avg = k_ms / max(k_n, 1) * 1e-3
+    return {"samples": Nt, "td_kernel_ms": k_avg * 1e3, "rfft_ms_per_channel": fft_ms,
+            "td_plus_rfft_ms": td_sec * 1e3,
+            "fd_step_ms": fd_sec * 1e3, "fd_speedup_over_td": td_sec / fd_sec,
+            "mode_sample_pairs_per_s": w.l.size * Nt / k_avg, "mismatch_fd_vs_windowed_td": mm}
 
 
 def loglike_measure(ctx, W, dw, hp, hc, dev, steps):

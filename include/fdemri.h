@@ -232,6 +232,23 @@ fdemri_status fdemri_loglike_batch(fdemri_ctx *ctx, int32_t B, const fdemri_wave
                                    hipStream_t stream);
 
 /*
+ * Time-domain waveform on a uniform grid, the comparison model of the
+ * paper's FD/TD study (Sec. 3.2): h(t) = sum over voices of H_V(t)
+ * e^{-i Phi_V(t)} (Eq. wave_voice) from the same splines, angles and partner
+ * convention as fdemri_waveform, with h_+ = Re h and h_x = -Im h
+ * (Eq. main_wave; h = h_+ - i h_x).
+ *   t0, dt, Nt : samples t_k = t0 + k dt (k*dt rounded, then added), k < Nt;
+ *                dt > 0, Nt >= 0.
+ *   hp_t, hc_t : [Nt] double, DEVICE, h_+(t_k) and h_x(t_k); 0 for samples
+ *                outside [t_0, t_{K-1}] of the trajectory.  Fully overwritten.
+ * The frequency array of desc is validated but not used.  The transform of
+ * the result with the sign of Eq. singlevoiceFT, x~(f_k) = dt conj(rfft(x))[k]
+ * for real x, is what the FD sum approximates.
+ */
+fdemri_status fdemri_td_waveform(fdemri_ctx *ctx, const fdemri_waveform_desc *desc, double t0, double dt,
+                                 int32_t Nt, double *hp_t, double *hc_t, hipStream_t stream);
+
+/*
  * Mode selection by power (Sec. 2.1: modes are kept by their share of the
  * total power; the share is taken at every knot and the union kept):
  * row mu of A is kept when |A_mu(t_i)|^2 > eps * sum_nu |A_nu(t_i)|^2 at one

@@ -34,7 +34,7 @@ EXPORTED = [
     "fdemri_create", "fdemri_destroy", "fdemri_last_error", "fdemri_sync_flags",
     "fdemri_waveform", "fdemri_waveform_batch", "fdemri_vjp", "fdemri_last_eval_count",
     "fdemri_profile_enable", "fdemri_profile_read", "fdemri_autotune", "fdemri_loglike",
-    "fdemri_loglike_batch", "fdemri_select_modes",
+    "fdemri_loglike_batch", "fdemri_select_modes", "fdemri_td_waveform",
 ]
 KERNEL_CLASSES = ["spline", "pieces", "gather", "vjp"]
 
@@ -91,6 +91,9 @@ def lib():
         L.fdemri_loglike.restype = ctypes.c_int
         L.fdemri_select_modes.argtypes = [vp, i32, i32, vp, ctypes.c_double, vp, vp, vp]
         L.fdemri_select_modes.restype = ctypes.c_int
+        L.fdemri_td_waveform.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_double, ctypes.c_double, i32,
+                                         vp, vp, vp]
+        L.fdemri_td_waveform.restype = ctypes.c_int
         L.fdemri_loglike_batch.argtypes = [vp, i32, ctypes.POINTER(WaveformDesc), ctypes.c_int,
                                            ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), u32, vp, vp]
         L.fdemri_loglike_batch.restype = ctypes.c_int
@@ -262,6 +265,19 @@ class Context:
         self._check(self._lib.fdemri_loglike(self._h, ctypes.byref(d), p, _ptr(d_p), _ptr(d_c), _ptr(wS),
                                              FDEMRI_LL_HANN if hann else 0, _ptr(out), _stream(self.device)))
         return out
+
+    def td_waveform_dev(self, dw: DeviceWaveform, t0, dt, Nt, out=None):
+        """h_+(t_k), h_x(t_k) (float64 device tensors) of the time-domain voice
+        sum on t_k = t0 + k dt, k < Nt (fdemri_td_waveform)."""
+        if out is None:
+            out = (torch.empty(Nt, dtype=torch.float64, device=dw.device),
+                   torch.empty(Nt, dtype=torch.float64, device=dw.device))
+        hp, hc = out
+        assert hp.dtype == torch.float64 and hc.dtype == torch.float64 and hp.numel() == Nt and hc.numel() == Nt
+        d = dw.desc()
+        self._check(self._lib.fdemri_td_waveform(self._h, ctypes.byref(d), float(t0), float(dt), int(Nt),
+                                                 _ptr(hp), _ptr(hc), _stream(self.device)))
+        return hp, hc
 
     def select_modes(self, A, eps):
         """fdemri_select_modes: indices (int32 device tensor, table order) of the

@@ -37,6 +37,9 @@ hipError_t launch_amp32_batch(const WaveItem* items, int B, const int32_t* amp_p
 hipError_t launch_gather_batch(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
                                int* counter, int Kmax, bool mixed, int bpl, hipStream_t stream);
 int gather_items_per_waveform(int Nf, int bpl);
+hipError_t launch_td(int K, int Nm, const double* t, const double* Phiphi, const double* Phir, const double* tcoef,
+                     const double* acoef, const ModeConst* modes, double t0, double dt, int Nt, double* hp, double* hc,
+                     hipStream_t stream);
 hipError_t launch_select_modes(int K, int Nm, const double* A, double eps, double* P, int32_t* keep, int32_t* idx,
                                int32_t* n_keep, hipStream_t stream);
 int loglike_tiles(int Nf, int bpl);
@@ -439,6 +442,32 @@ fdemri_status fdemri_loglike(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemr
                        (double*)(w + L.ll_partial), (double*)(w + L.ll_edge), out, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "likelihood kernel launch");
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_td_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, double t0, double dt, int32_t Nt,
+                                 double* hp_t, double* hc_t, hipStream_t stream) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  fdemri_status st = validate(c, d);
+  if (st != FDEMRI_OK) return st;
+  if (Nt < 0 || !std::isfinite(t0) || !std::isfinite(dt) || !(dt > 0.0))
+    return fail(c, FDEMRI_EINVAL, "invalid time grid (Nt=%d, dt must be finite and > 0)", Nt);
+  if (Nt > 0 && (!hp_t || !hc_t)) return fail(c, FDEMRI_EINVAL, "NULL output pointer");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const Layout L = layout_for(d->K, d->Nm, false);
+  st = ensure_ws(c, L.total);
+  if (st != FDEMRI_OK) return st;
+  Prepared p;
+  float* acoef32 = nullptr;
+  st = prepare(c, d, false, L, p, acoef32, stream);
+  if (st != FDEMRI_OK) return st;
+  {
+    ProfScope ps(c, FDEMRI_KERNEL_GATHER, stream);
+    e = launch_td(d->K, d->Nm, d->t, d->Phiphi, d->Phir, p.tcoef, p.acoef, p.modes, t0, dt, Nt, hp_t, hc_t, stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "time-domain kernel launch");
   return FDEMRI_OK;
 }
 
