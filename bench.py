@@ -280,6 +280,17 @@ def main():
                                         "rel_l2_vs_fp64": mix_err}
     secondary["loglike_fused_fp64"] = loglike_measure(ctx, W, dw, hp, hc, dev, max(5, args.steps // 2))
     secondary["td_vs_fd_fp64"] = td_measure(ctx, W, dw, hp, hc, dev, sec)
+    # trajectories on the device: 512 draws of the batch distribution, K = 100
+    prms = W.batch_params(512, 77)
+    tp = [dict(M=P["M"], mu=P["mu"], p0=P["p0"], e0=P["e0"], T=P["T"]) for P in prms]
+    ctx.trajectory(tp[:4], 100)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    ctx.trajectory(tp, 100)
+    torch.cuda.synchronize()
+    secondary["trajectory_batch"] = {"waveforms": len(tp), "knots": 100,
+                                     "ms_per_batch": (time.perf_counter() - ts) * 1e3,
+                                     "integrator": "Dormand-Prince 5(4), rtol 1e-12, one thread per waveform"}
     # mode selection on the device: the unselected 3843-row table of the same source
     full = W.inspiral_3842_modes(eps=0.0)
     At = torch.as_tensor(full.A, device=dev)

@@ -70,6 +70,9 @@ typedef enum {
 #define FDEMRI_FLAG_BAD_MODE 0x2u        /* a row had l outside [2, FDEMRI_MAX_L], |m| > l,
                                             or m < 0 without FDEMRI_NO_PARTNERS; such rows
                                             contribute nothing */
+#define FDEMRI_FLAG_TRAJ_STEPS 0x4u      /* fdemri_trajectory: a waveform needed more than
+                                            the step bound of its integrator; its knots
+                                            past that point repeat the last state */
 #define FDEMRI_MAX_PIECES 16
 #define FDEMRI_MAX_KNOTS 512
 #define FDEMRI_MAX_L 40
@@ -247,6 +250,33 @@ fdemri_status fdemri_loglike_batch(fdemri_ctx *ctx, int32_t B, const fdemri_wave
  */
 fdemri_status fdemri_td_waveform(fdemri_ctx *ctx, const fdemri_waveform_desc *desc, double t0, double dt,
                                  int32_t Nt, double *hp_t, double *hc_t, hipStream_t stream);
+
+/*
+ * Sparse trajectories on the device (Sec. 2.1: the adiabatic orbit is
+ * integrated to ~100 points before the mode sum), for the toy orbit-averaged
+ * fluxes of the synthetic workloads, one waveform per thread:
+ *   dp/dt = -(64/5) q (1-e^2)^{3/2} p^-3 (1 + 7e^2/8) / M_s,
+ *   de/dt = -(304/15) q e (1-e^2)^{3/2} p^-4 (1 + 121e^2/304) / M_s,
+ *   dPhi_phi/dt = Omega_phi / M_s, dPhi_r/dt = Omega_r / M_s,
+ *   Omega_phi = p^{-3/2} (1-e^2)^{3/2}, Omega_r = Omega_phi sqrt(1 - 6/p),
+ * q = mu/M, M_s = M G M_sun / c^3, from t = 0 to T or to the plunge
+ * p = 6 + 2e + 0.1; K knots uniform in [0, t_end].  Dormand-Prince 5(4)
+ * with relative tolerance 1e-12 (absolute 1e-12, 1e-14, 1e-9, 1e-9 for p, e
+ * and the two phases).
+ *   params : HOST array of B fdemri_traj_params (M in solar masses, mu in
+ *            solar masses, T in s, phases in rad); M, mu, T > 0,
+ *            0 <= e0 < 1, p0 > 6 + 2 e0 + 0.1.
+ *   out    : [B][7][K] double, DEVICE: per waveform the rows t, F_phi, F_r
+ *            (Hz), Phi_phi, Phi_r (rad), p, e - the first five are the
+ *            trajectory fields of fdemri_waveform_desc.
+ * 4 <= K <= FDEMRI_MAX_KNOTS.  FDEMRI_FLAG_TRAJ_STEPS (fdemri_sync_flags)
+ * reports a waveform that reached the integrator's step bound.
+ */
+typedef struct {
+  double M, mu, p0, e0, T, Phiphi0, Phir0;
+} fdemri_traj_params;
+fdemri_status fdemri_trajectory(fdemri_ctx *ctx, int32_t B, const fdemri_traj_params *params, int32_t K,
+                                double *out, hipStream_t stream);
 
 /*
  * Mode selection by power (Sec. 2.1: modes are kept by their share of the

@@ -27,6 +27,7 @@ FDEMRI_COEFFS_GIVEN = 0x2
 FDEMRI_CTX_BATCH_GRAPHS = 0x1
 FDEMRI_FLAG_PIECE_OVERFLOW = 0x1
 FDEMRI_FLAG_BAD_MODE = 0x2
+FDEMRI_FLAG_TRAJ_STEPS = 0x4
 FDEMRI_LL_HANN = 0x1
 PRECISIONS = {"fp64": FDEMRI_FP64, "mixed": FDEMRI_MIXED}
 
@@ -34,9 +35,14 @@ EXPORTED = [
     "fdemri_create", "fdemri_destroy", "fdemri_last_error", "fdemri_sync_flags",
     "fdemri_waveform", "fdemri_waveform_batch", "fdemri_vjp", "fdemri_last_eval_count",
     "fdemri_profile_enable", "fdemri_profile_read", "fdemri_autotune", "fdemri_loglike",
-    "fdemri_loglike_batch", "fdemri_select_modes", "fdemri_td_waveform",
+    "fdemri_loglike_batch", "fdemri_select_modes", "fdemri_td_waveform", "fdemri_trajectory",
 ]
 KERNEL_CLASSES = ["spline", "pieces", "gather", "vjp"]
+
+
+class TrajParams(ctypes.Structure):
+    """fdemri_traj_params: M, mu (solar masses), p0, e0, T (s), Phiphi0, Phir0 (rad)."""
+    _fields_ = [(n, ctypes.c_double) for n in ("M", "mu", "p0", "e0", "T", "Phiphi0", "Phir0")]
 
 
 class FdemriError(RuntimeError):
@@ -91,6 +97,8 @@ def lib():
         L.fdemri_loglike.restype = ctypes.c_int
         L.fdemri_select_modes.argtypes = [vp, i32, i32, vp, ctypes.c_double, vp, vp, vp]
         L.fdemri_select_modes.restype = ctypes.c_int
+        L.fdemri_trajectory.argtypes = [vp, i32, ctypes.POINTER(TrajParams), i32, vp, vp]
+        L.fdemri_trajectory.restype = ctypes.c_int
         L.fdemri_td_waveform.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_double, ctypes.c_double, i32,
                                          vp, vp, vp]
         L.fdemri_td_waveform.restype = ctypes.c_int
@@ -278,6 +286,17 @@ class Context:
         self._check(self._lib.fdemri_td_waveform(self._h, ctypes.byref(d), float(t0), float(dt), int(Nt),
                                                  _ptr(hp), _ptr(hc), _stream(self.device)))
         return hp, hc
+
+    def trajectory(self, params, K):
+        """fdemri_trajectory for a list of dicts with keys M, mu, p0, e0, T and
+        optionally Phiphi0, Phir0: a float64 device tensor [B, 7, K] with rows
+        t, Fphi, Fr, Phiphi, Phir, p, e."""
+        B = len(params)
+        arr = (TrajParams * B)(*[TrajParams(P["M"], P["mu"], P["p0"], P["e0"], P["T"], P.get("Phiphi0", 0.0),
+                                            P.get("Phir0", 0.0)) for P in params])
+        out = torch.empty(B, 7, K, dtype=torch.float64, device=self.device)
+        self._check(self._lib.fdemri_trajectory(self._h, B, arr, K, _ptr(out), _stream(self.device)))
+        return out
 
     def select_modes(self, A, eps):
         """fdemri_select_modes: indices (int32 device tensor, table order) of the

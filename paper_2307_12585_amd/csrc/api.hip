@@ -40,6 +40,7 @@ int gather_items_per_waveform(int Nf, int bpl);
 hipError_t launch_td(int K, int Nm, const double* t, const double* Phiphi, const double* Phir, const double* tcoef,
                      const double* acoef, const ModeConst* modes, double t0, double dt, int Nt, double* hp, double* hc,
                      hipStream_t stream);
+hipError_t launch_trajectory(const void* params, int B, int K, double* out, uint32_t* flag_word, hipStream_t stream);
 hipError_t launch_select_modes(int K, int Nm, const double* A, double eps, double* P, int32_t* keep, int32_t* idx,
                                int32_t* n_keep, hipStream_t stream);
 int loglike_tiles(int Nf, int bpl);
@@ -468,6 +469,35 @@ fdemri_status fdemri_td_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, d
     e = launch_td(d->K, d->Nm, d->t, d->Phiphi, d->Phir, p.tcoef, p.acoef, p.modes, t0, dt, Nt, hp_t, hc_t, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "time-domain kernel launch");
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_trajectory(fdemri_ctx* c, int32_t B, const fdemri_traj_params* params, int32_t K, double* out,
+                                hipStream_t stream) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  if (B < 0 || K < 4 || K > kMaxKnots) return fail(c, FDEMRI_EINVAL, "invalid sizes B=%d K=%d", B, K);
+  if (B == 0) return FDEMRI_OK;
+  if (!params || !out) return fail(c, FDEMRI_EINVAL, "NULL pointer");
+  for (int b = 0; b < B; ++b) {
+    const fdemri_traj_params& P = params[b];
+    const bool ok = std::isfinite(P.M) && P.M > 0 && std::isfinite(P.mu) && P.mu > 0 && std::isfinite(P.T) &&
+                    P.T > 0 && P.e0 >= 0 && P.e0 < 1 && std::isfinite(P.p0) && P.p0 > 6.0 + 2.0 * P.e0 + 0.1 &&
+                    std::isfinite(P.Phiphi0) && std::isfinite(P.Phir0);
+    if (!ok) return fail(c, FDEMRI_EINVAL, "waveform %d: invalid trajectory parameters", b);
+  }
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const size_t bytes = (size_t)B * sizeof(fdemri_traj_params);
+  fdemri_status st = ensure_ws(c, bytes);
+  if (st != FDEMRI_OK) return st;
+  // the parameters go through the workspace; the copy from pageable host
+  // memory completes before this call returns
+  e = hipMemcpyAsync(c->ws, params, bytes, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(c, e, "parameter upload");
+  e = launch_trajectory(c->ws, B, K, out, c->flag_word, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "trajectory kernel launch");
   return FDEMRI_OK;
 }
 
