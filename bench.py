@@ -280,6 +280,15 @@ def main():
                                         "rel_l2_vs_fp64": mix_err}
     secondary["loglike_fused_fp64"] = loglike_measure(ctx, W, dw, hp, hc, dev, max(5, args.steps // 2))
     secondary["td_vs_fd_fp64"] = td_measure(ctx, W, dw, hp, hc, dev, sec)
+    # adaptive downsampled grid (Sec. 3.3) for the same source, tol 1e-3 on <h|h>
+    from paper_2307_12585_amd.downsample import adaptive_grid, hh_on_grid
+    ts = time.perf_counter()
+    grid, hist = adaptive_grid(ctx, w, W.psd_closed_form, tol=1e-3, n0=256)
+    ds_ms = (time.perf_counter() - ts) * 1e3
+    hh_full = hh_on_grid(ctx, w, w.f, W.psd_closed_form)
+    secondary["downsampled_grid"] = {"bins": int(grid.size - 1), "full_grid_bins": int(w.f.size),
+                                     "hh_downsampled": hist[-2][1], "hh_full_grid": hh_full,
+                                     "levels": len(hist), "selection_ms": ds_ms}
     # trajectories on the device: 512 draws of the batch distribution, K = 100
     prms = W.batch_params(512, 77)
     tp = [dict(M=P["M"], mu=P["mu"], p0=P["p0"], e0=P["e0"], T=P["T"]) for P in prms]

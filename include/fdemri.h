@@ -279,6 +279,16 @@ fdemri_status fdemri_trajectory(fdemri_ctx *ctx, int32_t B, const fdemri_traj_pa
                                 double *out, hipStream_t stream);
 
 /*
+ * Frequency band occupied by the waveform of `desc` (Sec. 3.3: a downsampled
+ * grid spans only [0, f_max] of the signal): band[0], band[1] (DEVICE
+ * doubles) = the smallest and largest |F_V| at the ends of the monotonic
+ * pieces of all voices (0, 0 without voices).  The frequency array of desc
+ * is validated but not used.
+ */
+fdemri_status fdemri_signal_band(fdemri_ctx *ctx, const fdemri_waveform_desc *desc, double *band,
+                                 hipStream_t stream);
+
+/*
  * Mode selection by power (Sec. 2.1: modes are kept by their share of the
  * total power; the share is taken at every knot and the union kept):
  * row mu of A is kept when |A_mu(t_i)|^2 > eps * sum_nu |A_nu(t_i)|^2 at one

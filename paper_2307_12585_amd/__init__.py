@@ -36,6 +36,7 @@ EXPORTED = [
     "fdemri_waveform", "fdemri_waveform_batch", "fdemri_vjp", "fdemri_last_eval_count",
     "fdemri_profile_enable", "fdemri_profile_read", "fdemri_autotune", "fdemri_loglike",
     "fdemri_loglike_batch", "fdemri_select_modes", "fdemri_td_waveform", "fdemri_trajectory",
+    "fdemri_signal_band",
 ]
 KERNEL_CLASSES = ["spline", "pieces", "gather", "vjp"]
 
@@ -97,6 +98,8 @@ def lib():
         L.fdemri_loglike.restype = ctypes.c_int
         L.fdemri_select_modes.argtypes = [vp, i32, i32, vp, ctypes.c_double, vp, vp, vp]
         L.fdemri_select_modes.restype = ctypes.c_int
+        L.fdemri_signal_band.argtypes = [vp, ctypes.POINTER(WaveformDesc), vp, vp]
+        L.fdemri_signal_band.restype = ctypes.c_int
         L.fdemri_trajectory.argtypes = [vp, i32, ctypes.POINTER(TrajParams), i32, vp, vp]
         L.fdemri_trajectory.restype = ctypes.c_int
         L.fdemri_td_waveform.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_double, ctypes.c_double, i32,
@@ -297,6 +300,14 @@ class Context:
         out = torch.empty(B, 7, K, dtype=torch.float64, device=self.device)
         self._check(self._lib.fdemri_trajectory(self._h, B, arr, K, _ptr(out), _stream(self.device)))
         return out
+
+    def signal_band(self, dw: DeviceWaveform):
+        """(f_min, f_max) of the voices of dw (fdemri_signal_band; synchronises)."""
+        band = torch.empty(2, dtype=torch.float64, device=dw.device)
+        d = dw.desc()
+        self._check(self._lib.fdemri_signal_band(self._h, ctypes.byref(d), _ptr(band), _stream(self.device)))
+        b = band.cpu()
+        return float(b[0]), float(b[1])
 
     def select_modes(self, A, eps):
         """fdemri_select_modes: indices (int32 device tensor, table order) of the

@@ -41,6 +41,7 @@ hipError_t launch_td(int K, int Nm, const double* t, const double* Phiphi, const
                      const double* acoef, const ModeConst* modes, double t0, double dt, int Nt, double* hp, double* hc,
                      hipStream_t stream);
 hipError_t launch_trajectory(const void* params, int B, int K, double* out, uint32_t* flag_word, hipStream_t stream);
+hipError_t launch_band(int Nm, const ModeConst* modes, const Piece* pieces, double* band, hipStream_t stream);
 hipError_t launch_select_modes(int K, int Nm, const double* A, double eps, double* P, int32_t* keep, int32_t* idx,
                                int32_t* n_keep, hipStream_t stream);
 int loglike_tiles(int Nf, int bpl);
@@ -498,6 +499,26 @@ fdemri_status fdemri_trajectory(fdemri_ctx* c, int32_t B, const fdemri_traj_para
   if (e != hipSuccess) return hip_fail(c, e, "parameter upload");
   e = launch_trajectory(c->ws, B, K, out, c->flag_word, stream);
   if (e != hipSuccess) return hip_fail(c, e, "trajectory kernel launch");
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_signal_band(fdemri_ctx* c, const fdemri_waveform_desc* d, double* band, hipStream_t stream) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  fdemri_status st = validate(c, d);
+  if (st != FDEMRI_OK) return st;
+  if (!band) return fail(c, FDEMRI_EINVAL, "NULL output pointer");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  const Layout L = layout_for(d->K, d->Nm, false);
+  st = ensure_ws(c, L.total);
+  if (st != FDEMRI_OK) return st;
+  Prepared p;
+  float* acoef32 = nullptr;
+  st = prepare(c, d, false, L, p, acoef32, stream);
+  if (st != FDEMRI_OK) return st;
+  e = launch_band(d->Nm, p.modes, p.pieces, band, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "band kernel launch");
   return FDEMRI_OK;
 }
 

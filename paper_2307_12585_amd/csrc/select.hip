@@ -86,3 +86,44 @@ hipError_t launch_select_modes(int K, int Nm, const double* A, double eps, doubl
 }
 
 }  // namespace fdemri
+
+namespace fdemri {
+
+// Frequency band of a waveform's voices (Sec. 3.3: a downsampled grid spans
+// only the band the signal occupies): the smallest and largest |F_V| over the
+// ends of all monotonic pieces of all voices.  One workgroup; min and max are
+// exact, so the result does not depend on the order.
+__global__ __launch_bounds__(kSelThreads) void band_kernel(int Nm, const ModeConst* __restrict__ modes,
+                                                           const Piece* __restrict__ pieces, double* __restrict__ band) {
+  __shared__ double lo[kSelThreads], hi[kSelThreads];
+  double a = __builtin_inf(), b = 0.0;
+  for (int mu = threadIdx.x; mu < Nm; mu += kSelThreads) {
+    const int np = modes[mu].npieces;
+    for (int q = 0; q < np; ++q) {
+      const Piece& P = pieces[(size_t)mu * kMaxPieces + q];
+      a = fmin(a, fmin(P.g_a, P.g_b));
+      b = fmax(b, fmax(P.g_a, P.g_b));
+    }
+  }
+  lo[threadIdx.x] = a;
+  hi[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = kSelThreads / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + w]);
+      hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    band[0] = (lo[0] == __builtin_inf()) ? 0.0 : fabs(lo[0]);  // +0 for a zero crossing
+    band[1] = hi[0];
+  }
+}
+
+hipError_t launch_band(int Nm, const ModeConst* modes, const Piece* pieces, double* band, hipStream_t stream) {
+  band_kernel<<<1, kSelThreads, 0, stream>>>(Nm, modes, pieces, band);
+  return hipGetLastError();
+}
+
+}  // namespace fdemri
