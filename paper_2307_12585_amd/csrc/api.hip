@@ -29,7 +29,8 @@ struct GatherArgs;
 hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp, void* hc, bool mixed, int bpl,
                               hipStream_t stream);
 hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, hipStream_t stream);
-hipError_t launch_spline_batch(const WaveItem* items, int B, const int32_t* series_prefix, int total_series, int Kmax,
+int spline_blocks(int n_series);
+hipError_t launch_spline_batch(const WaveItem* items, int B, const int32_t* block_prefix, int total_blocks, int Kmax,
                                hipStream_t stream);
 hipError_t launch_pieces_batch(const WaveItem* items, int B, const int32_t* mode_prefix, int total_modes,
                                uint32_t* flag_word, hipStream_t stream);
@@ -629,7 +630,7 @@ fdemri_status plan_batch(fdemri_ctx* c, int B, const fdemri_waveform_desc* descs
     P.base[b] = off;
     off = align_up(off + P.Ls[b].total, 256);
     P.Kmax = std::max(P.Kmax, (int)descs[b].K);
-    P.n_series += 4 + ((descs[b].flags & FDEMRI_COEFFS_GIVEN) ? 0 : descs[b].Nm);
+    P.n_series += spline_blocks(4 + ((descs[b].flags & FDEMRI_COEFFS_GIVEN) ? 0 : descs[b].Nm));
     P.n_modes += descs[b].Nm;
     P.n_amp += (int64_t)descs[b].Nm * (descs[b].K - 1);
     P.n_items += gather_items_per_waveform(descs[b].Nf, c->bpl);
@@ -698,7 +699,7 @@ void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc*
     it.ll_partial = P.ll ? (double*)(wb + L.ll_partial) : nullptr;
     it.ll_edge = P.ll ? (double*)(wb + L.ll_edge) : nullptr;
     hitems[b] = it;
-    series_prefix[b + 1] = series_prefix[b] + 4 + ((d.flags & FDEMRI_COEFFS_GIVEN) ? 0 : d.Nm);
+    series_prefix[b + 1] = series_prefix[b] + spline_blocks(4 + ((d.flags & FDEMRI_COEFFS_GIVEN) ? 0 : d.Nm));
     mode_prefix[b + 1] = mode_prefix[b] + d.Nm;
     amp_prefix[b + 1] = amp_prefix[b] + d.Nm * (d.K - 1);
     item_prefix[b + 1] = item_prefix[b] + gather_items_per_waveform(d.Nf, c->bpl);
