@@ -29,6 +29,11 @@ FLOPS_PER_EVAL = 186
 PEAK_FP64_VALU = 78.6e12
 
 
+def progress(msg):
+    """A line on stderr as each stage of a long measurement ends."""
+    print(msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,9 +95,11 @@ def batch_measure(ctx, W, fd, dev, B):
     ws = [W.batch_workload(prm) for prm in W.batch_params(B, 4)]
     dws = [fd.DeviceWaveform.from_workload(w, device=dev) for w in ws]
     bins = sum(w.Nf for w in ws)
+    progress(f"batch: {B} waveforms, {bins} bins on the device")
     ref = ctx.waveform_batch(dws, "fp64")
     torch.cuda.synchronize()
     evals = ctx.last_eval_count()
+    progress(f"batch: FP64 reference done ({evals} evals)")
     outs = ctx.waveform_batch(dws, "mixed")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -101,6 +108,7 @@ def batch_measure(ctx, W, fd, dev, B):
         ctx.waveform_batch(dws, "mixed", outs=outs)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / reps
+    progress(f"batch: mixed {sec:.3f} s per batch")
     errs = []
     for (mp, mc), (rp, rc) in zip(outs, ref):
         for a, b in ((mp, rp), (mc, rc)):
@@ -111,7 +119,9 @@ def batch_measure(ctx, W, fd, dev, B):
     # FP64 waveform + noise of the closed-form PSD, Hann-windowed comparison
     import numpy as np
     dps, dcs, wss = [], [], []
-    for w, (rp, rc) in zip(ws, ref):
+    for i, (w, (rp, rc)) in enumerate(zip(ws, ref)):
+        if i % 64 == 63:
+            progress(f"batch: likelihood data {i + 1}/{B}")
         S = W.psd_closed_form(w.f)
         df = float(w.f[1] - w.f[0])
         wss.append(torch.as_tensor(np.where(np.isfinite(S), 4.0 * df / np.where(np.isfinite(S), S, 1.0), 0.0),
@@ -120,6 +130,7 @@ def batch_measure(ctx, W, fd, dev, B):
         dps.append((rp + torch.as_tensor(n_p, device=dev)).to(torch.complex64).contiguous())
         dcs.append((rc + torch.as_tensor(n_c, device=dev)).to(torch.complex64).contiguous())
     del ref, outs
+    progress("batch: likelihood data on the device")
     llo = ctx.loglike_batch(dws, dps, dcs, wss, prec="mixed", hann=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -127,6 +138,7 @@ def batch_measure(ctx, W, fd, dev, B):
         ctx.loglike_batch(dws, dps, dcs, wss, prec="mixed", hann=True, out=llo)
     torch.cuda.synchronize()
     sec_ll = (time.perf_counter() - t0) / reps
+    progress(f"batch: fused likelihood {sec_ll:.3f} s per batch")
     del dps, dcs, wss
     return {"waveforms": B, "bins": bins, "evals": evals, "seconds_per_batch": sec,
             "waveforms_per_s": B / sec, "evals_per_s": evals / sec,
@@ -161,7 +173,7 @@ def adjoint_measure(ctx, W, fd, dev, B):
         nb = float(torch.linalg.vector_norm(b))
         return float(torch.linalg.vector_norm(a.to(b.dtype) - b)) / nb if nb > 0 else 0.0
 
-    for w in ws:
+    for i, w in enumerate(ws):
         dw_true = fd.DeviceWaveform.from_workload(w, device=dev)
         traj = dataclasses.replace(w.traj, Phiphi=w.traj.Phiphi + 0.3)
         tpl = dataclasses.replace(w, traj=traj, A=w.A * (1.02 * np.exp(0.05j)), theta=w.theta + 0.01)
@@ -197,6 +209,7 @@ def adjoint_measure(ctx, W, fd, dev, B):
         for k in keys:
             e2e[k] = max(e2e[k], rel(g[k], ref[k]))
             vjp_only[k] = max(vjp_only[k], rel(only[k], ref[k]))
+        progress(f"forward+adjoint: {i + 1}/{B} draws, {evals} evals")
     return {"waveforms": B, "evals_forward": evals, "seconds": tot, "waveforms_per_s": B / tot,
             "evals_per_s_forward_plus_adjoint": evals / tot,
             "forward_rel_l2_vs_fp64_max": fwd_err,
