@@ -170,9 +170,29 @@ __device__ __forceinline__ void sincos_cw(double x, double* sn, double* cs) {
 
 // E = e^{i psi} G and the amplitude spline value A at the root (FP64);
 // w = 2 pi f, (ms, ns) = (s m, s n).
+// The amplitude spline coefficients of one segment, (re, im) pairs in
+// ascending powers: read as a whole by the caller, so that the loads can be
+// issued as soon as the segment is known and their latency overlaps the root
+// solve.
+struct AmpSeg64 {
+  double2 c[4];
+};
+struct AmpSeg32 {
+  float4 lo, hi;  // (re0, im0, re1, im1), (re2, im2, re3, im3)
+};
+
+__device__ __forceinline__ AmpSeg64 load_amp64(const double* __restrict__ ac_seg) {
+  const double2* q = (const double2*)ac_seg;
+  return AmpSeg64{{q[0], q[1], q[2], q[3]}};
+}
+
+__device__ __forceinline__ AmpSeg32 load_amp32(const float* __restrict__ ac32_seg) {
+  const float4* q = (const float4*)ac32_seg;
+  return AmpSeg32{q[0], q[1]};
+}
+
 __device__ __forceinline__ void root_terms64(double f, double w, double tau, int d, double ms, double ns,
-                                             const SegData& S, const double* __restrict__ ac_seg, double2& E,
-                                             double2& A) {
+                                             const SegData& S, const AmpSeg64& c, double2& E, double2& A) {
   const double gd = S.q1 + tau * (2.0 * S.q2 + 3.0 * S.q3 * tau);
   const double gdd = 2.0 * S.q2 + 6.0 * S.q3 * tau;
   const double psi = phase_psi(f, w, tau, ms, ns, S);
@@ -180,15 +200,20 @@ __device__ __forceinline__ void root_terms64(double f, double w, double tau, int
   double sn, cs;
   sincos_cw(psi, &sn, &cs);
   E = make_double2(cs * G.x - sn * G.y, cs * G.y + sn * G.x);
-  const double* c = ac_seg;
-  A = make_double2(c[0] + tau * (c[2] + tau * (c[4] + tau * c[6])), c[1] + tau * (c[3] + tau * (c[5] + tau * c[7])));
+  A = make_double2(c.c[0].x + tau * (c.c[1].x + tau * (c.c[2].x + tau * c.c[3].x)),
+                   c.c[0].y + tau * (c.c[1].y + tau * (c.c[2].y + tau * c.c[3].y)));
+}
+
+__device__ __forceinline__ void root_terms64(double f, double w, double tau, int d, double ms, double ns,
+                                             const SegData& S, const double* __restrict__ ac_seg, double2& E,
+                                             double2& A) {
+  root_terms64(f, w, tau, d, ms, ns, S, load_amp64(ac_seg), E, A);
 }
 
 // Mixed precision: root, derivatives, phase and its reduction in FP64; the
 // factor, sincos and the (normalised) amplitude spline in FP32.
 __device__ __forceinline__ void root_terms32(double f, double w, double tau, int d, double ms, double ns,
-                                             const SegData& S, const float* __restrict__ ac32_seg, float2& E,
-                                             float2& A) {
+                                             const SegData& S, const AmpSeg32& c, float2& E, float2& A) {
   const double gd = S.q1 + tau * (2.0 * S.q2 + 3.0 * S.q3 * tau);
   const double gdd = 2.0 * S.q2 + 6.0 * S.q3 * tau;
   const double psi = phase_psi(f, w, tau, ms, ns, S);
@@ -198,8 +223,13 @@ __device__ __forceinline__ void root_terms32(double f, double w, double tau, int
   sincosf((float)psr, &sn, &cs);
   E = make_float2(cs * G.x - sn * G.y, cs * G.y + sn * G.x);
   const float u = (float)tau * __builtin_amdgcn_rcpf((float)S.h);  // tau / h to FP32 accuracy
-  const float* c = ac32_seg;
-  A = make_float2(c[0] + u * (c[2] + u * (c[4] + u * c[6])), c[1] + u * (c[3] + u * (c[5] + u * c[7])));
+  A = make_float2(c.lo.x + u * (c.lo.z + u * (c.hi.x + u * c.hi.z)), c.lo.y + u * (c.lo.w + u * (c.hi.y + u * c.hi.w)));
+}
+
+__device__ __forceinline__ void root_terms32(double f, double w, double tau, int d, double ms, double ns,
+                                             const SegData& S, const float* __restrict__ ac32_seg, float2& E,
+                                             float2& A) {
+  root_terms32(f, w, tau, d, ms, ns, S, load_amp32(ac32_seg), E, A);
 }
 
 }  // namespace fdemri

@@ -147,6 +147,15 @@ __device__ __forceinline__ void eval_bin(const double f, const double w, const P
     G0 = knot_freq(ms, L.knot(i).Fp, ns, L.knot(i).Fr);
     G1 = knot_freq(ms, L.knot(i + 1).Fp, ns, L.knot(i + 1).Fr);
   }
+  // the segment's amplitude coefficients, requested now so that the loads
+  // are in flight during the root solve (32-bit byte offset from the mode's
+  // wave-uniform base: one shift)
+  AmpSeg64 a64;
+  AmpSeg32 a32;
+  if constexpr (!MIXED)
+    a64 = load_amp64((const double*)((const char*)ac + ((uint32_t)i << 6)));
+  else
+    a32 = load_amp32((const float*)((const char*)ac32 + ((uint32_t)i << 5)));
   SegData S;
   const klds KnotRec& kr = L.knot(i);
   S.ti = kr.t;
@@ -167,9 +176,7 @@ __device__ __forceinline__ void eval_bin(const double f, const double w, const P
 
   if constexpr (!MIXED) {
     double2 E, A;
-    // 32-bit byte offset from the mode's (wave-uniform) base: one shift
-    const double* acs = (const double*)((const char*)ac + ((uint32_t)i << 6));
-    root_terms64(f, w, tau, P.d, ms, ns, S, acs, E, A);
+    root_terms64(f, w, tau, P.d, ms, ns, S, a64, E, A);
     const double ay = A.y * P.sd;  // A conjugated on s < 0 pieces
     const double Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
     acc.v[0] += cP.x * Wr - cP.y * Wi;
@@ -178,8 +185,7 @@ __device__ __forceinline__ void eval_bin(const double f, const double w, const P
     acc.v[3] += cX.x * Wi + cX.y * Wr;
   } else {
     float2 E, A;
-    const float* acs = (const float*)((const char*)ac32 + ((uint32_t)i << 5));
-    root_terms32(f, w, tau, P.d, ms, ns, S, acs, E, A);
+    root_terms32(f, w, tau, P.d, ms, ns, S, a32, E, A);
     const float ay = A.y * (float)P.sd;
     const float Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
     const float pr = (float)cP.x, pi = (float)cP.y, xr = (float)cX.x, xi = (float)cX.y;
