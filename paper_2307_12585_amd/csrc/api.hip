@@ -20,11 +20,11 @@ hipError_t launch_spline(int K, const double* t, const double* Fphi, const doubl
                          const double* Phir, const double* A, int Nm, double* tcoef, double* acoef,
                          hipStream_t stream);
 struct PieceArgs;
-hipError_t launch_pieces_flat(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
-                              const double* f, const double* tcoef, const int32_t* l, const int32_t* m,
-                              const int32_t* n, double theta, double phi, double scale, uint32_t flags,
-                              ModeConst* modes, int2* mode_kr, Piece* pieces, int64_t* evals, int32_t* env,
-                              uint32_t* flag_word, hipStream_t stream);
+hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
+                             const double* f, const double* tcoef, const int32_t* l, const int32_t* m,
+                             const int32_t* n, double theta, double phi, double scale, uint32_t flags,
+                             const double* A, double* acoef, ModeConst* modes, int2* mode_kr, Piece* pieces,
+                             int64_t* evals, int32_t* env, uint32_t* flag_word, hipStream_t stream);
 struct GatherArgs;
 hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp, void* hc, bool mixed, int bpl,
                               hipStream_t stream);
@@ -357,14 +357,17 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   int32_t* env = (int32_t*)(w + L.env);
   hipError_t e;
   {
+    // the trajectory splines first: the piece tables need them
     ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream);
-    e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, given ? 0 : d->Nm, tcoef, acoef, stream);
+    e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, 0, tcoef, acoef, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "spline kernel launch");
   {
+    // piece tables and amplitude splines in one launch, then the envelope
     ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream);
-    e = launch_pieces_flat(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->f, tcoef, d->l, d->m, d->n, d->theta, d->phi,
-                           d->scale, d->flags, modes, mode_kr, pieces, evals, env, c->flag_word, stream);
+    e = launch_setup_flat(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->f, tcoef, d->l, d->m, d->n, d->theta,
+                          d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, modes, mode_kr, pieces, evals,
+                          env, c->flag_word, stream);
     if (e == hipSuccess && mixed) e = launch_amp32(d->Nm, d->K, d->t, acoef, acoef32, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "piece kernel launch");

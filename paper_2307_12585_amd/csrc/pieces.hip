@@ -24,6 +24,7 @@
 #include "fdemri_internal.hpp"
 #include "harmonics.hpp"
 #include "search.hpp"
+#include "spline_core.hpp"
 
 namespace fdemri {
 
@@ -378,16 +379,8 @@ __global__ __launch_bounds__(256) void envelope_batch_kernel(const WaveItem* __r
   envelope_block(w.mode_kr, w.Nm, w.env);
 }
 
-// One wavefront per mode, kPieceWaves modes per workgroup.
+// Batched pieces: one wavefront per mode, kPieceWaves modes per workgroup.
 constexpr int kPieceWaves = 4;
-
-__global__ __launch_bounds__(64 * kPieceWaves) void pieces_kernel(PieceArgs a) {
-  __shared__ Event ev[kPieceWaves][kMaxEvents];
-  const int wave = threadIdx.x >> 6;
-  const int mu = blockIdx.x * kPieceWaves + wave;
-  if (mu >= a.Nm) return;
-  piece_mode_wave(a, mu, ev[wave]);
-}
 
 __device__ PieceArgs piece_args_of(const WaveItem& w, uint32_t* flag_word) {
   PieceArgs a;
@@ -442,11 +435,39 @@ hipError_t launch_pieces_batch(const WaveItem* items, int B, const int32_t* mode
   return hipGetLastError();
 }
 
-hipError_t launch_pieces_flat(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
-                              const double* f, const double* tcoef, const int32_t* l, const int32_t* m,
-                              const int32_t* n, double theta, double phi, double scale, uint32_t flags,
-                              ModeConst* modes, int2* mode_kr, Piece* pieces, int64_t* evals, int32_t* env,
-                              uint32_t* flag_word, hipStream_t stream) {
+// Set-up of one waveform after its trajectory splines: the piece tables (one
+// wave per mode) and the amplitude splines (kSeriesPerBlock modes per
+// workgroup, all sharing the knot matrix) in one launch, the pieces'
+// workgroups first.  The two parts are independent, so the amplitude
+// splines fill the machine while the latency-bound piece walks run, instead
+// of taking a launch of their own before them.
+template <int NT>
+__global__ __launch_bounds__(NT) void setup_kernel(PieceArgs a, int piece_blocks, const double* __restrict__ A,
+                                                   double* __restrict__ acoef) {
+  constexpr int W = NT / 64;
+  // LDS of either part: the spline's tables or the waves' event buffers
+  constexpr size_t kBytes = sizeof(SplineLds<NT>) > sizeof(Event) * W * kMaxEvents ? sizeof(SplineLds<NT>)
+                                                                                     : sizeof(Event) * W * kMaxEvents;
+  __shared__ double lds[kBytes / sizeof(double)];
+  if ((int)blockIdx.x < piece_blocks) {
+    const int wave = threadIdx.x >> 6;
+    const int mu = (int)blockIdx.x * W + wave;
+    if (mu < a.Nm) piece_mode_wave(a, mu, (Event*)lds + wave * kMaxEvents);
+    return;
+  }
+  const int s0 = 4 + ((int)blockIdx.x - piece_blocks) * kSeriesPerBlock;
+  // series 4 + mu only: the trajectory arguments are never read here
+  spline_block<NT>(*(SplineLds<NT>*)lds, s0, 4 + a.Nm, a.K, a.t, a.Fphi, a.Fr, a.Fphi, a.Fr, A, acoef, acoef);
+}
+
+// The piece tables and, unless A is NULL, the amplitude splines of Nm modes
+// (acoef [Nm][K-1][8]) in one launch, then the bin envelope.  The trajectory
+// spline coefficients tcoef must be in place (stream order).
+hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
+                             const double* f, const double* tcoef, const int32_t* l, const int32_t* m,
+                             const int32_t* n, double theta, double phi, double scale, uint32_t flags,
+                             const double* A, double* acoef, ModeConst* modes, int2* mode_kr, Piece* pieces,
+                             int64_t* evals, int32_t* env, uint32_t* flag_word, hipStream_t stream) {
   PieceArgs a;
   a.K = K;
   a.Nm = Nm;
@@ -468,7 +489,14 @@ hipError_t launch_pieces_flat(int K, int Nm, int Nf, const double* t, const doub
   a.pieces = pieces;
   a.evals = evals;
   a.flag_word = flag_word;
-  pieces_kernel<<<(Nm + kPieceWaves - 1) / kPieceWaves, 64 * kPieceWaves, 0, stream>>>(a);
+  const int amp_blocks = A ? (Nm + kSeriesPerBlock - 1) / kSeriesPerBlock : 0;
+  if (K <= 256) {
+    const int pb = (Nm + 3) / 4;
+    setup_kernel<256><<<pb + amp_blocks, 256, 0, stream>>>(a, pb, A, acoef);
+  } else {
+    const int pb = (Nm + 7) / 8;
+    setup_kernel<512><<<pb + amp_blocks, 512, 0, stream>>>(a, pb, A, acoef);
+  }
   envelope_kernel<<<1, 256, 0, stream>>>(mode_kr, Nm, env);
   return hipGetLastError();
 }
