@@ -287,12 +287,13 @@ __device__ __forceinline__ void walk_list(const Prepared& p, const void* __restr
   const int lane = threadIdx.x & 63;
   const int k = ks + lane;
   const int nseg = p.K - 1;
-  const kconst int2* kr = (const kconst int2*)p.mode_kr;
   for (int e = 0; e < n; ++e) {
     const int mode = __builtin_amdgcn_readfirstlane(list[e]);
-    const int2 r = kr[mode];
-    if (r.x > ke || r.y < ks) continue;
+    // the whole 64-B record in one scalar load: its bin range decides, its
+    // constants follow (a test on the range table first, with short-circuit
+    // evaluation, would cost dependent round trips per entry)
     const ModeConst md = ((const kconst ModeConst*)p.modes)[mode];
+    if ((md.k_lo > ke) | (md.k_hi < ks)) continue;
     const kconst Piece* pcs = (const kconst Piece*)p.pieces + (size_t)mode * kMaxPieces;
     for (int q = 0; q < md.npieces; ++q) {
       const Piece P = pcs[q];
