@@ -44,6 +44,24 @@ def test_batch_equals_single_calls(ctx, prec):
     assert total == counts > 0
 
 
+def test_batch_with_maximum_knot_counts(ctx):
+    """Members with K = 512 (FDEMRI_MAX_KNOTS) and 257 beside a small one: the
+    batched spline, piece and gather kernels at their largest tables equal
+    single calls."""
+    ws = [W.inspiral_20_modes(K=512), W.inspiral_20_modes(K=257), W.inspiral_20_modes(K=40)]
+    for w in ws:
+        w.f = w.f[:200_000]
+    dws = [fd.DeviceWaveform.from_workload(w, device=ctx.device) for w in ws]
+    for prec in ("fp64", "mixed"):
+        outs = ctx.waveform_batch(dws, prec)
+        torch.cuda.synchronize()
+        assert ctx.sync_flags() == 0
+        for dw, (bp, bc) in zip(dws, outs):
+            sp, sc = ctx.waveform_dev(dw, prec)
+            torch.cuda.synchronize()
+            assert torch.equal(bp, sp) and torch.equal(bc, sc)
+
+
 def test_batch_repeat_deterministic(ctx):
     ws = batch_members()
     dws = [fd.DeviceWaveform.from_workload(w, device=ctx.device) for w in ws]

@@ -77,6 +77,19 @@ def test_3842_modes_sampled_bins(ctx):
     assert np.all(hp[w.f > 1.2e-2] == 0)
 
 
+@pytest.mark.parametrize("K", [129, 257, 512])
+def test_knot_counts_up_to_the_maximum(ctx, K):
+    """Knot counts past each block-size step of the spline and set-up kernels,
+    up to FDEMRI_MAX_KNOTS (the largest trajectory tables the gather stages in
+    LDS): FP64 against the oracle, mixed against FP64."""
+    w = W.inspiral_20_modes(K=K)
+    h64 = gpu_waveform(ctx, w)
+    _check64(h64, oracle.waveform(w), f"inspiral_20_modes K={K}")
+    hm = gpu_waveform(ctx, w, prec="mixed")
+    for g, o in zip(hm, h64):
+        assert rel_l2(g.astype(np.complex128), o) <= TOLMIX
+
+
 def test_linear_chirp_and_turnover(ctx):
     from test_oracle_waveform import turnover_workload
     for w in [W.linear_chirp_workload(f0=1e-4, fdot=1e-9, T=1e5, Nf=3001),

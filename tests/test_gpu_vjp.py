@@ -59,6 +59,24 @@ def test_vjp_matches_oracle(ctx, partners):
     assert rel_l2(out["gPhi_knots"].cpu().numpy(), knp) <= 1e-8
 
 
+def test_vjp_matches_oracle_at_max_knots(ctx):
+    """The adjoint and its transposed spline solve at FDEMRI_MAX_KNOTS knots."""
+    w0 = W.inspiral_20_modes(K=512)
+    sel = np.array([2, 9])
+    w0.l, w0.m, w0.n, w0.A = w0.l[sel], w0.m[sel], w0.n[sel], w0.A[sel]
+    w0.f = w0.f[::5]
+    g_p, g_c = cotangents(w0.Nf, 4)
+    ref = waveform_vjp(w0, g_p, g_c)
+    dw = fd.DeviceWaveform.from_workload(w0, device=ctx.device)
+    out = ctx.vjp_dev(dw, torch.as_tensor(g_p, device=ctx.device), torch.as_tensor(g_c, device=ctx.device))
+    torch.cuda.synchronize()
+    assert rel_l2(out["gA"].cpu().numpy(), ref["gA"]) <= 1e-9
+    kn = coef_grad_to_knots(w0.traj.t, ref["gA"])
+    assert rel_l2(out["gA_knots"].cpu().numpy(), kn) <= 1e-9
+    knp = coef_grad_to_knots(w0.traj.t, ref["gPhi"])
+    assert rel_l2(out["gPhi_knots"].cpu().numpy(), knp) <= 1e-8
+
+
 def _whittle(hp, hc, dp, dc, S, wts):
     L = 0.0
     for h, d in ((hp, dp), (hc, dc)):
