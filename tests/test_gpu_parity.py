@@ -90,6 +90,56 @@ def test_knot_counts_up_to_the_maximum(ctx, K):
         assert rel_l2(g.astype(np.complex128), o) <= TOLMIX
 
 
+def _replicas(w, sel, reps, seed, real=False):
+    """The rows `sel` of w repeated reps times, copy r of row j with amplitude
+    A_j c_rj (seeded factors, complex unless real); returns the new workload
+    and c."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.5, 1.5, (reps, sel.size))
+    if not real:
+        c = c * np.exp(1j * rng.uniform(0, 2 * np.pi, (reps, sel.size)))
+    r = W.inspiral_20_modes()
+    r.l, r.m, r.n = (np.tile(x[sel], reps) for x in (w.l, w.m, w.n))
+    r.A = (w.A[sel][None, :, :] * c[:, :, None]).reshape(-1, w.K)
+    return r, c
+
+
+def test_active_list_in_windows(ctx):
+    """520 voices active in the same bins: more than the 512-entry active list
+    of a workgroup, which is then built and walked window by window."""
+    w = W.inspiral_20_modes()
+    r, _ = _replicas(w, np.array([8]), 520, 5)
+    ho = oracle.waveform(r)
+    act = np.nonzero(ho[0])[0]
+    assert act.size > 256
+    f_idx = np.arange(max(act.min() - 70, 0), act.max() + 70)
+    hg = gpu_waveform(ctx, r, f=r.f[f_idx])
+    _check64(hg, tuple(x[f_idx] for x in ho), "520 replicas of one voice")
+
+
+def test_mode_table_scanned_in_rounds(ctx):
+    """4200 table rows (more than one scan round of 4096 rows per workgroup):
+    the sum equals the combination of the 20 single-row GPU waveforms with the
+    rows' factors.  The factors are real: a row's partner voice carries the
+    conjugate amplitude, so the waveform is linear in A over the reals only."""
+    w = W.inspiral_20_modes()
+    w.f = w.f[:70_000]
+    sel = np.arange(20)
+    r, c = _replicas(w, sel, 210, 6, real=True)
+    r.f = w.f
+    hg = gpu_waveform(ctx, r)
+    ref = [np.zeros(w.Nf, complex), np.zeros(w.Nf, complex)]
+    for j in sel:
+        one = W.inspiral_20_modes()
+        one.l, one.m, one.n, one.A, one.f = w.l[j:j + 1], w.m[j:j + 1], w.n[j:j + 1], w.A[j:j + 1], w.f
+        hj = gpu_waveform(ctx, one)
+        for q in range(2):
+            ref[q] += np.sum(c[:, j]) * hj[q]
+    for q in range(2):
+        assert support_mismatch(hg[q], ref[q]) == 0
+        assert rel_l2(hg[q], ref[q]) <= 1e-12
+
+
 def test_linear_chirp_and_turnover(ctx):
     from test_oracle_waveform import turnover_workload
     for w in [W.linear_chirp_workload(f0=1e-4, fdot=1e-9, T=1e5, Nf=3001),
