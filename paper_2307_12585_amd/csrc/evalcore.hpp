@@ -65,9 +65,10 @@ __device__ __forceinline__ Bracket make_bracket(const Piece& P, int i, const Seg
 // p1, p2, p3 the first three derivatives of p; a step is accepted as the
 // root once the iterate lies where that holds (|p p2| <= p1^2 / 2) and the
 // predicted error is below the tolerance.  On smooth trajectories the first
-// step from the secant start is accepted; otherwise the iteration restarts
-// from the secant start with every step kept inside the shrinking bracket
-// (bisection when a step leaves it).
+// step from the secant start is accepted; otherwise the iteration goes on
+// from that step, inside the bracket narrowed by the sign of p at the start,
+// with every step kept inside the shrinking bracket (bisection when a step
+// leaves it).
 __device__ __forceinline__ double solve_root(double f, double dd, const SegData& S, const Bracket& B) {
   double tau0 = B.tl;
   const double dg = B.gh - B.gl;
@@ -78,6 +79,7 @@ __device__ __forceinline__ double solve_root(double f, double dd, const SegData&
   const double q1 = S.q1, q2 = S.q2, q3 = S.q3;
   const double q2x2 = 2.0 * q2, q3x3 = 3.0 * q3, q3x6 = 6.0 * q3, aq3 = fabs(q3);
   // first Halley step, accepted when the error estimate allows
+  double blo = B.tl, bhi = B.th, tau;
   {
     const double r = c0 + tau0 * (q1 + tau0 * (q2 + tau0 * q3));
     const double p1 = q1 + tau0 * (q2x2 + q3x3 * tau0);
@@ -90,9 +92,14 @@ __device__ __forceinline__ double solve_root(double f, double dd, const SegData&
         (step <= tol ||
          (fabs(rp2) <= 0.5 * p1s && step * step * step * (0.25 * p2 * p2 + aq3 * fabs(p1)) <= tol * p1s)))
       return tn;
+    // not accepted: the start point's sign narrows the bracket, and the
+    // iteration continues from the step just taken
+    if (dd * r < 0.0)
+      blo = tau0;
+    else
+      bhi = tau0;
+    tau = (tn > blo && tn < bhi) ? tn : 0.5 * (blo + bhi);
   }
-  double tau = tau0;
-  double blo = B.tl, bhi = B.th;
   for (int it = 0; it < 100; ++it) {
     const double r = c0 + tau * (q1 + tau * (q2 + tau * q3));
     if (r == 0.0) break;
