@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-bins", type=int, default=20000)
+    ap.add_argument("--cpu-sample-bins", type=int, default=40000)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batch", type=int, default=8,
                     help="waveforms in the secondary batched mixed-precision measurement")
@@ -60,17 +60,21 @@ def cpu_baseline(w, n_sample_bins, gpu_hp, gpu_hc, evals_full, count_sample):
     a per-evaluation part (timed on a contiguous run of bins in the active
     band), extrapolated to the whole grid's evaluation count."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
+
     import oracle
 
-    t0 = time.perf_counter()
-    oracle.waveform(w, f=w.f[1:2])
-    t_fixed = time.perf_counter() - t0
-    k0 = int(np.searchsorted(w.f, 2.0e-3))
-    sl = slice(k0, k0 + n_sample_bins)
-    fs = w.f[sl]
-    t0 = time.perf_counter()
-    op, oc = oracle.waveform(w, f=fs)
-    t_sample = time.perf_counter() - t0
+    # one thread: the library pools numpy and scipy may use are held to one
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle.waveform(w, f=w.f[1:2])
+        t_fixed = time.perf_counter() - t0
+        k0 = int(np.searchsorted(w.f, 2.0e-3))
+        sl = slice(k0, k0 + n_sample_bins)
+        fs = w.f[sl]
+        t0 = time.perf_counter()
+        op, oc = oracle.waveform(w, f=fs)
+        t_sample = time.perf_counter() - t0
     ev_sample = count_sample(fs)
     per_eval = max(t_sample - t_fixed, 1e-9) / max(ev_sample, 1)
     t_full = t_fixed + per_eval * evals_full
