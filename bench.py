@@ -251,7 +251,10 @@ def main():
     assert ctx.sync_flags() == 0
     evals = ctx.last_eval_count()
 
-    ctx.profile(True)
+    # timed region: only the gather is bracketed by events (its duration is
+    # the roofline's); an event pair around every kernel would add its own
+    # gaps to the step
+    ctx.profile(True, classes=["gather"])
     ctx.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -260,11 +263,18 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile_read()
-    ctx.profile(False)
     sec = (t1 - t0) / args.steps
     g_ms, g_n = prof["gather"]
     g_avg = g_ms / max(g_n, 1) * 1e-3
     achieved = evals * FLOPS_PER_EVAL / g_avg
+    # the set-up kernels' durations, from a few more steps with every class bracketed
+    ctx.profile(True)
+    for _ in range(10):
+        ctx.waveform_dev(dw, "fp64", out=out)
+    setup = ctx.profile_read()
+    ctx.profile(False)
+    for k in ("spline", "pieces"):
+        prof[k] = setup[k]
 
     # secondary measurements (not the headline): mixed precision on the same
     # workload and the latency of the small and sparse-grid workloads

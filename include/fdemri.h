@@ -342,6 +342,14 @@ fdemri_status fdemri_last_eval_count(fdemri_ctx *ctx, hipStream_t stream, int64_
 #define FDEMRI_KERNEL_COUNT 4
 fdemri_status fdemri_profile_enable(fdemri_ctx *ctx, int enable);
 fdemri_status fdemri_profile_read(fdemri_ctx *ctx, hipStream_t stream, double *ms_out, int64_t *launches_out);
+/*
+ * The kernel classes bracketed while profiling is enabled: bit FDEMRI_KERNEL_x
+ * of class_mask (all classes after fdemri_create).  Each bracket is an event
+ * pair on the launch stream between consecutive kernels, so a measurement
+ * that needs one kernel's duration should record that class only.  Bits at
+ * or above FDEMRI_KERNEL_COUNT: FDEMRI_EINVAL, mask unchanged.
+ */
+fdemri_status fdemri_profile_classes(fdemri_ctx *ctx, uint32_t class_mask);
 
 #ifdef __cplusplus
 }

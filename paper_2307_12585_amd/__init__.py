@@ -36,7 +36,7 @@ EXPORTED = [
     "fdemri_waveform", "fdemri_waveform_batch", "fdemri_vjp", "fdemri_last_eval_count",
     "fdemri_profile_enable", "fdemri_profile_read", "fdemri_autotune", "fdemri_loglike",
     "fdemri_loglike_batch", "fdemri_select_modes", "fdemri_td_waveform", "fdemri_trajectory",
-    "fdemri_signal_band",
+    "fdemri_signal_band", "fdemri_profile_classes",
 ]
 KERNEL_CLASSES = ["spline", "pieces", "gather", "vjp"]
 
@@ -117,6 +117,8 @@ def lib():
         L.fdemri_profile_enable.restype = ctypes.c_int
         L.fdemri_profile_read.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.fdemri_profile_read.restype = ctypes.c_int
+        L.fdemri_profile_classes.argtypes = [vp, u32]
+        L.fdemri_profile_classes.restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
 
@@ -226,8 +228,14 @@ class Context:
         self._check(self._lib.fdemri_last_eval_count(self._h, _stream(self.device), ctypes.byref(v)))
         return int(v.value)
 
-    def profile(self, enable: bool):
-        """Bracket every kernel launch with HIP events on its stream."""
+    def profile(self, enable: bool, classes=None):
+        """Bracket kernel launches with HIP events on their stream: every
+        class, or only the kernel classes named in `classes` (KERNEL_CLASSES)."""
+        names = KERNEL_CLASSES if classes is None else classes
+        mask = 0
+        for k in names:
+            mask |= 1 << KERNEL_CLASSES.index(k)
+        self._check(self._lib.fdemri_profile_classes(self._h, mask))
         self._check(self._lib.fdemri_profile_enable(self._h, 1 if enable else 0))
 
     def profile_read(self):

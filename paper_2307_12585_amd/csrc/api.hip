@@ -94,8 +94,9 @@ struct fdemri_ctx {
   std::vector<std::array<int, 4>> tuned;  // {prec, batch, cls, bpl}
   bool tuning = false;                     // the autotuner fixes bpl itself
   int bpl = 4;
-  // profiling: event pairs per launch, by kernel class
+  // profiling: event pairs per launch, by kernel class (classes in prof_mask)
   bool prof = false;
+  uint32_t prof_mask = (1u << FDEMRI_KERNEL_COUNT) - 1u;
   struct Rec {
     int cls;
     hipEvent_t a, b;
@@ -241,7 +242,7 @@ struct ProfScope {
   hipStream_t s;
   hipEvent_t a = nullptr;
   ProfScope(fdemri_ctx* c_, int cls_, hipStream_t s_) : c(c_), cls(cls_), s(s_) {
-    if (c->prof) {
+    if (c->prof && ((c->prof_mask >> cls) & 1u)) {
       a = take_event(c);
       if (a) (void)hipEventRecord(a, s);
     }
@@ -993,6 +994,14 @@ fdemri_status fdemri_autotune(fdemri_ctx* c, int32_t B, const fdemri_waveform_de
 fdemri_status fdemri_profile_enable(fdemri_ctx* c, int enable) {
   if (!c) return FDEMRI_EINVAL;
   c->prof = enable != 0;
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_profile_classes(fdemri_ctx* c, uint32_t class_mask) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  if (class_mask >> FDEMRI_KERNEL_COUNT) return fail(c, FDEMRI_EINVAL, "unknown kernel class in mask 0x%x", class_mask);
+  c->prof_mask = class_mask;
   return FDEMRI_OK;
 }
 

@@ -299,3 +299,27 @@ def test_out_of_range_mode_rows_are_flagged_and_skipped(ctx):
     out = ctx.vjp_dev(dw, g[0], g[1], "fp64")
     assert all(bool(torch.isfinite(torch.view_as_real(v) if v.is_complex() else v).all()) for v in out.values())
     ctx.sync_flags()
+
+
+def test_profile_classes(ctx):
+    """Profiling brackets only the selected kernel classes; an unknown class
+    bit is rejected and leaves the selection as it was."""
+    w = W.inspiral_20_modes()
+    dw = fd.DeviceWaveform.from_workload(w, device=ctx.device)
+    ctx.profile(True, classes=["gather"])
+    ctx.profile_read()
+    ctx.waveform_dev(dw, "fp64")
+    got = ctx.profile_read()
+    assert got["gather"][1] == 1 and got["spline"][1] == 0 and got["pieces"][1] == 0
+    assert got["gather"][0] > 0
+    assert ctx._lib.fdemri_profile_classes(ctx._h, 1 << 7) == 1
+    ctx.waveform_dev(dw, "fp64")
+    got = ctx.profile_read()
+    assert got["gather"][1] == 1 and got["spline"][1] == 0
+    ctx.profile(True)
+    ctx.waveform_dev(dw, "fp64")
+    got = ctx.profile_read()
+    assert got["gather"][1] == 1 and got["spline"][1] == 1 and got["pieces"][1] == 1
+    ctx.profile(False)
+    ctx.waveform_dev(dw, "fp64")
+    assert all(v[1] == 0 for v in ctx.profile_read().values())
