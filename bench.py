@@ -152,6 +152,38 @@ def batch_measure(ctx, W, fd, dev, B):
                                    "waveform_bytes_not_written": bins * 16}}
 
 
+def graph_latency(fd, dw, reps=50):
+    """Microseconds per FP64 waveform when the call is captured once into a
+    HIP graph (torch's capture of the current stream) and replayed: the
+    launch-bound small workloads without per-call host launch work.  The
+    graph holds its context's workspace, so it gets a context of its own."""
+    import torch
+    gctx = fd.Context(dw.device.index if dw.device.index is not None else 0)
+    out = (torch.empty(dw.Nf, dtype=torch.complex128, device=dw.device),
+           torch.empty(dw.Nf, dtype=torch.complex128, device=dw.device))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            gctx.waveform_dev(dw, "fp64", out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gctx.waveform_dev(dw, "fp64", out=out)
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - t0) / reps * 1e6
+    del g
+    gctx.close()
+    return us
+
+
 def adjoint_measure(ctx, W, fd, dev, B):
     """Forward plus adjoint of the Whittle log-likelihood for B draws of the
     batched distribution in mixed precision.  Data: the FP64 waveform at the
@@ -352,7 +384,8 @@ def main():
         for _ in range(20):
             ctx.waveform_dev(d2, "fp64", out=o2)
         torch.cuda.synchronize()
-        secondary[name] = {"us_per_waveform": (time.perf_counter() - ts) / 20 * 1e6}
+        secondary[name] = {"us_per_waveform": (time.perf_counter() - ts) / 20 * 1e6,
+                           "us_per_waveform_graph_replay": graph_latency(fd, d2)}
 
     line = headline(args, w, evals, sec, prof, achieved, bpl, secondary)
     if not args.no_cpu_baseline:

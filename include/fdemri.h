@@ -141,6 +141,12 @@ fdemri_status fdemri_sync_flags(fdemri_ctx *ctx, hipStream_t stream, uint32_t *f
  * hp, hc : [Nf] complex outputs (interleaved re, im) of the precision's type
  * (double for FDEMRI_FP64, float for FDEMRI_MIXED).  Fully overwritten.
  * Returns FDEMRI_OK once the work is enqueued on `stream`.
+ * The call enqueues kernel launches only (no copies, no memsets), so a
+ * caller may capture it into a HIP graph after one eager call of the same
+ * shape and precision on the same context (that call sizes the context's
+ * workspace).  The graph reads the inputs and the workspace at replay; a
+ * later call on the context that needs a larger workspace reallocates it and
+ * invalidates such graphs, so other work should use its own context.
  */
 fdemri_status fdemri_waveform(fdemri_ctx *ctx, const fdemri_waveform_desc *desc,
                               fdemri_prec prec, void *hp, void *hc, hipStream_t stream);

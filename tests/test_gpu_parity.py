@@ -323,3 +323,40 @@ def test_profile_classes(ctx):
     ctx.profile(False)
     ctx.waveform_dev(dw, "fp64")
     assert all(v[1] == 0 for v in ctx.profile_read().values())
+
+
+@pytest.mark.parametrize("workload", ["inspiral_20_modes_log_grid", "inspiral_20_modes"])
+def test_single_waveform_graph_replays_match_eager(ctx, workload):
+    """fdemri_waveform captured into a HIP graph (through torch's graph
+    capture on the current stream) and replayed several times, with eager
+    work and synchronisations in between, equals the eager call every time."""
+    w = getattr(W, workload)()
+    dw = fd.DeviceWaveform.from_workload(w, device=ctx.device)
+    ref = ctx.waveform_dev(dw, "fp64")
+    torch.cuda.synchronize()
+    out = (torch.empty_like(ref[0]), torch.empty_like(ref[1]))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):          # warm-up on the capture stream
+        ctx.waveform_dev(dw, "fp64", out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx.waveform_dev(dw, "fp64", out=out)
+    # the graph holds the context's workspace: unrelated library work runs on
+    # a context of its own, so that nothing reallocates that workspace
+    other = fd.Context(0)
+    x = torch.randn(256, 256, device=ctx.device)
+    for rep in range(4):
+        out[0].fill_(float("nan"))
+        out[1].fill_(float("nan"))
+        g.replay()
+        y = x @ x
+        other.waveform_dev(dw, "mixed")
+        torch.cuda.synchronize()
+        assert torch.isfinite(y).all()
+        assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]), rep
+    other.close()
+    del g
+    assert ctx.sync_flags() == 0
