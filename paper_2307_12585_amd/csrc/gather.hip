@@ -505,9 +505,9 @@ __device__ __forceinline__ void process_block(const Prepared& p, const void* __r
 
 // Occupancy target of the gather kernels, in waves per SIMD (register
 // budget 512 / waves VGPRs).  The mixed evaluation fits 4 waves; the FP64
-// one needs about 160 VGPRs, and bounding it to 4 waves (a few spills) still
-// runs faster than 3 waves without spills in the single-waveform kernel.  The
-// persistent batch kernel holds more state and stays at 3 in FP64.
+// one would take more than 128 VGPRs, and bounding it to 4 waves (a few
+// spills, outside the evaluation loop) runs faster than 3 waves without
+// spills, in the single-waveform and in the persistent batch kernel alike.
 template <bool MIXED>
 constexpr int gather_min_waves() {
   return 4;
@@ -515,7 +515,7 @@ constexpr int gather_min_waves() {
 
 template <bool MIXED>
 constexpr int gather_batch_min_waves() {
-  return MIXED ? 4 : 3;
+  return 4;
 }
 
 // LL = false: the waveform; LL = true: the likelihood partials (Sink).
