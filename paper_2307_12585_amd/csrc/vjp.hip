@@ -77,8 +77,15 @@ __device__ __forceinline__ double wave_sum16(const double v[16]) {
   return a1;
 }
 
+// Occupancy target in waves per SIMD: the mixed adjoint fits 4 (a few spills
+// outside the bin loop); the FP64 one would spill inside it and stays at 3.
 template <bool MIXED>
-__global__ __launch_bounds__(256) void vjp_unit_kernel(VjpArgs a) {
+constexpr int vjp_min_waves() {
+  return MIXED ? 4 : 3;
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_unit_kernel(VjpArgs a) {
   const Prepared& p = a.p;
   const int nseg = p.K - 1;
   // the wave index is uniform; in a scalar register it makes the unit, and
