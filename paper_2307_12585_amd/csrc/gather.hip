@@ -504,18 +504,19 @@ __device__ __forceinline__ void process_block(const Prepared& p, const void* __r
 }
 
 // Occupancy target of the gather kernels, in waves per SIMD (register
-// budget 512 / waves VGPRs).  The mixed evaluation fits 4 waves; the FP64
-// one would take more than 128 VGPRs, and bounding it to 4 waves (a few
-// spills, outside the evaluation loop) runs faster than 3 waves without
-// spills, in the single-waveform and in the persistent batch kernel alike.
+// budget 512 / waves VGPRs).  The FP64 evaluation would take more than 128
+// VGPRs; bounded to 4 waves (a few spills, outside the evaluation loop) it
+// runs faster than at 3 without spills, and at 5 no faster.  The mixed one
+// fits 5 waves (96 VGPRs, spills outside the evaluation loop), which is
+// faster than 4 in the single-waveform and the batch kernel.
 template <bool MIXED>
 constexpr int gather_min_waves() {
-  return 4;
+  return MIXED ? 5 : 4;
 }
 
 template <bool MIXED>
 constexpr int gather_batch_min_waves() {
-  return 4;
+  return MIXED ? 5 : 4;
 }
 
 // LL = false: the waveform; LL = true: the likelihood partials (Sink).
