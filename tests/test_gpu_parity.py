@@ -140,6 +140,24 @@ def test_mode_table_scanned_in_rounds(ctx):
         assert rel_l2(hg[q], ref[q]) <= 1e-12
 
 
+def test_dense_batch_draw_sampled_bins(ctx):
+    """A dense draw of the batch distribution (M = 1.9e5, 3835 modes, 6.1e6
+    bins, about 1600 evaluations per bin): the first Halley step is rejected
+    on almost every lane there, the segment walk and the longer asymptotic
+    tiers of the special function are common.  FP64 against the oracle on
+    sampled bins; mixed against FP64 on the whole grid."""
+    w = W.batch_workload(W.batch_params(8, 4)[3])
+    assert w.Nm == 3835 and w.Nf == 6082894
+    hp, hc = gpu_waveform(ctx, w)
+    rng = np.random.default_rng(12)
+    idx = np.unique(np.concatenate([rng.choice(np.arange(1, w.Nf), 120, replace=False), [0, 1, w.Nf - 1]]))
+    op, oc = oracle.waveform(w, f=w.f[idx])
+    _check64((hp[idx], hc[idx]), (op, oc), "dense batch draw, sampled")
+    mp, mc = gpu_waveform(ctx, w, prec="mixed")
+    for g, o in ((mp, hp), (mc, hc)):
+        assert rel_l2(g.astype(np.complex128), o) <= TOLMIX
+
+
 def test_linear_chirp_and_turnover(ctx):
     from test_oracle_waveform import turnover_workload
     for w in [W.linear_chirp_workload(f0=1e-4, fdot=1e-9, T=1e5, Nf=3001),
