@@ -17,14 +17,15 @@
 
 namespace fdemri {
 hipError_t launch_spline(int K, const double* t, const double* Fphi, const double* Fr, const double* Phiphi,
-                         const double* Phir, const double* A, int Nm, double* tcoef, double* acoef,
+                         const double* Phir, const double* A, int Nm, double* tcoef, double* acoef, double* fac,
                          hipStream_t stream);
+size_t spline_factor_doubles(int K);
 struct PieceArgs;
 hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
                              const double* f, const double* tcoef, const int32_t* l, const int32_t* m,
                              const int32_t* n, double theta, double phi, double scale, uint32_t flags,
-                             const double* A, double* acoef, ModeConst* modes, int2* mode_kr, Piece* pieces,
-                             int64_t* evals, int32_t* env, uint32_t* flag_word, hipStream_t stream);
+                             const double* A, double* acoef, double* fac, ModeConst* modes, int2* mode_kr,
+                             Piece* pieces, int64_t* evals, int32_t* env, uint32_t* flag_word, hipStream_t stream);
 struct GatherArgs;
 hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp, void* hc, bool mixed, int bpl,
                               hipStream_t stream);
@@ -125,7 +126,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Scratch layout of one waveform.
 struct Layout {
-  size_t tcoef, acoef, acoef32, modes, mode_kr, pieces, evals, env;
+  size_t tcoef, fac, acoef, acoef32, modes, mode_kr, pieces, evals, env;
   size_t gA, PZ, Upart, T3, gPhi, gsc;  // adjoint scratch (0 bytes unless requested)
   size_t ll_partial, ll_edge;           // likelihood scratch (0 bytes unless requested)
   size_t total;
@@ -143,6 +144,7 @@ Layout layout_for(int K, int Nm, bool mixed, bool vjp = false, int ll_tiles = 0,
     return o;
   };
   L.tcoef = take(4 * nseg * 4 * sizeof(double));
+  L.fac = take(spline_factor_doubles(K) * sizeof(double));
   L.acoef = take((size_t)Nm * nseg * 8 * sizeof(double));
   L.acoef32 = take(mixed ? (size_t)Nm * nseg * 8 * sizeof(float) : 0);
   L.modes = take((size_t)Nm * sizeof(ModeConst));
@@ -360,15 +362,16 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   {
     // the trajectory splines first: the piece tables need them
     ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream);
-    e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, 0, tcoef, acoef, stream);
+    e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, 0, tcoef, acoef, (double*)(w + L.fac),
+                      stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "spline kernel launch");
   {
     // piece tables and amplitude splines in one launch, then the envelope
     ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream);
     e = launch_setup_flat(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->f, tcoef, d->l, d->m, d->n, d->theta,
-                          d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, modes, mode_kr, pieces, evals,
-                          env, c->flag_word, stream);
+                          d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, (double*)(w + L.fac), modes,
+                          mode_kr, pieces, evals, env, c->flag_word, stream);
     if (e == hipSuccess && mixed) e = launch_amp32(d->Nm, d->K, d->t, acoef, acoef32, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "piece kernel launch");

@@ -443,7 +443,7 @@ hipError_t launch_pieces_batch(const WaveItem* items, int B, const int32_t* mode
 // of taking a launch of their own before them.
 template <int NT>
 __global__ __launch_bounds__(NT) void setup_kernel(PieceArgs a, int piece_blocks, const double* __restrict__ A,
-                                                   double* __restrict__ acoef) {
+                                                   double* __restrict__ acoef, double* fac) {
   constexpr int W = NT / 64;
   // LDS of either part: the spline's tables or the waves' event buffers
   constexpr size_t kBytes = sizeof(SplineLds<NT>) > sizeof(Event) * W * kMaxEvents ? sizeof(SplineLds<NT>)
@@ -456,18 +456,22 @@ __global__ __launch_bounds__(NT) void setup_kernel(PieceArgs a, int piece_blocks
     return;
   }
   const int s0 = 4 + ((int)blockIdx.x - piece_blocks) * kSeriesPerBlock;
-  // series 4 + mu only: the trajectory arguments are never read here
-  spline_block<NT>(*(SplineLds<NT>*)lds, s0, 4 + a.Nm, a.K, a.t, a.Fphi, a.Fr, a.Fphi, a.Fr, A, acoef, acoef);
+  // series 4 + mu only (the trajectory arguments are never read here), with
+  // the knot matrix's reduction factors from the trajectory splines
+  spline_block<NT, true>(*(SplineLds<NT>*)lds, s0, 4 + a.Nm, a.K, a.t, a.Fphi, a.Fr, a.Fphi, a.Fr, A, acoef, acoef,
+                         fac);
 }
 
 // The piece tables and, unless A is NULL, the amplitude splines of Nm modes
 // (acoef [Nm][K-1][8]) in one launch, then the bin envelope.  The trajectory
-// spline coefficients tcoef must be in place (stream order).
+// spline coefficients tcoef and the knot matrix's reduction factors fac,
+// written by launch_spline with the same thread count, must be in place
+// (stream order).
 hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
                              const double* f, const double* tcoef, const int32_t* l, const int32_t* m,
                              const int32_t* n, double theta, double phi, double scale, uint32_t flags,
-                             const double* A, double* acoef, ModeConst* modes, int2* mode_kr, Piece* pieces,
-                             int64_t* evals, int32_t* env, uint32_t* flag_word, hipStream_t stream) {
+                             const double* A, double* acoef, double* fac, ModeConst* modes, int2* mode_kr,
+                             Piece* pieces, int64_t* evals, int32_t* env, uint32_t* flag_word, hipStream_t stream) {
   PieceArgs a;
   a.K = K;
   a.Nm = Nm;
@@ -492,10 +496,10 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
   const int amp_blocks = A ? (Nm + kSeriesPerBlock - 1) / kSeriesPerBlock : 0;
   if (K <= 256) {
     const int pb = (Nm + 3) / 4;
-    setup_kernel<256><<<pb + amp_blocks, 256, 0, stream>>>(a, pb, A, acoef);
+    setup_kernel<256><<<pb + amp_blocks, 256, 0, stream>>>(a, pb, A, acoef, fac);
   } else {
     const int pb = (Nm + 7) / 8;
-    setup_kernel<512><<<pb + amp_blocks, 512, 0, stream>>>(a, pb, A, acoef);
+    setup_kernel<512><<<pb + amp_blocks, 512, 0, stream>>>(a, pb, A, acoef, fac);
   }
   envelope_kernel<<<1, 256, 0, stream>>>(mode_kr, Nm, env);
   return hipGetLastError();

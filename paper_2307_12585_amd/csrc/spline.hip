@@ -9,9 +9,12 @@ __global__ __launch_bounds__(NT) void spline_pcr_kernel(int K, const double* __r
                                                         const double* __restrict__ y0, const double* __restrict__ y1,
                                                         const double* __restrict__ y2, const double* __restrict__ y3,
                                                         const double* __restrict__ A, int n_series,
-                                                        double* __restrict__ tcoef, double* __restrict__ acoef) {
+                                                        double* __restrict__ tcoef, double* __restrict__ acoef,
+                                                        double* fac) {
   __shared__ SplineLds<NT> S;
-  spline_block<NT>(S, (int)blockIdx.x * kSeriesPerBlock, n_series, K, t, y0, y1, y2, y3, A, tcoef, acoef);
+  // the first workgroup also records the reduction factors of the knot matrix
+  spline_block<NT>(S, (int)blockIdx.x * kSeriesPerBlock, n_series, K, t, y0, y1, y2, y3, A, tcoef, acoef,
+                   blockIdx.x == 0 ? fac : nullptr);
 }
 
 // Batched: block -> (waveform, group of series) through block_prefix (per
@@ -38,21 +41,24 @@ __global__ __launch_bounds__(NT) void spline_batch_kernel(const WaveItem* __rest
 int spline_blocks(int n_series) { return (n_series + kSeriesPerBlock - 1) / kSeriesPerBlock; }
 
 // Host launcher: coefficients of the four trajectory series and of Nm
-// complex amplitude series, all on knots t[K].
+// complex amplitude series, all on knots t[K], with NT = 256 threads per
+// workgroup for K <= 256 and 512 above; when fac is not null, the reduction
+// factors of the knot matrix are written to it (pcr_factor_doubles<NT>()).
 hipError_t launch_spline(int K, const double* t, const double* Fphi, const double* Fr, const double* Phiphi,
-                         const double* Phir, const double* A, int Nm, double* tcoef, double* acoef,
+                         const double* Phir, const double* A, int Nm, double* tcoef, double* acoef, double* fac,
                          hipStream_t stream) {
   const int n_series = 4 + Nm;
   const dim3 grid(spline_blocks(n_series));
-  if (K <= 64)
-    spline_pcr_kernel<64><<<grid, 64, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, n_series, tcoef, acoef);
-  else if (K <= 128)
-    spline_pcr_kernel<128><<<grid, 128, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, n_series, tcoef, acoef);
-  else if (K <= 256)
-    spline_pcr_kernel<256><<<grid, 256, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, n_series, tcoef, acoef);
+  if (K <= 256)
+    spline_pcr_kernel<256><<<grid, 256, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, n_series, tcoef, acoef, fac);
   else
-    spline_pcr_kernel<512><<<grid, 512, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, n_series, tcoef, acoef);
+    spline_pcr_kernel<512><<<grid, 512, 0, stream>>>(K, t, Fphi, Fr, Phiphi, Phir, A, n_series, tcoef, acoef, fac);
   return hipGetLastError();
+}
+
+// Doubles of the factor table written by launch_spline for K knots.
+size_t spline_factor_doubles(int K) {
+  return K <= 256 ? (size_t)pcr_factor_doubles<256>() : (size_t)pcr_factor_doubles<512>();
 }
 
 hipError_t launch_spline_batch(const WaveItem* items, int B, const int32_t* block_prefix, int total_blocks, int Kmax,
