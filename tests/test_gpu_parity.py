@@ -162,9 +162,49 @@ def test_linear_chirp_and_turnover(ctx):
     from test_oracle_waveform import turnover_workload
     for w in [W.linear_chirp_workload(f0=1e-4, fdot=1e-9, T=1e5, Nf=3001),
               W.linear_chirp_workload(f0=2e-4, fdot=-1e-9, T=1e5, Nf=3001),
-              turnover_workload(1e-2, 1e-9), turnover_workload(6e-2, -1e-9)]:
+              turnover_workload(1e-2, 1e-9), turnover_workload(6e-2, -1e-9),
+              turnover_workload(1e-2, 1e-9, K=40), turnover_workload(6e-2, -1e-9, K=40)]:
         _check64(gpu_waveform(ctx, w, partners=False), oracle.waveform(w, partners=False), "chirp/turnover")
         _check64(gpu_waveform(ctx, w, partners=True), oracle.waveform(w, partners=True), "chirp/turnover+partner")
+
+
+@pytest.mark.parametrize("fdot", [1e-9, -1e-9])
+@pytest.mark.parametrize("at_knot", [False, True])
+def test_zero_crossing_chirp(ctx, fdot, at_knot):
+    """A voice whose frequency passes through zero (between knots, or exactly
+    on a knot): the F_V < 0 piece feeds h(-f).  Against the oracle (itself
+    pinned to the exact Fresnel transforms on both sides), with and without
+    the partner voice, FP64 and mixed."""
+    from test_oracle_waveform import zero_crossing_workload
+    w, _ = zero_crossing_workload(fdot, at_knot)
+    for partners in (False, True):
+        ho = oracle.waveform(w, partners=partners)
+        assert all(np.count_nonzero(x) > 1000 for x in ho)
+        hg = gpu_waveform(ctx, w, partners=partners)
+        _check64(hg, ho, f"zero crossing fdot={fdot} at_knot={at_knot} partners={partners}")
+        hm = gpu_waveform(ctx, w, prec="mixed", partners=partners)
+        for g, o in zip(hm, hg):
+            assert rel_l2(g.astype(np.complex128), o) <= TOLMIX
+
+
+def test_3842_modes_zero_crossing_and_turnover_rows(ctx):
+    """The rows of the 3842-mode workload whose voice frequency crosses zero
+    (3 rows, (l,8,-11)) or turns over (15 rows) on their own, on every bin of
+    the full grid where any of them is active: element-wise against the
+    oracle."""
+    w = W.inspiral_3842_modes()
+    FV = w.m[:, None] * w.traj.Fphi[None, :] + w.n[:, None] * w.traj.Fr[None, :]
+    zc = np.nonzero((FV.min(1) < 0) & (FV.max(1) > 0))[0]
+    dF = np.diff(FV, axis=1)
+    to = np.nonzero((dF.min(1) < 0) & (dF.max(1) > 0))[0]
+    assert zc.size == 3 and to.size == 15
+    sel = np.concatenate([zc, to])
+    w.l, w.m, w.n, w.A = w.l[sel], w.m[sel], w.n[sel], w.A[sel]
+    w.f = w.f[: int(np.searchsorted(w.f, 1.05 * np.abs(FV[sel]).max()))]
+    ho = oracle.waveform(w)
+    hg = gpu_waveform(ctx, w)
+    _check64(hg, ho, "3842-mode workload: zero-crossing and turnover rows")
+    assert ctx.last_eval_count() == count_evals(w)
 
 
 def test_explicit_voices_no_partners(ctx):

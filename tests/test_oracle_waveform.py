@@ -44,6 +44,70 @@ def test_linear_chirp_closed_form(f0, fdot):
     assert np.all(hneg == 0)
 
 
+def chirp_ft(H, f0, fdot, Phi0, T, nu):
+    """Exact Fresnel transform at frequency nu (either sign) of the voice
+    H e^{-i Phi(t)}, Phi = Phi0 + 2 pi (f0 t + fdot t^2/2), on the infinite
+    line, kept where the stationary time (nu - f0)/fdot lies in [0, T] (the
+    method's hard edge)."""
+    tn = (nu - f0) / fdot
+    val = H * abs(fdot) ** -0.5 * np.exp(1j * (math.pi * (nu - f0) ** 2 / fdot - Phi0
+                                               - 0.25 * math.pi * np.sign(fdot)))
+    return np.where((tn >= 0) & (tn <= T), val, 0)
+
+
+def zero_crossing_workload(fdot, at_knot, T=1e5, K=40, Nf=3001):
+    """A (2,2,0) voice whose frequency F_V = f0 + fdot t passes through zero
+    inside the trajectory.  at_knot: the crossing falls exactly on knot 16
+    (F_V there is exactly 0); otherwise f0 puts it between knots."""
+    t = np.linspace(0.0, T, K)
+    f0 = -fdot * t[16] if at_knot else -fdot * 0.4123 * T
+    return W.linear_chirp_workload(f0=f0, fdot=fdot, T=T, K=K, Nf=Nf), f0
+
+
+@pytest.mark.parametrize("fdot", [1e-9, -1e-9])
+@pytest.mark.parametrize("at_knot", [False, True])
+def test_zero_crossing_chirp_closed_form(fdot, at_knot):
+    """F_V = f0 + fdot t changes sign (Sec. 2.2: all roots of F_V(t) = +-f;
+    reading R5): the method cuts the voice at the crossing; the part with
+    F_V < 0 feeds h(-f) and the part with F_V > 0 feeds h(+f).  Each side
+    must equal the exact Fresnel transform at +f and -f respectively, which
+    fixes the side chosen on each piece, the piece end 0 at the crossing, and
+    the phase 2 pi (-f) t - Phi on the negative side."""
+    A0, Phi0, T = 1.3 - 0.4j, 0.7, 1e5
+    w, f0 = zero_crossing_workload(fdot, at_knot)
+    if at_knot:
+        assert 2 * w.traj.Fphi[16] == 0.0
+    _, _, hpos, hneg = oracle.waveform(w, partners=False, return_sides=True)
+    H = w.scale * A0 * _y22(w)
+    f = w.f
+    ref_pos = chirp_ft(H, f0, fdot, Phi0, T, f)
+    ref_neg = chirp_ft(H, f0, fdot, Phi0, T, -f)
+    # both sides carry a few hundred bins, and a bin band where only one does
+    assert np.count_nonzero(ref_pos) > 500 and np.count_nonzero(ref_neg) > 500
+    assert rel_l2(hpos, ref_pos) <= 1e-13
+    assert rel_l2(hneg, ref_neg) <= 1e-13
+    assert np.array_equal(hpos != 0, ref_pos != 0) and np.array_equal(hneg != 0, ref_neg != 0)
+
+
+def test_zero_crossing_chirp_with_partner_polarizations():
+    """The same crossing with the (2,-2,0) partner (H' = scale (-1)^l conj(A0)
+    Y_{2,-2}, Phi' = -Phi_V): the partner's transform at nu is
+    conj of the voice's transform at -nu with H -> conj H', and O7 combines
+    both sides into h_+ and h_x.  Closed form against the oracle's
+    polarizations."""
+    A0, Phi0, T, fdot = 1.3 - 0.4j, 0.7, 1e5, 1e-9
+    w, f0 = zero_crossing_workload(fdot, False)
+    hp, hc = oracle.waveform(w, partners=True)
+    f = w.f
+    H = w.scale * A0 * _y22(w)
+    Hp = w.scale * (-1) ** 2 * np.conj(A0) * complex(swsh(-2, 2, -2, w.theta, w.phi))
+    pos = chirp_ft(H, f0, fdot, Phi0, T, f) + np.conj(chirp_ft(np.conj(Hp), f0, fdot, Phi0, T, -f))
+    neg = chirp_ft(H, f0, fdot, Phi0, T, -f) + np.conj(chirp_ft(np.conj(Hp), f0, fdot, Phi0, T, f))
+    ref_p = 0.5 * (pos + np.conj(neg))
+    ref_c = 0.5j * (pos - np.conj(neg))
+    assert rel_l2(hp, ref_p) <= 1e-13 and rel_l2(hc, ref_c) <= 1e-13
+
+
 # --- P2: quadratic frequency (turnover), exact Airy transform ---------------
 
 def turnover_workload(Fc, Fdd, Tc=1e4, K=41, Phic=0.3, A0=0.8 + 0.5j, Nf=3000):
@@ -60,14 +124,17 @@ def turnover_workload(Fc, Fdd, Tc=1e4, K=41, Phic=0.3, A0=0.8 + 0.5j, Nf=3000):
                       scale=1.0, f=f)
 
 
+@pytest.mark.parametrize("K", [41, 40])
 @pytest.mark.parametrize("Fc,Fdd", [(1e-2, 1e-9), (6e-2, -1e-9)])
-def test_turnover_two_roots_equal_airy_transform(Fc, Fdd):
+def test_turnover_two_roots_equal_airy_transform(Fc, Fdd, K):
     """F = Fc + Fdd (t-tc)^2/2 with cubic phase: the exact transform is
     H 2 pi (pi|Fdd|)^{-1/3} Ai(-sgn(Fdd) 2 pi (f-Fc) (pi|Fdd|)^{-1/3}) e^{i(2 pi f tc - Phi_c)},
     and the method's sum over the two roots reproduces it on the side where
     both roots exist (this fixes the sign of Eq. extendedspa1 and exercises
-    the special function from X ~ 0 to X ~ 1e3)."""
-    w = turnover_workload(Fc, Fdd)
+    the special function from X ~ 0 to X ~ 1e3).  K = 41 puts the turnover
+    exactly on a knot (t = 0), K = 40 inside a segment."""
+    w = turnover_workload(Fc, Fdd, K=K)
+    assert (0.0 in w.traj.t) == (K == 41)
     _, _, hpos, _ = oracle.waveform(w, partners=False, return_sides=True)
     H = w.scale * w.A[0, 0] * _y22(w)
     c = (math.pi * abs(Fdd)) ** (-1 / 3)
