@@ -152,6 +152,28 @@ fdemri_status fdemri_waveform(fdemri_ctx *ctx, const fdemri_waveform_desc *desc,
                               fdemri_prec prec, void *hp, void *hc, hipStream_t stream);
 
 /*
+ * fdemri_waveform without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results as
+ * fdemri_waveform (bit for bit), but the scratch tables (spline
+ * coefficients, piece tables, mode constants) live in a fixed device array
+ * of FDEMRI_NOALLOC_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends; the call makes no hipMalloc, hipFree or
+ * other allocating call and leaves the context's own workspace alone.
+ * Scratch needed: about 64 B per mode and spline segment (FP64; 96 B mixed)
+ * plus 1.6 KB per mode, i.e. up to 3843 modes at K = 200 in either
+ * precision; larger requests return FDEMRI_ENOTSUP with nothing enqueued.
+ * Every call on one device shares that device's array, and each call
+ * rewrites whatever it reads: calls that overlap in time on one device (two
+ * streams, two contexts, two host threads) race and give wrong results;
+ * serialise them (one stream, or events).  Kernel profiling
+ * (fdemri_profile_enable) does not bracket these launches.
+ */
+#define FDEMRI_NOALLOC_SCRATCH_BYTES (96u << 20)
+fdemri_status fdemri_waveform_noalloc(fdemri_ctx *ctx, const fdemri_waveform_desc *desc,
+                                      fdemri_prec prec, void *hp, void *hc, hipStream_t stream);
+
+/*
  * Several waveforms in one persistent launch (Sec. 3.2 timing studies
  * evaluate many parameter draws; the batch amortises launches).
  * descs : HOST array of B descriptors (device pointers inside).

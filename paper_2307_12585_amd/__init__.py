@@ -36,7 +36,7 @@ EXPORTED = [
     "fdemri_waveform", "fdemri_waveform_batch", "fdemri_vjp", "fdemri_last_eval_count",
     "fdemri_profile_enable", "fdemri_profile_read", "fdemri_autotune", "fdemri_loglike",
     "fdemri_loglike_batch", "fdemri_select_modes", "fdemri_td_waveform", "fdemri_trajectory",
-    "fdemri_signal_band", "fdemri_profile_classes",
+    "fdemri_signal_band", "fdemri_profile_classes", "fdemri_waveform_noalloc",
 ]
 KERNEL_CLASSES = ["spline", "pieces", "gather", "vjp"]
 
@@ -89,6 +89,8 @@ def lib():
         L.fdemri_sync_flags.restype = ctypes.c_int
         L.fdemri_waveform.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_int, vp, vp, vp]
         L.fdemri_waveform.restype = ctypes.c_int
+        L.fdemri_waveform_noalloc.argtypes = [vp, ctypes.POINTER(WaveformDesc), ctypes.c_int, vp, vp, vp]
+        L.fdemri_waveform_noalloc.restype = ctypes.c_int
         L.fdemri_waveform_batch.argtypes = [vp, i32, ctypes.POINTER(WaveformDesc), ctypes.c_int,
                                             ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         L.fdemri_waveform_batch.restype = ctypes.c_int
@@ -260,6 +262,19 @@ class Context:
         d = dw.desc()
         self._check(self._lib.fdemri_waveform(self._h, ctypes.byref(d), p, _ptr(hp), _ptr(hc),
                                               _stream(self.device)))
+        return hp, hc
+
+    def waveform_noalloc_dev(self, dw: DeviceWaveform, out, prec="fp64"):
+        """fdemri_waveform_noalloc into the caller's (h_+, h_x) tensors: the
+        library allocates nothing (its scratch is a fixed device array)."""
+        p = PRECISIONS[prec]
+        ctype = torch.complex128 if p == FDEMRI_FP64 else torch.complex64
+        hp, hc = out
+        assert hp.dtype == ctype and hc.dtype == ctype and hp.numel() == dw.Nf and hc.numel() == dw.Nf
+        assert hp.is_contiguous() and hc.is_contiguous()
+        d = dw.desc()
+        self._check(self._lib.fdemri_waveform_noalloc(self._h, ctypes.byref(d), p, _ptr(hp), _ptr(hc),
+                                                      _stream(self.device)))
         return hp, hc
 
     def waveform(self, t, Fphi, Fr, Phiphi, Phir, l, m, n, A, theta, phi, scale, f,

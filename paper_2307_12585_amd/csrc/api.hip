@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <vector>
 
@@ -65,6 +66,37 @@ hipError_t launch_spline_adjoint(int K, const double* t, int Nm, const double* g
 
 using namespace fdemri;
 
+// Fixed scratch of fdemri_waveform_noalloc: one copy per device, resident
+// from the module's load to the end of the process.  Host code must not use
+// the symbol's name as an address (it names a host-side stand-in); it uses
+// the device address that hipGetSymbolAddress returns for the current
+// device, kept per device below.
+static __device__ __align__(256) char scratch[FDEMRI_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of device dev's copy of `scratch`, looked up once per device
+// with dev current (the caller has made it current).
+hipError_t scratch_address(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
 struct fdemri_ctx {
   int device = 0;
   std::string err;
@@ -104,6 +136,10 @@ struct fdemri_ctx {
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
+  // this device's copy of the fixed scratch (fdemri_waveform_noalloc), or
+  // NULL with the lookup's error
+  char* scratch = nullptr;
+  hipError_t scratch_err = hipSuccess;
 };
 
 namespace {
@@ -243,8 +279,8 @@ struct ProfScope {
   int cls;
   hipStream_t s;
   hipEvent_t a = nullptr;
-  ProfScope(fdemri_ctx* c_, int cls_, hipStream_t s_) : c(c_), cls(cls_), s(s_) {
-    if (c->prof && ((c->prof_mask >> cls) & 1u)) {
+  ProfScope(fdemri_ctx* c_, int cls_, hipStream_t s_, bool enable = true) : c(c_), cls(cls_), s(s_) {
+    if (enable && c->prof && ((c->prof_mask >> cls) & 1u)) {
       a = take_event(c);
       if (a) (void)hipEventRecord(a, s);
     }
@@ -296,6 +332,14 @@ fdemri_status fdemri_create(fdemri_ctx** out, int hip_device, uint32_t flags) {
     }
   }
   load_tune_cache(c);
+  // the no-allocation entry point's scratch on this device (the device is
+  // current), and room for its bookkeeping, so that it needs no allocation
+  {
+    void* ptr = nullptr;
+    c->scratch_err = scratch_address(hip_device, &ptr);
+    c->scratch = (char*)ptr;
+    c->last_evals.reserve(1);
+  }
   *out = c;
   return FDEMRI_OK;
 }
@@ -344,10 +388,12 @@ fdemri_status fdemri_sync_flags(fdemri_ctx* c, hipStream_t stream, uint32_t* fla
 namespace {
 
 // Enqueue the per-waveform preparation (spline coefficients, mode constants,
-// piece table, FP32 amplitude table) into the workspace described by L.
+// piece table, FP32 amplitude table) into the scratch at w described by L
+// (the context's workspace unless given).  prof = false leaves the launches
+// unbracketed even while profiling is on (no event is created).
 fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, const Layout& L, Prepared& p,
-                      float*& acoef32, hipStream_t stream) {
-  char* w = c->ws;
+                      float*& acoef32, hipStream_t stream, char* w = nullptr, bool prof = true) {
+  if (!w) w = c->ws;
   double* tcoef = (double*)(w + L.tcoef);
   // with FDEMRI_COEFFS_GIVEN the caller's coefficients (same layout) are read in place
   const bool given = (d->flags & FDEMRI_COEFFS_GIVEN) != 0;
@@ -361,14 +407,14 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   hipError_t e;
   {
     // the trajectory splines first: the piece tables need them
-    ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream);
+    ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream, prof);
     e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, 0, tcoef, acoef, (double*)(w + L.fac),
                       stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "spline kernel launch");
   {
     // piece tables and amplitude splines in one launch, then the envelope
-    ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream);
+    ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream, prof);
     e = launch_setup_flat(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->f, tcoef, d->l, d->m, d->n, d->theta,
                           d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, (double*)(w + L.fac), modes,
                           mode_kr, pieces, evals, env, c->flag_word, stream);
@@ -421,6 +467,32 @@ fdemri_status fdemri_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, fdem
     ProfScope ps(c, FDEMRI_KERNEL_GATHER, stream);
     e = launch_gather_flat(p, acoef32, hp, hc, mixed, c->bpl, stream);
   }
+  if (e != hipSuccess) return hip_fail(c, e, "gather kernel launch");
+  return FDEMRI_OK;
+}
+
+fdemri_status fdemri_waveform_noalloc(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemri_prec prec, void* hp,
+                                      void* hc, hipStream_t stream) {
+  if (!c) return FDEMRI_EINVAL;
+  c->err.clear();
+  fdemri_status st = validate(c, d);
+  if (st != FDEMRI_OK) return st;
+  if (prec != FDEMRI_FP64 && prec != FDEMRI_MIXED) return fail(c, FDEMRI_EINVAL, "unknown precision %d", (int)prec);
+  if (!hp || !hc) return fail(c, FDEMRI_EINVAL, "NULL output pointer");
+  const bool mixed = prec == FDEMRI_MIXED;
+  const Layout L = layout_for(d->K, d->Nm, mixed);
+  if (L.total > (size_t)FDEMRI_NOALLOC_SCRATCH_BYTES)
+    return fail(c, FDEMRI_ENOTSUP, "K=%d, Nm=%d (%s) need %zu bytes of scratch, more than the fixed %zu", d->K, d->Nm,
+                mixed ? "mixed" : "fp64", L.total, (size_t)FDEMRI_NOALLOC_SCRATCH_BYTES);
+  if (!c->scratch) return hip_fail(c, c->scratch_err, "hipGetSymbolAddress(scratch)");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  Prepared p;
+  float* acoef32 = nullptr;
+  st = prepare(c, d, mixed, L, p, acoef32, stream, c->scratch, false);
+  if (st != FDEMRI_OK) return st;
+  const int bpl = c->tuning ? c->bpl : choose_bpl(c, (int)prec, false, d->Nf);
+  e = launch_gather_flat(p, acoef32, hp, hc, mixed, bpl, stream);
   if (e != hipSuccess) return hip_fail(c, e, "gather kernel launch");
   return FDEMRI_OK;
 }
