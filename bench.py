@@ -4,9 +4,12 @@ One step = one FP64 waveform of the realistic-size workload (M=2e6, mu=20,
 p0=13, e0=0.45, T=2 yr at dt=10 s: 3842 (l,m,n) modes, 200 knots, 3155816
 bins) through the C ABI: spline coefficients, mode constants and piece
 table, and the bin-major gather.  Inputs are resident in HBM before the
-timed region.  Prints one JSON line.
+timed region.  Prints one JSON line; besides the headline it measures the
+mixed-precision batch of 512 draws (one persistent launch, replayed from a
+HIP graph) and the forward+adjoint of 64 draws, each with the roofline of
+its dominant kernel, and the FP64 oracle on this host's cores.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--batch B] [--adjoint A]
 """
 from __future__ import annotations
 
@@ -23,9 +26,14 @@ sys.path.insert(0, ROOT)
 METRIC = "waveforms/s + mode·bin evals/s (fwd, fwd+adjoint) at stated error vs FP64"
 # Algorithmic work of one mode-bin evaluation (one root of Eq. cubic_equation,
 # the per-root factor of Eq. extendedspa1, the phase, the amplitude spline and
-# the two complex accumulations), in FP64 operations; see the design notes for
-# the breakdown.
-FLOPS_PER_EVAL = 186
+# the two complex accumulations): about 150 arithmetic operations (a fused
+# multiply-add counts 2) plus one sine/cosine pair, two divisions and one
+# reciprocal square root, each of these four counted as one.
+FLOPS_PER_EVAL = 154
+# The adjoint per evaluation: the forward terms it recomputes (the above
+# without the polarization products and the accumulation, 126) and the
+# contraction with the cotangent into its 16 gradient sums (88).
+ADJ_FLOPS_PER_EVAL = 214
 PEAK_FP64_VALU = 78.6e12
 
 
@@ -40,12 +48,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-bins", type=int, default=40000)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--batch", type=int, default=8,
-                    help="waveforms in the secondary batched mixed-precision measurement")
-    ap.add_argument("--adjoint", type=int, default=4,
-                    help="waveforms in the secondary forward+adjoint measurement")
+    ap.add_argument("--batch", type=int, default=512,
+                    help="waveforms in the batched mixed-precision measurement (0: skip)")
+    ap.add_argument("--adjoint", type=int, default=64,
+                    help="waveforms in the forward+adjoint measurement (0: skip)")
+    ap.add_argument("--only", choices=["batch", "adjoint"], default=None,
+                    help="run only this secondary measurement after the headline (profiling runs)")
     ap.add_argument("--headline-only", action="store_true",
                     help="skip the secondary measurements (used for counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -54,102 +63,212 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, n_sample_bins, gpu_hp, gpu_hc, evals_full, count_sample):
-    """Time the FP64 oracle on a bounded sample of the same workload: a fixed
-    part (spline and piece set-up of every voice, timed on a single bin) plus
-    a per-evaluation part (timed on a contiguous run of bins in the active
-    band), extrapolated to the whole grid's evaluation count."""
+def _oracle_worker_init():
+    """Each pool worker computes with one thread."""
+    from threadpoolctl import threadpool_limits
+    global _THREAD_LIMIT
+    _THREAD_LIMIT = threadpool_limits(limits=1)
+
+
+def _oracle_worker_probe(_):
+    return os.getpid()
+
+
+def _row_subset(w, j, P):
+    """The workload restricted to the mode rows j, j + P, j + 2P, ..."""
+    import dataclasses
+    return dataclasses.replace(w, l=w.l[j::P], m=w.m[j::P], n=w.n[j::P], A=w.A[j::P])
+
+
+def _oracle_rows(args):
+    """The oracle waveform of the mode rows j::P of w on its whole grid (one
+    pool task); the waveform is the sum of these parts (it is linear in the
+    voices)."""
+    w, j, P = args
+    import oracle
+    t0 = time.perf_counter()
+    hp, hc = oracle.waveform(_row_subset(w, j, P))
+    return j, hp, hc, time.perf_counter() - t0
+
+
+def pool_cores():
+    """Worker processes for the oracle's multiprocess leg: the cores this
+    process may run on, held to 16 (the host share of one GPU here)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def cpu_baseline(w, gpu_hp, gpu_hc, evals_full, small, sample_stride=32):
+    """The FP64 oracle timed on this host's cores.
+    * value: multiprocess, full size.  The oracle's cost is per voice (a mask
+      over the whole grid and a vectorised bisection per monotonic piece,
+      then the per-root terms), so the work is split by voices: worker j of
+      P computes the mode rows j::P on the whole grid and the parts are
+      summed.  The result is compared with the GPU waveform on every bin.
+    * single_process: every sample_stride-th mode row on the whole grid on
+      one core, scaled by sample_stride (flagged as extrapolated).
+    * full_size_single_process: the two 20-mode workloads (full DFT grid and
+      log grid), small = [(name, workload, GPU seconds per waveform)]."""
+    import multiprocessing as mp
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import oracle
 
-    # one thread: the library pools numpy and scipy may use are held to one
+    P = pool_cores()
+    res = {"kind": "oracle", "unit": "waveforms/s", "affinity_cores": len(os.sched_getaffinity(0))}
+    with mp.get_context("spawn").Pool(P, initializer=_oracle_worker_init) as pool:
+        pool.map(_oracle_worker_probe, range(P))  # every worker up before the clock starts
+        t0 = time.perf_counter()
+        parts = pool.map(_oracle_rows, [(w, j, P) for j in range(P)])
+        t_pool = time.perf_counter() - t0
+    op = np.zeros(w.Nf, np.complex128)
+    oc = np.zeros(w.Nf, np.complex128)
+    for _, hp, hc, _ in parts:
+        op += hp
+        oc += hc
+    err_full = max(float(np.linalg.norm(gpu_hp - op) / np.linalg.norm(op)),
+                   float(np.linalg.norm(gpu_hc - oc) / np.linalg.norm(oc)))
+    progress(f"cpu baseline: oracle on {P} processes, whole 3842-mode waveform in {t_pool:.1f} s "
+             f"(GPU rel L2 against it {err_full:.2e})")
+    res.update({
+        "value": 1.0 / t_pool, "cores": P,
+        "sample": (f"full size: the whole 3842-mode waveform ({w.Nf} bins, {evals_full} mode-bin evals) on "
+                   f"{P} worker processes, mode rows dealt round-robin, parts summed; {t_pool:.1f} s per "
+                   f"waveform (slowest worker {max(x[3] for x in parts):.1f} s)"),
+        "evals_per_s": evals_full / t_pool,
+        "gpu_rel_l2_vs_oracle_all_bins": err_full,
+    })
     with threadpool_limits(limits=1):
+        sub = _row_subset(w, 0, sample_stride)
         t0 = time.perf_counter()
-        oracle.waveform(w, f=w.f[1:2])
-        t_fixed = time.perf_counter() - t0
-        k0 = int(np.searchsorted(w.f, 2.0e-3))
-        sl = slice(k0, k0 + n_sample_bins)
-        fs = w.f[sl]
-        t0 = time.perf_counter()
-        op, oc = oracle.waveform(w, f=fs)
-        t_sample = time.perf_counter() - t0
-    ev_sample = count_sample(fs)
-    per_eval = max(t_sample - t_fixed, 1e-9) / max(ev_sample, 1)
-    t_full = t_fixed + per_eval * evals_full
-    err = max(float(np.linalg.norm(gpu_hp[sl] - op) / np.linalg.norm(op)),
-              float(np.linalg.norm(gpu_hc[sl] - oc) / np.linalg.norm(oc)))
-    return {
-        "value": 1.0 / t_full, "unit": "waveforms/s", "cores": 1, "kind": "oracle",
-        "sample": (f"{n_sample_bins} contiguous bins from 2 mHz ({ev_sample} mode-bin evals, "
-                   f"{t_sample:.1f} s) plus the per-voice set-up ({t_fixed:.1f} s), extrapolated to "
-                   f"{evals_full} evals: {t_full:.0f} s per waveform"),
-        "evals_per_s": ev_sample / max(t_sample - t_fixed, 1e-9),
-        "gpu_rel_l2_vs_oracle_on_sample": err,
-    }
+        oracle.waveform(sub)
+        t_s = time.perf_counter() - t0
+        t_full = t_s * sample_stride
+        res["single_process"] = {
+            "value": 1.0 / t_full, "cores": 1, "extrapolated": True,
+            "sample": (f"one mode row in {sample_stride} ({sub.Nm} of {w.Nm}) on the whole grid: {t_s:.1f} s, "
+                       f"scaled by {sample_stride}: {t_full:.0f} s per waveform"),
+        }
+        progress(f"cpu baseline: single process sample {t_s:.1f} s")
+        full_small = {}
+        for name, wl, gpu_s in small:
+            t0 = time.perf_counter()
+            oracle.waveform(wl)
+            ts = time.perf_counter() - t0
+            full_small[name] = {"oracle_s_per_waveform": ts, "gpu_s_per_waveform": gpu_s,
+                                "bins": wl.Nf, "cores": 1}
+        res["full_size_single_process"] = full_small
+    return res
 
 
-def batch_measure(ctx, W, fd, dev, B):
+def device_noise(f, df, seed, dev, dtype):
+    """Complex Gaussian noise per channel with Re, Im ~ N(0, S/(4 df)) drawn
+    on the device (torch's seeded generator), the distribution of
+    workloads.noise_draw without its host cost at batch size."""
+    import numpy as np
+    import torch
+    S = W_psd(f)
+    sig = torch.as_tensor(np.sqrt(np.where(np.isfinite(S), S, 0.0) / (4.0 * df)), device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    out = []
+    for _ in range(2):
+        re = torch.randn(sig.numel(), generator=g, device=dev, dtype=torch.float64)
+        im = torch.randn(sig.numel(), generator=g, device=dev, dtype=torch.float64)
+        out.append(torch.complex(sig * re, sig * im).to(dtype))
+    return out
+
+
+def W_psd(f):
+    import workloads as W
+    return W.psd_closed_form(f)
+
+
+def batch_measure(ctx, W, fd, dev, B, with_loglike=True):
     """Mixed-precision batch of B draws from the batched distribution (M
     log-U[1e5,1e7], mu U[1,100], e0 U[0.05,0.5], p0 U[10,16], T U[0.5,4] yr,
-    dt = 10 s, full DFT grids), one persistent launch per call; error of each
-    waveform against the FP64 batch."""
+    dt = 10 s, full DFT grids): one eager profiled call gives the persistent
+    gather kernel's own duration (its roofline); the timed calls are replays
+    of the captured batch (a context with batch graphs); each waveform's error
+    against the FP64 batch; then the same batch with the Hann-windowed Whittle
+    likelihood fused in (no waveform written)."""
     import torch
     ws = [W.batch_workload(prm) for prm in W.batch_params(B, 4)]
     dws = [fd.DeviceWaveform.from_workload(w, device=dev) for w in ws]
     bins = sum(w.Nf for w in ws)
     progress(f"batch: {B} waveforms, {bins} bins on the device")
-    ref = ctx.waveform_batch(dws, "fp64")
-    torch.cuda.synchronize()
+    outs = [(torch.empty(d.Nf, dtype=torch.complex64, device=dev),
+             torch.empty(d.Nf, dtype=torch.complex64, device=dev)) for d in dws]
+    # eager, profiled: the gather kernel's duration and the evaluation count
+    ctx.profile(True, classes=["gather"])
+    ctx.profile_read()
+    ctx.waveform_batch(dws, "mixed", outs=outs)
+    g_ms, g_n = ctx.profile_read()["gather"]
+    ctx.profile(False)
+    assert ctx.sync_flags() == 0
     evals = ctx.last_eval_count()
-    progress(f"batch: FP64 reference done ({evals} evals)")
-    outs = ctx.waveform_batch(dws, "mixed")
+    progress(f"batch: eager mixed batch, gather {g_ms:.0f} ms ({evals} evals)")
+    # graph path: capture on the first call, then replays
+    gctx = fd.Context(dev.index if dev.index is not None else 0, graphs=True)
+    gctx.waveform_batch(dws, "mixed", outs=outs)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     reps = 2
+    t0 = time.perf_counter()
     for _ in range(reps):
-        ctx.waveform_batch(dws, "mixed", outs=outs)
+        gctx.waveform_batch(dws, "mixed", outs=outs)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / reps
-    progress(f"batch: mixed {sec:.3f} s per batch")
+    progress(f"batch: mixed {sec:.3f} s per batch (graph replays)")
+    gctx.close()
+    ref = ctx.waveform_batch(dws, "fp64")
+    torch.cuda.synchronize()
     errs = []
     for (mp, mc), (rp, rc) in zip(outs, ref):
-        for a, b in ((mp, rp), (mc, rc)):
-            nb = float(torch.linalg.vector_norm(b))
+        for x, y in ((mp, rp), (mc, rc)):
+            nb = float(torch.linalg.vector_norm(y))
             if nb > 0:
-                errs.append(float(torch.linalg.vector_norm(a.to(torch.complex128) - b)) / nb)
-    # the same batch with the likelihood fused (no waveform stored): data =
-    # FP64 waveform + noise of the closed-form PSD, Hann-windowed comparison
-    import numpy as np
-    dps, dcs, wss = [], [], []
-    for i, (w, (rp, rc)) in enumerate(zip(ws, ref)):
-        if i % 64 == 63:
-            progress(f"batch: likelihood data {i + 1}/{B}")
-        S = W.psd_closed_form(w.f)
-        df = float(w.f[1] - w.f[0])
-        wss.append(torch.as_tensor(np.where(np.isfinite(S), 4.0 * df / np.where(np.isfinite(S), S, 1.0), 0.0),
-                                   device=dev))
-        n_p, n_c = W.noise_draw(w.f, df, 31)
-        dps.append((rp + torch.as_tensor(n_p, device=dev)).to(torch.complex64).contiguous())
-        dcs.append((rc + torch.as_tensor(n_c, device=dev)).to(torch.complex64).contiguous())
-    del ref, outs
-    progress("batch: likelihood data on the device")
-    llo = ctx.loglike_batch(dws, dps, dcs, wss, prec="mixed", hann=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
+                errs.append(float(torch.linalg.vector_norm(x.to(torch.complex128) - y)) / nb)
+    progress("batch: FP64 reference done")
+    g_avg = g_ms / max(g_n, 1) * 1e-3
+    achieved = evals * FLOPS_PER_EVAL / g_avg
+    res = {"waveforms": B, "bins": bins, "evals": evals, "seconds_per_batch": sec,
+           "path": "hipGraph replay (captured on the first call, FDEMRI_CTX_BATCH_GRAPHS)",
+           "waveforms_per_s": B / sec, "evals_per_s": evals / sec,
+           "rel_l2_vs_fp64_max": max(errs), "rel_l2_vs_fp64_median": sorted(errs)[len(errs) // 2],
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
+                        "traffic": profile_traffic(BATCH_TRAFFIC_FILE, "gather_batch_kernel<true, 1, 4, false>"),
+                        # no batch autotune runs here: the default block shape, 1 tile per wave
+                        "kernel": "gather_batch_kernel<true, 1, 4, false>", "kernel_ms": g_avg * 1e3,
+                        "flops_per_eval": FLOPS_PER_EVAL,
+                        "peak_note": ("without packed FP32 (off in this build) FP32 and FP64 vector instructions "
+                                      "issue at the same rate, so the FP64 vector peak bounds the mixed path")}}
+    del outs
+    if with_loglike:
+        # data = FP64 waveform + device noise of the closed-form PSD, Hann-windowed comparison
+        import numpy as np
+        dps, dcs, wss = [], [], []
+        for i, (w, (rp, rc)) in enumerate(zip(ws, ref)):
+            S = W.psd_closed_form(w.f)
+            df = float(w.f[1] - w.f[0])
+            wss.append(torch.as_tensor(np.where(np.isfinite(S), 4.0 * df / np.where(np.isfinite(S), S, 1.0), 0.0),
+                                       device=dev))
+            n_p, n_c = device_noise(w.f, df, 31 + i, dev, torch.complex128)
+            dps.append((rp + n_p).to(torch.complex64).contiguous())
+            dcs.append((rc + n_c).to(torch.complex64).contiguous())
+        del ref
+        progress("batch: likelihood data on the device")
+        llo = ctx.loglike_batch(dws, dps, dcs, wss, prec="mixed", hann=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         ctx.loglike_batch(dws, dps, dcs, wss, prec="mixed", hann=True, out=llo)
-    torch.cuda.synchronize()
-    sec_ll = (time.perf_counter() - t0) / reps
-    progress(f"batch: fused likelihood {sec_ll:.3f} s per batch")
-    del dps, dcs, wss
-    return {"waveforms": B, "bins": bins, "evals": evals, "seconds_per_batch": sec,
-            "waveforms_per_s": B / sec, "evals_per_s": evals / sec,
-            "rel_l2_vs_fp64_max": max(errs), "rel_l2_vs_fp64_median": sorted(errs)[len(errs) // 2],
-            "loglike_fused_hann": {"seconds_per_batch": sec_ll, "waveforms_per_s": B / sec_ll,
-                                   "evals_per_s": evals / sec_ll,
-                                   "waveform_bytes_not_written": bins * 16}}
+        torch.cuda.synchronize()
+        sec_ll = time.perf_counter() - t0
+        progress(f"batch: fused likelihood {sec_ll:.3f} s per batch")
+        del dps, dcs, wss
+        res["loglike_fused_hann"] = {"seconds_per_batch": sec_ll, "waveforms_per_s": B / sec_ll,
+                                     "evals_per_s": evals / sec_ll, "waveform_bytes_not_written": bins * 16}
+    return res
 
 
 def graph_latency(fd, dw, reps=50):
@@ -186,71 +305,97 @@ def graph_latency(fd, dw, reps=50):
 
 def adjoint_measure(ctx, W, fd, dev, B):
     """Forward plus adjoint of the Whittle log-likelihood for B draws of the
-    batched distribution in mixed precision.  Data: the FP64 waveform at the
-    drawn parameters plus noise with the closed-form PSD; template: the same
-    source with perturbed amplitudes, phase offset and inclination, so that
-    the residual carries signal as well as noise.  Errors against the FP64
-    forward+adjoint are reported per gradient group, end to end (mixed
-    forward and mixed adjoint) and for the adjoint alone (the FP64 cotangent
-    rounded to complex64)."""
+    batched distribution (seed 1) in mixed precision: the forward of all B
+    templates in one persistent launch, then per draw the cotangent
+    wS (d - h) and fdemri_vjp, all enqueued before one synchronisation.
+    Data: the FP64 waveform at the drawn parameters plus device noise of the
+    closed-form PSD; template: the same source with perturbed amplitudes,
+    phase offset and inclination, so that the residual carries signal as well
+    as noise.  Errors against the FP64 forward+adjoint are reported per
+    gradient group, end to end (mixed forward and mixed adjoint) and for the
+    adjoint alone (the FP64 cotangent rounded to complex64).  The adjoint
+    kernel's duration comes from HIP events around its launches in a
+    separate (warm-up) pass."""
     import dataclasses
     import numpy as np
     import torch
     ws = [W.batch_workload(prm) for prm in W.batch_params(B, 1)]
-    tot = 0.0
-    evals = 0
     keys = ("gA_knots", "gPhi_knots", "g_scalars")
-    e2e = {k: 0.0 for k in keys}
-    vjp_only = {k: 0.0 for k in keys}
-    fwd_err = 0.0
-    kms = {}
+    dws, data = [], []
+    for i, w in enumerate(ws):
+        dw_true = fd.DeviceWaveform.from_workload(w, device=dev)
+        traj = dataclasses.replace(w.traj, Phiphi=w.traj.Phiphi + 0.3)
+        tpl = dataclasses.replace(w, traj=traj, A=w.A * (1.02 * np.exp(0.05j)), theta=w.theta + 0.01)
+        dws.append(fd.DeviceWaveform.from_workload(tpl, device=dev))
+        df = float(w.f[1] - w.f[0])
+        S = W.psd_closed_form(w.f)
+        wS = torch.as_tensor(np.where(np.isfinite(S), 4.0 * df / np.where(np.isfinite(S), S, 1.0), 0.0), device=dev)
+        tp, tc = ctx.waveform_dev(dw_true, "fp64")
+        n1, n2 = device_noise(w.f, df, 7 + i, dev, torch.complex128)
+        data.append((tp + n1, tc + n2, wS))
+        del tp, tc, dw_true
+    torch.cuda.synchronize()
+    progress(f"forward+adjoint: data of {B} draws on the device")
+    mouts = [(torch.empty(d.Nf, dtype=torch.complex64, device=dev),
+              torch.empty(d.Nf, dtype=torch.complex64, device=dev)) for d in dws]
+
+    def adjoints():
+        grads = []
+        for dw, (mp, mc), (dp, dc, wS) in zip(dws, mouts, data):
+            gp = (wS * (dp - mp.to(torch.complex128))).to(torch.complex64)
+            gc = (wS * (dc - mc.to(torch.complex128))).to(torch.complex64)
+            grads.append(ctx.vjp_dev(dw, gp, gc, "mixed", coef=False))
+        return grads
+
+    def run():
+        ctx.waveform_batch(dws, "mixed", outs=mouts)
+        return adjoints()
+
+    # warm-up pass: the forward's evaluation count, then the adjoints with
+    # their unit kernel bracketed
+    ctx.waveform_batch(dws, "mixed", outs=mouts)
+    evals = ctx.last_eval_count()
+    ctx.profile(True, classes=["vjp"])
+    ctx.profile_read()
+    adjoints()
+    v_ms, v_n = ctx.profile_read()["vjp"]
+    ctx.profile(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grads = run()
+    torch.cuda.synchronize()
+    tot = time.perf_counter() - t0
+    progress(f"forward+adjoint: {B} draws in {tot:.2f} s ({evals} forward evals)")
 
     def rel(a, b):
         nb = float(torch.linalg.vector_norm(b))
         return float(torch.linalg.vector_norm(a.to(b.dtype) - b)) / nb if nb > 0 else 0.0
 
-    for i, w in enumerate(ws):
-        dw_true = fd.DeviceWaveform.from_workload(w, device=dev)
-        traj = dataclasses.replace(w.traj, Phiphi=w.traj.Phiphi + 0.3)
-        tpl = dataclasses.replace(w, traj=traj, A=w.A * (1.02 * np.exp(0.05j)), theta=w.theta + 0.01)
-        dw = fd.DeviceWaveform.from_workload(tpl, device=dev)
-        S = torch.as_tensor(W.psd_closed_form(w.f), device=dev)
-        wts = torch.full_like(S, float(w.f[1] - w.f[0]))
-        wts[0] = 0
-        n1, n2 = W.noise_draw(w.f, float(w.f[1] - w.f[0]), 7)
-        tp, tc = ctx.waveform_dev(dw_true, "fp64")
-        dp = tp + torch.as_tensor(n1, device=dev)
-        dc = tc + torch.as_tensor(n2, device=dev)
-        del tp, tc, dw_true
+    e2e = {k: 0.0 for k in keys}
+    vjp_only = {k: 0.0 for k in keys}
+    fwd_err = 0.0
+    for dw, (mp, mc), (dp, dc, wS), g in zip(dws, mouts, data, grads):
         hp, hc = ctx.waveform_dev(dw, "fp64")
-        g64p = 4 * wts * (dp - hp) / S
-        g64c = 4 * wts * (dc - hc) / S
+        g64p = wS * (dp - hp)
+        g64c = wS * (dc - hc)
         ref = ctx.vjp_dev(dw, g64p, g64c, "fp64", coef=False)
         only = ctx.vjp_dev(dw, g64p.to(torch.complex64), g64c.to(torch.complex64), "mixed", coef=False)
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        ctx.profile_read()
-        t0 = time.perf_counter()
-        mp, mc = ctx.waveform_dev(dw, "mixed")
-        evals += ctx.last_eval_count()
-        gp = (4 * wts * (dp - mp.to(torch.complex128)) / S).to(torch.complex64)
-        gc = (4 * wts * (dc - mc.to(torch.complex128)) / S).to(torch.complex64)
-        g = ctx.vjp_dev(dw, gp, gc, "mixed", coef=False)
-        torch.cuda.synchronize()
-        tot += time.perf_counter() - t0
-        for k, (ms, n) in ctx.profile_read().items():
-            kms[k] = kms.get(k, 0.0) + ms / B
-        ctx.profile(False)
         fwd_err = max(fwd_err, rel(mp, hp), rel(mc, hc))
         for k in keys:
             e2e[k] = max(e2e[k], rel(g[k], ref[k]))
             vjp_only[k] = max(vjp_only[k], rel(only[k], ref[k]))
-        progress(f"forward+adjoint: {i + 1}/{B} draws, {evals} evals")
+    progress("forward+adjoint: FP64 references done")
+    achieved = evals * ADJ_FLOPS_PER_EVAL / (v_ms * 1e-3)
     return {"waveforms": B, "evals_forward": evals, "seconds": tot, "waveforms_per_s": B / tot,
             "evals_per_s_forward_plus_adjoint": evals / tot,
             "forward_rel_l2_vs_fp64_max": fwd_err,
-            "kernel_ms_per_waveform": kms,
-            "grad_rel_l2_vs_fp64_max": e2e, "adjoint_only_rel_l2_vs_fp64_max": vjp_only}
+            "vjp_kernel_ms_per_waveform": v_ms / max(v_n, 1),
+            "grad_rel_l2_vs_fp64_max": e2e, "adjoint_only_rel_l2_vs_fp64_max": vjp_only,
+            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
+                         "traffic": profile_traffic(VJP_TRAFFIC_FILE, "vjp_unit_kernel<true>"),
+                         "kernel": "vjp_unit_kernel<true>", "kernel_ms_total": v_ms,
+                         "launches": v_n, "flops_per_eval": ADJ_FLOPS_PER_EVAL}}
 
 
 def main():
@@ -317,7 +462,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         secondary["copy_calibration_bytes"] = src.numel() * 8
-    if args.headline_only:
+    if args.headline_only or args.only:
+        if args.only == "batch":
+            secondary["batch_mixed"] = batch_measure(ctx, W, fd, dev, args.batch, with_loglike=False)
+        elif args.only == "adjoint":
+            secondary["forward_adjoint"] = adjoint_measure(ctx, W, fd, dev, args.adjoint)
         line = headline(args, w, evals, sec, prof, achieved, bpl, secondary)
         print(json.dumps(line), flush=True)
         ctx.close()
@@ -370,8 +519,11 @@ def main():
     secondary["mode_selection"] = {"rows": int(full.l.size), "knots": int(full.traj.t.size), "kept": int(kept.numel()),
                                    "us_per_call": (time.perf_counter() - ts) / 20 * 1e6,
                                    "note": "includes the device-to-host read of the kept count"}
-    secondary["batch_mixed"] = batch_measure(ctx, W, fd, dev, args.batch)
-    secondary["forward_adjoint"] = adjoint_measure(ctx, W, fd, dev, args.adjoint)
+    if args.batch > 0:
+        secondary["batch_mixed"] = batch_measure(ctx, W, fd, dev, args.batch)
+    if args.adjoint > 0:
+        secondary["forward_adjoint"] = adjoint_measure(ctx, W, fd, dev, args.adjoint)
+    small = []
     for name, wl in (("inspiral_20_modes_fp64", W.inspiral_20_modes()),
                      ("inspiral_20_modes_log_grid_fp64", W.inspiral_20_modes_log_grid())):
         d2 = fd.DeviceWaveform.from_workload(wl, device=dev)
@@ -386,15 +538,11 @@ def main():
         torch.cuda.synchronize()
         secondary[name] = {"us_per_waveform": (time.perf_counter() - ts) / 20 * 1e6,
                            "us_per_waveform_graph_replay": graph_latency(fd, d2)}
+        small.append((name, wl, secondary[name]["us_per_waveform"] * 1e-6))
 
     line = headline(args, w, evals, sec, prof, achieved, bpl, secondary)
     if not args.no_cpu_baseline:
-        def count_sample(fs):
-            ds = fd.DeviceWaveform.from_workload(w, device=dev, f=fs)
-            ctx.waveform_dev(ds, "fp64")
-            return ctx.last_eval_count()
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_bins, hp.cpu().numpy(), hc.cpu().numpy(), evals,
-                                            count_sample)
+        line["cpu_baseline"] = cpu_baseline(w, hp.cpu().numpy(), hc.cpu().numpy(), evals, small)
     print(json.dumps(line), flush=True)
     ctx.close()
 
@@ -514,39 +662,52 @@ def loglike_measure(ctx, W, dw, hp, hc, dev, steps):
     return res
 
 
-# HBM bytes per launch of the FP64 gather from rocprofv3 FETCH_SIZE/WRITE_SIZE
-# passes (scaled by a device copy of known size), recorded with a digest of
-# the kernel's sources; reported only while the sources and the launched
-# instantiation are those the counters were taken on.
+# HBM bytes per launch of a kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
+# passes (each scaled by what the same counter reads for a device copy of
+# known size), recorded with a digest of the kernel's sources; a figure is
+# reported only while the sources and the launched instantiation are those
+# the counters were taken on (else null).
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gather_fp64_3842modes_hbm_traffic.txt")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gather_batch_mixed_512waveforms_hbm_traffic.txt")
+VJP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vjp_mixed_64waveforms_hbm_traffic.txt")
+GATHER_SOURCES = ["paper_2307_12585_amd/csrc/gather.hip", "paper_2307_12585_amd/csrc/evalcore.hpp",
+                  "paper_2307_12585_amd/csrc/spa.hpp", "paper_2307_12585_amd/csrc/w_table.inc",
+                  "paper_2307_12585_amd/csrc/fdemri_internal.hpp"]
 
 
-def gather_traffic(bpl):
+def sources_digest(files):
     import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profile_traffic(path, kernel, key="traffic_bytes_per_launch"):
+    """The recorded figure `key` of `kernel` from a counter summary, or None."""
+    rec = {}
     try:
-        rec = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             for ln in fh:
                 if "=" in ln and not ln.lstrip().startswith("#"):
                     k, v = ln.split("=", 1)
                     rec[k.strip()] = v.strip()
-        files = ["paper_2307_12585_amd/csrc/gather.hip", "paper_2307_12585_amd/csrc/evalcore.hpp",
-                 "paper_2307_12585_amd/csrc/spa.hpp", "paper_2307_12585_amd/csrc/w_table.inc",
-                 "paper_2307_12585_amd/csrc/fdemri_internal.hpp"]
-        h = hashlib.sha256()
-        for f in files:
-            with open(os.path.join(ROOT, f), "rb") as fh:
-                h.update(fh.read())
-    except OSError:
+        files = [x.strip() for x in rec.get("sources", ",".join(GATHER_SOURCES)).split(",") if x.strip()]
+        digest = sources_digest(files)
+    except (OSError, KeyError):
         return None
-    if h.hexdigest() != rec.get("kernel_sources_sha256"):
+    if digest != rec.get("kernel_sources_sha256") or rec.get("kernel") != kernel or key not in rec:
         return None
-    if rec.get("kernel") != f"gather_kernel<false, {bpl}, 4, false>":
-        return None
-    return float(rec["traffic_bytes_per_launch"])
+    return float(rec[key])
+
+
+def gather_traffic(bpl):
+    return profile_traffic(TRAFFIC_FILE, f"gather_kernel<false, {bpl}, 4, false>")
 
 
 def headline(args, w, evals, sec, prof, achieved, bpl, secondary):
+    bpl = bpl or 1  # without the autotuner: the default block shape, 1 tile per wave
     return {
         "metric": METRIC,
         "value": 1.0 / sec,
@@ -570,7 +731,9 @@ def headline(args, w, evals, sec, prof, achieved, bpl, secondary):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": gather_traffic(bpl),
                      "traffic_unit": "HBM bytes per launch (read + write)",
-                     "kernel": f"gather_kernel<false, {bpl}, 4, false>", "flops_per_eval": FLOPS_PER_EVAL},
+                     "kernel": f"gather_kernel<false, {bpl}, 4, false>", "flops_per_eval": FLOPS_PER_EVAL,
+                     "issued_fp64_flops_per_eval": profile_traffic(
+                         TRAFFIC_FILE, f"gather_kernel<false, {bpl}, 4, false>", "issued_fp64_flops_per_eval")},
         "secondary": secondary,
     }
 

@@ -26,7 +26,10 @@
  *    holds, mode rows outside the supported range) are recorded in a
  *    per-context flag word; fdemri_sync_flags synchronises the stream,
  *    returns the word and clears it.
- *  - One context per host thread (contexts are not internally locked).
+ *  - One context per host thread (contexts are not internally locked).  All
+ *    calls on one context use its workspace: issue them on one stream, or
+ *    order their streams (events); calls on a context that overlap in time on
+ *    different streams race on its scratch tables and give wrong results.
  *  - Transform convention of Eq. singlevoiceFT: h(f) = int h(t) e^{+2 pi i f t} dt,
  *    with h = h_+ - i h_x (Eq. main_wave).
  */
@@ -73,6 +76,13 @@ typedef enum {
 #define FDEMRI_FLAG_TRAJ_STEPS 0x4u      /* fdemri_trajectory: a waveform needed more than
                                             the step bound of its integrator; its knots
                                             past that point repeat the last state */
+#define FDEMRI_FLAG_BAD_INPUT 0x8u       /* a waveform's device data failed the input checks
+                                            (t not finite or not strictly increasing; a
+                                            trajectory or amplitude value not finite; f not
+                                            finite, negative or descending; FDEMRI_LL_HANN on
+                                            a grid other than f_k = k f_1): its outputs are
+                                            zeros (waveform, adjoint; the likelihood of a
+                                            zero model) */
 #define FDEMRI_MAX_PIECES 16
 #define FDEMRI_MAX_KNOTS 512
 #define FDEMRI_MAX_L 40
@@ -101,9 +111,13 @@ typedef enum {
  * Host scalars: theta, phi (source-frame polar/azimuthal viewing angles),
  *   scale = mu/d_L (dimensionless strain scale of Eq. main_wave).
  * Limits: 4 <= K <= FDEMRI_MAX_KNOTS, 1 <= Nm, 1 <= Nf < 2^31.
- * Data-dependent conditions (ordering of t and f, finiteness) are not read
- * back by the host; with invalid data the kernels stay in bounds and the
- * output is unspecified.
+ * Data-dependent conditions are checked on the device, since the host does
+ * not read device data (the device-side form of FDEMRI_EINVAL): t finite and
+ * strictly increasing; Fphi, Fr, Phiphi, Phir and A finite; f finite, >= 0
+ * and ascending.  A waveform that fails them gets zero outputs and raises
+ * FDEMRI_FLAG_BAD_INPUT (fdemri_sync_flags); the kernels stay in bounds.
+ * (fdemri_td_waveform and fdemri_signal_band raise the flag too; their
+ * outputs are then unspecified.)
  */
 typedef struct {
   int32_t K;
@@ -123,7 +137,10 @@ typedef struct {
                                          use and replay it on later calls */
 
 /* Create a context on HIP device `hip_device` (0-based) with FDEMRI_CTX_* flags.
- * On success *out receives the context. */
+ * On success *out receives the context.  Test hook: with the environment
+ * variable FDEMRI_TEST_FAIL_ALLOC=n (n >= 1) set at creation, the n-th growth
+ * of the context's workspace fails as a failed device allocation would
+ * (FDEMRI_ENOMEM, nothing enqueued, outputs untouched, the context usable). */
 fdemri_status fdemri_create(fdemri_ctx **out, int hip_device, uint32_t flags);
 
 /* Release the context and its scratch memory (synchronises the device). */
@@ -221,7 +238,14 @@ fdemri_status fdemri_vjp(fdemri_ctx *ctx, const fdemri_waveform_desc *desc, fdem
                                 3-tap Hann kernel h_w(f_k) = h(f_k)/2 - h(f_{k+1})/4
                                 - h(f_{k-1})/4 (the frequency-domain form of a Hann
                                 window on the DFT grid; h = 0 past the last bin and
-                                h(f_{-1}) = conj h(f_1) before the first) */
+                                h(f_{-1}) = conj h(f_1) before the first).  Only on
+                                a grid f_k = k f_1 (f_0 = 0, uniform to 1e-12), the
+                                grid on which it is the transform of the windowed
+                                series; other grids raise FDEMRI_FLAG_BAD_INPUT.
+                                Past the last bin the model is taken as 0 also when
+                                that bin is the Nyquist bin (whose neighbour would
+                                be the conjugate reflection): the signal band is
+                                expected to end below Nyquist */
 
 /*
  * Whittle log-likelihood of data against the waveform of `desc` (Eq. likelihood
@@ -350,6 +374,25 @@ fdemri_status fdemri_autotune(fdemri_ctx *ctx, int32_t B, const fdemri_waveform_
                               hipStream_t stream, int32_t *bpl_out);
 
 /*
+ * The per-root factor of Eq. extendedspa1,
+ *   G = |Fd|^{-1/2} e^{-i pi/4 sgn Fd} W(X),  X = 2 pi Fd^3 / (3 Fdd^2),
+ * W(X) = sqrt(2|X|/pi) e^{-i pi/4 sgn X} e^{-iX} K_{1/3}(-iX) (the printed
+ * constant taken with the opposite sign, the reading under which the factor
+ * reduces to the standard stationary-phase one as Fdd -> 0), for n pairs
+ * (Fd, Fdd) = (dF/dt, d2F/dt2) at a root, evaluated by the device code of the
+ * mode sum.  As there, the length of the large-argument series is chosen per
+ * 64 consecutive elements (one wavefront) from the largest |1/X| among them.
+ *   gd, gdd : [n] double, DEVICE; dir : [n] int32, DEVICE, the direction (+1 or
+ *             -1) of the monotonic piece, used only where Fd == 0 (then
+ *             G = pi (pi |Fdd|)^{-1/3} [Ai(0) - i dir Bi(0)]).
+ *   G       : [n] complex (interleaved re, im) of the precision's type.
+ * Fdd == 0 gives the standard factor (W = 1); Fd == Fdd == 0 gives 0.
+ * FDEMRI_EINVAL for n < 0 or NULL pointers (nothing enqueued).
+ */
+fdemri_status fdemri_spa_factor(fdemri_ctx *ctx, fdemri_prec prec, int32_t n, const double *gd,
+                                const double *gdd, const int32_t *dir, void *G, hipStream_t stream);
+
+/*
  * Count of mode-bin evaluations of the last fdemri_waveform call on this
  * context: the number of (monotonic piece of |F_V|, bin) pairs with the bin
  * inside the piece's frequency range.  Synchronises `stream`.
@@ -366,7 +409,8 @@ fdemri_status fdemri_last_eval_count(fdemri_ctx *ctx, hipStream_t stream, int64_
 #define FDEMRI_KERNEL_SPLINE 0
 #define FDEMRI_KERNEL_PIECES 1
 #define FDEMRI_KERNEL_GATHER 2
-#define FDEMRI_KERNEL_VJP 3
+#define FDEMRI_KERNEL_VJP 3      /* the adjoint's per-(mode, segment) kernel (its reductions
+                                    and the transposed spline are not bracketed) */
 #define FDEMRI_KERNEL_COUNT 4
 fdemri_status fdemri_profile_enable(fdemri_ctx *ctx, int enable);
 fdemri_status fdemri_profile_read(fdemri_ctx *ctx, hipStream_t stream, double *ms_out, int64_t *launches_out);

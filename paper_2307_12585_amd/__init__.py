@@ -28,6 +28,7 @@ FDEMRI_CTX_BATCH_GRAPHS = 0x1
 FDEMRI_FLAG_PIECE_OVERFLOW = 0x1
 FDEMRI_FLAG_BAD_MODE = 0x2
 FDEMRI_FLAG_TRAJ_STEPS = 0x4
+FDEMRI_FLAG_BAD_INPUT = 0x8
 FDEMRI_LL_HANN = 0x1
 PRECISIONS = {"fp64": FDEMRI_FP64, "mixed": FDEMRI_MIXED}
 
@@ -36,7 +37,7 @@ EXPORTED = [
     "fdemri_waveform", "fdemri_waveform_batch", "fdemri_vjp", "fdemri_last_eval_count",
     "fdemri_profile_enable", "fdemri_profile_read", "fdemri_autotune", "fdemri_loglike",
     "fdemri_loglike_batch", "fdemri_select_modes", "fdemri_td_waveform", "fdemri_trajectory",
-    "fdemri_signal_band", "fdemri_profile_classes", "fdemri_waveform_noalloc",
+    "fdemri_signal_band", "fdemri_profile_classes", "fdemri_waveform_noalloc", "fdemri_spa_factor",
 ]
 KERNEL_CLASSES = ["spline", "pieces", "gather", "vjp"]
 
@@ -119,6 +120,8 @@ def lib():
         L.fdemri_profile_enable.restype = ctypes.c_int
         L.fdemri_profile_read.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.fdemri_profile_read.restype = ctypes.c_int
+        L.fdemri_spa_factor.argtypes = [vp, ctypes.c_int, i32, vp, vp, vp, vp, vp]
+        L.fdemri_spa_factor.restype = ctypes.c_int
         L.fdemri_profile_classes.argtypes = [vp, u32]
         L.fdemri_profile_classes.restype = ctypes.c_int
         _lib_handle = L
@@ -276,6 +279,20 @@ class Context:
         self._check(self._lib.fdemri_waveform_noalloc(self._h, ctypes.byref(d), p, _ptr(hp), _ptr(hc),
                                                       _stream(self.device)))
         return hp, hc
+
+    def spa_factor(self, gd, gdd, direction, prec="fp64"):
+        """fdemri_spa_factor: G of Eq. extendedspa1 for float64 device tensors
+        gd, gdd and int32 piece directions; complex128 (fp64) or complex64."""
+        p = PRECISIONS[prec]
+        ctype = torch.complex128 if p == FDEMRI_FP64 else torch.complex64
+        gd = gd.to(torch.float64).contiguous()
+        gdd = gdd.to(torch.float64).contiguous()
+        direction = direction.to(torch.int32).contiguous()
+        assert gd.numel() == gdd.numel() == direction.numel()
+        out = torch.empty(gd.numel(), dtype=ctype, device=gd.device)
+        self._check(self._lib.fdemri_spa_factor(self._h, p, gd.numel(), _ptr(gd), _ptr(gdd), _ptr(direction),
+                                                _ptr(out), _stream(self.device)))
+        return out
 
     def waveform(self, t, Fphi, Fr, Phiphi, Phir, l, m, n, A, theta, phi, scale, f,
                  prec="fp64", partners=True):

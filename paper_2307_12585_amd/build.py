@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfdemri.so")
-SOURCES = ["spline.hip", "pieces.hip", "gather.hip", "vjp.hip", "select.hip", "td.hip", "traj.hip", "api.hip"]
+SOURCES = ["spline.hip", "pieces.hip", "gather.hip", "vjp.hip", "select.hip", "td.hip", "traj.hip", "spa_eval.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -67,7 +67,7 @@ struct Prepared {
   const ModeConst* modes;  // [Nm]
   const int2* mode_kr;     // [Nm] bin range of each mode (union of its pieces)
   const Piece* pieces;     // [Nm][kMaxPieces]
-  const int32_t* env;      // [2] bin envelope of all modes
+  const int32_t* env;      // [4] bin envelope of all modes, then the input status (0: valid)
 };
 
 // Device-resident record of one waveform of a batch: caller inputs, the
@@ -85,7 +85,7 @@ struct WaveItem {
   int2* mode_kr;
   Piece* pieces;
   int64_t* evals;
-  int32_t* env;
+  int32_t* env;  // [4]: bin envelope, input status, unused
   void* hp;
   void* hc;
   // fused likelihood of the batch: data, per-bin weights and this waveform's
@@ -115,6 +115,28 @@ __host__ __device__ inline Prepared prepared_of(const WaveItem& w) {
   p.pieces = w.pieces;
   p.env = w.env;
   return p;
+}
+
+// Input checks on the device (the host does not read device data): a
+// waveform whose inputs fail them has status bits in env[2], every kernel
+// writes zeros for it, and FDEMRI_FLAG_BAD_INPUT is raised.  The first launch
+// of a call clears the status; the checks run in the launch that also forms
+// the bin envelope; the gather and the adjoint read it.
+constexpr int32_t kBadKnots = 1;     // t not finite or not strictly increasing
+constexpr int32_t kBadValues = 2;    // a trajectory or amplitude value not finite
+constexpr int32_t kBadGrid = 4;      // f not finite, negative or descending
+constexpr int32_t kBadHannGrid = 8;  // Hann kernel asked for on a grid that is not k f_1
+// Elements checked per workgroup of the checks.
+constexpr int kCheckChunk = 4096;
+
+// Workgroups of the checks of one waveform: the trajectory, the amplitude
+// array (knot values or given coefficients), the frequency grid.
+__host__ __device__ inline long check_amp_count(int K, int Nm, uint32_t flags) {
+  return (flags & FDEMRI_COEFFS_GIVEN) ? (long)Nm * (K - 1) * 8 : (long)Nm * K * 2;
+}
+__host__ __device__ inline int check_blocks(int K, int Nm, int Nf, uint32_t flags) {
+  return 1 + (int)((check_amp_count(K, Nm, flags) + kCheckChunk - 1) / kCheckChunk) +
+         (int)(((long)Nf + kCheckChunk - 1) / kCheckChunk);
 }
 
 // Qualifier of read-only device tables read through the constant address

@@ -526,8 +526,9 @@ __global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_
   const Prepared& p = a.p;
   const int kb = (int)blockIdx.x * block_bins<BPL, WAVES>();
   const int kbe = kb + block_bins<BPL, WAVES>() - 1;
-  // blocks outside the bin envelope of all modes hold a zero model
-  if (kbe < p.env[0] || kb > p.env[1]) {
+  // blocks outside the bin envelope of all modes hold a zero model, and so
+  // does every block of a waveform whose inputs failed the checks
+  if (kbe < p.env[0] || kb > p.env[1] || p.env[2] != 0) {
     if constexpr (LL) {
       const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
       Acc<MIXED> z;
@@ -708,7 +709,7 @@ __global__ __launch_bounds__(64 * WAVES, gather_batch_min_waves<MIXED>()) void g
       out.edge = w.ll_edge;
       out.hann = hann;
     }
-    if (kbe < p.env[0] || kb > p.env[1]) {
+    if (kbe < p.env[0] || kb > p.env[1] || p.env[2] != 0) {
       if constexpr (LL) {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         Acc<MIXED> z;

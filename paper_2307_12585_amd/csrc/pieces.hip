@@ -368,15 +368,77 @@ __device__ __forceinline__ void envelope_block(const int2* __restrict__ mode_kr,
   }
 }
 
-__global__ __launch_bounds__(256) void envelope_kernel(const int2* __restrict__ mode_kr, int Nm,
-                                                       int32_t* __restrict__ env) {
-  envelope_block(mode_kr, Nm, env);
+// Inputs of one waveform's checks (device pointers of the caller's arrays).
+struct CheckArgs {
+  int32_t K, Nm, Nf;
+  uint32_t flags;
+  int hann;  // the grid must be f_k = k f_1 (the 3-tap Hann kernel's DFT grid)
+  const double *t, *Fphi, *Fr, *Phiphi, *Phir, *A, *f;
+};
+
+// Workgroup blk of the checks of one waveform (check_blocks of them): 0 the
+// trajectory (t finite and strictly increasing, the frequencies and phases
+// finite), then the amplitude array in chunks (finite), then the frequency
+// grid in chunks (finite, >= 0, ascending; with hann also |f_k - k f_1| <=
+// 1e-12 f_k, so f_0 = 0).  Failures set status bits in env[2] and the
+// context's flag bit; nothing is written otherwise.
+__device__ void check_block(const CheckArgs& c, int blk, int32_t* env, uint32_t* flag_word) {
+  int32_t bad = 0;
+  const long na = check_amp_count(c.K, c.Nm, c.flags);
+  const int nab = (int)((na + kCheckChunk - 1) / kCheckChunk);
+  if (blk == 0) {
+    for (int i = threadIdx.x; i < c.K; i += blockDim.x) {
+      const double ti = c.t[i];
+      if (!isfinite(ti) || (i > 0 && !(ti > c.t[i - 1]))) bad |= kBadKnots;
+      if (!isfinite(c.Fphi[i]) || !isfinite(c.Fr[i]) || !isfinite(c.Phiphi[i]) || !isfinite(c.Phir[i]))
+        bad |= kBadValues;
+    }
+  } else if (blk <= nab) {
+    const long base = (long)(blk - 1) * kCheckChunk;
+    for (int j = threadIdx.x; j < kCheckChunk; j += blockDim.x) {
+      const long e = base + j;
+      if (e < na && !isfinite(c.A[e])) bad |= kBadValues;
+    }
+  } else {
+    const long base = (long)(blk - 1 - nab) * kCheckChunk;
+    const double f1 = c.Nf > 1 ? c.f[1] : 0.0;
+    for (int j = threadIdx.x; j < kCheckChunk; j += blockDim.x) {
+      const long k = base + j;
+      if (k >= c.Nf) break;
+      const double fk = c.f[k];
+      if (!isfinite(fk) || !(fk >= 0.0) || (k > 0 && !(fk >= c.f[k - 1]))) bad |= kBadGrid;
+      if (c.hann && !(fabs(fk - (double)k * f1) <= 1e-12 * fk)) bad |= kBadHannGrid;
+    }
+  }
+  if (bad) {
+    atomicOr(env + 2, bad);
+    atomicOr(flag_word, (uint32_t)FDEMRI_FLAG_BAD_INPUT);
+  }
 }
 
-// Batched: one workgroup per waveform.
-__global__ __launch_bounds__(256) void envelope_batch_kernel(const WaveItem* __restrict__ items) {
-  const WaveItem& w = items[blockIdx.x];
-  envelope_block(w.mode_kr, w.Nm, w.env);
+// Workgroup 0: the bin envelope; workgroups 1..: the input checks.
+__global__ __launch_bounds__(256) void envelope_kernel(const int2* __restrict__ mode_kr, int Nm,
+                                                       int32_t* __restrict__ env, CheckArgs c, uint32_t* flag_word) {
+  if (blockIdx.x == 0)
+    envelope_block(mode_kr, Nm, env);
+  else
+    check_block(c, (int)blockIdx.x - 1, env, flag_word);
+}
+
+// Batched: grid row y is waveform y; workgroup 0 of a row forms its bin
+// envelope, workgroups 1.. run its checks (rows of smaller waveforms leave
+// the rest idle).
+__global__ __launch_bounds__(256) void envelope_batch_kernel(const WaveItem* __restrict__ items, int hann,
+                                                             uint32_t* flag_word) {
+  const WaveItem& w = items[blockIdx.y];
+  if (blockIdx.x == 0) {
+    envelope_block(w.mode_kr, w.Nm, w.env);
+    return;
+  }
+  const int blk = (int)blockIdx.x - 1;
+  if (blk >= check_blocks(w.K, w.Nm, w.Nf, w.flags)) return;
+  const CheckArgs c{w.K, w.Nm, w.Nf, w.flags, hann, w.t, w.Fphi, w.Fr, w.Phiphi, w.Phir, w.A, w.f};
+  check_block(c, blk, w.env, flag_word);
 }
 
 // Batched pieces: one wavefront per mode, kPieceWaves modes per workgroup.
@@ -427,11 +489,14 @@ __global__ __launch_bounds__(64 * kPieceWaves) void pieces_batch_kernel(const Wa
   piece_mode_wave(a, g - mode_prefix[lo], ev[wave]);
 }
 
+// The batch's piece tables, then its envelopes and input checks
+// (max_checks: the largest check_blocks of its waveforms; hann: the
+// likelihood's Hann kernel needs DFT grids).
 hipError_t launch_pieces_batch(const WaveItem* items, int B, const int32_t* mode_prefix, int total_modes,
-                               uint32_t* flag_word, hipStream_t stream) {
+                               int max_checks, int hann, uint32_t* flag_word, hipStream_t stream) {
   const int blocks = (total_modes + kPieceWaves - 1) / kPieceWaves;
   pieces_batch_kernel<<<blocks, 64 * kPieceWaves, 0, stream>>>(items, B, mode_prefix, total_modes, flag_word);
-  envelope_batch_kernel<<<B, 256, 0, stream>>>(items);
+  envelope_batch_kernel<<<dim3((unsigned)(1 + max_checks), (unsigned)B), 256, 0, stream>>>(items, hann, flag_word);
   return hipGetLastError();
 }
 
@@ -463,7 +528,9 @@ __global__ __launch_bounds__(NT) void setup_kernel(PieceArgs a, int piece_blocks
 }
 
 // The piece tables and, unless A is NULL, the amplitude splines of Nm modes
-// (acoef [Nm][K-1][8]) in one launch, then the bin envelope.  The trajectory
+// (acoef [Nm][K-1][8]) in one launch, then the bin envelope with the input
+// checks (A_in: the caller's amplitude array, knot values or coefficients;
+// hann: the grid must be the Hann kernel's DFT grid).  The trajectory
 // spline coefficients tcoef and the knot matrix's reduction factors fac,
 // written by launch_spline with the same thread count, must be in place
 // (stream order).
@@ -471,7 +538,8 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
                              const double* f, const double* tcoef, const int32_t* l, const int32_t* m,
                              const int32_t* n, double theta, double phi, double scale, uint32_t flags,
                              const double* A, double* acoef, double* fac, ModeConst* modes, int2* mode_kr,
-                             Piece* pieces, int64_t* evals, int32_t* env, uint32_t* flag_word, hipStream_t stream) {
+                             Piece* pieces, int64_t* evals, int32_t* env, uint32_t* flag_word, const double* Phiphi,
+                             const double* Phir, const double* A_in, int hann, hipStream_t stream) {
   PieceArgs a;
   a.K = K;
   a.Nm = Nm;
@@ -501,7 +569,8 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
     const int pb = (Nm + 7) / 8;
     setup_kernel<512><<<pb + amp_blocks, 512, 0, stream>>>(a, pb, A, acoef, fac);
   }
-  envelope_kernel<<<1, 256, 0, stream>>>(mode_kr, Nm, env);
+  const CheckArgs c{K, Nm, Nf, flags, hann, t, Fphi, Fr, Phiphi, Phir, A_in, f};
+  envelope_kernel<<<1 + check_blocks(K, Nm, Nf, flags), 256, 0, stream>>>(mode_kr, Nm, env, c, flag_word);
   return hipGetLastError();
 }
 

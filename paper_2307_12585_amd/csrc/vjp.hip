@@ -118,7 +118,9 @@ __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_unit_kernel(V
   const double Ppr = reduce_2pi(((const kconst double*)p.Phiphi)[i]);
   const double Prr = reduce_2pi(((const kconst double*)p.Phir)[i]);
 
-  for (int q = 0; q < md.npieces; ++q) {
+  // a waveform whose inputs failed the checks has a zero gradient
+  const int npieces = p.env[2] != 0 ? 0 : md.npieces;
+  for (int q = 0; q < npieces; ++q) {
     const Piece P = ((const kconst Piece*)p.pieces)[(size_t)mu * kMaxPieces + q];
     if (i < P.seg_a || i > P.seg_b || P.k_lo > P.k_hi) continue;
     const int s = P.s, d = P.d;
@@ -366,7 +368,8 @@ __global__ __launch_bounds__(NT) void spline_adjoint_kernel(int K, const double*
                                                             const double* __restrict__ gPhi_coef,
                                                             const double* __restrict__ gA_coef,
                                                             double* __restrict__ gPhi_knots,
-                                                            double* __restrict__ gA_knots) {
+                                                            double* __restrict__ gA_knots,
+                                                            const int32_t* __restrict__ env) {
   __shared__ double sa[NT], sb[NT], sc[NT], sr[NT], sh[NT], sdb[NT];
   const int i = threadIdx.x;
   const int series = blockIdx.x;
@@ -375,6 +378,17 @@ __global__ __launch_bounds__(NT) void spline_adjoint_kernel(int K, const double*
   if (!amp && gPhi_knots == nullptr) return;
   if (amp && gA_knots == nullptr) return;
   const int mode = amp ? (series - 2) >> 1 : 0, part = amp ? (series - 2) & 1 : 0;
+  if (env[2] != 0) {
+    // inputs that failed the checks (the knots may not even be increasing):
+    // a zero gradient, without the solve
+    if (i < K) {
+      if (amp)
+        gA_knots[((size_t)mode * K + i) * 2 + part] = 0.0;
+      else
+        gPhi_knots[(size_t)series * K + i] = 0.0;
+    }
+    return;
+  }
   auto gcoef = [&](int seg, int k) -> double {
     if (amp) return gA_coef[(((size_t)mode * n + seg) * 4 + k) * 2 + part];
     return gPhi_coef[((size_t)series * n + seg) * 4 + k];
@@ -476,10 +490,10 @@ __global__ __launch_bounds__(NT) void spline_adjoint_kernel(int K, const double*
   }
 }
 
-hipError_t launch_vjp(const Prepared& p, const float* acoef32, bool mixed, const void* g_hp, const void* g_hc,
-                      double* gA_coef, double* PZ, double* Upart, double* T3, double* gPhi_coef,
-                      double* g_scalars, const int32_t* l, const int32_t* m, double theta, double phi, double scale,
-                      uint32_t flags, hipStream_t stream) {
+// The per-(mode, segment) unit kernel of the adjoint (its partial sums into
+// gA_coef, PZ and Upart).
+hipError_t launch_vjp_units(const Prepared& p, const float* acoef32, bool mixed, const void* g_hp, const void* g_hc,
+                            double* gA_coef, double* PZ, double* Upart, hipStream_t stream) {
   VjpArgs a;
   a.p = p;
   a.acoef32 = acoef32;
@@ -495,8 +509,15 @@ hipError_t launch_vjp(const Prepared& p, const float* acoef32, bool mixed, const
     vjp_unit_kernel<true><<<blocks, 256, 0, stream>>>(a);
   else
     vjp_unit_kernel<false><<<blocks, 256, 0, stream>>>(a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// The reductions after the unit kernel: phase-coefficient gradients, per-mode
+// angle and scale terms, and the five scalars.
+hipError_t launch_vjp_reduce(const Prepared& p, double* PZ, double* Upart, double* T3, double* gPhi_coef,
+                             double* g_scalars, const int32_t* l, const int32_t* m, double theta, double phi,
+                             double scale, uint32_t flags, hipStream_t stream) {
+  const int nseg = p.K - 1;
   vjp_phi_kernel<<<nseg, 256, 0, stream>>>(p.Nm, nseg, p.modes, PZ, gPhi_coef);
   vjp_modes_kernel<<<(p.Nm + 63) / 64, 64, 0, stream>>>(p.Nm, nseg, l, m, theta, phi, scale, flags, p.modes, Upart, T3);
   vjp_final_kernel<<<1, 256, 0, stream>>>(p.Nm, nseg, T3, gPhi_coef, g_scalars);
@@ -504,16 +525,16 @@ hipError_t launch_vjp(const Prepared& p, const float* acoef32, bool mixed, const
 }
 
 hipError_t launch_spline_adjoint(int K, const double* t, int Nm, const double* gPhi_coef, const double* gA_coef,
-                                 double* gPhi_knots, double* gA_knots, hipStream_t stream) {
+                                 double* gPhi_knots, double* gA_knots, const int32_t* env, hipStream_t stream) {
   dim3 grid(2 + 2 * Nm);
   if (K <= 64)
-    spline_adjoint_kernel<64><<<grid, 64, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots);
+    spline_adjoint_kernel<64><<<grid, 64, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, env);
   else if (K <= 128)
-    spline_adjoint_kernel<128><<<grid, 128, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots);
+    spline_adjoint_kernel<128><<<grid, 128, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, env);
   else if (K <= 256)
-    spline_adjoint_kernel<256><<<grid, 256, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots);
+    spline_adjoint_kernel<256><<<grid, 256, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, env);
   else
-    spline_adjoint_kernel<512><<<grid, 512, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots);
+    spline_adjoint_kernel<512><<<grid, 512, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, env);
   return hipGetLastError();
 }
 

@@ -97,6 +97,39 @@ def test_batch_graph_replays_match_eager(ctx):
     gctx.close()
 
 
+def test_batch_graph_follows_changed_angles_and_scale(ctx):
+    """The graph of a batch is keyed on its pointers and shapes only: new
+    viewing angles and scales (same buffers) are written into the records the
+    replay reads, so every replay equals the eager batch at the new values;
+    more distinct buffers than the graph cache holds evict the least recently
+    used graph, which is captured again when it comes back."""
+    ws = batch_members()[:5]
+    dws = [fd.DeviceWaveform.from_workload(w, device=ctx.device) for w in ws]
+    gctx = fd.Context(0, graphs=True)
+    outs = [(torch.empty(d.Nf, dtype=torch.complex128, device=ctx.device),
+             torch.empty(d.Nf, dtype=torch.complex128, device=ctx.device)) for d in dws]
+    rng = np.random.default_rng(5)
+    for rep in range(10):
+        for d in dws:
+            d.theta, d.phi, d.scale = float(rng.uniform(0.1, 3.0)), float(rng.uniform(0, 6.2)), float(rng.uniform(0.5, 2.0)) * 1e-20
+        gctx.waveform_batch(dws, "fp64", outs=outs)
+        ref = ctx.waveform_batch(dws, "fp64")
+        torch.cuda.synchronize()
+        for (gp, gc), (rp, rc) in zip(outs, ref):
+            assert torch.equal(gp, rp) and torch.equal(gc, rc), rep
+    # 10 distinct output sets (10 graph keys) against a cache of 8, then the first again
+    sets = [[(torch.empty(d.Nf, dtype=torch.complex128, device=ctx.device),
+              torch.empty(d.Nf, dtype=torch.complex128, device=ctx.device)) for d in dws[:2]] for _ in range(10)]
+    ref = ctx.waveform_batch(dws[:2], "fp64")
+    for o in sets + sets[:1]:
+        gctx.waveform_batch(dws[:2], "fp64", outs=o)
+    torch.cuda.synchronize()
+    for o in sets:
+        for (gp, gc), (rp, rc) in zip(o, ref):
+            assert torch.equal(gp, rp) and torch.equal(gc, rc)
+    gctx.close()
+
+
 def test_autotune_choice_and_invariance(ctx, tmp_path, monkeypatch):
     """The autotuner picks one of the tile sizes, records it in the cache
     file, and results do not depend on the tile size."""

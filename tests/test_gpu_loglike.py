@@ -38,7 +38,7 @@ def data_for(h, f, seed):
     return (1.1 * np.exp(0.3j) * h[0] + n_p, 0.9 * np.exp(-0.2j) * h[1] + n_c)
 
 
-def gpu_loglike(ctx, w, d, wS, prec="fp64", hann=False, f=None):
+def gpu_loglike(ctx, w, d, wS, prec="fp64", hann=False, f=None, flags=0):
     dw = fd.DeviceWaveform.from_workload(w, device=ctx.device, f=f)
     ctype = torch.complex128 if prec == "fp64" else torch.complex64
     dp = torch.as_tensor(d[0], device=ctx.device).to(ctype).contiguous()
@@ -46,7 +46,7 @@ def gpu_loglike(ctx, w, d, wS, prec="fp64", hann=False, f=None):
     ws = torch.as_tensor(wS, dtype=torch.float64, device=ctx.device).contiguous()
     out = ctx.loglike_dev(dw, dp, dc, ws, prec=prec, hann=hann)
     torch.cuda.synchronize()
-    assert ctx.sync_flags() == 0
+    assert ctx.sync_flags() == flags
     return out.cpu().numpy()
 
 
@@ -112,9 +112,15 @@ def test_loglike_3842_modes_fused_equals_unfused(ctx, hann):
 
 
 def test_loglike_ragged_and_offset_grids(ctx):
+    """Ragged grid lengths (the Hann edge records across tiles and at the grid
+    end) on DFT grids from f = 0, with and without the Hann kernel; offset
+    grids without it.  The Hann kernel on an offset grid (not f_k = k f_1)
+    raises FDEMRI_FLAG_BAD_INPUT and compares the data with a zero model."""
     w = W.inspiral_20_modes()
     rng = np.random.default_rng(3)
-    for lo, hi in [(0, 1), (0, 63), (0, 64), (0, 65), (3, 1000), (12345, 12345 + 257), (100001, 100001 + 65 * 64 + 3)]:
+    grids = [(0, 1), (0, 63), (0, 64), (0, 65), (0, 257), (0, 1000), (0, 65 * 64 + 3), (0, 100001 + 65 * 64 + 3),
+             (3, 1000), (12345, 12345 + 257), (100001, 100001 + 65 * 64 + 3)]
+    for lo, hi in grids:
         f = w.f[lo:hi]
         hg = gpu_waveform(ctx, w, f=f)
         wS = rng.uniform(0.5, 2.0, f.size)
@@ -122,6 +128,14 @@ def test_loglike_ragged_and_offset_grids(ctx):
         scale = max(np.max(np.abs(hg[0])), 1e-30)
         d = tuple(x * scale for x in d)
         for hann in (False, True):
+            dft = lo == 0
+            if hann and not dft:
+                got = gpu_loglike(ctx, w, d, wS, hann=True, f=f, flags=fd.FDEMRI_FLAG_BAD_INPUT)
+                zero = tuple(np.zeros(f.size, complex) for _ in range(2))
+                ref = fused_sums(d, zero, wS, hann=True)
+                assert got[1] == 0.0 and got[2] == 0.0
+                assert abs(got[0] - ref[0]) <= 1e-12 * abs(ref[0]), (lo, hi)
+                continue
             got = gpu_loglike(ctx, w, d, wS, hann=hann, f=f)
             ref = fused_sums(d, hg, wS, hann=hann)
             for q in range(3):
@@ -156,7 +170,7 @@ def test_loglike_deterministic_and_invalid(ctx):
 @pytest.mark.parametrize("prec,hann", [("fp64", False), ("fp64", True), ("mixed", True)])
 def test_loglike_batch_equals_single_calls(ctx, prec, hann):
     """fdemri_loglike_batch over waveforms of uneven sizes (ragged grids, a
-    log grid) equals one fdemri_loglike call per waveform, bit for bit."""
+    log grid) equals one fdemri_loglike call per waveform, bit for bit.""" 
     ws = [W.inspiral_20_modes(), W.inspiral_20_modes_log_grid()]
     for prm in W.batch_params(3, 321):
         prm["T"] = min(prm["T"], 0.6 * W.YRSID_SI)
@@ -177,7 +191,11 @@ def test_loglike_batch_equals_single_calls(ctx, prec, hann):
         dws.append(dw)
     out = ctx.loglike_batch(dws, dps, dcs, wss, prec=prec, hann=hann)
     torch.cuda.synchronize()
-    assert ctx.sync_flags() == 0
+    # the log-grid member is not a DFT grid: with the Hann kernel it is flagged
+    # and compared with a zero model, in the batch as in its single call
+    assert ctx.sync_flags() == (fd.FDEMRI_FLAG_BAD_INPUT if hann else 0)
+    if hann:
+        assert float(out[1, 1]) == 0.0 and float(out[1, 2]) == 0.0 and float(out[0, 1]) > 0
     for b, dw in enumerate(dws):
         single = ctx.loglike_dev(dw, dps[b], dcs[b], wss[b], prec=prec, hann=hann)
         torch.cuda.synchronize()
