@@ -31,7 +31,8 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
 struct GatherArgs;
 hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp, void* hc, bool mixed, int bpl,
                               hipStream_t stream);
-hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, hipStream_t stream);
+hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, const ModeConst* modes,
+                        float4* modes32, hipStream_t stream);
 int spline_blocks(int n_series);
 hipError_t launch_spline_batch(const WaveItem* items, int B, const int32_t* block_prefix, int total_blocks, int Kmax,
                                hipStream_t stream);
@@ -173,7 +174,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Scratch layout of one waveform.
 struct Layout {
-  size_t tcoef, fac, acoef, acoef32, modes, mode_kr, pieces, evals, env;
+  size_t tcoef, fac, acoef, acoef32, modes, modes32, mode_kr, pieces, evals, env;
   size_t gA, PZ, Upart, T3, gPhi, gsc;  // adjoint scratch (0 bytes unless requested)
   size_t ll_partial, ll_edge;           // likelihood scratch (0 bytes unless requested)
   size_t total;
@@ -195,6 +196,7 @@ Layout layout_for(int K, int Nm, bool mixed, bool vjp = false, int ll_tiles = 0,
   L.acoef = take((size_t)Nm * nseg * 8 * sizeof(double));
   L.acoef32 = take(mixed ? (size_t)Nm * nseg * 8 * sizeof(float) : 0);
   L.modes = take((size_t)Nm * sizeof(ModeConst));
+  L.modes32 = take(mixed ? (size_t)Nm * sizeof(float4) : 0);
   L.mode_kr = take((size_t)Nm * sizeof(int2));
   L.pieces = take((size_t)Nm * kMaxPieces * sizeof(Piece));
   L.evals = take((size_t)Nm * sizeof(int64_t));
@@ -434,7 +436,8 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
     e = launch_setup_flat(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->f, tcoef, d->l, d->m, d->n, d->theta,
                           d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, (double*)(w + L.fac), modes,
                           mode_kr, pieces, evals, env, c->flag_word, d->Phiphi, d->Phir, d->A, hann, stream);
-    if (e == hipSuccess && mixed) e = launch_amp32(d->Nm, d->K, d->t, acoef, acoef32, stream);
+    if (e == hipSuccess && mixed)
+      e = launch_amp32(d->Nm, d->K, d->t, acoef, acoef32, modes, (float4*)(w + L.modes32), stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "piece kernel launch");
   p.K = d->K;
@@ -452,6 +455,7 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   p.mode_kr = mode_kr;
   p.pieces = pieces;
   p.env = env;
+  p.modes32 = mixed ? (const float4*)(w + L.modes32) : nullptr;
   c->last_evals.assign(1, {evals, d->Nm});
   return FDEMRI_OK;
 }
@@ -801,6 +805,7 @@ void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc*
     it.acoef = (d.flags & FDEMRI_COEFFS_GIVEN) ? const_cast<double*>(d.A) : (double*)(wb + L.acoef);
     it.acoef32 = P.mixed ? (float*)(wb + L.acoef32) : nullptr;
     it.modes = (ModeConst*)(wb + L.modes);
+    it.modes32 = P.mixed ? (float4*)(wb + L.modes32) : nullptr;
     it.mode_kr = (int2*)(wb + L.mode_kr);
     it.pieces = (Piece*)(wb + L.pieces);
     it.evals = (int64_t*)(wb + L.evals);

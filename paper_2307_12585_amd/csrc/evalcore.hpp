@@ -175,6 +175,33 @@ __device__ __forceinline__ void sincos_cw(double x, double* sn, double* cs) {
   *cs = ((q + 1) & 2) ? -c1 : c1;
 }
 
+// sin and cos of psi for the mixed path: the reduction by pi/2 in FP64 (the
+// two-part split of sincos_cw), then degree-2 least-squares polynomials in
+// FP32 on [-pi/4, pi/4] (gen_sincos_coeffs.py; approximation errors 1.4e-8
+// relative for sin and 7.6e-10 for cos, below FP32 rounding) and the
+// quadrant rotation.
+__device__ __forceinline__ void sincos_mixed(double x, float* sn, float* cs) {
+  constexpr double kPio2A = 1.5707963267341256;
+  constexpr double kPio2B = 6.077100506506192e-11;
+  constexpr double k2OverPi = 0.6366197723675814;
+  const double k = rint(x * k2OverPi);
+  double r = __builtin_fma(-k, kPio2A, x);
+  r = __builtin_fma(-k, kPio2B, r);
+  const float rf = (float)r;
+  const float z = rf * rf;
+  float ps = __builtin_fmaf(-0.00019587949872019718f, z, 0.008332748634609668f);
+  ps = __builtin_fmaf(ps, z, -0.16666664665122977f);
+  const float s_r = __builtin_fmaf(rf * z, ps, rf);
+  float pc = __builtin_fmaf(2.4547991314265332e-05f, z, -0.001388830333962966f);
+  pc = __builtin_fmaf(pc, z, 0.04166666466184568f);
+  const float c_r = __builtin_fmaf(z * z, pc, __builtin_fmaf(-0.5f, z, 1.0f));
+  const int q = cvt_i32_sat(k) & 3;
+  const float s1 = (q & 1) ? c_r : s_r;
+  const float c1 = (q & 1) ? s_r : c_r;
+  *sn = (q & 2) ? -s1 : s1;
+  *cs = ((q + 1) & 2) ? -c1 : c1;
+}
+
 // E = e^{i psi} G and the amplitude spline value A at the root (FP64);
 // w = 2 pi f, (ms, ns) = (s m, s n).
 // The amplitude spline coefficients of one segment, (re, im) pairs in
@@ -224,10 +251,9 @@ __device__ __forceinline__ void root_terms32(double f, double w, double tau, int
   const double gd = S.q1 + tau * (2.0 * S.q2 + 3.0 * S.q3 * tau);
   const double gdd = 2.0 * S.q2 + 6.0 * S.q3 * tau;
   const double psi = phase_psi(f, w, tau, ms, ns, S);
-  const double psr = psi - kTwoPiHi * rint(psi * kInvTwoPi);
   const float2 G = spa_factor32(gd, gdd, d);
   float sn, cs;
-  sincosf((float)psr, &sn, &cs);
+  sincos_mixed(psi, &sn, &cs);
   E = make_float2(cs * G.x - sn * G.y, cs * G.y + sn * G.x);
   const float u = (float)tau * __builtin_amdgcn_rcpf((float)S.h);  // tau / h to FP32 accuracy
   A = make_float2(c.lo.x + u * (c.lo.z + u * (c.hi.x + u * c.hi.z)), c.lo.y + u * (c.lo.w + u * (c.hi.y + u * c.hi.w)));

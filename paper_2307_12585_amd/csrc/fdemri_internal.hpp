@@ -68,6 +68,7 @@ struct Prepared {
   const int2* mode_kr;     // [Nm] bin range of each mode (union of its pieces)
   const Piece* pieces;     // [Nm][kMaxPieces]
   const int32_t* env;      // [4] bin envelope of all modes, then the input status (0: valid)
+  const float4* modes32;   // [Nm] (c_+, c_x) of each mode in FP32 (mixed path only)
 };
 
 // Device-resident record of one waveform of a batch: caller inputs, the
@@ -82,6 +83,7 @@ struct WaveItem {
   double* acoef;
   float* acoef32;
   ModeConst* modes;
+  float4* modes32;  // mixed path: (c_+, c_x) in FP32
   int2* mode_kr;
   Piece* pieces;
   int64_t* evals;
@@ -114,6 +116,7 @@ __host__ __device__ inline Prepared prepared_of(const WaveItem& w) {
   p.mode_kr = w.mode_kr;
   p.pieces = w.pieces;
   p.env = w.env;
+  p.modes32 = w.modes32;
   return p;
 }
 

@@ -117,8 +117,9 @@ struct Lds {
 //   cP (A^(s) E) and cX (A^(s) E), A^(s) being A conjugated when s < 0.
 template <bool MIXED>
 __device__ __forceinline__ void eval_bin(const double f, const double w, const Piece& P, const double ms, const double ns,
-                                         const double2 cP, const double2 cX, const double* __restrict__ ac,
-                                         const float* __restrict__ ac32, const Lds& L, Acc<MIXED>& acc) {
+                                         const double2 cP, const double2 cX, const float4 c32,
+                                         const double* __restrict__ ac, const float* __restrict__ ac32, const Lds& L,
+                                         Acc<MIXED>& acc) {
   const double dd_ = P.dd;
   const double fd = dd_ * f;
   // the conversion saturates (and takes NaN to 0); the clamp keeps the guess
@@ -188,7 +189,7 @@ __device__ __forceinline__ void eval_bin(const double f, const double w, const P
     root_terms32(f, w, tau, P.d, ms, ns, S, a32, E, A);
     const float ay = A.y * (float)P.sd;
     const float Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
-    const float pr = (float)cP.x, pi = (float)cP.y, xr = (float)cX.x, xi = (float)cX.y;
+    const float pr = c32.x, pi = c32.y, xr = c32.z, xi = c32.w;
     acc.add(0, pr * Wr - pi * Wi);
     acc.add(1, pr * Wi + pi * Wr);
     acc.add(2, xr * Wr - xi * Wi);
@@ -306,9 +307,18 @@ __device__ __forceinline__ void walk_list(const Prepared& p, const void* __restr
         const double ms = neg ? -md.m : md.m, ns = neg ? -md.n : md.n;
         const double2 cP = make_double2(md.cp_re, neg ? -md.cp_im : md.cp_im);
         const double2 cX = make_double2(md.cx_re, neg ? -md.cx_im : md.cx_im);
+        float4 c32 = make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (MIXED) {
+          // the FP32 mode constants, wave-uniform (scalar load), conjugated on s < 0
+          c32 = ((const kconst float4*)p.modes32)[mode];
+          if (neg) {
+            c32.y = -c32.y;
+            c32.w = -c32.w;
+          }
+        }
         const double* ac = MIXED ? nullptr : (const double*)amp + (size_t)mode * nseg * 8;
         const float* ac32 = MIXED ? (const float*)amp + (size_t)mode * nseg * 8 : nullptr;
-        eval_bin<MIXED>(f, w, P, ms, ns, cP, cX, ac, ac32, L, acc);
+        eval_bin<MIXED>(f, w, P, ms, ns, cP, cX, c32, ac, ac32, L, acc);
       }
     }
   }
@@ -737,13 +747,20 @@ __global__ __launch_bounds__(64 * WAVES, gather_batch_min_waves<MIXED>()) void g
 __global__ void reset_counter_kernel(int* counter) { *counter = 0; }
 
 // Normalised FP32 amplitude coefficients for the mixed path:
-// A(t_i + u h) = sum_k (a_k h^k) u^k, u in [0, 1].
+// A(t_i + u h) = sum_k (a_k h^k) u^k, u in [0, 1]; the thread of segment 0 of
+// a mode also rounds the mode's c_+ and c_x to FP32.
+__device__ __forceinline__ void mode_consts32(const ModeConst& mc, float4* dst) {
+  *dst = make_float4((float)mc.cp_re, (float)mc.cp_im, (float)mc.cx_re, (float)mc.cx_im);
+}
+
 __global__ void amp32_kernel(int Nm, int K, const double* __restrict__ t, const double* __restrict__ acoef,
-                             float* __restrict__ acoef32) {
+                             float* __restrict__ acoef32, const ModeConst* __restrict__ modes,
+                             float4* __restrict__ modes32) {
   const int nseg = K - 1;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)Nm * nseg) return;
   const int i = (int)(idx % nseg);
+  if (i == 0) mode_consts32(modes[idx / nseg], modes32 + idx / nseg);
   const double h = t[i + 1] - t[i];
   const double* c = acoef + idx * 8;
   float* o = acoef32 + idx * 8;
@@ -773,6 +790,7 @@ __global__ void amp32_batch_kernel(const WaveItem* __restrict__ items, int B, co
   const int idx = g - amp_prefix[lo];
   const int nseg = w.K - 1;
   const int i = idx % nseg;
+  if (i == 0) mode_consts32(w.modes[idx / nseg], w.modes32 + idx / nseg);
   const double h = w.t[i + 1] - w.t[i];
   const double* c = w.acoef + (size_t)idx * 8;
   float* o = w.acoef32 + (size_t)idx * 8;
@@ -950,10 +968,12 @@ hipError_t launch_amp32_batch(const WaveItem* items, int B, const int32_t* amp_p
   return hipGetLastError();
 }
 
-hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, hipStream_t stream) {
+hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, const ModeConst* modes,
+                        float4* modes32, hipStream_t stream) {
   const long total = (long)Nm * (K - 1);
   const int threads = 256;
-  amp32_kernel<<<dim3((unsigned)((total + threads - 1) / threads)), threads, 0, stream>>>(Nm, K, t, acoef, acoef32);
+  amp32_kernel<<<dim3((unsigned)((total + threads - 1) / threads)), threads, 0, stream>>>(Nm, K, t, acoef, acoef32,
+                                                                                        modes, modes32);
   return hipGetLastError();
 }
 

@@ -155,12 +155,21 @@ __device__ __forceinline__ float2 spa_factor32(double gd, double gdd, int dir) {
   if (gd != 0.0 && au <= 1.0 / FDW_X_B) {
     const float uf = (float)au;
     const float v = uf * uf;
-    float re = 0.f, im = 0.f;
+    float re, im;
+    if (__all(au <= 1e-3)) {
+      // every active lane has |u| <= 1e-3: terms to u^3 (the first omitted
+      // one, a_4 u^4, is below 1e-13)
+      re = __builtin_fmaf(-fdw_asym32[2], v, fdw_asym32[0]);
+      im = __builtin_fmaf(-fdw_asym32[3], v, fdw_asym32[1]);
+    } else {
+      re = 0.f;
+      im = 0.f;
 #pragma unroll
-    for (int j = (FDW_NASYM32 - 1) / 2; j >= 0; --j) {
-      const float sgn = (j & 1) ? -1.f : 1.f;
-      re = re * v + sgn * fdw_asym32[2 * j];
-      if (2 * j + 1 < FDW_NASYM32) im = im * v + sgn * fdw_asym32[2 * j + 1];
+      for (int j = (FDW_NASYM32 - 1) / 2; j >= 0; --j) {
+        const float sgn = (j & 1) ? -1.f : 1.f;
+        re = re * v + sgn * fdw_asym32[2 * j];
+        if (2 * j + 1 < FDW_NASYM32) im = im * v + sgn * fdw_asym32[2 * j + 1];
+      }
     }
     im *= uf;
     const float c = kRsqrt2 * rsqrtf((float)agd);
