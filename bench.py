@@ -53,7 +53,9 @@ def parse():
                     help="waveforms in the batched mixed-precision measurement (0: skip)")
     ap.add_argument("--adjoint", type=int, default=64,
                     help="waveforms in the forward+adjoint measurement (0: skip)")
-    ap.add_argument("--only", choices=["batch", "adjoint"], default=None,
+    ap.add_argument("--batch-reps", type=int, default=2,
+                    help="timed graph replays of the batch (counter runs use 1)")
+    ap.add_argument("--only", choices=["batch", "adjoint", "small"], default=None,
                     help="run only this secondary measurement after the headline (profiling runs)")
     ap.add_argument("--headline-only", action="store_true",
                     help="skip the secondary measurements (used for counter runs)")
@@ -184,7 +186,7 @@ def W_psd(f):
     return W.psd_closed_form(f)
 
 
-def batch_measure(ctx, W, fd, dev, B, with_loglike=True):
+def batch_measure(ctx, W, fd, dev, B, with_loglike=True, reps=2):
     """Mixed-precision batch of B draws from the batched distribution (M
     log-U[1e5,1e7], mu U[1,100], e0 U[0.05,0.5], p0 U[10,16], T U[0.5,4] yr,
     dt = 10 s, full DFT grids): one eager profiled call gives the persistent
@@ -212,7 +214,6 @@ def batch_measure(ctx, W, fd, dev, B, with_loglike=True):
     gctx = fd.Context(dev.index if dev.index is not None else 0, graphs=True)
     gctx.waveform_batch(dws, "mixed", outs=outs)
     torch.cuda.synchronize()
-    reps = 2
     t0 = time.perf_counter()
     for _ in range(reps):
         gctx.waveform_batch(dws, "mixed", outs=outs)
@@ -269,6 +270,31 @@ def batch_measure(ctx, W, fd, dev, B, with_loglike=True):
         res["loglike_fused_hann"] = {"seconds_per_batch": sec_ll, "waveforms_per_s": B / sec_ll,
                                      "evals_per_s": evals / sec_ll, "waveform_bytes_not_written": bins * 16}
     return res
+
+
+def small_workloads(W):
+    """The latency-bound workloads: 20 modes on the full DFT grid and on 1e4
+    log-spaced bins."""
+    return (("inspiral_20_modes_fp64", W.inspiral_20_modes()),
+            ("inspiral_20_modes_log_grid_fp64", W.inspiral_20_modes_log_grid()))
+
+
+def small_latency(ctx, fd, dev, wl, reps=200):
+    """Microseconds per FP64 waveform for back-to-back eager calls (host
+    launch work included) and per replay of the call captured in a graph."""
+    import torch
+    d2 = fd.DeviceWaveform.from_workload(wl, device=dev)
+    o2 = (torch.empty(d2.Nf, dtype=torch.complex128, device=dev),
+          torch.empty(d2.Nf, dtype=torch.complex128, device=dev))
+    for _ in range(5):
+        ctx.waveform_dev(d2, "fp64", out=o2)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(reps):
+        ctx.waveform_dev(d2, "fp64", out=o2)
+    torch.cuda.synchronize()
+    return {"us_per_waveform": (time.perf_counter() - ts) / reps * 1e6,
+            "us_per_waveform_graph_replay": graph_latency(fd, d2)}
 
 
 def graph_latency(fd, dw, reps=50):
@@ -464,9 +490,13 @@ def main():
         secondary["copy_calibration_bytes"] = src.numel() * 8
     if args.headline_only or args.only:
         if args.only == "batch":
-            secondary["batch_mixed"] = batch_measure(ctx, W, fd, dev, args.batch, with_loglike=False)
+            secondary["batch_mixed"] = batch_measure(ctx, W, fd, dev, args.batch, with_loglike=False,
+                                                     reps=args.batch_reps)
         elif args.only == "adjoint":
             secondary["forward_adjoint"] = adjoint_measure(ctx, W, fd, dev, args.adjoint)
+        elif args.only == "small":
+            for name, wl in small_workloads(W):
+                secondary[name] = small_latency(ctx, fd, dev, wl)
         line = headline(args, w, evals, sec, prof, achieved, bpl, secondary)
         print(json.dumps(line), flush=True)
         ctx.close()
@@ -520,24 +550,12 @@ def main():
                                    "us_per_call": (time.perf_counter() - ts) / 20 * 1e6,
                                    "note": "includes the device-to-host read of the kept count"}
     if args.batch > 0:
-        secondary["batch_mixed"] = batch_measure(ctx, W, fd, dev, args.batch)
+        secondary["batch_mixed"] = batch_measure(ctx, W, fd, dev, args.batch, reps=args.batch_reps)
     if args.adjoint > 0:
         secondary["forward_adjoint"] = adjoint_measure(ctx, W, fd, dev, args.adjoint)
     small = []
-    for name, wl in (("inspiral_20_modes_fp64", W.inspiral_20_modes()),
-                     ("inspiral_20_modes_log_grid_fp64", W.inspiral_20_modes_log_grid())):
-        d2 = fd.DeviceWaveform.from_workload(wl, device=dev)
-        o2 = (torch.empty(d2.Nf, dtype=torch.complex128, device=dev),
-              torch.empty(d2.Nf, dtype=torch.complex128, device=dev))
-        for _ in range(3):
-            ctx.waveform_dev(d2, "fp64", out=o2)
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        for _ in range(20):
-            ctx.waveform_dev(d2, "fp64", out=o2)
-        torch.cuda.synchronize()
-        secondary[name] = {"us_per_waveform": (time.perf_counter() - ts) / 20 * 1e6,
-                           "us_per_waveform_graph_replay": graph_latency(fd, d2)}
+    for name, wl in small_workloads(W):
+        secondary[name] = small_latency(ctx, fd, dev, wl)
         small.append((name, wl, secondary[name]["us_per_waveform"] * 1e-6))
 
     line = headline(args, w, evals, sec, prof, achieved, bpl, secondary)

@@ -19,26 +19,27 @@
 namespace fdemri {
 hipError_t launch_spline(int K, const double* t, const double* Fphi, const double* Fr, const double* Phiphi,
                          const double* Phir, const double* A, int Nm, double* tcoef, double* acoef, double* fac,
-                         int32_t* env, hipStream_t stream);
+                         int32_t* status, hipStream_t stream);
 size_t spline_factor_doubles(int K);
 struct PieceArgs;
 hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
                              const double* f, const double* tcoef, const int32_t* l, const int32_t* m,
                              const int32_t* n, double theta, double phi, double scale, uint32_t flags,
-                             const double* A, double* acoef, double* fac, ModeConst* modes, int2* mode_kr,
-                             Piece* pieces, int64_t* evals, int32_t* env, uint32_t* flag_word, const double* Phiphi,
-                             const double* Phir, const double* A_in, int hann, hipStream_t stream);
+                             const double* A, double* acoef, float* acoef32, double* fac, ModeConst* modes,
+                             float4* modes32, int2* mode_kr, Piece* pieces, int64_t* evals, int32_t* status,
+                             uint32_t* flag_word, const double* Phiphi, const double* Phir, const double* A_in,
+                             int hann, hipStream_t stream);
 struct GatherArgs;
 hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp, void* hc, bool mixed, int bpl,
                               hipStream_t stream);
-hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, const ModeConst* modes,
-                        float4* modes32, hipStream_t stream);
 int spline_blocks(int n_series);
 hipError_t launch_spline_batch(const WaveItem* items, int B, const int32_t* block_prefix, int total_blocks, int Kmax,
                                hipStream_t stream);
-hipError_t launch_pieces_batch(const WaveItem* items, int B, const int32_t* mode_prefix, int total_modes,
-                               int max_checks, int hann, uint32_t* flag_word, hipStream_t stream);
+hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, hipStream_t stream);
 hipError_t launch_amp32_batch(const WaveItem* items, int B, const int32_t* amp_prefix, int total, hipStream_t stream);
+hipError_t launch_pieces_batch(const WaveItem* items, int B, const int32_t* mode_prefix, int total_modes,
+                               const int32_t* check_prefix, int total_checks, int hann, uint32_t* flag_word,
+                               hipStream_t stream);
 hipError_t launch_gather_batch(const WaveItem* items, int B, const int32_t* item_prefix, int total_items,
                                int* counter, int Kmax, bool mixed, int bpl, hipStream_t stream);
 int gather_items_per_waveform(int Nf, int bpl);
@@ -66,7 +67,7 @@ hipError_t launch_vjp_reduce(const Prepared& p, double* PZ, double* Upart, doubl
 hipError_t launch_spa_factor(int n, const double* gd, const double* gdd, const int32_t* dir, void* out, bool mixed,
                              hipStream_t stream);
 hipError_t launch_spline_adjoint(int K, const double* t, int Nm, const double* gPhi_coef, const double* gA_coef,
-                                 double* gPhi_knots, double* gA_knots, const int32_t* env, hipStream_t stream);
+                                 double* gPhi_knots, double* gA_knots, const int32_t* status, hipStream_t stream);
 }  // namespace fdemri
 
 using namespace fdemri;
@@ -174,7 +175,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Scratch layout of one waveform.
 struct Layout {
-  size_t tcoef, fac, acoef, acoef32, modes, modes32, mode_kr, pieces, evals, env;
+  size_t tcoef, fac, acoef, acoef32, modes, modes32, mode_kr, pieces, evals, status;
   size_t gA, PZ, Upart, T3, gPhi, gsc;  // adjoint scratch (0 bytes unless requested)
   size_t ll_partial, ll_edge;           // likelihood scratch (0 bytes unless requested)
   size_t total;
@@ -200,7 +201,7 @@ Layout layout_for(int K, int Nm, bool mixed, bool vjp = false, int ll_tiles = 0,
   L.mode_kr = take((size_t)Nm * sizeof(int2));
   L.pieces = take((size_t)Nm * kMaxPieces * sizeof(Piece));
   L.evals = take((size_t)Nm * sizeof(int64_t));
-  L.env = take(4 * sizeof(int32_t));
+  L.status = take(4 * sizeof(int32_t));
   const size_t units = vjp ? (size_t)Nm * nseg : 0;
   L.gA = take(units * 8 * sizeof(double));
   L.PZ = take(units * 4 * sizeof(double));
@@ -421,23 +422,25 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   int2* mode_kr = (int2*)(w + L.mode_kr);
   Piece* pieces = (Piece*)(w + L.pieces);
   int64_t* evals = (int64_t*)(w + L.evals);
-  int32_t* env = (int32_t*)(w + L.env);
+  int32_t* status = (int32_t*)(w + L.status);
   hipError_t e;
   {
     // the trajectory splines first: the piece tables need them
     ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream, prof);
     e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, 0, tcoef, acoef, (double*)(w + L.fac),
-                      env, stream);
+                      status, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "spline kernel launch");
   {
-    // piece tables and amplitude splines in one launch, then the envelope
+    // piece tables, amplitude splines (and their FP32 form) and the input
+    // checks in one launch
     ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream, prof);
     e = launch_setup_flat(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->f, tcoef, d->l, d->m, d->n, d->theta,
-                          d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, (double*)(w + L.fac), modes,
-                          mode_kr, pieces, evals, env, c->flag_word, d->Phiphi, d->Phir, d->A, hann, stream);
-    if (e == hipSuccess && mixed)
-      e = launch_amp32(d->Nm, d->K, d->t, acoef, acoef32, modes, (float4*)(w + L.modes32), stream);
+                          d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, acoef32, (double*)(w + L.fac),
+                          modes, mixed ? (float4*)(w + L.modes32) : nullptr, mode_kr, pieces, evals, status,
+                          c->flag_word, d->Phiphi, d->Phir, d->A, hann, stream);
+    // given coefficients were not splined: their FP32 form separately
+    if (e == hipSuccess && mixed && given) e = launch_amp32(d->Nm, d->K, d->t, acoef, acoef32, stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "piece kernel launch");
   p.K = d->K;
@@ -454,7 +457,7 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   p.modes = modes;
   p.mode_kr = mode_kr;
   p.pieces = pieces;
-  p.env = env;
+  p.status = status;
   p.modes32 = mixed ? (const float4*)(w + L.modes32) : nullptr;
   c->last_evals.assign(1, {evals, d->Nm});
   return FDEMRI_OK;
@@ -674,7 +677,7 @@ fdemri_status fdemri_vjp(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemri_pr
     e = launch_vjp_reduce(p, (double*)(w + L.PZ), (double*)(w + L.Upart), (double*)(w + L.T3), gPhi_coef, gsc, d->l,
                           d->m, d->theta, d->phi, d->scale, d->flags, stream);
   if (e == hipSuccess && (gA_knots || gPhi_knots))
-    e = launch_spline_adjoint(d->K, d->t, d->Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, p.env, stream);
+    e = launch_spline_adjoint(d->K, d->t, d->Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, p.status, stream);
   if (e != hipSuccess) return hip_fail(c, e, "vjp kernel launch");
   return FDEMRI_OK;
 }
@@ -720,7 +723,9 @@ namespace {
 // doubles) at ll_off.
 struct BatchPlan {
   bool mixed = false, ll = false;
-  int B = 0, Kmax = 0, Nf_max = 0, nbmax = 0, max_checks = 0;
+  int B = 0, Kmax = 0, Nf_max = 0, nbmax = 0;
+  int64_t n_checks = 0;
+  bool given_mixed = false;  // a member with given coefficients in a mixed batch
   int64_t n_series = 0, n_modes = 0, n_amp = 0, n_items = 0;
   std::vector<Layout> Ls;
   std::vector<size_t> base;
@@ -751,13 +756,15 @@ fdemri_status plan_batch(fdemri_ctx* c, int B, const fdemri_waveform_desc* descs
     P.n_modes += descs[b].Nm;
     P.n_amp += (int64_t)descs[b].Nm * (descs[b].K - 1);
     P.n_items += gather_items_per_waveform(descs[b].Nf, c->bpl);
-    P.max_checks = std::max(P.max_checks, check_blocks(descs[b].K, descs[b].Nm, descs[b].Nf, descs[b].flags));
+    P.n_checks += check_blocks(descs[b].K, descs[b].Nm, descs[b].Nf, descs[b].flags);
+    if (mixed && (descs[b].flags & FDEMRI_COEFFS_GIVEN)) P.given_mixed = true;
   }
-  if (P.n_amp > 0x7fffffff || P.n_items > 0x7fffffff || P.n_series > 0x7fffffff)
+  if (P.n_amp > 0x7fffffff || P.n_items > 0x7fffffff || P.n_series > 0x7fffffff ||
+      P.n_modes / 4 + P.n_checks > 0x7fffffff)
     return fail(c, FDEMRI_ENOTSUP, "batch too large for 32-bit work indices");
   P.items_off = off;
   P.pref_off = align_up(P.items_off + (size_t)B * sizeof(WaveItem), 256);
-  P.pref_bytes = 4 * (size_t)(B + 1) * sizeof(int32_t);
+  P.pref_bytes = 5 * (size_t)(B + 1) * sizeof(int32_t);
   P.counter_off = align_up(P.pref_off + P.pref_bytes, 256);
   P.ll_off = P.counter_off + 256;
   P.nbmax = ll ? loglike_batch_reduce_blocks(P.Nf_max) : 0;
@@ -776,8 +783,8 @@ void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc*
   WaveItem* hitems = (WaveItem*)rec;
   int32_t* hpref = (int32_t*)(rec + (P.pref_off - P.items_off));
   int32_t *series_prefix = hpref, *mode_prefix = hpref + (B + 1), *amp_prefix = hpref + 2 * (B + 1),
-          *item_prefix = hpref + 3 * (B + 1);
-  series_prefix[0] = mode_prefix[0] = amp_prefix[0] = item_prefix[0] = 0;
+          *item_prefix = hpref + 3 * (B + 1), *check_prefix = hpref + 4 * (B + 1);
+  series_prefix[0] = mode_prefix[0] = amp_prefix[0] = item_prefix[0] = check_prefix[0] = 0;
   c->last_evals.clear();
   for (int b = 0; b < B; ++b) {
     const fdemri_waveform_desc& d = descs[b];
@@ -809,7 +816,7 @@ void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc*
     it.mode_kr = (int2*)(wb + L.mode_kr);
     it.pieces = (Piece*)(wb + L.pieces);
     it.evals = (int64_t*)(wb + L.evals);
-    it.env = (int32_t*)(wb + L.env);
+    it.status = (int32_t*)(wb + L.status);
     it.hp = P.ll ? nullptr : hp[b];
     it.hc = P.ll ? nullptr : hc[b];
     it.d_p = P.ll ? ll_d_p[b] : nullptr;
@@ -822,6 +829,7 @@ void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc*
     mode_prefix[b + 1] = mode_prefix[b] + d.Nm;
     amp_prefix[b + 1] = amp_prefix[b] + d.Nm * (d.K - 1);
     item_prefix[b + 1] = item_prefix[b] + gather_items_per_waveform(d.Nf, c->bpl);
+    check_prefix[b + 1] = check_prefix[b] + check_blocks(d.K, d.Nm, d.Nf, d.flags);
     c->last_evals.push_back({it.evals, d.Nm});
   }
 }
@@ -844,8 +852,10 @@ hipError_t enqueue_batch(fdemri_ctx* c, const BatchPlan& P, const char* rec, hip
   if (e != hipSuccess) return e;
   {
     ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream);
-    e = launch_pieces_batch(ditems, B, dpref + (B + 1), (int)P.n_modes, P.max_checks, hann, c->flag_word, stream);
-    if (e == hipSuccess && P.mixed) e = launch_amp32_batch(ditems, B, dpref + 2 * (B + 1), (int)P.n_amp, stream);
+    e = launch_pieces_batch(ditems, B, dpref + (B + 1), (int)P.n_modes, dpref + 4 * (B + 1), (int)P.n_checks, hann,
+                            c->flag_word, stream);
+    if (e == hipSuccess && P.given_mixed)
+      e = launch_amp32_batch(ditems, B, dpref + 2 * (B + 1), (int)P.n_amp, stream);
   }
   if (e != hipSuccess) return e;
   ProfScope ps(c, FDEMRI_KERNEL_GATHER, stream);

@@ -67,7 +67,8 @@ struct Prepared {
   const ModeConst* modes;  // [Nm]
   const int2* mode_kr;     // [Nm] bin range of each mode (union of its pieces)
   const Piece* pieces;     // [Nm][kMaxPieces]
-  const int32_t* env;      // [4] bin envelope of all modes, then the input status (0: valid)
+  const int32_t* status;   // [3] input status of the call (0: valid; see the input checks below),
+                           // then the bin envelope [lo, hi] of all voices (the whole grid unless formed)
   const float4* modes32;   // [Nm] (c_+, c_x) of each mode in FP32 (mixed path only)
 };
 
@@ -87,7 +88,7 @@ struct WaveItem {
   int2* mode_kr;
   Piece* pieces;
   int64_t* evals;
-  int32_t* env;  // [4]: bin envelope, input status, unused
+  int32_t* status;  // [3] input status of the waveform, bin envelope [lo, hi]
   void* hp;
   void* hc;
   // fused likelihood of the batch: data, per-bin weights and this waveform's
@@ -115,16 +116,16 @@ __host__ __device__ inline Prepared prepared_of(const WaveItem& w) {
   p.modes = w.modes;
   p.mode_kr = w.mode_kr;
   p.pieces = w.pieces;
-  p.env = w.env;
+  p.status = w.status;
   p.modes32 = w.modes32;
   return p;
 }
 
 // Input checks on the device (the host does not read device data): a
-// waveform whose inputs fail them has status bits in env[2], every kernel
-// writes zeros for it, and FDEMRI_FLAG_BAD_INPUT is raised.  The first launch
-// of a call clears the status; the checks run in the launch that also forms
-// the bin envelope; the gather and the adjoint read it.
+// waveform whose inputs fail them has status bits in its status word, every
+// kernel writes zeros for it, and FDEMRI_FLAG_BAD_INPUT is raised.  The first
+// launch of a call clears the status; workgroups of the set-up launch run the
+// checks; the gather and the adjoint read it.
 constexpr int32_t kBadKnots = 1;     // t not finite or not strictly increasing
 constexpr int32_t kBadValues = 2;    // a trajectory or amplitude value not finite
 constexpr int32_t kBadGrid = 4;      // f not finite, negative or descending

@@ -7,9 +7,10 @@
 // all contributions to its bins in registers, so every output element is
 // written once, coalesced, in a fixed order of voices and pieces
 // (deterministic, no atomics):
-//   1. the workgroup stages the shared trajectory tables (knots and spline
-//      coefficients of F_phi, F_r, Phi_phi, Phi_r) in LDS and lists, in LDS,
-//      the modes whose bin range meets its block of bins;
+//   1. the workgroup lists, in LDS, the modes whose bin range meets its block
+//      of bins and, if there are any, stages the shared trajectory tables
+//      (knots and spline coefficients of F_phi, F_r, Phi_phi, Phi_r) in LDS
+//      (a block no voice reaches only writes zeros);
 //   2. for each listed mode and each of its monotonic pieces with bins in the
 //      tile, each lane with a bin inside the piece's range finds the spline
 //      segment holding f, solves the cubic of Eq. cubic_equation for the root
@@ -22,6 +23,8 @@
 // its reduction in double; the special function, sincos, amplitude spline and
 // products in float, each contribution added to a double accumulator (fewer
 // instructions than compensated float sums, at least as accurate).
+#include <climits>
+
 #include "evalcore.hpp"
 
 namespace fdemri {
@@ -417,6 +420,24 @@ __device__ __forceinline__ void emit(const Sink& o, int tile, int k, int Nf, con
   }
 }
 
+// A block with no bins in any voice's range: zeros (the waveform) or a zero
+// model (the likelihood).
+template <bool MIXED, int BPL, int WAVES, bool LL>
+__device__ __forceinline__ void zero_tiles(const Sink& out, int Nf, int kb) {
+  if constexpr (LL) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    Acc<MIXED> z;
+    z.zero();
+#pragma unroll 1
+    for (int j = 0; j < BPL; ++j) {
+      const int ks = kb + (wave * BPL + j) * 64;
+      emit<MIXED, true>(out, ks >> 6, ks + (int)(threadIdx.x & 63), Nf, z);
+    }
+  } else {
+    zero_block<MIXED, BPL, WAVES>(out.hp, out.hc, Nf, kb);
+  }
+}
+
 // One workgroup's block of WAVES * BPL * 64 contiguous bins starting at kb;
 // wave w owns the BPL tiles [kb + 64 (w BPL + j), + 64).
 //  1. The workgroup lists the modes whose bin range meets the block: wave w
@@ -430,9 +451,14 @@ __device__ __forceinline__ void emit(const Sink& o, int tile, int k, int Nf, con
 // The sum of every bin is taken by one lane in a fixed order, so the result
 // does not depend on scheduling, on the block shape or on the tile size.
 // list: LDS of kListCap + 8 ints.
-template <bool MIXED, int BPL, int WAVES, bool LL>
+// stage(): the caller's staging of the waveform's trajectory tables in LDS
+// (called by every thread; process_block then synchronises), returning their
+// addresses.  eager: stage before the scan of the mode table, so that the two
+// latencies overlap other work (the block is known to lie inside the bin
+// envelope of the voices); otherwise only once the scan has found voices.
+template <bool MIXED, int BPL, int WAVES, bool LL, typename Stage>
 __device__ __forceinline__ void process_block(const Prepared& p, const void* __restrict__ amp, const Sink& out,
-                                              int kb, const Lds& L, int* list) {
+                                              int kb, int* list, Stage stage, bool eager) {
   constexpr int CHUNK = 64 * kModesPerLane;
   // the wave index is uniform: taken into a scalar register, it makes the
   // tile bounds and every test against them scalar
@@ -473,15 +499,27 @@ __device__ __forceinline__ void process_block(const Prepared& p, const void* __r
       total += c;
     }
   };
+  Lds L;
+  if (eager) {
+    L = stage();
+    __syncthreads();
+  }
   if (rounds == 1) {
     scan(0);
+    if (total == 0) {
+      // no voice has bins here: nothing (more) to stage or evaluate
+      zero_tiles<MIXED, BPL, WAVES, LL>(out, Nf, kb);
+      return;
+    }
+    if (!eager) L = stage();
     if (total <= kListCap) {
       single = true;
-      if (total > 0) {
-        write_list(list, hits, wbase, off, 0);
-        __syncthreads();
-      }
+      write_list(list, hits, wbase, off, 0);
     }
+    __syncthreads();  // the tables and the list are in place
+  } else if (!eager) {
+    L = stage();
+    __syncthreads();
   }
 
   // 2. evaluate, tile by tile
@@ -535,28 +573,19 @@ __global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_
   extern __shared__ __align__(16) double lds[];
   const Prepared& p = a.p;
   const int kb = (int)blockIdx.x * block_bins<BPL, WAVES>();
-  const int kbe = kb + block_bins<BPL, WAVES>() - 1;
-  // blocks outside the bin envelope of all modes hold a zero model, and so
-  // does every block of a waveform whose inputs failed the checks
-  if (kbe < p.env[0] || kb > p.env[1] || p.env[2] != 0) {
-    if constexpr (LL) {
-      const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-      Acc<MIXED> z;
-      z.zero();
-#pragma unroll 1
-      for (int j = 0; j < BPL; ++j) {
-        const int ks = kb + (wave * BPL + j) * 64;
-        emit<MIXED, true>(a.out, ks >> 6, ks + (int)(threadIdx.x & 63), p.Nf, z);
-      }
-    } else {
-      zero_block<MIXED, BPL, WAVES>(a.out.hp, a.out.hc, p.Nf, kb);
-    }
+  // a waveform whose inputs failed the checks has a zero model, and so do
+  // the blocks outside the bin envelope of its voices
+  const kconst int32_t* st = (const kconst int32_t*)p.status;
+  if (st[0] != 0 || kb + block_bins<BPL, WAVES>() - 1 < st[1] || kb > st[2]) {
+    zero_tiles<MIXED, BPL, WAVES, LL>(a.out, p.Nf, kb);
     return;
   }
   int* list = (int*)lds;
-  const Lds L = stage_lds(p, lds + kHeadDoubles);
-  __syncthreads();
-  process_block<MIXED, BPL, WAVES, LL>(p, a.amp, a.out, kb, L, list);
+  // a formed envelope (large mode tables) means the block most likely has
+  // voices: stage the tables at once
+  const bool eager = st[1] > 0 || st[2] < INT_MAX;
+  process_block<MIXED, BPL, WAVES, LL>(p, a.amp, a.out, kb, list, [&]() { return stage_lds(p, lds + kHeadDoubles); },
+                                      eager);
 }
 
 // Completes the likelihood of one waveform from the gather's per-tile
@@ -707,7 +736,6 @@ __global__ __launch_bounds__(64 * WAVES, gather_batch_min_waves<MIXED>()) void g
     const WaveItem w = ((const kconst WaveItem*)items)[lo];
     const Prepared p = prepared_of(w);
     const int kb = (it - pre[lo]) * block_bins<BPL, WAVES>();
-    const int kbe = kb + block_bins<BPL, WAVES>() - 1;
     Sink out{};
     out.hp = w.hp;
     out.hc = w.hc;
@@ -719,61 +747,53 @@ __global__ __launch_bounds__(64 * WAVES, gather_batch_min_waves<MIXED>()) void g
       out.edge = w.ll_edge;
       out.hann = hann;
     }
-    if (kbe < p.env[0] || kb > p.env[1] || p.env[2] != 0) {
-      if constexpr (LL) {
-        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        Acc<MIXED> z;
-        z.zero();
-#pragma unroll 1
-        for (int j = 0; j < BPL; ++j) {
-          const int ks = kb + (wave * BPL + j) * 64;
-          emit<MIXED, true>(out, ks >> 6, ks + (int)(threadIdx.x & 63), p.Nf, z);
-        }
-      } else {
-        zero_block<MIXED, BPL, WAVES>(w.hp, w.hc, p.Nf, kb);
-      }
+    const kconst int32_t* st = (const kconst int32_t*)p.status;
+    if (st[0] != 0 || kb + block_bins<BPL, WAVES>() - 1 < st[1] || kb > st[2]) {
+      zero_tiles<MIXED, BPL, WAVES, LL>(out, p.Nf, kb);
       continue;
     }
-    if (lo != cached) {
-      L = stage_lds(p, tables);
-      __syncthreads();
-      cached = lo;
-    }
-    process_block<MIXED, BPL, WAVES, LL>(p, MIXED ? (const void*)w.acoef32 : (const void*)w.acoef, out, kb, L,
-                                        list);
+    // the tables are restaged only when the waveform changes
+    process_block<MIXED, BPL, WAVES, LL>(p, MIXED ? (const void*)w.acoef32 : (const void*)w.acoef, out, kb, list,
+                                        [&]() {
+                                          if (lo != cached) {
+                                            L = stage_lds(p, tables);
+                                            cached = lo;
+                                          }
+                                          return L;
+                                        },
+                                        true);
   }
 }
 
 __global__ void reset_counter_kernel(int* counter) { *counter = 0; }
 
-// Normalised FP32 amplitude coefficients for the mixed path:
-// A(t_i + u h) = sum_k (a_k h^k) u^k, u in [0, 1]; the thread of segment 0 of
-// a mode also rounds the mode's c_+ and c_x to FP32.
-__device__ __forceinline__ void mode_consts32(const ModeConst& mc, float4* dst) {
-  *dst = make_float4((float)mc.cp_re, (float)mc.cp_im, (float)mc.cx_re, (float)mc.cx_im);
+// FP32 normalised amplitude coefficients for the mixed path when the caller
+// gives the FP64 coefficients (FDEMRI_COEFFS_GIVEN); splined amplitudes get
+// them from the spline kernels, with the same arithmetic:
+// A(t_i + u h) = sum_k (a_k h^k) u^k, u in [0, 1].
+__device__ __forceinline__ void amp32_segment(const double* __restrict__ c, double h, float* __restrict__ o) {
+  const double h2 = h * h, h3 = h2 * h;
+  o[0] = (float)c[0];
+  o[1] = (float)c[1];
+  o[2] = (float)(c[2] * h);
+  o[3] = (float)(c[3] * h);
+  o[4] = (float)(c[4] * h2);
+  o[5] = (float)(c[5] * h2);
+  o[6] = (float)(c[6] * h3);
+  o[7] = (float)(c[7] * h3);
 }
 
 __global__ void amp32_kernel(int Nm, int K, const double* __restrict__ t, const double* __restrict__ acoef,
-                             float* __restrict__ acoef32, const ModeConst* __restrict__ modes,
-                             float4* __restrict__ modes32) {
+                             float* __restrict__ acoef32) {
   const int nseg = K - 1;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)Nm * nseg) return;
   const int i = (int)(idx % nseg);
-  if (i == 0) mode_consts32(modes[idx / nseg], modes32 + idx / nseg);
-  const double h = t[i + 1] - t[i];
-  const double* c = acoef + idx * 8;
-  float* o = acoef32 + idx * 8;
-  double hk = 1.0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    o[2 * k] = (float)(c[2 * k] * hk);
-    o[2 * k + 1] = (float)(c[2 * k + 1] * hk);
-    hk *= h;
-  }
+  amp32_segment(acoef + idx * 8, t[i + 1] - t[i], acoef32 + idx * 8);
 }
 
-// Batched: one thread per (waveform, mode, segment) through the prefix of Nm_b (K_b - 1).
+// Batched: one thread per (waveform, mode, segment) through the prefix of
+// Nm_b (K_b - 1); members without given coefficients have theirs already.
 __global__ void amp32_batch_kernel(const WaveItem* __restrict__ items, int B, const int32_t* __restrict__ amp_prefix,
                                    int total) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -787,20 +807,23 @@ __global__ void amp32_batch_kernel(const WaveItem* __restrict__ items, int B, co
       hi = mid - 1;
   }
   const WaveItem& w = items[lo];
+  if (!(w.flags & FDEMRI_COEFFS_GIVEN)) return;
   const int idx = g - amp_prefix[lo];
-  const int nseg = w.K - 1;
-  const int i = idx % nseg;
-  if (i == 0) mode_consts32(w.modes[idx / nseg], w.modes32 + idx / nseg);
-  const double h = w.t[i + 1] - w.t[i];
-  const double* c = w.acoef + (size_t)idx * 8;
-  float* o = w.acoef32 + (size_t)idx * 8;
-  double hk = 1.0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    o[2 * k] = (float)(c[2 * k] * hk);
-    o[2 * k + 1] = (float)(c[2 * k + 1] * hk);
-    hk *= h;
-  }
+  const int i = idx % (w.K - 1);
+  amp32_segment(w.acoef + (size_t)idx * 8, w.t[i + 1] - w.t[i], w.acoef32 + (size_t)idx * 8);
+}
+
+hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, hipStream_t stream) {
+  const long total = (long)Nm * (K - 1);
+  const int threads = 256;
+  amp32_kernel<<<dim3((unsigned)((total + threads - 1) / threads)), threads, 0, stream>>>(Nm, K, t, acoef, acoef32);
+  return hipGetLastError();
+}
+
+hipError_t launch_amp32_batch(const WaveItem* items, int B, const int32_t* amp_prefix, int total, hipStream_t stream) {
+  const int threads = 256;
+  amp32_batch_kernel<<<(total + threads - 1) / threads, threads, 0, stream>>>(items, B, amp_prefix, total);
+  return hipGetLastError();
 }
 
 size_t gather_lds_bytes(int K) { return (size_t)K * sizeof(KnotRec) + (size_t)(K - 1) * sizeof(SegCoef); }
@@ -959,21 +982,6 @@ hipError_t launch_loglike_batch(const WaveItem* items, int B, const int32_t* ite
   else
     loglike_tiles_batch_kernel<false><<<grid, kLLThreads, 0, stream>>>(items, hann, nbmax, block_sums);
   loglike_total_kernel<<<B, kLLThreads, 0, stream>>>(block_sums, nbmax, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_amp32_batch(const WaveItem* items, int B, const int32_t* amp_prefix, int total, hipStream_t stream) {
-  const int threads = 256;
-  amp32_batch_kernel<<<(total + threads - 1) / threads, threads, 0, stream>>>(items, B, amp_prefix, total);
-  return hipGetLastError();
-}
-
-hipError_t launch_amp32(int Nm, int K, const double* t, const double* acoef, float* acoef32, const ModeConst* modes,
-                        float4* modes32, hipStream_t stream) {
-  const long total = (long)Nm * (K - 1);
-  const int threads = 256;
-  amp32_kernel<<<dim3((unsigned)((total + threads - 1) / threads)), threads, 0, stream>>>(Nm, K, t, acoef, acoef32,
-                                                                                        modes, modes32);
   return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ struct PieceArgs {
   double theta, phi, scale;
   uint32_t flags;
   ModeConst* modes;
+  float4* modes32;  // (c_+, c_x) in FP32 for the mixed path, or NULL
   int2* mode_kr;
   Piece* pieces;
   int64_t* evals;  // [Nm]
@@ -331,6 +332,7 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
     mc.k_lo = kr_lo;
     mc.k_hi = kr_hi;
     a.modes[mu] = mc;
+    if (a.modes32) a.modes32[mu] = make_float4((float)mc.cp_re, (float)mc.cp_im, (float)mc.cx_re, (float)mc.cx_im);
     a.mode_kr[mu] = make_int2(kr_lo, kr_hi);
     a.evals[mu] = evals;
     if (n_valid > kMaxPieces || ev_overflow) atomicOr(a.flag_word, (uint32_t)FDEMRI_FLAG_PIECE_OVERFLOW);
@@ -338,9 +340,10 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
   }
 }
 
-// Bin envelope [env[0], env[1]] of one waveform's modes (min and max over
+// Bin envelope [env[0], env[1]] of one waveform's voices (min and max over
 // the non-empty per-mode ranges; {INT_MAX, -1} when all are empty), by one
-// workgroup in a fixed reduction order.
+// workgroup in a fixed reduction order.  The gather skips the blocks outside
+// it without reading the mode table.
 __device__ __forceinline__ void envelope_block(const int2* __restrict__ mode_kr, int Nm, int32_t* __restrict__ env) {
   __shared__ int s_lo[4], s_hi[4];
   int lo = INT_MAX, hi = -1;
@@ -368,6 +371,17 @@ __device__ __forceinline__ void envelope_block(const int2* __restrict__ mode_kr,
   }
 }
 
+__global__ __launch_bounds__(256) void envelope_kernel(const int2* __restrict__ mode_kr, int Nm,
+                                                       int32_t* __restrict__ env) {
+  envelope_block(mode_kr, Nm, env);
+}
+
+// Batched: one workgroup per waveform.
+__global__ __launch_bounds__(256) void envelope_batch_kernel(const WaveItem* __restrict__ items) {
+  const WaveItem& w = items[blockIdx.x];
+  envelope_block(w.mode_kr, w.Nm, w.status + 1);
+}
+
 // Inputs of one waveform's checks (device pointers of the caller's arrays).
 struct CheckArgs {
   int32_t K, Nm, Nf;
@@ -380,9 +394,9 @@ struct CheckArgs {
 // trajectory (t finite and strictly increasing, the frequencies and phases
 // finite), then the amplitude array in chunks (finite), then the frequency
 // grid in chunks (finite, >= 0, ascending; with hann also |f_k - k f_1| <=
-// 1e-12 f_k, so f_0 = 0).  Failures set status bits in env[2] and the
-// context's flag bit; nothing is written otherwise.
-__device__ void check_block(const CheckArgs& c, int blk, int32_t* env, uint32_t* flag_word) {
+// 1e-12 f_k, so f_0 = 0).  Failures set bits in the waveform's status word
+// and the context's flag bit; nothing is written otherwise.
+__device__ void check_block(const CheckArgs& c, int blk, int32_t* status, uint32_t* flag_word) {
   int32_t bad = 0;
   const long na = check_amp_count(c.K, c.Nm, c.flags);
   const int nab = (int)((na + kCheckChunk - 1) / kCheckChunk);
@@ -411,35 +425,13 @@ __device__ void check_block(const CheckArgs& c, int blk, int32_t* env, uint32_t*
     }
   }
   if (bad) {
-    atomicOr(env + 2, bad);
+    atomicOr(status, bad);
     atomicOr(flag_word, (uint32_t)FDEMRI_FLAG_BAD_INPUT);
   }
 }
 
-// Workgroup 0: the bin envelope; workgroups 1..: the input checks.
-__global__ __launch_bounds__(256) void envelope_kernel(const int2* __restrict__ mode_kr, int Nm,
-                                                       int32_t* __restrict__ env, CheckArgs c, uint32_t* flag_word) {
-  if (blockIdx.x == 0)
-    envelope_block(mode_kr, Nm, env);
-  else
-    check_block(c, (int)blockIdx.x - 1, env, flag_word);
-}
-
-// Batched: grid row y is waveform y; workgroup 0 of a row forms its bin
-// envelope, workgroups 1.. run its checks (rows of smaller waveforms leave
-// the rest idle).
-__global__ __launch_bounds__(256) void envelope_batch_kernel(const WaveItem* __restrict__ items, int hann,
-                                                             uint32_t* flag_word) {
-  const WaveItem& w = items[blockIdx.y];
-  if (blockIdx.x == 0) {
-    envelope_block(w.mode_kr, w.Nm, w.env);
-    return;
-  }
-  const int blk = (int)blockIdx.x - 1;
-  if (blk >= check_blocks(w.K, w.Nm, w.Nf, w.flags)) return;
-  const CheckArgs c{w.K, w.Nm, w.Nf, w.flags, hann, w.t, w.Fphi, w.Fr, w.Phiphi, w.Phir, w.A, w.f};
-  check_block(c, blk, w.env, flag_word);
-}
+// Mode tables up to this size are not given a bin envelope (single waveform).
+constexpr int kEnvelopeMinModes = 256;
 
 // Batched pieces: one wavefront per mode, kPieceWaves modes per workgroup.
 constexpr int kPieceWaves = 4;
@@ -462,6 +454,7 @@ __device__ PieceArgs piece_args_of(const WaveItem& w, uint32_t* flag_word) {
   a.scale = w.scale;
   a.flags = w.flags;
   a.modes = w.modes;
+  a.modes32 = w.modes32;
   a.mode_kr = w.mode_kr;
   a.pieces = w.pieces;
   a.evals = w.evals;
@@ -469,46 +462,68 @@ __device__ PieceArgs piece_args_of(const WaveItem& w, uint32_t* flag_word) {
   return a;
 }
 
-// Batched: one wavefront per (waveform, mode) through the prefix of Nm_b.
-__global__ __launch_bounds__(64 * kPieceWaves) void pieces_batch_kernel(const WaveItem* __restrict__ items, int B,
-                                                                        const int32_t* __restrict__ mode_prefix,
-                                                                        int total, uint32_t* flag_word) {
-  __shared__ Event ev[kPieceWaves][kMaxEvents];
-  const int wave = threadIdx.x >> 6;
-  const int g = blockIdx.x * kPieceWaves + wave;
-  if (g >= total) return;
+// Index b of the prefix array pre[0..B] with pre[b] <= g < pre[b + 1].
+__device__ __forceinline__ int prefix_find(const int32_t* __restrict__ pre, int B, int g) {
   int lo = 0, hi = B - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (mode_prefix[mid] <= g)
+    if (pre[mid] <= g)
       lo = mid;
     else
       hi = mid - 1;
   }
+  return lo;
+}
+
+// Batched: the first piece_blocks workgroups run one wavefront per (waveform,
+// mode) through the prefix of Nm_b; the rest run the input checks of every
+// waveform through the prefix of its check_blocks (check_prefix).
+__global__ __launch_bounds__(64 * kPieceWaves) void pieces_batch_kernel(const WaveItem* __restrict__ items, int B,
+                                                                        const int32_t* __restrict__ mode_prefix,
+                                                                        int total, int piece_blocks,
+                                                                        const int32_t* __restrict__ check_prefix,
+                                                                        int hann, uint32_t* flag_word) {
+  __shared__ Event ev[kPieceWaves][kMaxEvents];
+  if ((int)blockIdx.x >= piece_blocks) {
+    const int g = (int)blockIdx.x - piece_blocks;
+    const int b = prefix_find(check_prefix, B, g);
+    const WaveItem& w = items[b];
+    const CheckArgs c{w.K, w.Nm, w.Nf, w.flags, hann, w.t, w.Fphi, w.Fr, w.Phiphi, w.Phir, w.A, w.f};
+    check_block(c, g - check_prefix[b], w.status, flag_word);
+    return;
+  }
+  const int wave = threadIdx.x >> 6;
+  const int g = blockIdx.x * kPieceWaves + wave;
+  if (g >= total) return;
+  const int lo = prefix_find(mode_prefix, B, g);
   const PieceArgs a = piece_args_of(items[lo], flag_word);
   piece_mode_wave(a, g - mode_prefix[lo], ev[wave]);
 }
 
-// The batch's piece tables, then its envelopes and input checks
-// (max_checks: the largest check_blocks of its waveforms; hann: the
-// likelihood's Hann kernel needs DFT grids).
+// The batch's piece tables and its input checks in one launch (total_checks:
+// the sum of the waveforms' check_blocks; hann: the likelihood's Hann kernel
+// needs DFT grids), then the waveforms' bin envelopes.
 hipError_t launch_pieces_batch(const WaveItem* items, int B, const int32_t* mode_prefix, int total_modes,
-                               int max_checks, int hann, uint32_t* flag_word, hipStream_t stream) {
+                               const int32_t* check_prefix, int total_checks, int hann, uint32_t* flag_word,
+                               hipStream_t stream) {
   const int blocks = (total_modes + kPieceWaves - 1) / kPieceWaves;
-  pieces_batch_kernel<<<blocks, 64 * kPieceWaves, 0, stream>>>(items, B, mode_prefix, total_modes, flag_word);
-  envelope_batch_kernel<<<dim3((unsigned)(1 + max_checks), (unsigned)B), 256, 0, stream>>>(items, hann, flag_word);
+  pieces_batch_kernel<<<blocks + total_checks, 64 * kPieceWaves, 0, stream>>>(
+      items, B, mode_prefix, total_modes, blocks, check_prefix, hann, flag_word);
+  envelope_batch_kernel<<<B, 256, 0, stream>>>(items);
   return hipGetLastError();
 }
 
 // Set-up of one waveform after its trajectory splines: the piece tables (one
-// wave per mode) and the amplitude splines (kSeriesPerBlock modes per
-// workgroup, all sharing the knot matrix) in one launch, the pieces'
-// workgroups first.  The two parts are independent, so the amplitude
+// wave per mode), the amplitude splines (kSeriesPerBlock modes per
+// workgroup, all sharing the knot matrix; with acoef32 also their FP32 form)
+// and the input checks in one launch, the pieces' workgroups first.  The two parts are independent, so the amplitude
 // splines fill the machine while the latency-bound piece walks run, instead
 // of taking a launch of their own before them.
 template <int NT>
-__global__ __launch_bounds__(NT) void setup_kernel(PieceArgs a, int piece_blocks, const double* __restrict__ A,
-                                                   double* __restrict__ acoef, double* fac) {
+__global__ __launch_bounds__(NT) void setup_kernel(PieceArgs a, int piece_blocks, int amp_blocks,
+                                                   const double* __restrict__ A, double* __restrict__ acoef,
+                                                   float* __restrict__ acoef32, double* fac, CheckArgs c,
+                                                   int32_t* __restrict__ status) {
   constexpr int W = NT / 64;
   // LDS of either part: the spline's tables or the waves' event buffers
   constexpr size_t kBytes = sizeof(SplineLds<NT>) > sizeof(Event) * W * kMaxEvents ? sizeof(SplineLds<NT>)
@@ -520,26 +535,32 @@ __global__ __launch_bounds__(NT) void setup_kernel(PieceArgs a, int piece_blocks
     if (mu < a.Nm) piece_mode_wave(a, mu, (Event*)lds + wave * kMaxEvents);
     return;
   }
+  if ((int)blockIdx.x >= piece_blocks + amp_blocks) {
+    check_block(c, (int)blockIdx.x - piece_blocks - amp_blocks, status, a.flag_word);
+    return;
+  }
   const int s0 = 4 + ((int)blockIdx.x - piece_blocks) * kSeriesPerBlock;
   // series 4 + mu only (the trajectory arguments are never read here), with
   // the knot matrix's reduction factors from the trajectory splines
   spline_block<NT, true>(*(SplineLds<NT>*)lds, s0, 4 + a.Nm, a.K, a.t, a.Fphi, a.Fr, a.Fphi, a.Fr, A, acoef, acoef,
-                         fac);
+                         fac, acoef32);
 }
 
-// The piece tables and, unless A is NULL, the amplitude splines of Nm modes
-// (acoef [Nm][K-1][8]) in one launch, then the bin envelope with the input
-// checks (A_in: the caller's amplitude array, knot values or coefficients;
-// hann: the grid must be the Hann kernel's DFT grid).  The trajectory
+// The piece tables, unless A is NULL the amplitude splines of Nm modes
+// (acoef [Nm][K-1][8]; with acoef32 also the FP32 normalised form, and the
+// FP32 mode constants in modes32), and the input checks (A_in: the caller's
+// amplitude array, knot values or coefficients; hann: the grid must be the
+// Hann kernel's DFT grid), in one launch.  The trajectory
 // spline coefficients tcoef and the knot matrix's reduction factors fac,
 // written by launch_spline with the same thread count, must be in place
 // (stream order).
 hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
                              const double* f, const double* tcoef, const int32_t* l, const int32_t* m,
                              const int32_t* n, double theta, double phi, double scale, uint32_t flags,
-                             const double* A, double* acoef, double* fac, ModeConst* modes, int2* mode_kr,
-                             Piece* pieces, int64_t* evals, int32_t* env, uint32_t* flag_word, const double* Phiphi,
-                             const double* Phir, const double* A_in, int hann, hipStream_t stream) {
+                             const double* A, double* acoef, float* acoef32, double* fac, ModeConst* modes,
+                             float4* modes32, int2* mode_kr, Piece* pieces, int64_t* evals, int32_t* status,
+                             uint32_t* flag_word, const double* Phiphi, const double* Phir, const double* A_in,
+                             int hann, hipStream_t stream) {
   PieceArgs a;
   a.K = K;
   a.Nm = Nm;
@@ -557,20 +578,27 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
   a.scale = scale;
   a.flags = flags;
   a.modes = modes;
+  a.modes32 = modes32;
   a.mode_kr = mode_kr;
   a.pieces = pieces;
   a.evals = evals;
   a.flag_word = flag_word;
   const int amp_blocks = A ? (Nm + kSeriesPerBlock - 1) / kSeriesPerBlock : 0;
+  const int checks = check_blocks(K, Nm, Nf, flags);
+  const CheckArgs c{K, Nm, Nf, flags, hann, t, Fphi, Fr, Phiphi, Phir, A_in, f};
   if (K <= 256) {
     const int pb = (Nm + 3) / 4;
-    setup_kernel<256><<<pb + amp_blocks, 256, 0, stream>>>(a, pb, A, acoef, fac);
+    setup_kernel<256><<<pb + amp_blocks + checks, 256, 0, stream>>>(a, pb, amp_blocks, A, acoef, acoef32, fac, c,
+                                                                     status);
   } else {
     const int pb = (Nm + 7) / 8;
-    setup_kernel<512><<<pb + amp_blocks, 512, 0, stream>>>(a, pb, A, acoef, fac);
+    setup_kernel<512><<<pb + amp_blocks + checks, 512, 0, stream>>>(a, pb, amp_blocks, A, acoef, acoef32, fac, c,
+                                                                     status);
   }
-  const CheckArgs c{K, Nm, Nf, flags, hann, t, Fphi, Fr, Phiphi, Phir, A_in, f};
-  envelope_kernel<<<1 + check_blocks(K, Nm, Nf, flags), 256, 0, stream>>>(mode_kr, Nm, env, c, flag_word);
+  // a large mode table gets its bin envelope (one small launch), so that the
+  // gather skips the blocks no voice reaches without scanning the table; a
+  // small table is scanned as cheaply as the launch would cost
+  if (Nm > kEnvelopeMinModes) envelope_kernel<<<1, 256, 0, stream>>>(mode_kr, Nm, status + 1);
   return hipGetLastError();
 }
 

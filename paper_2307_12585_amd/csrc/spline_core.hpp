@@ -130,6 +130,8 @@ __device__ __forceinline__ double pcr_rhs(double r, double rm, double k1, double
 // Series [s0, s0 + kSeriesPerBlock) of one waveform (0..3: F_phi, F_r,
 // Phi_phi, Phi_r, real; 4 + mu: the complex amplitude of mode mu), n_series
 // in all, by the NT threads of the calling workgroup.
+// With acoef32 (the mixed path), the amplitude series also get FP32
+// coefficients in the normalised variable u = tau / h ([Nm][K-1][8]).
 // FAC_IN = false: the matrix is reduced beside the right-hand sides; when
 // fac is not null, the reduction factors are written to it
 // ([pcr_factor_doubles<NT>()]).  FAC_IN = true: the factors are read from
@@ -141,7 +143,7 @@ __device__ void spline_block(SplineLds<NT>& S, int s0, int n_series, int K, cons
                              const double* __restrict__ y0, const double* __restrict__ y1,
                              const double* __restrict__ y2, const double* __restrict__ y3,
                              const double* __restrict__ A, double* __restrict__ tcoef, double* __restrict__ acoef,
-                             double* fac = nullptr) {
+                             double* fac = nullptr, float* __restrict__ acoef32 = nullptr) {
   constexpr int SB = kSeriesPerBlock;
   constexpr int LOG = pcr_steps<NT>();
   const int i = threadIdx.x;
@@ -291,6 +293,20 @@ __device__ void spline_block(SplineLds<NT>& S, int s0, int n_series, int K, cons
         o[5] = c2i;
         o[6] = c3r;
         o[7] = c3i;
+        if (acoef32) {
+          // the mixed path's FP32 coefficients in the normalised variable
+          // u = tau / h: A(t_i + u h) = sum_k (a_k h^k) u^k
+          const double h2 = h * h, h3 = h2 * h;
+          float* o32 = acoef32 + ((size_t)(series - 4) * n + i) * 8;
+          o32[0] = (float)y0v.x;
+          o32[1] = (float)y0v.y;
+          o32[2] = (float)(s0r * h);
+          o32[3] = (float)(s0i * h);
+          o32[4] = (float)(c2r * h2);
+          o32[5] = (float)(c2i * h2);
+          o32[6] = (float)(c3r * h3);
+          o32[7] = (float)(c3i * h3);
+        }
       }
     }
   }

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_unit_kernel(V
   const double Prr = reduce_2pi(((const kconst double*)p.Phir)[i]);
 
   // a waveform whose inputs failed the checks has a zero gradient
-  const int npieces = p.env[2] != 0 ? 0 : md.npieces;
+  const int npieces = *(const kconst int32_t*)p.status != 0 ? 0 : md.npieces;
   for (int q = 0; q < npieces; ++q) {
     const Piece P = ((const kconst Piece*)p.pieces)[(size_t)mu * kMaxPieces + q];
     if (i < P.seg_a || i > P.seg_b || P.k_lo > P.k_hi) continue;
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(NT) void spline_adjoint_kernel(int K, const double*
                                                             const double* __restrict__ gA_coef,
                                                             double* __restrict__ gPhi_knots,
                                                             double* __restrict__ gA_knots,
-                                                            const int32_t* __restrict__ env) {
+                                                            const int32_t* __restrict__ status) {
   __shared__ double sa[NT], sb[NT], sc[NT], sr[NT], sh[NT], sdb[NT];
   const int i = threadIdx.x;
   const int series = blockIdx.x;
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(NT) void spline_adjoint_kernel(int K, const double*
   if (!amp && gPhi_knots == nullptr) return;
   if (amp && gA_knots == nullptr) return;
   const int mode = amp ? (series - 2) >> 1 : 0, part = amp ? (series - 2) & 1 : 0;
-  if (env[2] != 0) {
+  if (*status != 0) {
     // inputs that failed the checks (the knots may not even be increasing):
     // a zero gradient, without the solve
     if (i < K) {
@@ -525,16 +525,16 @@ hipError_t launch_vjp_reduce(const Prepared& p, double* PZ, double* Upart, doubl
 }
 
 hipError_t launch_spline_adjoint(int K, const double* t, int Nm, const double* gPhi_coef, const double* gA_coef,
-                                 double* gPhi_knots, double* gA_knots, const int32_t* env, hipStream_t stream) {
+                                 double* gPhi_knots, double* gA_knots, const int32_t* status, hipStream_t stream) {
   dim3 grid(2 + 2 * Nm);
   if (K <= 64)
-    spline_adjoint_kernel<64><<<grid, 64, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, env);
+    spline_adjoint_kernel<64><<<grid, 64, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, status);
   else if (K <= 128)
-    spline_adjoint_kernel<128><<<grid, 128, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, env);
+    spline_adjoint_kernel<128><<<grid, 128, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, status);
   else if (K <= 256)
-    spline_adjoint_kernel<256><<<grid, 256, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, env);
+    spline_adjoint_kernel<256><<<grid, 256, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, status);
   else
-    spline_adjoint_kernel<512><<<grid, 512, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, env);
+    spline_adjoint_kernel<512><<<grid, 512, 0, stream>>>(K, t, Nm, gPhi_coef, gA_coef, gPhi_knots, gA_knots, status);
   return hipGetLastError();
 }
 
