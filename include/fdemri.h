@@ -55,9 +55,14 @@ typedef enum {
 
 typedef enum {
   FDEMRI_FP64 = 0,     /* everything in FP64; output complex128 (2 x double per bin) */
-  FDEMRI_MIXED = 1     /* FP64 root, phase and range reduction; FP32 special function,
+  FDEMRI_MIXED = 1,    /* FP64 root, phase and range reduction; FP32 special function,
                           sincos and amplitude spline, contributions summed in FP64;
                           output complex64 (2 x float per bin) */
+  /* range markers, not precisions: the enumeration spans int32, so that any
+     value a caller passes is a value of the type; every entry point rejects
+     values other than the two above with FDEMRI_EINVAL */
+  FDEMRI_PREC_RANGE_LO_ = -2147483647 - 1,
+  FDEMRI_PREC_RANGE_HI_ = 2147483647
 } fdemri_prec;
 
 /* flags of fdemri_waveform_desc.flags */
@@ -406,8 +411,10 @@ fdemri_status fdemri_last_eval_count(fdemri_ctx *ctx, hipStream_t stream, int64_
  * milliseconds and launch counts per kernel class (FDEMRI_KERNEL_*; arrays of
  * FDEMRI_KERNEL_COUNT entries, host memory) and resets the accumulators.
  */
-#define FDEMRI_KERNEL_SPLINE 0
-#define FDEMRI_KERNEL_PIECES 1
+#define FDEMRI_KERNEL_SPLINE 0  /* the trajectory splines (none when the set-up is fused) */
+#define FDEMRI_KERNEL_PIECES 1  /* the set-up: piece tables, amplitude splines, input checks;
+                                   for at most 256 modes and 256 knots one fused launch that
+                                   also solves the trajectory splines */
 #define FDEMRI_KERNEL_GATHER 2
 #define FDEMRI_KERNEL_VJP 3      /* the adjoint's per-(mode, segment) kernel (its reductions
                                     and the transposed spline are not bracketed) */

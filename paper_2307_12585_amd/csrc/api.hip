@@ -29,6 +29,14 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
                              float4* modes32, int2* mode_kr, Piece* pieces, int64_t* evals, int32_t* status,
                              uint32_t* flag_word, const double* Phiphi, const double* Phir, const double* A_in,
                              int hann, hipStream_t stream);
+bool setup_fusable(int K, int Nm, int Nf, uint32_t flags);
+hipError_t launch_setup_fused(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
+                              const double* Phiphi, const double* Phir, const double* f, double* tcoef,
+                              const int32_t* l, const int32_t* m, const int32_t* n, double theta, double phi,
+                              double scale, uint32_t flags, const double* A, double* acoef, float* acoef32,
+                              ModeConst* modes, float4* modes32, int2* mode_kr, Piece* pieces, int64_t* evals,
+                              int32_t* slots, uint32_t* flag_word, const double* A_in, int hann,
+                              hipStream_t stream);
 struct GatherArgs;
 hipError_t launch_gather_flat(const Prepared& p, const float* acoef32, void* hp, void* hc, bool mixed, int bpl,
                               hipStream_t stream);
@@ -175,7 +183,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Scratch layout of one waveform.
 struct Layout {
-  size_t tcoef, fac, acoef, acoef32, modes, modes32, mode_kr, pieces, evals, status;
+  size_t tcoef, fac, acoef, acoef32, modes, modes32, mode_kr, pieces, evals, status, slots;
   size_t gA, PZ, Upart, T3, gPhi, gsc;  // adjoint scratch (0 bytes unless requested)
   size_t ll_partial, ll_edge;           // likelihood scratch (0 bytes unless requested)
   size_t total;
@@ -202,6 +210,7 @@ Layout layout_for(int K, int Nm, bool mixed, bool vjp = false, int ll_tiles = 0,
   L.pieces = take((size_t)Nm * kMaxPieces * sizeof(Piece));
   L.evals = take((size_t)Nm * sizeof(int64_t));
   L.status = take(4 * sizeof(int32_t));
+  L.slots = take(kFusedMaxSlots * sizeof(int32_t));
   const size_t units = vjp ? (size_t)Nm * nseg : 0;
   L.gA = take(units * 8 * sizeof(double));
   L.PZ = take(units * 4 * sizeof(double));
@@ -409,9 +418,12 @@ namespace {
 // piece table, FP32 amplitude table) into the scratch at w described by L
 // (the context's workspace unless given).  prof = false leaves the launches
 // unbracketed even while profiling is on (no event is created); hann: the
-// input checks also require the Hann kernel's DFT grid.
+// input checks also require the Hann kernel's DFT grid; fuse: a gather that
+// reads the status slots follows, so a small waveform may have its set-up
+// fused into one launch.
 fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, const Layout& L, Prepared& p,
-                      float*& acoef32, hipStream_t stream, char* w = nullptr, bool prof = true, int hann = 0) {
+                      float*& acoef32, hipStream_t stream, char* w = nullptr, bool prof = true, int hann = 0,
+                      bool fuse = false) {
   if (!w) w = c->ws;
   double* tcoef = (double*)(w + L.tcoef);
   // with FDEMRI_COEFFS_GIVEN the caller's coefficients (same layout) are read in place
@@ -423,26 +435,39 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   Piece* pieces = (Piece*)(w + L.pieces);
   int64_t* evals = (int64_t*)(w + L.evals);
   int32_t* status = (int32_t*)(w + L.status);
+  int32_t* slots = (int32_t*)(w + L.slots);
   hipError_t e;
-  {
-    // the trajectory splines first: the piece tables need them
-    ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream, prof);
-    e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, 0, tcoef, acoef, (double*)(w + L.fac),
-                      status, stream);
-  }
-  if (e != hipSuccess) return hip_fail(c, e, "spline kernel launch");
-  {
-    // piece tables, amplitude splines (and their FP32 form) and the input
-    // checks in one launch
+  const bool fused = fuse && setup_fusable(d->K, d->Nm, d->Nf, d->flags);
+  if (fused) {
+    // trajectory splines, pieces, amplitude splines and checks in one launch
     ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream, prof);
-    e = launch_setup_flat(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->f, tcoef, d->l, d->m, d->n, d->theta,
-                          d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, acoef32, (double*)(w + L.fac),
-                          modes, mixed ? (float4*)(w + L.modes32) : nullptr, mode_kr, pieces, evals, status,
-                          c->flag_word, d->Phiphi, d->Phir, d->A, hann, stream);
-    // given coefficients were not splined: their FP32 form separately
+    e = launch_setup_fused(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->f, tcoef, d->l, d->m,
+                           d->n, d->theta, d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, acoef32,
+                           modes, mixed ? (float4*)(w + L.modes32) : nullptr, mode_kr, pieces, evals, slots,
+                           c->flag_word, d->A, hann, stream);
     if (e == hipSuccess && mixed && given) e = launch_amp32(d->Nm, d->K, d->t, acoef, acoef32, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "set-up kernel launch");
+  } else {
+    {
+      // the trajectory splines first: the piece tables need them
+      ProfScope ps(c, FDEMRI_KERNEL_SPLINE, stream, prof);
+      e = launch_spline(d->K, d->t, d->Fphi, d->Fr, d->Phiphi, d->Phir, d->A, 0, tcoef, acoef,
+                        (double*)(w + L.fac), status, stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "spline kernel launch");
+    {
+      // piece tables, amplitude splines (and their FP32 form) and the input
+      // checks in one launch
+      ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream, prof);
+      e = launch_setup_flat(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->f, tcoef, d->l, d->m, d->n, d->theta,
+                            d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, acoef32,
+                            (double*)(w + L.fac), modes, mixed ? (float4*)(w + L.modes32) : nullptr, mode_kr,
+                            pieces, evals, status, c->flag_word, d->Phiphi, d->Phir, d->A, hann, stream);
+      // given coefficients were not splined: their FP32 form separately
+      if (e == hipSuccess && mixed && given) e = launch_amp32(d->Nm, d->K, d->t, acoef, acoef32, stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "piece kernel launch");
   }
-  if (e != hipSuccess) return hip_fail(c, e, "piece kernel launch");
   p.K = d->K;
   p.Nm = d->Nm;
   p.Nf = d->Nf;
@@ -459,6 +484,8 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   p.pieces = pieces;
   p.status = status;
   p.modes32 = mixed ? (const float4*)(w + L.modes32) : nullptr;
+  p.slots = fused ? slots : nullptr;
+  p.nslots = fused ? check_blocks(d->K, d->Nm, d->Nf, d->flags) : 0;
   c->last_evals.assign(1, {evals, d->Nm});
   return FDEMRI_OK;
 }
@@ -483,7 +510,7 @@ fdemri_status fdemri_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, fdem
   if (st != FDEMRI_OK) return st;
   Prepared p;
   float* acoef32 = nullptr;
-  st = prepare(c, d, mixed, L, p, acoef32, stream);
+  st = prepare(c, d, mixed, L, p, acoef32, stream, nullptr, true, 0, true);
   if (st != FDEMRI_OK) return st;
   if (!c->tuning) c->bpl = choose_bpl(c, (int)prec, false, d->Nf);
   {
@@ -512,7 +539,7 @@ fdemri_status fdemri_waveform_noalloc(fdemri_ctx* c, const fdemri_waveform_desc*
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   Prepared p;
   float* acoef32 = nullptr;
-  st = prepare(c, d, mixed, L, p, acoef32, stream, c->scratch, false);
+  st = prepare(c, d, mixed, L, p, acoef32, stream, c->scratch, false, 0, true);
   if (st != FDEMRI_OK) return st;
   const int bpl = c->tuning ? c->bpl : choose_bpl(c, (int)prec, false, d->Nf);
   e = launch_gather_flat(p, acoef32, hp, hc, mixed, bpl, stream);
@@ -539,7 +566,7 @@ fdemri_status fdemri_loglike(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemr
   Prepared p;
   float* acoef32 = nullptr;
   const int hann = (ll_flags & FDEMRI_LL_HANN) ? 1 : 0;
-  st = prepare(c, d, mixed, L, p, acoef32, stream, nullptr, true, hann);
+  st = prepare(c, d, mixed, L, p, acoef32, stream, nullptr, true, hann, true);
   if (st != FDEMRI_OK) return st;
   char* w = c->ws;
   {

@@ -35,15 +35,16 @@ __device__ __forceinline__ double reduce_2pi(double x) {
 // Bracket of the root inside segment i of piece P: [tl, th] in tau, with
 // |F_V| = gl, gh at its ends (piece end values at the piece's first/last
 // segment, knot values elsewhere).  A piece over the whole trajectory has
-// knot values at both ends, so its bracket is the segment's (a wave-uniform
-// test that saves the per-lane selects).
+// knot values at both ends, and so does a wave none of whose lanes is in the
+// first or last segment of its piece: their bracket is the segment's
+// (wave-uniform tests that save the per-lane selects).
 struct Bracket {
   double tl, th, gl, gh;
 };
 
 __device__ __forceinline__ Bracket make_bracket(const Piece& P, int i, const SegData& S) {
   Bracket B;
-  if (P.whole) {
+  if (P.whole || !__any(i == P.seg_a || i == P.seg_b)) {
     B = Bracket{0.0, S.h, S.G0, S.G1};
   } else {
     // an empty volatile statement keeps this a branch: if-converted, both

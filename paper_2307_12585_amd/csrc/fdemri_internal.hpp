@@ -70,6 +70,8 @@ struct Prepared {
   const int32_t* status;   // [3] input status of the call (0: valid; see the input checks below),
                            // then the bin envelope [lo, hi] of all voices (the whole grid unless formed)
   const float4* modes32;   // [Nm] (c_+, c_x) of each mode in FP32 (mixed path only)
+  const int32_t* slots;    // [nslots] input status per check workgroup, when the set-up was fused
+  int32_t nslots;          // (then status is not read and the envelope is the whole grid); 0 otherwise
 };
 
 // Device-resident record of one waveform of a batch: caller inputs, the
@@ -118,6 +120,8 @@ __host__ __device__ inline Prepared prepared_of(const WaveItem& w) {
   p.pieces = w.pieces;
   p.status = w.status;
   p.modes32 = w.modes32;
+  p.slots = nullptr;
+  p.nslots = 0;
   return p;
 }
 
@@ -132,6 +136,15 @@ constexpr int32_t kBadGrid = 4;      // f not finite, negative or descending
 constexpr int32_t kBadHannGrid = 8;  // Hann kernel asked for on a grid that is not k f_1
 // Elements checked per workgroup of the checks.
 constexpr int kCheckChunk = 4096;
+
+// Fused set-up of small waveforms (one launch for the trajectory splines, the
+// piece tables, the amplitude splines and the checks): at most this many
+// modes (the tables the gather scans without an envelope), knots and check
+// workgroups, whose statuses then go to one slot each instead of a status
+// word that an earlier launch would have to clear.
+constexpr int kFusedMaxModes = 256;
+constexpr int kFusedMaxKnots = 256;
+constexpr int kFusedMaxSlots = 256;
 
 // Workgroups of the checks of one waveform: the trajectory, the amplitude
 // array (knot values or given coefficients), the frequency grid.

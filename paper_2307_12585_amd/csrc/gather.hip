@@ -108,12 +108,19 @@ struct Lds {
   }
 };
 
+// Secant steps on the segment index of a piece: at most this many, the first
+// in every lane, the others in the lanes whose segment still fails the check
+// while any lane of the wave does (dense inspirals, whose knot frequencies
+// crowd at one end of the piece, need two to four; a slowly chirping voice
+// one).
+constexpr int kSecantSteps = 4;
+
 // One (bin, piece) evaluation.  The spline segment holding f is the largest i
 // in [seg_a, seg_b] whose start value precedes f in the direction of the
 // piece (i == seg_a or d g_i < d f; ties go to the lower segment).  It is
-// guessed from the piece's rate, refined by one secant step on the segment
-// index through the knot frequencies at the guess, and checked against the
-// definition; the rare misses walk to the right segment.
+// guessed from the piece's rate, refined by secant steps on the segment
+// index through the knot frequencies at the current segment, and checked
+// against the definition; the rare misses walk to the right segment.
 //   f, w: the bin frequency and 2 pi f;
 //   ms, ns: s m and s n of the piece, so that |F_V| = ms F_phi + ns F_r;
 //   cP, cX: c_+ and c_x, conjugated when s < 0, so that the contribution is
@@ -130,7 +137,7 @@ __device__ __forceinline__ void eval_bin(const double f, const double w, const P
   int i = min(max(cvt_i32_sat(__builtin_fma(f, P.rate, P.rate0)), P.seg_a), P.seg_b);
   double G0 = knot_freq(ms, L.knot(i).Fp, ns, L.knot(i).Fr);
   double G1 = knot_freq(ms, L.knot(i + 1).Fp, ns, L.knot(i + 1).Fr);
-  {
+  auto secant = [&]() {
     const float num = (float)(f - G0);
     const float den = (float)(G1 - G0);
     float di = 0.f;
@@ -144,8 +151,18 @@ __device__ __forceinline__ void eval_bin(const double f, const double w, const P
       G0 = knot_freq(ms, L.knot(i).Fp, ns, L.knot(i).Fr);
       G1 = knot_freq(ms, L.knot(i + 1).Fp, ns, L.knot(i + 1).Fr);
     }
+  };
+  auto misses = [&]() { return (i > P.seg_a && !(dd_ * G0 < fd)) || (i < P.seg_b && dd_ * G1 < fd); };
+  secant();
+  bool miss = misses();
+#pragma unroll 1
+  for (int it = 1; it < kSecantSteps && __any(miss); ++it) {
+    if (miss) {
+      secant();
+      miss = misses();
+    }
   }
-  if ((i > P.seg_a && !(dd_ * G0 < fd)) || (i < P.seg_b && dd_ * G1 < fd)) {
+  if (miss) {
     while (i > P.seg_a && !(dd_ * knot_freq(ms, L.knot(i).Fp, ns, L.knot(i).Fr) < fd)) --i;
     while (i < P.seg_b && dd_ * knot_freq(ms, L.knot(i + 1).Fp, ns, L.knot(i + 1).Fr) < fd) ++i;
     G0 = knot_freq(ms, L.knot(i).Fp, ns, L.knot(i).Fr);
@@ -574,16 +591,29 @@ __global__ __launch_bounds__(64 * WAVES, gather_min_waves<MIXED>()) void gather_
   const Prepared& p = a.p;
   const int kb = (int)blockIdx.x * block_bins<BPL, WAVES>();
   // a waveform whose inputs failed the checks has a zero model, and so do
-  // the blocks outside the bin envelope of its voices
-  const kconst int32_t* st = (const kconst int32_t*)p.status;
-  if (st[0] != 0 || kb + block_bins<BPL, WAVES>() - 1 < st[1] || kb > st[2]) {
+  // the blocks outside the bin envelope of its voices (after a fused set-up:
+  // the check workgroups' slots, every wave reading all of them, and no
+  // envelope)
+  bool bad;
+  int env_lo = 0, env_hi = INT_MAX;
+  if (p.nslots > 0) {
+    int v = 0;
+    for (int j = (int)(threadIdx.x & 63); j < p.nslots; j += 64) v |= p.slots[j];
+    bad = __any(v != 0);
+  } else {
+    const kconst int32_t* st = (const kconst int32_t*)p.status;
+    bad = st[0] != 0;
+    env_lo = st[1];
+    env_hi = st[2];
+  }
+  if (bad || kb + block_bins<BPL, WAVES>() - 1 < env_lo || kb > env_hi) {
     zero_tiles<MIXED, BPL, WAVES, LL>(a.out, p.Nf, kb);
     return;
   }
   int* list = (int*)lds;
   // a formed envelope (large mode tables) means the block most likely has
   // voices: stage the tables at once
-  const bool eager = st[1] > 0 || st[2] < INT_MAX;
+  const bool eager = env_lo > 0 || env_hi < INT_MAX;
   process_block<MIXED, BPL, WAVES, LL>(p, a.amp, a.out, kb, list, [&]() { return stage_lds(p, lds + kHeadDoubles); },
                                       eager);
 }

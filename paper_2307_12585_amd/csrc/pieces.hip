@@ -395,8 +395,11 @@ struct CheckArgs {
 // finite), then the amplitude array in chunks (finite), then the frequency
 // grid in chunks (finite, >= 0, ascending; with hann also |f_k - k f_1| <=
 // 1e-12 f_k, so f_0 = 0).  Failures set bits in the waveform's status word
-// and the context's flag bit; nothing is written otherwise.
-__device__ void check_block(const CheckArgs& c, int blk, int32_t* status, uint32_t* flag_word) {
+// and the context's flag bit; nothing is written otherwise.  With slot, the
+// workgroup instead writes its result to *slot (0 when its part passed),
+// every time.
+__device__ void check_block(const CheckArgs& c, int blk, int32_t* status, uint32_t* flag_word,
+                            int32_t* slot = nullptr) {
   int32_t bad = 0;
   const long na = check_amp_count(c.K, c.Nm, c.flags);
   const int nab = (int)((na + kCheckChunk - 1) / kCheckChunk);
@@ -423,6 +426,18 @@ __device__ void check_block(const CheckArgs& c, int blk, int32_t* status, uint32
       if (!isfinite(fk) || !(fk >= 0.0) || (k > 0 && !(fk >= c.f[k - 1]))) bad |= kBadGrid;
       if (c.hann && !(fabs(fk - (double)k * f1) <= 1e-12 * fk)) bad |= kBadHannGrid;
     }
+  }
+  if (slot) {
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    if (bad) atomicOr(&s_bad, bad);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      *slot = s_bad;
+      if (s_bad) atomicOr(flag_word, (uint32_t)FDEMRI_FLAG_BAD_INPUT);
+    }
+    return;
   }
   if (bad) {
     atomicOr(status, bad);
@@ -599,6 +614,96 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
   // gather skips the blocks no voice reaches without scanning the table; a
   // small table is scanned as cheaply as the launch would cost
   if (Nm > kEnvelopeMinModes) envelope_kernel<<<1, 256, 0, stream>>>(mode_kr, Nm, status + 1);
+  return hipGetLastError();
+}
+
+// Fused set-up of a small waveform (kFusedMax* limits), one launch in place
+// of the trajectory splines' launch and setup_kernel's: the piece workgroups
+// first solve the splines of F_phi and F_r themselves (the same arithmetic as
+// the spline launch, so the same coefficients, which each writes to tcoef),
+// then walk their modes; one workgroup solves those of Phi_phi and Phi_r;
+// the amplitude workgroups reduce the knot matrix themselves instead of
+// reading its factors; the check workgroups write one status slot each.
+template <int NT>
+__global__ __launch_bounds__(NT) void setup_fused_kernel(PieceArgs a, int piece_blocks, int amp_blocks,
+                                                         const double* __restrict__ A, double* __restrict__ acoef,
+                                                         float* __restrict__ acoef32, double* __restrict__ tcoef,
+                                                         const double* __restrict__ Phiphi,
+                                                         const double* __restrict__ Phir, CheckArgs c,
+                                                         int32_t* __restrict__ slots) {
+  constexpr int W = NT / 64;
+  constexpr size_t kBytes = sizeof(SplineLds<NT>) > sizeof(Event) * W * kMaxEvents ? sizeof(SplineLds<NT>)
+                                                                                     : sizeof(Event) * W * kMaxEvents;
+  __shared__ double lds[kBytes / sizeof(double)];
+  const int b = (int)blockIdx.x;
+  if (b < piece_blocks) {
+    // series 0 and 1 (F_phi, F_r) into tcoef, read back by this workgroup's
+    // piece walks (every piece workgroup writes the same values)
+    spline_block<NT>(*(SplineLds<NT>*)lds, 0, 4, a.K, a.t, a.Fphi, a.Fr, Phiphi, Phir, A, tcoef, acoef);
+    __syncthreads();  // the coefficients are written, the LDS free
+    const int wave = threadIdx.x >> 6;
+    const int mu = b * W + wave;
+    if (mu < a.Nm) piece_mode_wave(a, mu, (Event*)lds + wave * kMaxEvents);
+    return;
+  }
+  if (b == piece_blocks) {
+    spline_block<NT>(*(SplineLds<NT>*)lds, 2, 4, a.K, a.t, a.Fphi, a.Fr, Phiphi, Phir, A, tcoef, acoef);
+    return;
+  }
+  if (b > piece_blocks + amp_blocks) {
+    const int blk = b - piece_blocks - amp_blocks - 1;
+    check_block(c, blk, nullptr, a.flag_word, slots + blk);
+    return;
+  }
+  const int s0 = 4 + (b - piece_blocks - 1) * kSeriesPerBlock;
+  spline_block<NT>(*(SplineLds<NT>*)lds, s0, 4 + a.Nm, a.K, a.t, a.Fphi, a.Fr, a.Fphi, a.Fr, A, acoef, acoef,
+                   nullptr, acoef32);
+}
+
+// Whether the set-up of a waveform of this shape can be fused (and then
+// how many status slots it writes: check_blocks).
+bool setup_fusable(int K, int Nm, int Nf, uint32_t flags) {
+  return Nm <= kFusedMaxModes && K <= kFusedMaxKnots && check_blocks(K, Nm, Nf, flags) <= kFusedMaxSlots;
+}
+
+// The fused set-up (setup_fused_kernel) of a waveform for which setup_fusable
+// holds: as launch_spline followed by launch_setup_flat, with the input
+// statuses in slots[check_blocks] instead of the status word.
+hipError_t launch_setup_fused(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
+                              const double* Phiphi, const double* Phir, const double* f, double* tcoef,
+                              const int32_t* l, const int32_t* m, const int32_t* n, double theta, double phi,
+                              double scale, uint32_t flags, const double* A, double* acoef, float* acoef32,
+                              ModeConst* modes, float4* modes32, int2* mode_kr, Piece* pieces, int64_t* evals,
+                              int32_t* slots, uint32_t* flag_word, const double* A_in, int hann,
+                              hipStream_t stream) {
+  PieceArgs a;
+  a.K = K;
+  a.Nm = Nm;
+  a.Nf = Nf;
+  a.t = t;
+  a.Fphi = Fphi;
+  a.Fr = Fr;
+  a.f = f;
+  a.tcoef = tcoef;
+  a.l = l;
+  a.m = m;
+  a.n = n;
+  a.theta = theta;
+  a.phi = phi;
+  a.scale = scale;
+  a.flags = flags;
+  a.modes = modes;
+  a.modes32 = modes32;
+  a.mode_kr = mode_kr;
+  a.pieces = pieces;
+  a.evals = evals;
+  a.flag_word = flag_word;
+  const int amp_blocks = A ? (Nm + kSeriesPerBlock - 1) / kSeriesPerBlock : 0;
+  const int checks = check_blocks(K, Nm, Nf, flags);
+  const CheckArgs c{K, Nm, Nf, flags, hann, t, Fphi, Fr, Phiphi, Phir, A_in, f};
+  const int pb = (Nm + 3) / 4;
+  setup_fused_kernel<256><<<pb + 1 + amp_blocks + checks, 256, 0, stream>>>(a, pb, amp_blocks, A, acoef, acoef32,
+                                                                            tcoef, Phiphi, Phir, c, slots);
   return hipGetLastError();
 }
 

@@ -1,59 +1,78 @@
 // Searches in an ascending frequency array f[0..Nf) (the grid of the
 // frequency-domain sum).  Bin ranges of pieces and segments are found by
-// these, so their cost is a chain of dependent global loads: the first probe
-// is a linear-interpolation guess between the bracket ends, checked together
-// with its right neighbour in one round trip (exact on a uniform grid), and
-// the search then alternates interpolation and bisection steps, so that any
-// ascending grid is resolved in at most about 2 log2(Nf) probes.
+// these, so their cost is a chain of dependent global loads.  Each
+// interpolation round probes, in one round trip, the index that linear
+// interpolation between the bracket ends predicts and, when both ends are
+// positive, the index that interpolation in log f predicts (FP32 logarithms:
+// only a guess, the probes decide), each with its right neighbour: on a
+// uniform grid the first, on a logarithmic grid the second ends the search.
+// Rounds alternate with bisection steps, so that any ascending grid is
+// resolved in at most about 2 log2(Nf) round trips.
 #pragma once
 
 #include "fdemri_internal.hpp"
 
 namespace fdemri {
 
+// Index in (a, b) that interpolation predicts for y(x) between y(f[a]) = ya
+// and y(f[b]) = yb.
+__device__ __forceinline__ int interp_index(int a, int b, double ya, double yb, double yx) {
+  const double u = (yx - ya) / (yb - ya) * (double)(b - a);
+  const int g = a + (int)fmin(fmax(u, 0.0), (double)(b - a));
+  return min(max(g, a + 1), b - 1);
+}
+
 // First index k in [0, Nf] with f[k] >= x (strict = false) or f[k] > x
-// (strict = true).
+// (strict = true).  Invariant: f[a] precedes the answer, f[b] does not; a
+// probe at index g with value v narrows (a, b] whatever the order of probes.
 template <bool STRICT>
 __device__ __forceinline__ int first_index(const double* __restrict__ f, int Nf, double x) {
   if (Nf <= 0) return 0;
-  auto before = [&](double v) { return STRICT ? !(v > x) : (v < x); };  // v precedes the answer
+#define FDEMRI_BEFORE(v) (STRICT ? !((v) > x) : ((v) < x))
+#define FDEMRI_PROBE(g, v)      \
+  if (FDEMRI_BEFORE(v)) {       \
+    if ((g) > a) {              \
+      a = (g);                  \
+      fa = (v);                 \
+    }                           \
+  } else if ((g) < b) {         \
+    b = (g);                    \
+    fb = (v);                   \
+  }
   double fa = f[0], fb = f[Nf - 1];
-  if (!before(fa)) return 0;
-  if (before(fb)) return Nf;
-  // invariant: before(f[a]) and !before(f[b]); the answer lies in (a, b]
+  if (!FDEMRI_BEFORE(fa)) return 0;
+  if (FDEMRI_BEFORE(fb)) return Nf;
   int a = 0, b = Nf - 1;
   bool interp = true;
   while (b - a > 1) {
-    int g;
     if (interp && fb > fa) {
-      const double u = (x - fa) / (fb - fa) * (double)(b - a);
-      g = a + (int)fmin(fmax(u, 0.0), (double)(b - a));
-      g = min(max(g, a + 1), b - 1);
-      // probe g and g + 1 together: on a uniform grid one of them ends the search
+      const int b0 = b;
+      const int g = interp_index(a, b, fa, fb, x);
       const double v0 = f[g];
-      const double v1 = (g + 1 < b) ? f[g + 1] : fb;
-      if (!before(v0)) {
-        b = g;
-        fb = v0;
-      } else if (before(v1)) {
-        a = g + 1;
-        fa = v1;
-      } else {
-        return g + 1;
+      const double v1 = (g + 1 < b0) ? f[g + 1] : fb;
+      if (fa > 0.0 && x > 0.0) {
+        // the log-interpolated pair too, in the same round trip
+        const int g2 = interp_index(a, b, __log2f((float)fa), __log2f((float)fb), __log2f((float)x));
+        const double w0 = f[g2];
+        const double w1 = (g2 + 1 < b0) ? f[g2 + 1] : fb;
+        FDEMRI_PROBE(g2, w0)
+        if (g2 + 1 < b0) {
+          FDEMRI_PROBE(g2 + 1, w1)
+        }
+      }
+      FDEMRI_PROBE(g, v0)
+      if (g + 1 < b0) {
+        FDEMRI_PROBE(g + 1, v1)
       }
     } else {
-      g = a + ((b - a) >> 1);
+      const int g = a + ((b - a) >> 1);
       const double v = f[g];
-      if (before(v)) {
-        a = g;
-        fa = v;
-      } else {
-        b = g;
-        fb = v;
-      }
+      FDEMRI_PROBE(g, v)
     }
     interp = !interp;
   }
+#undef FDEMRI_PROBE
+#undef FDEMRI_BEFORE
   return b;
 }
 

@@ -377,6 +377,12 @@ def test_profile_classes(ctx):
     ctx.profile(True)
     ctx.waveform_dev(dw, "fp64")
     got = ctx.profile_read()
+    # a 20-mode waveform has its set-up fused into one launch (the pieces class)
+    assert got["gather"][1] == 1 and got["spline"][1] == 0 and got["pieces"][1] == 1
+    w2 = W.inspiral_20_modes(K=300)  # above the fused set-up's knot limit: splines, then set-up
+    dw2 = fd.DeviceWaveform.from_workload(w2, device=ctx.device)
+    ctx.waveform_dev(dw2, "fp64")
+    got = ctx.profile_read()
     assert got["gather"][1] == 1 and got["spline"][1] == 1 and got["pieces"][1] == 1
     ctx.profile(False)
     ctx.waveform_dev(dw, "fp64")
