@@ -203,6 +203,9 @@ constexpr int kMaxEvents = 64;
 
 __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
   const int lane = threadIdx.x & 63;
+  // the grid's end values, for the bin-range searches at the end (requested
+  // first, so that their latency overlaps the segment scan)
+  const double fbeg = a.f[0], fend = a.f[a.Nf - 1];
   const int li = a.l[mu], mi = a.m[mu], ni = a.n[mu];
   const double m = (double)mi, n = (double)ni;
   const int K = a.K, nseg = K - 1;
@@ -252,7 +255,7 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
   wave_lds_sync();
 
   // ---- pieces between consecutive events, one per lane
-  const int kpos = first_gt(a.f, a.Nf, 0.0);  // first bin with f > 0 (wave-uniform)
+  const int kpos = first_gt(a.f, a.Nf, 0.0, fbeg, fend);  // first bin with f > 0 (wave-uniform)
   const int n_cand = flat_voice ? 0 : n_all;
   bool valid = false;
   Piece P{};
@@ -282,10 +285,10 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
       P.whole = (n_all == 1) ? 1 : 0;  // lane 0 from the first knot to the final event
       P.pad = 0;
       const double glo = fmin(P.g_a, P.g_b), ghi = fmax(P.g_a, P.g_b);
-      int klo = first_ge(a.f, a.Nf, glo);
+      int klo = first_ge(a.f, a.Nf, glo, fbeg, fend);
       if (klo < kpos) klo = kpos;
       P.k_lo = klo;
-      P.k_hi = first_gt(a.f, a.Nf, ghi) - 1;
+      P.k_hi = first_gt(a.f, a.Nf, ghi, fbeg, fend) - 1;
     }
   }
   const unsigned long long vmask = __ballot(valid);

@@ -23,11 +23,12 @@ __device__ __forceinline__ int interp_index(int a, int b, double ya, double yb, 
 }
 
 // First index k in [0, Nf] with f[k] >= x (strict = false) or f[k] > x
-// (strict = true).  Invariant: f[a] precedes the answer, f[b] does not; a
-// probe at index g with value v narrows (a, b] whatever the order of probes.
+// (strict = true), given the end values f0 = f[0] and fN = f[Nf - 1] (Nf >= 1;
+// a caller with several searches loads them once).  Invariant: f[a] precedes
+// the answer, f[b] does not; a probe at index g with value v narrows (a, b]
+// whatever the order of probes.
 template <bool STRICT>
-__device__ __forceinline__ int first_index(const double* __restrict__ f, int Nf, double x) {
-  if (Nf <= 0) return 0;
+__device__ __forceinline__ int first_index(const double* __restrict__ f, int Nf, double x, double f0, double fN) {
 #define FDEMRI_BEFORE(v) (STRICT ? !((v) > x) : ((v) < x))
 #define FDEMRI_PROBE(g, v)      \
   if (FDEMRI_BEFORE(v)) {       \
@@ -39,7 +40,7 @@ __device__ __forceinline__ int first_index(const double* __restrict__ f, int Nf,
     b = (g);                    \
     fb = (v);                   \
   }
-  double fa = f[0], fb = f[Nf - 1];
+  double fa = f0, fb = fN;
   if (!FDEMRI_BEFORE(fa)) return 0;
   if (FDEMRI_BEFORE(fb)) return Nf;
   int a = 0, b = Nf - 1;
@@ -76,12 +77,20 @@ __device__ __forceinline__ int first_index(const double* __restrict__ f, int Nf,
   return b;
 }
 
+__device__ __forceinline__ int first_ge(const double* __restrict__ f, int Nf, double x, double f0, double fN) {
+  return first_index<false>(f, Nf, x, f0, fN);
+}
+
+__device__ __forceinline__ int first_gt(const double* __restrict__ f, int Nf, double x, double f0, double fN) {
+  return first_index<true>(f, Nf, x, f0, fN);
+}
+
 __device__ __forceinline__ int first_ge(const double* __restrict__ f, int Nf, double x) {
-  return first_index<false>(f, Nf, x);
+  return Nf <= 0 ? 0 : first_ge(f, Nf, x, f[0], f[Nf - 1]);
 }
 
 __device__ __forceinline__ int first_gt(const double* __restrict__ f, int Nf, double x) {
-  return first_index<true>(f, Nf, x);
+  return Nf <= 0 ? 0 : first_gt(f, Nf, x, f[0], f[Nf - 1]);
 }
 
 }  // namespace fdemri
