@@ -168,7 +168,9 @@ fdemri_status fdemri_sync_flags(fdemri_ctx *ctx, hipStream_t stream, uint32_t *f
  * shape and precision on the same context (that call sizes the context's
  * workspace).  The graph reads the inputs and the workspace at replay; a
  * later call on the context that needs a larger workspace reallocates it and
- * invalidates such graphs, so other work should use its own context.
+ * invalidates such graphs, so other work should use its own context.  (The
+ * old workspace is released once the work enqueued before that call has
+ * completed, without synchronising the device.)
  */
 fdemri_status fdemri_waveform(fdemri_ctx *ctx, const fdemri_waveform_desc *desc,
                               fdemri_prec prec, void *hp, void *hc, hipStream_t stream);

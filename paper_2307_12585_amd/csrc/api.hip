@@ -140,6 +140,9 @@ struct fdemri_ctx {
   uint64_t graph_clock = 0;
   std::vector<char> rec_tmp;  // host image of a batch's records, compared with a graph's
   uint64_t ws_generation = 0;
+  // workspaces replaced by a larger one, each with an event recorded on the
+  // stream of the call that replaced it; freed once that event has passed
+  std::vector<std::pair<char*, hipEvent_t>> retired;
   // autotuned bins-per-lane by (precision, batch?, log2 of total bins)
   std::string device_key;
   std::vector<std::array<int, 4>> tuned;  // {prec, batch, cls, bpl}
@@ -224,25 +227,52 @@ Layout layout_for(int K, int Nm, bool mixed, bool vjp = false, int ll_tiles = 0,
   return L;
 }
 
-fdemri_status ensure_ws(fdemri_ctx* c, size_t bytes) {
+// Frees the retired workspaces whose events have passed (all of them, after
+// a synchronisation, when wait is set).
+void reclaim_retired(fdemri_ctx* c, bool wait) {
+  size_t keep = 0;
+  for (auto& r : c->retired) {
+    if (wait || hipEventQuery(r.second) == hipSuccess) {
+      (void)hipEventSynchronize(r.second);
+      (void)hipEventDestroy(r.second);
+      (void)hipFree(r.first);
+    } else {
+      c->retired[keep++] = r;
+    }
+  }
+  c->retired.resize(keep);
+}
+
+// Grows the workspace to at least `bytes`.  The old workspace may still be
+// read by kernels of earlier calls; calls on a context are ordered (one
+// stream, or events), so those kernels finish before any work enqueued on
+// `stream` from now on starts.  The old workspace is therefore retired with
+// an event recorded on `stream` and freed once the event has passed (checked
+// here and at destruction), without synchronising the device or other
+// streams.
+fdemri_status ensure_ws(fdemri_ctx* c, size_t bytes, hipStream_t stream) {
+  reclaim_retired(c, false);
   if (bytes <= c->ws_bytes) return FDEMRI_OK;
   if (c->fail_alloc > 0 && --c->fail_alloc == 0)
     return fail(c, FDEMRI_ENOMEM, "hipMalloc(workspace): out of memory (injected by FDEMRI_TEST_FAIL_ALLOC)");
+  const size_t want = align_up(bytes + bytes / 4, 1 << 20);
+  char* fresh = nullptr;
+  hipError_t e = hipMalloc((void**)&fresh, want);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMalloc(workspace)");
   if (c->ws) {
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
-    (void)hipFree(c->ws);
-    c->ws = nullptr;
-    c->ws_bytes = 0;
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, stream);
+    if (e != hipSuccess) {
+      if (ev) (void)hipEventDestroy(ev);
+      (void)hipFree(fresh);
+      return hip_fail(c, e, "workspace retirement event");
+    }
+    c->retired.emplace_back(c->ws, ev);
   }
-  size_t want = align_up(bytes + bytes / 4, 1 << 20);
-  c->ws_generation++;
-  hipError_t e = hipMalloc((void**)&c->ws, want);
-  if (e != hipSuccess) {
-    c->ws = nullptr;
-    return hip_fail(c, e, "hipMalloc(workspace)");
-  }
+  c->ws = fresh;
   c->ws_bytes = want;
+  c->ws_generation++;
   return FDEMRI_OK;
 }
 
@@ -374,6 +404,7 @@ void fdemri_destroy(fdemri_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  reclaim_retired(c, true);
   if (c->ws) (void)hipFree(c->ws);
   if (c->flag_word) (void)hipFree(c->flag_word);
   for (auto& r : c->recs) {
@@ -506,7 +537,7 @@ fdemri_status fdemri_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, fdem
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   const Layout L = layout_for(d->K, d->Nm, mixed);
-  st = ensure_ws(c, L.total);
+  st = ensure_ws(c, L.total, stream);
   if (st != FDEMRI_OK) return st;
   Prepared p;
   float* acoef32 = nullptr;
@@ -561,7 +592,7 @@ fdemri_status fdemri_loglike(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemr
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   const int bpl = c->tuning ? c->bpl : choose_bpl(c, (int)prec, false, d->Nf);
   const Layout L = layout_for(d->K, d->Nm, mixed, false, loglike_tiles(d->Nf, bpl), loglike_partial_doubles(d->Nf, bpl));
-  st = ensure_ws(c, L.total);
+  st = ensure_ws(c, L.total, stream);
   if (st != FDEMRI_OK) return st;
   Prepared p;
   float* acoef32 = nullptr;
@@ -590,7 +621,7 @@ fdemri_status fdemri_td_waveform(fdemri_ctx* c, const fdemri_waveform_desc* d, d
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   const Layout L = layout_for(d->K, d->Nm, false);
-  st = ensure_ws(c, L.total);
+  st = ensure_ws(c, L.total, stream);
   if (st != FDEMRI_OK) return st;
   Prepared p;
   float* acoef32 = nullptr;
@@ -621,7 +652,7 @@ fdemri_status fdemri_trajectory(fdemri_ctx* c, int32_t B, const fdemri_traj_para
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   const size_t bytes = (size_t)B * sizeof(fdemri_traj_params);
-  fdemri_status st = ensure_ws(c, bytes);
+  fdemri_status st = ensure_ws(c, bytes, stream);
   if (st != FDEMRI_OK) return st;
   // the parameters go through the workspace; the copy from pageable host
   // memory completes before this call returns
@@ -642,7 +673,7 @@ fdemri_status fdemri_signal_band(fdemri_ctx* c, const fdemri_waveform_desc* d, d
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   const Layout L = layout_for(d->K, d->Nm, false);
-  st = ensure_ws(c, L.total);
+  st = ensure_ws(c, L.total, stream);
   if (st != FDEMRI_OK) return st;
   Prepared p;
   float* acoef32 = nullptr;
@@ -663,7 +694,7 @@ fdemri_status fdemri_select_modes(fdemri_ctx* c, int32_t K, int32_t Nm, const do
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   const size_t p_bytes = align_up((size_t)K * sizeof(double), 256);
-  fdemri_status st = ensure_ws(c, p_bytes + (size_t)Nm * sizeof(int32_t) + 256);
+  fdemri_status st = ensure_ws(c, p_bytes + (size_t)Nm * sizeof(int32_t) + 256, stream);
   if (st != FDEMRI_OK) return st;
   e = launch_select_modes(K, Nm, A, eps, (double*)c->ws, (int32_t*)(c->ws + p_bytes), idx, n_keep, stream);
   if (e != hipSuccess) return hip_fail(c, e, "mode selection launch");
@@ -685,7 +716,7 @@ fdemri_status fdemri_vjp(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemri_pr
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   const Layout L = layout_for(d->K, d->Nm, mixed, true);
-  st = ensure_ws(c, L.total);
+  st = ensure_ws(c, L.total, stream);
   if (st != FDEMRI_OK) return st;
   Prepared p;
   float* acoef32 = nullptr;
@@ -957,7 +988,7 @@ fdemri_status fdemri_waveform_batch(fdemri_ctx* c, int32_t B, const fdemri_wavef
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   const uint64_t gen0 = c->ws_generation;
-  st = ensure_ws(c, P.total);
+  st = ensure_ws(c, P.total, stream);
   if (st != FDEMRI_OK) return st;
   if (c->ws_generation != gen0) drop_graphs(c);  // recorded graphs point into the old workspace
 
@@ -1086,7 +1117,7 @@ fdemri_status fdemri_loglike_batch(fdemri_ctx* c, int32_t B, const fdemri_wavefo
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
   const uint64_t gen0 = c->ws_generation;
-  st = ensure_ws(c, P.total);
+  st = ensure_ws(c, P.total, stream);
   if (st != FDEMRI_OK) return st;
   if (c->ws_generation != gen0) drop_graphs(c);  // recorded graphs point into the old workspace
   // records through the shared pinned staging buffer (eager; not captured)

@@ -238,6 +238,37 @@ def test_deterministic_bitwise(ctx):
     assert all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
+def test_workspace_growth_between_queued_calls():
+    """A context whose workspace grows while the kernels of earlier calls are
+    still queued on the stream (no synchronisation between the calls): the
+    old workspace is retired behind an event, not freed under them, and every
+    result equals the same call on a fresh context."""
+    small = W.inspiral_20_modes()
+    large = W.inspiral_3842_modes()
+    large.f = large.f[:400_000]
+    c = fd.Context(0)
+    try:
+        ds = fd.DeviceWaveform.from_workload(small, device=c.device)
+        dl = fd.DeviceWaveform.from_workload(large, device=c.device)
+        a = c.waveform_dev(ds, "fp64")
+        b = c.waveform_dev(dl, "fp64")   # grows the workspace behind the queued small call
+        a2 = c.waveform_dev(ds, "mixed")
+        b2 = c.waveform_dev(dl, "mixed")
+        torch.cuda.synchronize()
+        got = [x.cpu().numpy() for x in (*a, *b, *a2, *b2)]
+    finally:
+        c.close()
+    ref = []
+    for dw_, prec in ((ds, "fp64"), (dl, "fp64"), (ds, "mixed"), (dl, "mixed")):
+        f = fd.Context(0)
+        try:
+            ref += [x.cpu().numpy() for x in f.waveform_dev(dw_, prec)]
+            torch.cuda.synchronize()
+        finally:
+            f.close()
+    assert all(np.array_equal(x, y) for x, y in zip(got, ref))
+
+
 def test_outputs_fully_overwritten(ctx):
     w = W.inspiral_20_modes()
     dw = fd.DeviceWaveform.from_workload(w, device=ctx.device)
