@@ -138,42 +138,44 @@ __device__ __forceinline__ double phase_psi(double f, double w, double tau, doub
   return big + small;
 }
 
-// sin and cos of x in double precision: Cody-Waite reduction by pi/2 split
-// into two parts (a 33-bit head, so k times it is exact for the quadrant
-// counts that occur, and the rounded remainder; residual 3.5e-27), each
-// product subtracted with one fused multiply-add; then on [-pi/4, pi/4]
+// sin and cos of x in double precision: Cody-Waite reduction by pi split
+// into two parts (a 34-bit head, so k times it is exact for the multiples
+// that occur, and the rounded remainder), each product subtracted with one
+// fused multiply-add; then on r in [-pi/2, pi/2]
 //   sin r = r + r z P(z),  cos r = 1 - z/2 + z^2 Q(z),  z = r^2,
-// with P, Q degree-5 least-squares fits in extended precision
-// (gen_sincos_coeffs.py; approximation errors 1e-17 and 5e-19), and a
-// quadrant rotation.  The phases passed here are reduced modulo 2 pi up to a
-// few hundred radians and the segment-local part, a few thousand radians at
-// most, so the quadrant count fits an int.  Error against extended precision:
-// 2.2e-16 absolute for |x| <= 1e4.
+// with P, Q degree-7 least-squares fits in extended precision
+// (gen_sincos_coeffs.py; approximation errors 1.3e-18 relative and 1.0e-19),
+// and the sign (-1)^k of the multiple k of pi given to both results (one
+// exclusive or of the sign bit each: no quadrant selects).  The phases
+// passed here are reduced modulo 2 pi up to a few hundred radians and the
+// segment-local part, a few thousand radians at most, so k fits an int.
 __device__ __forceinline__ void sincos_cw(double x, double* sn, double* cs) {
-  constexpr double kPio2A = 1.5707963267341256;
-  constexpr double kPio2B = 6.077100506506192e-11;
-  constexpr double k2OverPi = 0.6366197723675814;
-  const double k = rint(x * k2OverPi);
-  double r = __builtin_fma(-k, kPio2A, x);
-  r = __builtin_fma(-k, kPio2B, r);
+  constexpr double kPiA = 3.1415926534682512;
+  constexpr double kPiB = 1.2154201013012384e-10;
+  constexpr double kInvPi = 0.3183098861837907;
+  const double k = rint(x * kInvPi);
+  double r = __builtin_fma(-k, kPiA, x);
+  r = __builtin_fma(-k, kPiB, r);
   const double z = r * r;
-  double ps = __builtin_fma(1.5918135932869774e-10, z, -2.5051131947374594e-08);
-  ps = fma_sc(ps, z, 2.7557316103105014e-06);
-  ps = fma_sc(ps, z, -0.0001984126983675979);
-  ps = fma_sc(ps, z, 0.00833333333333095);
+  double ps = __builtin_fma(2.7314520351307035e-15, z, -7.643970924523278e-13);
+  ps = fma_sc(ps, z, 1.605897733376295e-10);
+  ps = fma_sc(ps, z, -2.5052107617354543e-08);
+  ps = fma_sc(ps, z, 2.755731921916633e-06);
+  ps = fma_sc(ps, z, -0.00019841269841254988);
+  ps = fma_sc(ps, z, 0.008333333333333316);
   ps = fma_sc(ps, z, -0.16666666666666666);
   const double s_r = __builtin_fma(r * z, ps, r);
-  double pc = __builtin_fma(-1.1382636115964061e-11, z, 2.087614632531677e-09);
-  pc = fma_sc(pc, z, -2.7557317272036996e-07);
-  pc = fma_sc(pc, z, 2.4801587298766363e-05);
-  pc = fma_sc(pc, z, -0.0013888888888887398);
+  double pc = __builtin_fma(-1.5218671473552762e-16, z, 4.7778782111543295e-14);
+  pc = fma_sc(pc, z, -1.1470712282450332e-11);
+  pc = fma_sc(pc, z, 2.087675660303868e-09);
+  pc = fma_sc(pc, z, -2.755731922157097e-07);
+  pc = fma_sc(pc, z, 2.4801587301579858e-05);
+  pc = fma_sc(pc, z, -0.001388888888888888);
   pc = fma_sc(pc, z, 0.041666666666666664);
   const double c_r = __builtin_fma(z * z, pc, __builtin_fma(-0.5, z, 1.0));
-  const int q = ((int)k) & 3;
-  const double s1 = (q & 1) ? c_r : s_r;
-  const double c1 = (q & 1) ? s_r : c_r;
-  *sn = (q & 2) ? -s1 : s1;
-  *cs = ((q + 1) & 2) ? -c1 : c1;
+  const long long sign = (long long)((uint32_t)cvt_i32_sat(k) << 31) << 32;
+  *sn = __longlong_as_double(__double_as_longlong(s_r) ^ sign);
+  *cs = __longlong_as_double(__double_as_longlong(c_r) ^ sign);
 }
 
 // sin and cos of psi for the mixed path: the reduction by pi/2 in FP64 (the

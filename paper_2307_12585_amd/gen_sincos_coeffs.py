@@ -1,13 +1,16 @@
 """Polynomial coefficients of the device sin/cos kernels (csrc/evalcore.hpp).
 
-On r in [-pi/4, pi/4], with z = r^2:
-    sin r = r + r z P(z),          P of degree 5 (FP64 path), 2 (FP32, mixed path),
-    cos r = 1 - z/2 + z^2 Q(z),    Q of degree 5 (FP64 path), 2 (FP32, mixed path),
+With z = r^2:
+    sin r = r + r z P(z),   cos r = 1 - z/2 + z^2 Q(z),
 with P, Q the least-squares fits (in 60-digit arithmetic) of
 (sin sqrt(z) - sqrt(z)) / z^(3/2) and (cos sqrt(z) - 1 + z/2) / z^2 on 400
-Chebyshev nodes of [0, (pi/4)^2].  Also prints the two-part split of pi/2
-used by the range reduction (33-bit head, rounded remainder) and the maximum
-approximation errors (relative for sin, absolute for cos).
+Chebyshev nodes of [0, R^2]:
+    FP64 path: R = pi/2 (the argument reduced by pi), P, Q of degree 7;
+    FP32 (mixed) path: R = pi/4 (reduced by pi/2), P, Q of degree 2.
+Also prints the two-part splits of pi and pi/2 used by the range reductions
+(head to 34 and 33 bits, so that k times it is exact for the multiples that
+occur; rounded remainder) and the maximum approximation errors (relative
+for sin, absolute for cos).
 
     python -m paper_2307_12585_amd.gen_sincos_coeffs
 """
@@ -28,10 +31,9 @@ def fit(fun, deg, z_max, npts=400):
     return [x[j] for j in range(deg + 1)]
 
 
-def main():
+def coefficients():
+    """{path: (P, Q, sin error, cos error)} for the two device kernels."""
     mp.mp.dps = 60
-    R = mp.pi / 4
-    Z = R * R
 
     def p_sin(z):
         if z == 0:
@@ -44,19 +46,34 @@ def main():
             return mp.mpf(1) / 24
         return (mp.cos(mp.sqrt(z)) - 1 + z / 2) / (z * z)
 
-    grid = [R * k / 400 for k in range(401)]
-    for deg, what in ((5, "FP64"), (2, "FP32")):
+    out = {}
+    for what, R, deg in (("FP64", mp.pi / 2, 7), ("FP32", mp.pi / 4, 2)):
+        Z = R * R
+        grid = [R * k / 400 for k in range(401)]
         ps = fit(p_sin, deg, Z)
         pc = fit(p_cos, deg, Z)
         es = max(abs(mp.sin(r) - (r + r ** 3 * sum(ps[j] * (r * r) ** j for j in range(deg + 1)))) / abs(mp.sin(r))
                  for r in grid[1:])
         ec = max(abs(mp.cos(r) - (1 - r * r / 2 + (r * r) ** 2 * sum(pc[j] * (r * r) ** j for j in range(deg + 1))))
                  for r in grid)
-        print(f"{what} sin P (ascending):", [repr(float(c)) for c in ps])
-        print(f"{what} cos Q (ascending):", [repr(float(c)) for c in pc])
-        print(f"{what} approximation error: sin {float(es):.2e} (relative), cos {float(ec):.2e}")
-    head = mp.mpf(1.5707963267341256)  # pi/2 to 33 bits
-    print("pi/2 split:", repr(float(head)), repr(float(mp.pi / 2 - head)))
+        out[what] = ([float(c) for c in ps], [float(c) for c in pc], float(es), float(ec))
+    return out
+
+
+def splits():
+    """(head, remainder) of pi and of pi/2."""
+    mp.mp.dps = 60
+    h2 = mp.mpf(1.5707963267341256)  # pi/2 to 33 bits
+    return {"pi": (float(2 * h2), float(mp.pi - 2 * h2)), "pi/2": (float(h2), float(mp.pi / 2 - h2))}
+
+
+def main():
+    for what, (ps, pc, es, ec) in coefficients().items():
+        print(f"{what} sin P (ascending):", [repr(c) for c in ps])
+        print(f"{what} cos Q (ascending):", [repr(c) for c in pc])
+        print(f"{what} approximation error: sin {es:.2e} (relative), cos {ec:.2e}")
+    for name, (h, l) in splits().items():
+        print(f"{name} split:", repr(h), repr(l))
 
 
 if __name__ == "__main__":
