@@ -30,6 +30,20 @@ METRIC = "waveforms/s + mode·bin evals/s (fwd, fwd+adjoint) at stated error vs 
 # multiply-add counts 2) plus one sine/cosine pair, two divisions and one
 # reciprocal square root, each of these four counted as one.
 FLOPS_PER_EVAL = 154
+# Of these, the root, its derivatives, the factor of Eq. extendedspa1 and the
+# phase (120) depend on the voice frequency only, so rows with the same (m, n)
+# share them: they are counted once per (voice group, piece, bin).  The
+# amplitude spline, its product with the factor, the two polarization
+# products and the accumulation (34) are counted per row.
+SHARED_FLOPS_PER_EVAL = 120
+ROW_FLOPS_PER_EVAL = FLOPS_PER_EVAL - SHARED_FLOPS_PER_EVAL
+
+
+def algorithmic_flops(evals, group_evals):
+    """Algorithmic flops of a gather launch from its mode-bin and group-bin evaluation counts."""
+    return SHARED_FLOPS_PER_EVAL * group_evals + ROW_FLOPS_PER_EVAL * evals
+
+
 # The adjoint per evaluation: the forward terms it recomputes (the above
 # without the polarization products and the accumulation, 126) and the
 # contraction with the cotangent into its 16 gradient sums (88).
@@ -209,7 +223,8 @@ def batch_measure(ctx, W, fd, dev, B, with_loglike=True, reps=2):
     ctx.profile(False)
     assert ctx.sync_flags() == 0
     evals = ctx.last_eval_count()
-    progress(f"batch: eager mixed batch, gather {g_ms:.0f} ms ({evals} evals)")
+    group_evals = ctx.last_group_eval_count()
+    progress(f"batch: eager mixed batch, gather {g_ms:.0f} ms ({evals} evals, {group_evals} group evals)")
     # graph path: capture on the first call, then replays
     gctx = fd.Context(dev.index if dev.index is not None else 0, graphs=True)
     gctx.waveform_batch(dws, "mixed", outs=outs)
@@ -231,8 +246,8 @@ def batch_measure(ctx, W, fd, dev, B, with_loglike=True, reps=2):
                 errs.append(float(torch.linalg.vector_norm(x.to(torch.complex128) - y)) / nb)
     progress("batch: FP64 reference done")
     g_avg = g_ms / max(g_n, 1) * 1e-3
-    achieved = evals * FLOPS_PER_EVAL / g_avg
-    res = {"waveforms": B, "bins": bins, "evals": evals, "seconds_per_batch": sec,
+    achieved = algorithmic_flops(evals, group_evals) / g_avg
+    res = {"waveforms": B, "bins": bins, "evals": evals, "group_evals": group_evals, "seconds_per_batch": sec,
            "path": "hipGraph replay (captured on the first call, FDEMRI_CTX_BATCH_GRAPHS)",
            "waveforms_per_s": B / sec, "evals_per_s": evals / sec,
            "rel_l2_vs_fp64_max": max(errs), "rel_l2_vs_fp64_median": sorted(errs)[len(errs) // 2],
@@ -241,7 +256,8 @@ def batch_measure(ctx, W, fd, dev, B, with_loglike=True, reps=2):
                         "traffic": profile_traffic(BATCH_TRAFFIC_FILE, "gather_batch_kernel<true, 1, 4, false>"),
                         # no batch autotune runs here: the default block shape, 1 tile per wave
                         "kernel": "gather_batch_kernel<true, 1, 4, false>", "kernel_ms": g_avg * 1e3,
-                        "flops_per_eval": FLOPS_PER_EVAL,
+                        "flops_per_eval": FLOPS_PER_EVAL, "shared_flops_per_group_eval": SHARED_FLOPS_PER_EVAL,
+                        "flops_per_row_eval": ROW_FLOPS_PER_EVAL,
                         "peak_note": ("without packed FP32 (off in this build) FP32 and FP64 vector instructions "
                                       "issue at the same rate, so the FP64 vector peak bounds the mixed path")}}
     del outs
@@ -453,6 +469,7 @@ def main():
     torch.cuda.synchronize()
     assert ctx.sync_flags() == 0
     evals = ctx.last_eval_count()
+    group_evals = ctx.last_group_eval_count()
 
     # timed region: only the gather is bracketed by events (its duration is
     # the roofline's); an event pair around every kernel would add its own
@@ -469,7 +486,7 @@ def main():
     sec = (t1 - t0) / args.steps
     g_ms, g_n = prof["gather"]
     g_avg = g_ms / max(g_n, 1) * 1e-3
-    achieved = evals * FLOPS_PER_EVAL / g_avg
+    achieved = algorithmic_flops(evals, group_evals) / g_avg
     # the set-up kernels' durations, from a few more steps with every class bracketed
     ctx.profile(True)
     for _ in range(10):
@@ -497,7 +514,7 @@ def main():
         elif args.only == "small":
             for name, wl in small_workloads(W):
                 secondary[name] = small_latency(ctx, fd, dev, wl)
-        line = headline(args, w, evals, sec, prof, achieved, bpl, secondary)
+        line = headline(args, w, evals, group_evals, sec, prof, achieved, bpl, secondary)
         print(json.dumps(line), flush=True)
         ctx.close()
         return
@@ -558,7 +575,7 @@ def main():
         secondary[name] = small_latency(ctx, fd, dev, wl)
         small.append((name, wl, secondary[name]["us_per_waveform"] * 1e-6))
 
-    line = headline(args, w, evals, sec, prof, achieved, bpl, secondary)
+    line = headline(args, w, evals, group_evals, sec, prof, achieved, bpl, secondary)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, hp.cpu().numpy(), hc.cpu().numpy(), evals, small)
     print(json.dumps(line), flush=True)
@@ -724,7 +741,7 @@ def gather_traffic(bpl):
     return profile_traffic(TRAFFIC_FILE, f"gather_kernel<false, {bpl}, 4, false>")
 
 
-def headline(args, w, evals, sec, prof, achieved, bpl, secondary):
+def headline(args, w, evals, group_evals, sec, prof, achieved, bpl, secondary):
     bpl = bpl or 1  # without the autotuner: the default block shape, 1 tile per wave
     return {
         "metric": METRIC,
@@ -742,7 +759,7 @@ def headline(args, w, evals, sec, prof, achieved, bpl, secondary):
         "config": {"workload": ("FP64 single waveform, Peters-type toy inspiral M=2e6 mu=20 "
                                 "p0=13 e0=0.45, T=2 yr, dt=10 s; l=2..10, m=0..l, n=-30..30 at 1e-5 "
                                 "power: 3842 modes, K=200 knots, 3155816 bins"),
-                   "modes": w.Nm, "knots": w.K, "bins": w.Nf, "evals": evals,
+                   "modes": w.Nm, "knots": w.K, "bins": w.Nf, "evals": evals, "group_evals": group_evals,
                    "bins_per_lane": bpl},
         "evals_per_s": evals / sec,
         "kernel_ms": {k: (v[0] / max(v[1], 1)) for k, v in prof.items() if v[1]},
@@ -750,6 +767,7 @@ def headline(args, w, evals, sec, prof, achieved, bpl, secondary):
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": gather_traffic(bpl),
                      "traffic_unit": "HBM bytes per launch (read + write)",
                      "kernel": f"gather_kernel<false, {bpl}, 4, false>", "flops_per_eval": FLOPS_PER_EVAL,
+                     "shared_flops_per_group_eval": SHARED_FLOPS_PER_EVAL, "flops_per_row_eval": ROW_FLOPS_PER_EVAL,
                      "issued_fp64_flops_per_eval": profile_traffic(
                          TRAFFIC_FILE, f"gather_kernel<false, {bpl}, 4, false>", "issued_fp64_flops_per_eval")},
         "secondary": secondary,

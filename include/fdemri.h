@@ -407,6 +407,19 @@ fdemri_status fdemri_spa_factor(fdemri_ctx *ctx, fdemri_prec prec, int32_t n, co
 fdemri_status fdemri_last_eval_count(fdemri_ctx *ctx, hipStream_t stream, int64_t *count_out);
 
 /*
+ * Count of the evaluations of the last fdemri_waveform (or batch) call whose
+ * root was solved.  Rows with the same (m, n) have the same voice frequency
+ * m Omega_phi + n Omega_r (Eq. main_wave), hence the same pieces, roots
+ * (Eq. cubic_equation) and per-root factors of Eq. extendedspa1 up to the
+ * amplitude A_lmn and the harmonics; a table of more than 256 and at most
+ * 4096 rows is evaluated by voice groups of such rows, each (piece of a
+ * group, bin) pair once, and this counts those pairs.  Equals
+ * fdemri_last_eval_count when the rows were not grouped.  Synchronises
+ * `stream`.
+ */
+fdemri_status fdemri_last_group_eval_count(fdemri_ctx *ctx, hipStream_t stream, int64_t *count_out);
+
+/*
  * Per-kernel timing for measurement.  While enabled, every kernel launch of
  * this context is bracketed by HIP events recorded on its launch stream.
  * fdemri_profile_read synchronises `stream`, returns the accumulated

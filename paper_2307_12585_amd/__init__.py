@@ -38,6 +38,7 @@ EXPORTED = [
     "fdemri_profile_enable", "fdemri_profile_read", "fdemri_autotune", "fdemri_loglike",
     "fdemri_loglike_batch", "fdemri_select_modes", "fdemri_td_waveform", "fdemri_trajectory",
     "fdemri_signal_band", "fdemri_profile_classes", "fdemri_waveform_noalloc", "fdemri_spa_factor",
+    "fdemri_last_group_eval_count",
 ]
 KERNEL_CLASSES = ["spline", "pieces", "gather", "vjp"]
 
@@ -113,6 +114,8 @@ def lib():
         L.fdemri_loglike_batch.restype = ctypes.c_int
         L.fdemri_last_eval_count.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
         L.fdemri_last_eval_count.restype = ctypes.c_int
+        L.fdemri_last_group_eval_count.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
+        L.fdemri_last_group_eval_count.restype = ctypes.c_int
         L.fdemri_autotune.argtypes = [vp, i32, ctypes.POINTER(WaveformDesc), ctypes.c_int,
                                       ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.POINTER(i32)]
         L.fdemri_autotune.restype = ctypes.c_int
@@ -231,6 +234,13 @@ class Context:
     def last_eval_count(self) -> int:
         v = ctypes.c_int64()
         self._check(self._lib.fdemri_last_eval_count(self._h, _stream(self.device), ctypes.byref(v)))
+        return int(v.value)
+
+    def last_group_eval_count(self) -> int:
+        """Evaluations of the last call whose root was solved (one per voice
+        group of rows with the same (m, n), piece and bin)."""
+        v = ctypes.c_int64()
+        self._check(self._lib.fdemri_last_group_eval_count(self._h, _stream(self.device), ctypes.byref(v)))
         return int(v.value)
 
     def profile(self, enable: bool, classes=None):

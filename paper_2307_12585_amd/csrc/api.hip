@@ -28,7 +28,8 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
                              const double* A, double* acoef, float* acoef32, double* fac, ModeConst* modes,
                              float4* modes32, int2* mode_kr, Piece* pieces, int64_t* evals, int32_t* status,
                              uint32_t* flag_word, const double* Phiphi, const double* Phir, const double* A_in,
-                             int hann, hipStream_t stream);
+                             int hann, int2* gkr, int32_t* gsize, GroupMember* gmem,
+                             GroupMember32* gmem32, hipStream_t stream);
 bool setup_fusable(int K, int Nm, int Nf, uint32_t flags);
 hipError_t launch_setup_fused(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
                               const double* Phiphi, const double* Phir, const double* f, double* tcoef,
@@ -117,8 +118,16 @@ struct fdemri_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   uint32_t* flag_word = nullptr;  // device
-  // per-mode evaluation counts of the last call: (device pointer, Nm) per waveform
-  std::vector<std::pair<int64_t*, int>> last_evals;
+  // per-mode evaluation counts of the last call, per waveform: the device
+  // counts of its Nm rows and, when its rows were grouped, the group sizes
+  // and members by sorted position (device)
+  struct EvalRecord {
+    const int64_t* evals;
+    int Nm;
+    const int32_t* gsize;
+    const GroupMember* gmem;
+  };
+  std::vector<EvalRecord> last_evals;
   // pinned staging of batch records (reused; guarded by an event)
   char* stage = nullptr;
   size_t stage_bytes = 0;
@@ -187,6 +196,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Scratch layout of one waveform.
 struct Layout {
   size_t tcoef, fac, acoef, acoef32, modes, modes32, mode_kr, pieces, evals, status, slots;
+  size_t gkr, gsize, gmem, gmem32;  // voice groups
   size_t gA, PZ, Upart, T3, gPhi, gsc;  // adjoint scratch (0 bytes unless requested)
   size_t ll_partial, ll_edge;           // likelihood scratch (0 bytes unless requested)
   size_t total;
@@ -214,6 +224,11 @@ Layout layout_for(int K, int Nm, bool mixed, bool vjp = false, int ll_tiles = 0,
   L.evals = take((size_t)Nm * sizeof(int64_t));
   L.status = take(4 * sizeof(int32_t));
   L.slots = take(kFusedMaxSlots * sizeof(int32_t));
+  const size_t ng = modes_grouped(Nm) ? (size_t)Nm : 0;
+  L.gkr = take(ng * sizeof(int2));
+  L.gsize = take(ng * sizeof(int32_t));
+  L.gmem = take(ng * sizeof(GroupMember));
+  L.gmem32 = take(mixed ? ng * sizeof(GroupMember32) : 0);
   const size_t units = vjp ? (size_t)Nm * nseg : 0;
   L.gA = take(units * 8 * sizeof(double));
   L.PZ = take(units * 4 * sizeof(double));
@@ -493,7 +508,9 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
       e = launch_setup_flat(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->f, tcoef, d->l, d->m, d->n, d->theta,
                             d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, acoef32,
                             (double*)(w + L.fac), modes, mixed ? (float4*)(w + L.modes32) : nullptr, mode_kr,
-                            pieces, evals, status, c->flag_word, d->Phiphi, d->Phir, d->A, hann, stream);
+                            pieces, evals, status, c->flag_word, d->Phiphi, d->Phir, d->A, hann,
+                            (int2*)(w + L.gkr), (int32_t*)(w + L.gsize), (GroupMember*)(w + L.gmem),
+                            mixed ? (GroupMember32*)(w + L.gmem32) : nullptr, stream);
       // given coefficients were not splined: their FP32 form separately
       if (e == hipSuccess && mixed && given) e = launch_amp32(d->Nm, d->K, d->t, acoef, acoef32, stream);
     }
@@ -515,9 +532,14 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   p.pieces = pieces;
   p.status = status;
   p.modes32 = mixed ? (const float4*)(w + L.modes32) : nullptr;
+  const bool grouped = !fused && modes_grouped(d->Nm);
+  p.gkr = grouped ? (const int2*)(w + L.gkr) : nullptr;
+  p.gsize = grouped ? (const int32_t*)(w + L.gsize) : nullptr;
+  p.gmem = grouped ? (const GroupMember*)(w + L.gmem) : nullptr;
+  p.gmem32 = grouped && mixed ? (const GroupMember32*)(w + L.gmem32) : nullptr;
   p.slots = fused ? slots : nullptr;
   p.nslots = fused ? check_blocks(d->K, d->Nm, d->Nf, d->flags) : 0;
-  c->last_evals.assign(1, {evals, d->Nm});
+  c->last_evals.assign(1, {evals, d->Nm, p.gsize, p.gmem});
   return FDEMRI_OK;
 }
 
@@ -753,21 +775,44 @@ fdemri_status fdemri_spa_factor(fdemri_ctx* c, fdemri_prec prec, int32_t n, cons
   return FDEMRI_OK;
 }
 
-fdemri_status fdemri_last_eval_count(fdemri_ctx* c, hipStream_t stream, int64_t* count_out) {
+// Sums, over the last call's waveforms, the evaluation counts of all rows
+// (groups = false) or of the first row of every voice group (groups = true;
+// a waveform whose rows were not grouped counts every row).
+static fdemri_status sum_last_evals(fdemri_ctx* c, hipStream_t stream, bool groups, int64_t* count_out) {
   if (!c || !count_out) return fail(c, FDEMRI_EINVAL, "NULL argument");
   if (c->last_evals.empty()) return fail(c, FDEMRI_EINVAL, "no waveform evaluated on this context yet");
   (void)hipSetDevice(c->device);
   hipError_t e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
   int64_t s = 0;
-  for (auto& pr : c->last_evals) {
-    std::vector<int64_t> v(pr.second);
-    e = hipMemcpy(v.data(), pr.first, v.size() * sizeof(int64_t), hipMemcpyDeviceToHost);
+  for (const auto& r : c->last_evals) {
+    std::vector<int64_t> v(r.Nm);
+    e = hipMemcpy(v.data(), r.evals, v.size() * sizeof(int64_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(c, e, "eval count read");
-    for (int64_t x : v) s += x;
+    if (!groups || !r.gsize) {
+      for (int64_t x : v) s += x;
+      continue;
+    }
+    std::vector<int32_t> size(r.Nm);
+    std::vector<GroupMember> mem(r.Nm);
+    e = hipMemcpy(size.data(), r.gsize, size.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(mem.data(), r.gmem, mem.size() * sizeof(GroupMember), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "group table read");
+    for (int j = 0; j < r.Nm; ++j) {
+      const int row = mem[j].mode;
+      if (size[j] > 0 && row >= 0 && row < r.Nm) s += v[row];
+    }
   }
   *count_out = s;
   return FDEMRI_OK;
+}
+
+fdemri_status fdemri_last_eval_count(fdemri_ctx* c, hipStream_t stream, int64_t* count_out) {
+  return sum_last_evals(c, stream, false, count_out);
+}
+
+fdemri_status fdemri_last_group_eval_count(fdemri_ctx* c, hipStream_t stream, int64_t* count_out) {
+  return sum_last_evals(c, stream, true, count_out);
 }
 
 }  // extern "C"
@@ -875,6 +920,11 @@ void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc*
     it.pieces = (Piece*)(wb + L.pieces);
     it.evals = (int64_t*)(wb + L.evals);
     it.status = (int32_t*)(wb + L.status);
+    const bool grouped = modes_grouped(d.Nm);
+    it.gkr = grouped ? (int2*)(wb + L.gkr) : nullptr;
+    it.gsize = grouped ? (int32_t*)(wb + L.gsize) : nullptr;
+    it.gmem = grouped ? (GroupMember*)(wb + L.gmem) : nullptr;
+    it.gmem32 = grouped && P.mixed ? (GroupMember32*)(wb + L.gmem32) : nullptr;
     it.hp = P.ll ? nullptr : hp[b];
     it.hc = P.ll ? nullptr : hc[b];
     it.d_p = P.ll ? ll_d_p[b] : nullptr;
@@ -888,7 +938,7 @@ void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc*
     amp_prefix[b + 1] = amp_prefix[b] + d.Nm * (d.K - 1);
     item_prefix[b + 1] = item_prefix[b] + gather_items_per_waveform(d.Nf, c->bpl);
     check_prefix[b + 1] = check_prefix[b] + check_blocks(d.K, d.Nm, d.Nf, d.flags);
-    c->last_evals.push_back({it.evals, d.Nm});
+    c->last_evals.push_back({it.evals, d.Nm, it.gsize, it.gmem});
   }
 }
 

@@ -205,8 +205,8 @@ __device__ __forceinline__ void sincos_mixed(double x, float* sn, float* cs) {
   *cs = ((q + 1) & 2) ? -c1 : c1;
 }
 
-// E = e^{i psi} G and the amplitude spline value A at the root (FP64);
-// w = 2 pi f, (ms, ns) = (s m, s n).
+// E = e^{i psi} G and the amplitude spline value A at the root; w = 2 pi f,
+// (ms, ns) = (s m, s n).
 // The amplitude spline coefficients of one segment, (re, im) pairs in
 // ascending powers: read as a whole by the caller, so that the loads can be
 // issued as soon as the segment is known and their latency overlaps the root
@@ -228,17 +228,28 @@ __device__ __forceinline__ AmpSeg32 load_amp32(const float* __restrict__ ac32_se
   return AmpSeg32{q[0], q[1]};
 }
 
-__device__ __forceinline__ void root_terms64(double f, double w, double tau, int d, double ms, double ns,
-                                             const SegData& S, const AmpSeg64& c, double2& E, double2& A) {
+// E = e^{i psi} G at the root (FP64).
+__device__ __forceinline__ double2 root_E64(double f, double w, double tau, int d, double ms, double ns,
+                                            const SegData& S) {
   const double gd = S.q1 + tau * (2.0 * S.q2 + 3.0 * S.q3 * tau);
   const double gdd = 2.0 * S.q2 + 6.0 * S.q3 * tau;
   const double psi = phase_psi(f, w, tau, ms, ns, S);
   const double2 G = spa_factor64(gd, gdd, d);
   double sn, cs;
   sincos_cw(psi, &sn, &cs);
-  E = make_double2(cs * G.x - sn * G.y, cs * G.y + sn * G.x);
-  A = make_double2(c.c[0].x + tau * (c.c[1].x + tau * (c.c[2].x + tau * c.c[3].x)),
-                   c.c[0].y + tau * (c.c[1].y + tau * (c.c[2].y + tau * c.c[3].y)));
+  return make_double2(cs * G.x - sn * G.y, cs * G.y + sn * G.x);
+}
+
+// The amplitude spline of one segment at tau (FP64).
+__device__ __forceinline__ double2 amp64(const AmpSeg64& c, double tau) {
+  return make_double2(c.c[0].x + tau * (c.c[1].x + tau * (c.c[2].x + tau * c.c[3].x)),
+                      c.c[0].y + tau * (c.c[1].y + tau * (c.c[2].y + tau * c.c[3].y)));
+}
+
+__device__ __forceinline__ void root_terms64(double f, double w, double tau, int d, double ms, double ns,
+                                             const SegData& S, const AmpSeg64& c, double2& E, double2& A) {
+  E = root_E64(f, w, tau, d, ms, ns, S);
+  A = amp64(c, tau);
 }
 
 __device__ __forceinline__ void root_terms64(double f, double w, double tau, int d, double ms, double ns,
@@ -249,17 +260,30 @@ __device__ __forceinline__ void root_terms64(double f, double w, double tau, int
 
 // Mixed precision: root, derivatives, phase and its reduction in FP64; the
 // factor, sincos and the (normalised) amplitude spline in FP32.
-__device__ __forceinline__ void root_terms32(double f, double w, double tau, int d, double ms, double ns,
-                                             const SegData& S, const AmpSeg32& c, float2& E, float2& A) {
+__device__ __forceinline__ float2 root_E32(double f, double w, double tau, int d, double ms, double ns,
+                                           const SegData& S) {
   const double gd = S.q1 + tau * (2.0 * S.q2 + 3.0 * S.q3 * tau);
   const double gdd = 2.0 * S.q2 + 6.0 * S.q3 * tau;
   const double psi = phase_psi(f, w, tau, ms, ns, S);
   const float2 G = spa_factor32(gd, gdd, d);
   float sn, cs;
   sincos_mixed(psi, &sn, &cs);
-  E = make_float2(cs * G.x - sn * G.y, cs * G.y + sn * G.x);
-  const float u = (float)tau * __builtin_amdgcn_rcpf((float)S.h);  // tau / h to FP32 accuracy
-  A = make_float2(c.lo.x + u * (c.lo.z + u * (c.hi.x + u * c.hi.z)), c.lo.y + u * (c.lo.w + u * (c.hi.y + u * c.hi.w)));
+  return make_float2(cs * G.x - sn * G.y, cs * G.y + sn * G.x);
+}
+
+// tau / h to FP32 accuracy: the variable of the normalised FP32 amplitude.
+__device__ __forceinline__ float amp_u32(double tau, const SegData& S) {
+  return (float)tau * __builtin_amdgcn_rcpf((float)S.h);
+}
+
+__device__ __forceinline__ float2 amp32(const AmpSeg32& c, float u) {
+  return make_float2(c.lo.x + u * (c.lo.z + u * (c.hi.x + u * c.hi.z)), c.lo.y + u * (c.lo.w + u * (c.hi.y + u * c.hi.w)));
+}
+
+__device__ __forceinline__ void root_terms32(double f, double w, double tau, int d, double ms, double ns,
+                                             const SegData& S, const AmpSeg32& c, float2& E, float2& A) {
+  E = root_E32(f, w, tau, d, ms, ns, S);
+  A = amp32(c, amp_u32(tau, S));
 }
 
 __device__ __forceinline__ void root_terms32(double f, double w, double tau, int d, double ms, double ns,

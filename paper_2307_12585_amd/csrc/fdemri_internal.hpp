@@ -53,6 +53,31 @@ struct alignas(64) ModeConst {
 };
 static_assert(sizeof(ModeConst) == 64, "ModeConst layout");
 
+// Voice-frequency groups.  Rows with the same (m, n) have the same voice
+// frequency F_V = m F_phi + n F_r, hence the same monotonic pieces, roots,
+// phases and factors G; only the amplitude A_lmn and the harmonics in c_+,
+// c_x differ.  The set-up sorts the rows by (m, n) (then by row index) into
+// groups; the gather solves each root once per group and adds every member's
+// amplitude term.  A member: its row and its fused polarization factors.
+struct alignas(16) GroupMember {
+  double cp_re, cp_im, cx_re, cx_im;
+  int32_t mode, pad[3];
+};
+static_assert(sizeof(GroupMember) == 48, "GroupMember layout");
+struct alignas(16) GroupMember32 {
+  float4 c;  // (c_+, c_x) in FP32
+  int32_t mode, pad[3];
+};
+static_assert(sizeof(GroupMember32) == 32, "GroupMember32 layout");
+
+// Mode tables above this size get a bin envelope (a launch after the set-up;
+// a smaller table is scanned by the gather as cheaply as the launch would
+// cost) and, up to kGroupMaxModes rows (the keys the set-up's sort holds
+// in registers), voice groups.
+constexpr int kEnvelopeMinModes = 256;
+constexpr int kGroupMaxModes = 4096;
+__host__ __device__ inline bool modes_grouped(int Nm) { return Nm > kEnvelopeMinModes && Nm <= kGroupMaxModes; }
+
 // Device pointers of one waveform's prepared tables.
 struct Prepared {
   int32_t K, Nm, Nf;
@@ -70,6 +95,13 @@ struct Prepared {
   const int32_t* status;   // [3] input status of the call (0: valid; see the input checks below),
                            // then the bin envelope [lo, hi] of all voices (the whole grid unless formed)
   const float4* modes32;   // [Nm] (c_+, c_x) of each mode in FP32 (mixed path only)
+  // voice groups (all NULL when the rows are not grouped): per position of
+  // the sorted rows, the group's bin range at its first position (empty
+  // elsewhere), the group size there (0 elsewhere), and the member
+  const int2* gkr;
+  const int32_t* gsize;
+  const GroupMember* gmem;
+  const GroupMember32* gmem32;  // mixed path
   const int32_t* slots;    // [nslots] input status per check workgroup, when the set-up was fused
   int32_t nslots;          // (then status is not read and the envelope is the whole grid); 0 otherwise
 };
@@ -91,6 +123,10 @@ struct WaveItem {
   Piece* pieces;
   int64_t* evals;
   int32_t* status;  // [3] input status of the waveform, bin envelope [lo, hi]
+  int2* gkr;        // voice groups (NULL unless modes_grouped(Nm))
+  int32_t* gsize;
+  GroupMember* gmem;
+  GroupMember32* gmem32;
   void* hp;
   void* hc;
   // fused likelihood of the batch: data, per-bin weights and this waveform's
@@ -120,6 +156,10 @@ __host__ __device__ inline Prepared prepared_of(const WaveItem& w) {
   p.pieces = w.pieces;
   p.status = w.status;
   p.modes32 = w.modes32;
+  p.gkr = w.gkr;
+  p.gsize = w.gsize;
+  p.gmem = w.gmem;
+  p.gmem32 = w.gmem32;
   p.slots = nullptr;
   p.nslots = 0;
   return p;

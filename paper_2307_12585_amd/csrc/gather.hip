@@ -115,21 +115,56 @@ struct Lds {
 // one).
 constexpr int kSecantSteps = 4;
 
-// One (bin, piece) evaluation.  The spline segment holding f is the largest i
-// in [seg_a, seg_b] whose start value precedes f in the direction of the
-// piece (i == seg_a or d g_i < d f; ties go to the lower segment).  It is
-// guessed from the piece's rate, refined by secant steps on the segment
-// index through the knot frequencies at the current segment, and checked
-// against the definition; the rare misses walk to the right segment.
+// The members of a voice group as the evaluation reads them: with gm (and
+// gm32 on the mixed path) the g rows of a sorted group, else the one row
+// `mode` with the factors cP, cX (c32).
+template <bool MIXED>
+struct Members {
+  const kconst GroupMember* gm;
+  const kconst GroupMember32* gm32;
+  int g;
+  int mode;
+  double2 cP, cX;
+  float4 c32;
+};
+
+// The amplitude coefficients of row `mode` (wave-uniform: its base is scalar
+// arithmetic) at segment i (a 32-bit byte offset from that base: one shift).
+template <bool MIXED>
+struct AmpOf;
+template <>
+struct AmpOf<false> {
+  using T = AmpSeg64;
+  __device__ __forceinline__ static T load(const void* __restrict__ amp, int nseg, int mode, int i) {
+    const char* base = (const char*)amp + (size_t)mode * (size_t)nseg * 64;
+    return load_amp64((const double*)(base + ((uint32_t)i << 6)));
+  }
+};
+template <>
+struct AmpOf<true> {
+  using T = AmpSeg32;
+  __device__ __forceinline__ static T load(const void* __restrict__ amp, int nseg, int mode, int i) {
+    const char* base = (const char*)amp + (size_t)mode * (size_t)nseg * 32;
+    return load_amp32((const float*)(base + ((uint32_t)i << 5)));
+  }
+};
+
+// One (bin, piece) evaluation of a voice group.  The spline segment holding f
+// is the largest i in [seg_a, seg_b] whose start value precedes f in the
+// direction of the piece (i == seg_a or d g_i < d f; ties go to the lower
+// segment).  It is guessed from the piece's rate, refined by secant steps on
+// the segment index through the knot frequencies at the current segment, and
+// checked against the definition; the rare misses walk to the right segment.
+// The root and E = e^{i psi} G are formed once; every member then adds
+// cP (A^(s) E) and cX (A^(s) E) with its own amplitude spline A at the root
+// (A^(s): A conjugated when s < 0), in member order.
 //   f, w: the bin frequency and 2 pi f;
 //   ms, ns: s m and s n of the piece, so that |F_V| = ms F_phi + ns F_r;
-//   cP, cX: c_+ and c_x, conjugated when s < 0, so that the contribution is
-//   cP (A^(s) E) and cX (A^(s) E), A^(s) being A conjugated when s < 0.
+//   neg: s < 0 (the factors of the members are then conjugated).
 template <bool MIXED>
 __device__ __forceinline__ void eval_bin(const double f, const double w, const Piece& P, const double ms, const double ns,
-                                         const double2 cP, const double2 cX, const float4 c32,
-                                         const double* __restrict__ ac, const float* __restrict__ ac32, const Lds& L,
-                                         Acc<MIXED>& acc) {
+                                         const bool neg, const Members<MIXED>& M, const void* __restrict__ amp,
+                                         int nseg, const Lds& L, Acc<MIXED>& acc) {
   const double dd_ = P.dd;
   const double fd = dd_ * f;
   // the conversion saturates (and takes NaN to 0); the clamp keeps the guess
@@ -168,15 +203,10 @@ __device__ __forceinline__ void eval_bin(const double f, const double w, const P
     G0 = knot_freq(ms, L.knot(i).Fp, ns, L.knot(i).Fr);
     G1 = knot_freq(ms, L.knot(i + 1).Fp, ns, L.knot(i + 1).Fr);
   }
-  // the segment's amplitude coefficients, requested now so that the loads
-  // are in flight during the root solve (32-bit byte offset from the mode's
-  // wave-uniform base: one shift)
-  AmpSeg64 a64;
-  AmpSeg32 a32;
-  if constexpr (!MIXED)
-    a64 = load_amp64((const double*)((const char*)ac + ((uint32_t)i << 6)));
-  else
-    a32 = load_amp32((const float*)((const char*)ac32 + ((uint32_t)i << 5)));
+  // the first member's amplitude coefficients, requested now so that the
+  // loads are in flight during the root solve
+  const int mode0 = M.gm ? M.gm[0].mode : M.mode;
+  typename AmpOf<MIXED>::T a_next = AmpOf<MIXED>::load(amp, nseg, mode0, i);
   SegData S;
   const klds KnotRec& kr = L.knot(i);
   S.ti = kr.t;
@@ -196,24 +226,50 @@ __device__ __forceinline__ void eval_bin(const double f, const double w, const P
   const double tau = solve_root(f, dd_, S, B);
 
   if constexpr (!MIXED) {
-    double2 E, A;
-    root_terms64(f, w, tau, P.d, ms, ns, S, a64, E, A);
-    const double ay = A.y * P.sd;  // A conjugated on s < 0 pieces
-    const double Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
-    acc.v[0] += cP.x * Wr - cP.y * Wi;
-    acc.v[1] += cP.x * Wi + cP.y * Wr;
-    acc.v[2] += cX.x * Wr - cX.y * Wi;
-    acc.v[3] += cX.x * Wi + cX.y * Wr;
+    const double2 E = root_E64(f, w, tau, P.d, ms, ns, S);
+#pragma unroll 1
+    for (int t = 0; t < M.g; ++t) {
+      const AmpSeg64 a = a_next;
+      // the next member's coefficients are in flight while this one is added
+      if (t + 1 < M.g) a_next = AmpOf<false>::load(amp, nseg, M.gm[t + 1].mode, i);
+      double2 cP = M.cP, cX = M.cX;
+      if (M.gm) {
+        const GroupMember mb = M.gm[t];
+        cP = make_double2(mb.cp_re, neg ? -mb.cp_im : mb.cp_im);
+        cX = make_double2(mb.cx_re, neg ? -mb.cx_im : mb.cx_im);
+      }
+      const double2 A = amp64(a, tau);
+      const double ay = A.y * P.sd;  // A conjugated on s < 0 pieces
+      const double Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
+      acc.v[0] += cP.x * Wr - cP.y * Wi;
+      acc.v[1] += cP.x * Wi + cP.y * Wr;
+      acc.v[2] += cX.x * Wr - cX.y * Wi;
+      acc.v[3] += cX.x * Wi + cX.y * Wr;
+    }
   } else {
-    float2 E, A;
-    root_terms32(f, w, tau, P.d, ms, ns, S, a32, E, A);
-    const float ay = A.y * (float)P.sd;
-    const float Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
-    const float pr = c32.x, pi = c32.y, xr = c32.z, xi = c32.w;
-    acc.add(0, pr * Wr - pi * Wi);
-    acc.add(1, pr * Wi + pi * Wr);
-    acc.add(2, xr * Wr - xi * Wi);
-    acc.add(3, xr * Wi + xi * Wr);
+    const float2 E = root_E32(f, w, tau, P.d, ms, ns, S);
+    const float u = amp_u32(tau, S);
+#pragma unroll 1
+    for (int t = 0; t < M.g; ++t) {
+      const AmpSeg32 a = a_next;
+      if (t + 1 < M.g) a_next = AmpOf<true>::load(amp, nseg, M.gm32[t + 1].mode, i);
+      float4 c32 = M.c32;
+      if (M.gm32) {
+        c32 = M.gm32[t].c;
+        if (neg) {
+          c32.y = -c32.y;
+          c32.w = -c32.w;
+        }
+      }
+      const float2 A = amp32(a, u);
+      const float ay = A.y * (float)P.sd;
+      const float Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
+      const float pr = c32.x, pi = c32.y, xr = c32.z, xi = c32.w;
+      acc.add(0, pr * Wr - pi * Wi);
+      acc.add(1, pr * Wi + pi * Wr);
+      acc.add(2, xr * Wr - xi * Wi);
+      acc.add(3, xr * Wi + xi * Wr);
+    }
   }
 }
 
@@ -297,19 +353,34 @@ __device__ __forceinline__ void write_list(int* list, uint32_t hits, int wbase, 
 }
 
 // One wave's pass over list entries [0, n) for its 64-bin tile [ks, ke]:
-// every piece of every listed mode that has bins in the tile is evaluated by
-// the lanes whose bin lies in the piece's range, in list (mode) order and
-// piece order.  The mode, range and piece tables are read-only here and are
-// read through the constant address space, so that their wave-uniform
-// records come in by scalar loads.
+// every piece of every listed voice group (or, ungrouped, mode) that has bins
+// in the tile is evaluated by the lanes whose bin lies in the piece's range,
+// in list order and piece order.  A group's pieces, range and mode numbers
+// are its first member's.  The mode, range, piece and member tables are
+// read-only here and are read through the constant address space, so that
+// their wave-uniform records come in by scalar loads.
 template <bool MIXED>
 __device__ __forceinline__ void walk_list(const Prepared& p, const void* __restrict__ amp, const int* list, int n,
                                           int ks, int ke, double f, double w, const Lds& L, Acc<MIXED>& acc) {
   const int lane = threadIdx.x & 63;
   const int k = ks + lane;
   const int nseg = p.K - 1;
+  const bool grouped = p.gmem != nullptr;
   for (int e = 0; e < n; ++e) {
-    const int mode = __builtin_amdgcn_readfirstlane(list[e]);
+    // a position of the sorted rows (grouped) or a row
+    const int j = __builtin_amdgcn_readfirstlane(list[e]);
+    Members<MIXED> M;
+    M.gm = nullptr;
+    M.gm32 = nullptr;
+    M.g = 1;
+    M.mode = j;
+    if (grouped) {
+      M.gm = (const kconst GroupMember*)p.gmem + j;
+      if constexpr (MIXED) M.gm32 = (const kconst GroupMember32*)p.gmem32 + j;
+      M.g = ((const kconst int32_t*)p.gsize)[j];
+      M.mode = M.gm[0].mode;
+    }
+    const int mode = M.mode;
     // the whole 64-B record in one scalar load: its bin range decides, its
     // constants follow (a test on the range table first, with short-circuit
     // evaluation, would cost dependent round trips per entry)
@@ -325,20 +396,19 @@ __device__ __forceinline__ void walk_list(const Prepared& p, const void* __restr
       if (k >= ka && k <= kz) {
         const bool neg = P.s < 0;
         const double ms = neg ? -md.m : md.m, ns = neg ? -md.n : md.n;
-        const double2 cP = make_double2(md.cp_re, neg ? -md.cp_im : md.cp_im);
-        const double2 cX = make_double2(md.cx_re, neg ? -md.cx_im : md.cx_im);
-        float4 c32 = make_float4(0.f, 0.f, 0.f, 0.f);
-        if constexpr (MIXED) {
-          // the FP32 mode constants, wave-uniform (scalar load), conjugated on s < 0
-          c32 = ((const kconst float4*)p.modes32)[mode];
-          if (neg) {
-            c32.y = -c32.y;
-            c32.w = -c32.w;
+        if (!grouped) {
+          M.cP = make_double2(md.cp_re, neg ? -md.cp_im : md.cp_im);
+          M.cX = make_double2(md.cx_re, neg ? -md.cx_im : md.cx_im);
+          if constexpr (MIXED) {
+            // the FP32 mode constants, wave-uniform (scalar load), conjugated on s < 0
+            M.c32 = ((const kconst float4*)p.modes32)[mode];
+            if (neg) {
+              M.c32.y = -M.c32.y;
+              M.c32.w = -M.c32.w;
+            }
           }
         }
-        const double* ac = MIXED ? nullptr : (const double*)amp + (size_t)mode * nseg * 8;
-        const float* ac32 = MIXED ? (const float*)amp + (size_t)mode * nseg * 8 : nullptr;
-        eval_bin<MIXED>(f, w, P, ms, ns, cP, cX, c32, ac, ac32, L, acc);
+        eval_bin<MIXED>(f, w, P, ms, ns, neg, M, amp, nseg, L, acc);
       }
     }
   }
@@ -492,7 +562,7 @@ __device__ __forceinline__ void process_block(const Prepared& p, const void* __r
   auto scan = [&](int base) {
     wbase = base + wave * CHUNK;
     hits = 0;
-    const kconst int2* kr = (const kconst int2*)p.mode_kr + wbase + lane;
+    const kconst int2* kr = (const kconst int2*)(p.gkr ? p.gkr : p.mode_kr) + wbase + lane;
     const int lim = p.Nm - wbase - lane;
 #pragma unroll 4
     for (int j = 0; j < kModesPerLane; ++j) {

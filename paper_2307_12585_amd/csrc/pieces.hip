@@ -19,6 +19,7 @@
 //   c_+ = scale/2 (Y_lm + (-1)^l conj Y_{l,-m}),  c_x = i scale/2 (Y_lm - (-1)^l conj Y_{l,-m}),
 // where (.)^(s) conjugates on pieces with F_V < 0 and
 // E = e^{i(2 pi f t - s Phi_V)} G(s dF_V/dt, s d2F_V/dt2) for the root t.
+#include <algorithm>
 #include <climits>
 
 #include "fdemri_internal.hpp"
@@ -192,6 +193,12 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Rows outside the harmonics' range (or, unless the caller lists both signs,
+// with m < 0) contribute nothing and are flagged.
+__device__ __forceinline__ bool rejected_row(int l, int m, uint32_t flags) {
+  return l < 2 || l > kMaxL || m > l || m < -l || (m < 0 && !(flags & FDEMRI_NO_PARTNERS));
+}
+
 // Mode constants and monotonic pieces of one voice, computed by one full
 // wavefront: lanes walk 64 spline segments at a time; the running direction
 // is carried across segments by a ballot scan, the events are compacted in
@@ -213,8 +220,7 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
   // ---- ordered events over all segments
   int n_ev = 0;           // events found so far (may exceed kMaxEvents)
   int carry_dir = 0;      // last non-zero direction before the current chunk
-  // rows outside the harmonics' range contribute nothing and are flagged
-  const bool bad_mode = li < 2 || li > kMaxL || mi > li || mi < -li || (mi < 0 && !(a.flags & FDEMRI_NO_PARTNERS));
+  const bool bad_mode = rejected_row(li, mi, a.flags);
   const bool flat_voice = (mi == 0 && ni == 0) || bad_mode;
   if (!flat_voice) {
     for (int c0 = 0; c0 < nseg; c0 += 64) {
@@ -343,46 +349,283 @@ __device__ void piece_mode_wave(const PieceArgs& a, const int mu, Event* ev) {
   }
 }
 
+// ---- voice groups
+// Rows are grouped by (m, n) through a 32-bit sort key: bits 31..25 hold
+// m + 64, bits 24..13 n + 2048, bits 12..0 the row (kGroupMaxModes <= 2^13).
+// A row that can join no group, because the set-up rejects it (it gets no
+// pieces) or its n does not fit the 12-bit field, has the m-field kAlone and
+// n-field 0: it sorts after every group and stays on its own.  Keys are
+// distinct, so their order (the sort is not stable) is unique: members
+// follow each other in row order and a group's first member is its lowest
+// row.
+static_assert(kGroupMaxModes <= 1 << 13, "row field of the group key");
+constexpr uint32_t kAlone = 127u;
+
+__device__ __forceinline__ uint32_t group_key(int l, int m, int n, uint32_t flags, int row) {
+  if (rejected_row(l, m, flags) || n < -2048 || n > 2047) return (kAlone << 25) | (uint32_t)row;
+  return ((uint32_t)(m + 64) << 25) | ((uint32_t)(n + 2048) << 13) | (uint32_t)row;
+}
+
+// Keys the sort of Nm rows holds: a power of two >= Nm, and at least two per
+// thread.
+__host__ __device__ inline int group_sort_size(int Nm, int NT) {
+  int n2 = 2 * NT;
+  while (n2 < Nm) n2 <<= 1;
+  return n2;
+}
+
+__device__ __forceinline__ void compare_exchange(uint32_t& a, uint32_t& b, bool up) {
+  const uint32_t lo = min(a, b), hi = max(a, b);
+  a = up ? lo : hi;
+  b = up ? hi : lo;
+}
+
+// Stage of stride S < KPL of the bitonic merge of blocks of `size` keys: both
+// partners are in the thread's registers.
+template <int KPL, int S>
+__device__ __forceinline__ void sort_stage_in_lane(uint32_t (&k)[KPL], int base, int size) {
+  if constexpr (S < KPL) {
+#pragma unroll
+    for (int q = 0; q < KPL; ++q)
+      if ((q & S) == 0) compare_exchange(k[q], k[q + S], ((base + q) & size) == 0);
+  }
+}
+
+// Sort of the rows' keys by one workgroup of NT threads, KPL keys per thread
+// in registers (thread t holds positions t KPL .. t KPL + KPL - 1; n2 = NT KPL
+// keys, padded with ~0): a bitonic network whose stages exchange partners
+// within a thread's registers (stride < KPL), across the lanes of a wave
+// (shuffles), or, for strides of a wave's keys or more, through LDS (lds, n2
+// words).  Then, from the sorted keys, the group size at every first
+// position of a group (0 elsewhere) into gsize and the row of every position
+// into gmem[].mode.  The workgroup runs at raised wave priority: it shares
+// its SIMDs with the set-up's other work, and the gather waits for it.
+template <int NT, int KPL>
+__device__ void group_sort_kpl(const int32_t* __restrict__ l, const int32_t* __restrict__ m,
+                               const int32_t* __restrict__ n, uint32_t flags, int Nm, uint32_t* lds,
+                               int32_t* __restrict__ gsize, GroupMember* __restrict__ gmem) {
+  constexpr int N2 = NT * KPL, WK = 64 * KPL, NW = NT / 64;
+  static_assert(N2 <= kGroupMaxModes && KPL <= 32, "sort size");
+  __shared__ int wmin[NW];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int base = t * KPL;
+  uint32_t k[KPL];
+#pragma unroll
+  for (int q = 0; q < KPL; ++q) {
+    const int j = base + q;
+    k[q] = j < Nm ? group_key(l[j], m[j], n[j], flags, j) : ~0u;
+  }
+  for (int size = 2; size <= N2; size <<= 1) {
+    for (int s = size >> 1; s > 0; s >>= 1) {
+      if (s >= WK) {
+        __syncthreads();  // the previous stage's readers are done
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) lds[base + q] = k[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) {
+          const int i = base + q;
+          const uint32_t o = lds[i ^ s];
+          const bool keep_min = ((i & s) == 0) == ((i & size) == 0);
+          k[q] = keep_min ? min(k[q], o) : max(k[q], o);
+        }
+      } else if (s >= KPL) {
+        const int d = s / KPL;  // partner lane: lane ^ d, same register
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) {
+          const int i = base + q;
+          const uint32_t o = (uint32_t)__shfl_xor((int)k[q], d, 64);
+          const bool keep_min = ((i & s) == 0) == ((i & size) == 0);
+          k[q] = keep_min ? min(k[q], o) : max(k[q], o);
+        }
+      } else if (s == 1) {
+        sort_stage_in_lane<KPL, 1>(k, base, size);
+      } else if (s == 2) {
+        sort_stage_in_lane<KPL, 2>(k, base, size);
+      } else if (s == 4) {
+        sort_stage_in_lane<KPL, 4>(k, base, size);
+      } else if (s == 8) {
+        sort_stage_in_lane<KPL, 8>(k, base, size);
+      } else {
+        sort_stage_in_lane<KPL, 16>(k, base, size);
+      }
+    }
+  }
+  // first positions of groups (a padding position counts as one)
+  __syncthreads();
+  lds[base + KPL - 1] = k[KPL - 1];  // each thread's last key, for its successor
+  __syncthreads();
+  uint32_t prev = base > 0 ? lds[base - 1] : 0u;
+  uint32_t first = 0;
+  int my_first = INT_MAX;
+#pragma unroll
+  for (int q = 0; q < KPL; ++q) {
+    const int j = base + q;
+    const bool f = j >= Nm || j == 0 || (k[q] >> 25) == kAlone || (prev >> 13) != (k[q] >> 13);
+    if (f) {
+      first |= 1u << q;
+      my_first = min(my_first, j);
+    }
+    prev = k[q];
+  }
+  // the nearest first position after this thread's: a suffix minimum
+  int v = my_first;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_down(v, off, 64);
+    if (lane + off < 64) v = min(v, o);
+  }
+  if (lane == 0) wmin[wave] = v;
+  int next = __shfl_down(v, 1, 64);
+  if (lane == 63) next = INT_MAX;
+  __syncthreads();
+  for (int w = wave + 1; w < NW; ++w) next = min(next, wmin[w]);
+  int e = min(next, Nm);
+#pragma unroll
+  for (int q = KPL - 1; q >= 0; --q) {
+    const int j = base + q;
+    const bool f = (first >> q) & 1u;
+    if (j < Nm) {
+      gsize[j] = f ? e - j : 0;
+      gmem[j].mode = (int)(k[q] & (uint32_t)(kGroupMaxModes - 1));
+    }
+    if (f) e = j;
+  }
+}
+
+// The voice groups' sort (gsize, gmem[].mode) of Nm rows by one workgroup of
+// NT threads, LDS lds of group_sort_size(Nm, NT) words.
+template <int NT>
+__device__ void group_sort(const int32_t* __restrict__ l, const int32_t* __restrict__ m,
+                           const int32_t* __restrict__ n, uint32_t flags, int Nm, uint32_t* lds,
+                           int32_t* __restrict__ gsize, GroupMember* __restrict__ gmem) {
+  __builtin_amdgcn_s_setprio(3);
+  switch (group_sort_size(Nm, NT) / NT) {
+    case 2:
+      group_sort_kpl<NT, 2>(l, m, n, flags, Nm, lds, gsize, gmem);
+      break;
+    case 4:
+      group_sort_kpl<NT, 4>(l, m, n, flags, Nm, lds, gsize, gmem);
+      break;
+    case 8:
+      if constexpr (NT * 8 <= kGroupMaxModes) group_sort_kpl<NT, 8>(l, m, n, flags, Nm, lds, gsize, gmem);
+      break;
+    case 16:
+      if constexpr (NT * 16 <= kGroupMaxModes) group_sort_kpl<NT, 16>(l, m, n, flags, Nm, lds, gsize, gmem);
+      break;
+    case 32:
+      if constexpr (NT * 32 <= kGroupMaxModes) group_sort_kpl<NT, 32>(l, m, n, flags, Nm, lds, gsize, gmem);
+      break;
+  }
+  __builtin_amdgcn_s_setprio(0);
+}
+
+// Position j of the voice groups, once the sort and the row's mode table are
+// written: the group's bin range at its first position (empty elsewhere),
+// the member's polarization factors (gsize[j] and gmem[j].mode are the
+// sort's); returns the bin range written to gkr[j].
+__device__ __forceinline__ int2 group_fill(int j, const ModeConst* __restrict__ modes,
+                                           const float4* __restrict__ modes32, const int2* __restrict__ mode_kr,
+                                           int2* __restrict__ gkr, const int32_t* __restrict__ gsize,
+                                           GroupMember* __restrict__ gmem, GroupMember32* __restrict__ gmem32) {
+  const int row = gmem[j].mode;
+  const int2 kr = gsize[j] > 0 ? mode_kr[row] : make_int2(INT_MAX, -1);
+  gkr[j] = kr;
+  const ModeConst md = modes[row];
+  gmem[j] = GroupMember{md.cp_re, md.cp_im, md.cx_re, md.cx_im, row, {0, 0, 0}};
+  if (gmem32) gmem32[j] = GroupMember32{modes32[row], row, {0, 0, 0}};
+  return kr;
+}
+
 // Bin envelope [env[0], env[1]] of one waveform's voices (min and max over
 // the non-empty per-mode ranges; {INT_MAX, -1} when all are empty), by one
-// workgroup in a fixed reduction order.  The gather skips the blocks outside
-// it without reading the mode table.
-__device__ __forceinline__ void envelope_block(const int2* __restrict__ mode_kr, int Nm, int32_t* __restrict__ env) {
-  __shared__ int s_lo[4], s_hi[4];
+// workgroup of kGroupThreads threads.  The gather skips the blocks outside
+// the envelope without reading the mode table.
+constexpr int kGroupThreads = 1024;
+
+// Minimum of lo and maximum of hi over a workgroup of NT threads (valid in
+// thread 0).
+template <int NT>
+__device__ __forceinline__ void block_min_max(int& lo, int& hi) {
+  constexpr int NW = NT / 64;
+  __shared__ int s_lo[NW], s_hi[NW];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    lo = min(lo, __shfl_xor(lo, off, 64));
+    hi = max(hi, __shfl_xor(hi, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_lo[threadIdx.x >> 6] = lo;
+    s_hi[threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < NW; ++w) {
+      lo = min(lo, s_lo[w]);
+      hi = max(hi, s_hi[w]);
+    }
+  }
+}
+
+__device__ void envelope_block(const int2* __restrict__ mode_kr, int Nm, int32_t* __restrict__ env) {
   int lo = INT_MAX, hi = -1;
-  for (int mu = threadIdx.x; mu < Nm; mu += 256) {
+  for (int mu = threadIdx.x; mu < Nm; mu += kGroupThreads) {
     const int2 r = mode_kr[mu];
     if (r.x <= r.y) {
       lo = min(lo, r.x);
       hi = max(hi, r.y);
     }
   }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    lo = min(lo, __shfl_xor(lo, off, 64));
-    hi = max(hi, __shfl_xor(hi, off, 64));
-  }
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    s_lo[wave] = lo;
-    s_hi[wave] = hi;
-  }
-  __syncthreads();
+  block_min_max<kGroupThreads>(lo, hi);
   if (threadIdx.x == 0) {
-    env[0] = min(min(s_lo[0], s_lo[1]), min(s_lo[2], s_lo[3]));
-    env[1] = max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3]));
+    env[0] = lo;
+    env[1] = hi;
   }
 }
 
-__global__ __launch_bounds__(256) void envelope_kernel(const int2* __restrict__ mode_kr, int Nm,
-                                                       int32_t* __restrict__ env) {
+// One waveform's envelope (more than kGroupMaxModes rows: not grouped).
+__global__ __launch_bounds__(kGroupThreads) void envelope_kernel(const int2* __restrict__ mode_kr, int Nm,
+                                                                 int32_t* __restrict__ env) {
   envelope_block(mode_kr, Nm, env);
 }
 
-// Batched: one workgroup per waveform.
-__global__ __launch_bounds__(256) void envelope_batch_kernel(const WaveItem* __restrict__ items) {
+// One grouped waveform after its set-up launch, one position per thread: the
+// groups' tables and the envelope, as the minimum and maximum over the
+// groups' ranges into env (set to {INT_MAX, -1} by the sort).
+constexpr int kFillThreads = 256;
+__global__ __launch_bounds__(kFillThreads) void group_fill_kernel(const ModeConst* __restrict__ modes,
+                                                                  const float4* __restrict__ modes32,
+                                                                  const int2* __restrict__ mode_kr, int Nm,
+                                                                  int32_t* __restrict__ env, int2* gkr,
+                                                                  const int32_t* gsize, GroupMember* gmem,
+                                                                  GroupMember32* gmem32) {
+  const int j = (int)blockIdx.x * kFillThreads + (int)threadIdx.x;
+  int lo = INT_MAX, hi = -1;
+  if (j < Nm) {
+    const int2 kr = group_fill(j, modes, modes32, mode_kr, gkr, gsize, gmem, gmem32);
+    if (kr.x <= kr.y) {
+      lo = kr.x;
+      hi = kr.y;
+    }
+  }
+  block_min_max<kFillThreads>(lo, hi);
+  if (threadIdx.x == 0 && lo <= hi) {
+    atomicMin(&env[0], lo);
+    atomicMax(&env[1], hi);
+  }
+}
+
+// Batched: one workgroup per waveform, which also sorts the rows of a
+// grouped waveform.
+__global__ __launch_bounds__(kGroupThreads) void envelope_batch_kernel(const WaveItem* __restrict__ items) {
+  __shared__ uint32_t key[kGroupMaxModes];
   const WaveItem& w = items[blockIdx.x];
   envelope_block(w.mode_kr, w.Nm, w.status + 1);
+  if (!w.gkr) return;
+  group_sort<kGroupThreads>(w.l, w.m, w.n, w.flags, w.Nm, key, w.gsize, w.gmem);
+  __syncthreads();  // the sort's gsize and gmem[].mode, written to global memory
+  for (int j = threadIdx.x; j < w.Nm; j += kGroupThreads)
+    group_fill(j, w.modes, w.modes32, w.mode_kr, w.gkr, w.gsize, w.gmem, w.gmem32);
 }
 
 // Inputs of one waveform's checks (device pointers of the caller's arrays).
@@ -447,9 +690,6 @@ __device__ void check_block(const CheckArgs& c, int blk, int32_t* status, uint32
     atomicOr(flag_word, (uint32_t)FDEMRI_FLAG_BAD_INPUT);
   }
 }
-
-// Mode tables up to this size are not given a bin envelope (single waveform).
-constexpr int kEnvelopeMinModes = 256;
 
 // Batched pieces: one wavefront per mode, kPieceWaves modes per workgroup.
 constexpr int kPieceWaves = 4;
@@ -527,7 +767,7 @@ hipError_t launch_pieces_batch(const WaveItem* items, int B, const int32_t* mode
   const int blocks = (total_modes + kPieceWaves - 1) / kPieceWaves;
   pieces_batch_kernel<<<blocks + total_checks, 64 * kPieceWaves, 0, stream>>>(
       items, B, mode_prefix, total_modes, blocks, check_prefix, hann, flag_word);
-  envelope_batch_kernel<<<B, 256, 0, stream>>>(items);
+  envelope_batch_kernel<<<B, kGroupThreads, 0, stream>>>(items);
   return hipGetLastError();
 }
 
@@ -541,34 +781,59 @@ template <int NT>
 __global__ __launch_bounds__(NT) void setup_kernel(PieceArgs a, int piece_blocks, int amp_blocks,
                                                    const double* __restrict__ A, double* __restrict__ acoef,
                                                    float* __restrict__ acoef32, double* fac, CheckArgs c,
-                                                   int32_t* __restrict__ status) {
+                                                   int32_t* __restrict__ status, int32_t* __restrict__ gsize,
+                                                   GroupMember* __restrict__ gmem, int32_t* __restrict__ env) {
   constexpr int W = NT / 64;
-  // LDS of either part: the spline's tables or the waves' event buffers
-  constexpr size_t kBytes = sizeof(SplineLds<NT>) > sizeof(Event) * W * kMaxEvents ? sizeof(SplineLds<NT>)
-                                                                                     : sizeof(Event) * W * kMaxEvents;
-  __shared__ double lds[kBytes / sizeof(double)];
-  if ((int)blockIdx.x < piece_blocks) {
+  // LDS (setup_lds_bytes) of any part: the spline's tables, the waves' event
+  // buffers or the sort's keys
+  extern __shared__ double lds[];
+  int b = (int)blockIdx.x;
+  if (gsize) {
+    // workgroup 0 sorts the rows into voice groups, concurrently with the rest
+    if (b == 0) {
+      if (threadIdx.x == 0) {
+        env[0] = INT_MAX;  // for the fill's atomics
+        env[1] = -1;
+      }
+      group_sort<NT>(a.l, a.m, a.n, a.flags, a.Nm, (uint32_t*)lds, gsize, gmem);
+      return;
+    }
+    --b;
+  }
+  if (b < piece_blocks) {
     const int wave = threadIdx.x >> 6;
-    const int mu = (int)blockIdx.x * W + wave;
+    const int mu = b * W + wave;
     if (mu < a.Nm) piece_mode_wave(a, mu, (Event*)lds + wave * kMaxEvents);
     return;
   }
-  if ((int)blockIdx.x >= piece_blocks + amp_blocks) {
-    check_block(c, (int)blockIdx.x - piece_blocks - amp_blocks, status, a.flag_word);
+  if (b >= piece_blocks + amp_blocks) {
+    check_block(c, b - piece_blocks - amp_blocks, status, a.flag_word);
     return;
   }
-  const int s0 = 4 + ((int)blockIdx.x - piece_blocks) * kSeriesPerBlock;
+  const int s0 = 4 + (b - piece_blocks) * kSeriesPerBlock;
   // series 4 + mu only (the trajectory arguments are never read here), with
   // the knot matrix's reduction factors from the trajectory splines
   spline_block<NT, true>(*(SplineLds<NT>*)lds, s0, 4 + a.Nm, a.K, a.t, a.Fphi, a.Fr, a.Fphi, a.Fr, A, acoef, acoef,
                          fac, acoef32);
 }
 
+// Dynamic LDS of setup_kernel<NT> (with the sort of Nm rows when grouped).
+template <int NT>
+size_t setup_lds_bytes(int Nm, bool grouped) {
+  constexpr size_t W = NT / 64;
+  size_t bytes = sizeof(SplineLds<NT>) > sizeof(Event) * W * kMaxEvents ? sizeof(SplineLds<NT>)
+                                                                         : sizeof(Event) * W * kMaxEvents;
+  if (grouped) bytes = std::max(bytes, sizeof(uint32_t) * (size_t)group_sort_size(Nm, NT));
+  return bytes;
+}
+
 // The piece tables, unless A is NULL the amplitude splines of Nm modes
 // (acoef [Nm][K-1][8]; with acoef32 also the FP32 normalised form, and the
 // FP32 mode constants in modes32), and the input checks (A_in: the caller's
 // amplitude array, knot values or coefficients; hann: the grid must be the
-// Hann kernel's DFT grid), in one launch.  The trajectory
+// Hann kernel's DFT grid), in one launch; then, for more than
+// kEnvelopeMinModes modes, the bin envelope and (modes_grouped) the voice
+// groups in gkr, gsize, gmem and gmem32 (mixed).  The trajectory
 // spline coefficients tcoef and the knot matrix's reduction factors fac,
 // written by launch_spline with the same thread count, must be in place
 // (stream order).
@@ -578,7 +843,8 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
                              const double* A, double* acoef, float* acoef32, double* fac, ModeConst* modes,
                              float4* modes32, int2* mode_kr, Piece* pieces, int64_t* evals, int32_t* status,
                              uint32_t* flag_word, const double* Phiphi, const double* Phir, const double* A_in,
-                             int hann, hipStream_t stream) {
+                             int hann, int2* gkr, int32_t* gsize, GroupMember* gmem, GroupMember32* gmem32,
+                             hipStream_t stream) {
   PieceArgs a;
   a.K = K;
   a.Nm = Nm;
@@ -604,19 +870,28 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
   const int amp_blocks = A ? (Nm + kSeriesPerBlock - 1) / kSeriesPerBlock : 0;
   const int checks = check_blocks(K, Nm, Nf, flags);
   const CheckArgs c{K, Nm, Nf, flags, hann, t, Fphi, Fr, Phiphi, Phir, A_in, f};
+  const bool grouped = modes_grouped(Nm);
+  const int sb = grouped ? 1 : 0;  // the sort's workgroup
+  int32_t* sort_gsize = grouped ? gsize : nullptr;
   if (K <= 256) {
     const int pb = (Nm + 3) / 4;
-    setup_kernel<256><<<pb + amp_blocks + checks, 256, 0, stream>>>(a, pb, amp_blocks, A, acoef, acoef32, fac, c,
-                                                                     status);
+    setup_kernel<256><<<sb + pb + amp_blocks + checks, 256, setup_lds_bytes<256>(Nm, grouped), stream>>>(
+        a, pb, amp_blocks, A, acoef, acoef32, fac, c, status, sort_gsize, gmem, status + 1);
   } else {
     const int pb = (Nm + 7) / 8;
-    setup_kernel<512><<<pb + amp_blocks + checks, 512, 0, stream>>>(a, pb, amp_blocks, A, acoef, acoef32, fac, c,
-                                                                     status);
+    setup_kernel<512><<<sb + pb + amp_blocks + checks, 512, setup_lds_bytes<512>(Nm, grouped), stream>>>(
+        a, pb, amp_blocks, A, acoef, acoef32, fac, c, status, sort_gsize, gmem, status + 1);
   }
-  // a large mode table gets its bin envelope (one small launch), so that the
-  // gather skips the blocks no voice reaches without scanning the table; a
-  // small table is scanned as cheaply as the launch would cost
-  if (Nm > kEnvelopeMinModes) envelope_kernel<<<1, 256, 0, stream>>>(mode_kr, Nm, status + 1);
+  // a large mode table gets its bin envelope (and, up to kGroupMaxModes
+  // rows, its voice groups from the set-up's sort, one position per thread),
+  // so that the gather skips the blocks no voice reaches without scanning the
+  // table and solves each root once per group; a small table is scanned as
+  // cheaply as the launch would cost
+  if (grouped)
+    group_fill_kernel<<<(Nm + kFillThreads - 1) / kFillThreads, kFillThreads, 0, stream>>>(
+        modes, modes32, mode_kr, Nm, status + 1, gkr, gsize, gmem, gmem32);
+  else if (Nm > kEnvelopeMinModes)
+    envelope_kernel<<<1, kGroupThreads, 0, stream>>>(mode_kr, Nm, status + 1);
   return hipGetLastError();
 }
 

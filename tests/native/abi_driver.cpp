@@ -68,6 +68,8 @@ int nodevice() {
   check(std::strlen(fdemri_last_error(nullptr)) > 0, "last error of a NULL context");
   uint32_t fl = 0;
   check(fdemri_sync_flags(nullptr, nullptr, &fl) == FDEMRI_EINVAL, "sync flags on a NULL context");
+  int64_t count = 0;
+  check(fdemri_last_group_eval_count(nullptr, nullptr, &count) == FDEMRI_EINVAL, "group count on a NULL context");
   fdemri_destroy(nullptr);
   check(fdemri_create(nullptr, 0, 0) != FDEMRI_OK, "create without an output pointer");
   fdemri_ctx* c = nullptr;
@@ -198,6 +200,10 @@ int device() {
   check(finite && norm > 0.0, "fp64 output finite and nonzero");
   int64_t evals = 0;
   check(fdemri_last_eval_count(c, nullptr, &evals) == FDEMRI_OK && evals > 0, "evaluation count");
+  int64_t group_evals = 0;
+  check(fdemri_last_group_eval_count(c, nullptr, &group_evals) == FDEMRI_OK && group_evals > 0 &&
+            group_evals <= evals,
+        "group evaluation count");
 
   check(fdemri_waveform(c, &d.desc, FDEMRI_MIXED, mp, mc, nullptr) == FDEMRI_OK, "waveform mixed");
   {

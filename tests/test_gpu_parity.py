@@ -105,8 +105,9 @@ def _replicas(w, sel, reps, seed, real=False):
 
 
 def test_active_list_in_windows(ctx):
-    """520 voices active in the same bins: more than the 512-entry active list
-    of a workgroup, which is then built and walked window by window."""
+    """520 rows of one voice, active in the same bins: one voice group of 520
+    members (more than the 512-entry active list of a workgroup would hold as
+    single rows)."""
     w = W.inspiral_20_modes()
     r, _ = _replicas(w, np.array([8]), 520, 5)
     ho = oracle.waveform(r)
@@ -138,6 +139,107 @@ def test_mode_table_scanned_in_rounds(ctx):
     for q in range(2):
         assert support_mismatch(hg[q], ref[q]) == 0
         assert rel_l2(hg[q], ref[q]) <= 1e-12
+
+
+def test_more_rows_than_groups_hold(ctx):
+    """4200 rows (more than the 4096 that are sorted into voice groups, so
+    each row is solved on its own) active in the same bins: the workgroups'
+    active lists take more than 512 entries and are walked window by window.
+    The sum equals the single row's GPU waveform times the sum of the (real)
+    factors."""
+    w = W.inspiral_20_modes()
+    w.f = w.f[:70_000]
+    r, c = _replicas(w, np.array([8]), 4200, 7, real=True)
+    r.f = w.f
+    hg = gpu_waveform(ctx, r)
+    one = W.inspiral_20_modes()
+    one.l, one.m, one.n, one.A, one.f = w.l[8:9], w.m[8:9], w.n[8:9], w.A[8:9], w.f
+    h1 = gpu_waveform(ctx, one)
+    assert np.count_nonzero(h1[0]) > 256
+    for q in range(2):
+        ref = np.sum(c) * h1[q]
+        assert support_mismatch(hg[q], ref) == 0
+        assert rel_l2(hg[q], ref) <= 1e-12
+
+
+def _rows(w, idx, n_shift=0):
+    import copy
+    r = copy.copy(w)
+    r.l, r.m, r.n, r.A = w.l[idx], w.m[idx], w.n[idx] + n_shift, w.A[idx]
+    return r
+
+
+@pytest.mark.parametrize("K", [200, 300])
+def test_voice_groups_row_order(ctx, K):
+    """Rows with the same (m, n) share one root per bin (voice groups, set up
+    by a sort whose workgroup size follows the knot count): a permutation of
+    the rows changes only the order of the sum, within rounding, FP64 and
+    mixed."""
+    w = W.inspiral_3842_modes(K=K)
+    assert 256 < w.Nm <= 4096
+    perm = np.random.default_rng(21).permutation(w.Nm)
+    wp = _rows(w, perm)
+    for prec, tol in (("fp64", 1e-13), ("mixed", 1e-6)):
+        h0 = gpu_waveform(ctx, w, prec=prec)
+        h1 = gpu_waveform(ctx, wp, prec=prec)
+        for a, b in zip(h0, h1):
+            assert support_mismatch(a, b) == 0
+            err = rel_l2(b.astype(np.complex128), a.astype(np.complex128))
+            print(f"K={K} {prec}: rel L2 {err:.3e}")
+            assert err <= tol
+
+
+def test_group_eval_count(ctx):
+    """fdemri_last_group_eval_count counts the (piece, bin) pairs of one row
+    per distinct (m, n): the oracle's count over those rows; the row count
+    stays the oracle's count over all rows."""
+    w = W.inspiral_3842_modes()
+    f = w.f[::97]
+    gpu_waveform(ctx, w, f=f)
+    ev, gev = ctx.last_eval_count(), ctx.last_group_eval_count()
+    _, first = np.unique(np.stack([w.m, w.n], 1), axis=0, return_index=True)
+    assert ev == count_evals(w, f)
+    assert gev == count_evals(_rows(w, np.sort(first)), f)
+    assert gev < ev / 4
+    small = W.inspiral_20_modes()
+    gpu_waveform(ctx, small)
+    assert ctx.last_group_eval_count() == ctx.last_eval_count() == 8724
+
+
+def test_voice_groups_with_rejected_and_lone_rows(ctx):
+    """Rejected rows (l above FDEMRI_MAX_L, |m| > l, m < 0 without
+    FDEMRI_NO_PARTNERS) that share (m, n) with valid rows join no group: the
+    sum is bitwise the one without them.  Rows whose n lies outside the group
+    key's field (n +- 4096 of a valid row) are solved on their own: the sum is
+    the valid table's plus their single-row waveforms."""
+    w = W.inspiral_3842_modes()
+    h0 = gpu_waveform(ctx, w)
+    j = [5, 400, 2000]
+    bad_l = np.array([50, 2, 3], dtype=w.l.dtype)
+    bad_m = np.array([w.m[5], 3, -2], dtype=w.m.dtype)
+    bad_n = np.array([w.n[5], 0, 0], dtype=w.n.dtype)
+    ins = [100, 1500, w.Nm]
+    wb = _rows(w, np.arange(w.Nm))
+    wb.l = np.insert(w.l, ins, bad_l)
+    wb.m = np.insert(w.m, ins, bad_m)
+    wb.n = np.insert(w.n, ins, bad_n)
+    wb.A = np.insert(w.A, ins, w.A[j], axis=0)
+    hb = gpu_waveform(ctx, wb, check_flags=False)
+    assert ctx.sync_flags() == fd.FDEMRI_FLAG_BAD_MODE
+    assert np.array_equal(hb[0], h0[0]) and np.array_equal(hb[1], h0[1])
+    lone = np.array([7, 900, 3000])
+    wl = _rows(w, np.concatenate([np.arange(w.Nm), lone, lone]))
+    wl.n = np.concatenate([w.n, w.n[lone] + 4096, w.n[lone] - 4096]).astype(w.n.dtype)
+    hl = gpu_waveform(ctx, wl)
+    ref = [h0[0].copy(), h0[1].copy()]
+    for shift in (4096, -4096):
+        for i in lone:
+            hi = gpu_waveform(ctx, _rows(w, np.array([i]), shift))
+            ref[0] += hi[0]
+            ref[1] += hi[1]
+    for g, o in zip(hl, ref):
+        assert support_mismatch(g, o) == 0
+        assert rel_l2(g, o) <= 1e-13
 
 
 def test_dense_batch_draw_sampled_bins(ctx):
