@@ -30,25 +30,22 @@ METRIC = "waveforms/s + mode·bin evals/s (fwd, fwd+adjoint) at stated error vs 
 # multiply-add counts 2) plus one sine/cosine pair, two divisions and one
 # reciprocal square root, each of these four counted as one.
 FLOPS_PER_EVAL = 154
-# Of these, the root, its derivatives, the factor of Eq. extendedspa1 and the
-# phase (120) depend on the voice frequency only, so rows with the same (m, n)
-# share them: they are counted once per (voice group, piece, bin).  The
-# amplitude spline, its product with the factor, the two polarization
-# products and the accumulation (34) are counted per row.
-SHARED_FLOPS_PER_EVAL = 120
-ROW_FLOPS_PER_EVAL = FLOPS_PER_EVAL - SHARED_FLOPS_PER_EVAL
+# Rows with the same (m, n) share the voice frequency, hence the pieces, the
+# roots, the factor of Eq. extendedspa1 and the phase, and the sum over such
+# a group of c_t A_t(t(f)) E is one cubic per polarization, (sum_t c_t A_t)
+# times E, whose coefficients the set-up combines once per segment.  The
+# gather's algorithmic work is therefore counted per (group, piece, bin):
+# the 154 flops above (for a group of two or more rows: two cubics of
+# combined coefficients and two products with E, 40 flops, in place of one
+# cubic, one product with E and two polarization products, 34; the lower
+# count is used).  fdemri_last_group_eval_count gives those evaluations; for
+# ungrouped tables it equals the mode-bin count.
 
 
 def algorithmic_flops(evals, group_evals):
-    """Algorithmic flops of a gather launch from its mode-bin and group-bin evaluation counts."""
-    return SHARED_FLOPS_PER_EVAL * group_evals + ROW_FLOPS_PER_EVAL * evals
-
-
-# The adjoint per evaluation: the forward terms it recomputes (the above
-# without the polarization products and the accumulation, 126) and the
-# contraction with the cotangent into its 16 gradient sums (88).
-ADJ_FLOPS_PER_EVAL = 214
-PEAK_FP64_VALU = 78.6e12
+    """Algorithmic flops of a gather launch from its evaluation counts (the
+    mode-bin count `evals` is the metric's unit and not used here)."""
+    return FLOPS_PER_EVAL * group_evals
 
 
 def progress(msg):
@@ -256,8 +253,8 @@ def batch_measure(ctx, W, fd, dev, B, with_loglike=True, reps=2):
                         "traffic": profile_traffic(BATCH_TRAFFIC_FILE, "gather_batch_kernel<true, 1, 4, false>"),
                         # no batch autotune runs here: the default block shape, 1 tile per wave
                         "kernel": "gather_batch_kernel<true, 1, 4, false>", "kernel_ms": g_avg * 1e3,
-                        "flops_per_eval": FLOPS_PER_EVAL, "shared_flops_per_group_eval": SHARED_FLOPS_PER_EVAL,
-                        "flops_per_row_eval": ROW_FLOPS_PER_EVAL,
+                        "flops_per_group_eval": FLOPS_PER_EVAL,
+                        "mode_bin_evals_per_s_in_kernel": evals / g_avg,
                         "peak_note": ("without packed FP32 (off in this build) FP32 and FP64 vector instructions "
                                       "issue at the same rate, so the FP64 vector peak bounds the mixed path")}}
     del outs
@@ -766,10 +763,10 @@ def headline(args, w, evals, group_evals, sec, prof, achieved, bpl, secondary):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": gather_traffic(bpl),
                      "traffic_unit": "HBM bytes per launch (read + write)",
-                     "kernel": f"gather_kernel<false, {bpl}, 4, false>", "flops_per_eval": FLOPS_PER_EVAL,
-                     "shared_flops_per_group_eval": SHARED_FLOPS_PER_EVAL, "flops_per_row_eval": ROW_FLOPS_PER_EVAL,
-                     "issued_fp64_flops_per_eval": profile_traffic(
-                         TRAFFIC_FILE, f"gather_kernel<false, {bpl}, 4, false>", "issued_fp64_flops_per_eval")},
+                     "kernel": f"gather_kernel<false, {bpl}, 4, false>", "flops_per_group_eval": FLOPS_PER_EVAL,
+                     "mode_bin_evals_per_s_in_kernel": evals / (prof["gather"][0] / max(prof["gather"][1], 1) * 1e-3),
+                     "issued_fp64_flops_per_group_eval": profile_traffic(
+                         TRAFFIC_FILE, f"gather_kernel<false, {bpl}, 4, false>", "issued_fp64_flops_per_group_eval")},
         "secondary": secondary,
     }
 

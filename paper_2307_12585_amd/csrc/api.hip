@@ -28,7 +28,7 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
                              const double* A, double* acoef, float* acoef32, double* fac, ModeConst* modes,
                              float4* modes32, int2* mode_kr, Piece* pieces, int64_t* evals, int32_t* status,
                              uint32_t* flag_word, const double* Phiphi, const double* Phir, const double* A_in,
-                             int hann, int2* gkr, int32_t* gsize, GroupMember* gmem,
+                             int hann, bool grouped, int2* gkr, int32_t* gsize, GroupMember* gmem,
                              GroupMember32* gmem32, hipStream_t stream);
 bool setup_fusable(int K, int Nm, int Nf, uint32_t flags);
 hipError_t launch_setup_fused(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
@@ -484,6 +484,10 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   int32_t* slots = (int32_t*)(w + L.slots);
   hipError_t e;
   const bool fused = fuse && setup_fusable(d->K, d->Nm, d->Nf, d->flags);
+  // voice groups for the forward sum only (the other users read every row's
+  // own amplitude coefficients, which the groups' combined splines replace),
+  // and only on the context's own coefficients
+  const bool grouped = fuse && !fused && !given && modes_grouped(d->Nm);
   if (fused) {
     // trajectory splines, pieces, amplitude splines and checks in one launch
     ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream, prof);
@@ -508,7 +512,7 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
       e = launch_setup_flat(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->f, tcoef, d->l, d->m, d->n, d->theta,
                             d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, acoef32,
                             (double*)(w + L.fac), modes, mixed ? (float4*)(w + L.modes32) : nullptr, mode_kr,
-                            pieces, evals, status, c->flag_word, d->Phiphi, d->Phir, d->A, hann,
+                            pieces, evals, status, c->flag_word, d->Phiphi, d->Phir, d->A, hann, grouped,
                             (int2*)(w + L.gkr), (int32_t*)(w + L.gsize), (GroupMember*)(w + L.gmem),
                             mixed ? (GroupMember32*)(w + L.gmem32) : nullptr, stream);
       // given coefficients were not splined: their FP32 form separately
@@ -532,7 +536,6 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   p.pieces = pieces;
   p.status = status;
   p.modes32 = mixed ? (const float4*)(w + L.modes32) : nullptr;
-  const bool grouped = !fused && modes_grouped(d->Nm);
   p.gkr = grouped ? (const int2*)(w + L.gkr) : nullptr;
   p.gsize = grouped ? (const int32_t*)(w + L.gsize) : nullptr;
   p.gmem = grouped ? (const GroupMember*)(w + L.gmem) : nullptr;
@@ -920,7 +923,7 @@ void fill_records(fdemri_ctx* c, const BatchPlan& P, const fdemri_waveform_desc*
     it.pieces = (Piece*)(wb + L.pieces);
     it.evals = (int64_t*)(wb + L.evals);
     it.status = (int32_t*)(wb + L.status);
-    const bool grouped = modes_grouped(d.Nm);
+    const bool grouped = modes_grouped(d.Nm) && !(d.flags & FDEMRI_COEFFS_GIVEN);
     it.gkr = grouped ? (int2*)(wb + L.gkr) : nullptr;
     it.gsize = grouped ? (int32_t*)(wb + L.gsize) : nullptr;
     it.gmem = grouped ? (GroupMember*)(wb + L.gmem) : nullptr;

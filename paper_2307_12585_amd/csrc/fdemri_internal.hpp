@@ -78,6 +78,21 @@ constexpr int kEnvelopeMinModes = 256;
 constexpr int kGroupMaxModes = 4096;
 __host__ __device__ inline bool modes_grouped(int Nm) { return Nm > kEnvelopeMinModes && Nm <= kGroupMaxModes; }
 
+// FP32 coefficients of one amplitude segment (8 doubles: re, im of the powers
+// 0..3 of tau) in the normalised variable u = tau / h, as the mixed path
+// reads them: A(t_i + u h) = sum_k (a_k h^k) u^k, u in [0, 1].
+__device__ __forceinline__ void amp32_segment(const double* __restrict__ c, double h, float* __restrict__ o) {
+  const double h2 = h * h, h3 = h2 * h;
+  o[0] = (float)c[0];
+  o[1] = (float)c[1];
+  o[2] = (float)(c[2] * h);
+  o[3] = (float)(c[3] * h);
+  o[4] = (float)(c[4] * h2);
+  o[5] = (float)(c[5] * h2);
+  o[6] = (float)(c[6] * h3);
+  o[7] = (float)(c[7] * h3);
+}
+
 // Device pointers of one waveform's prepared tables.
 struct Prepared {
   int32_t K, Nm, Nf;

@@ -155,9 +155,11 @@ struct AmpOf<true> {
 // segment).  It is guessed from the piece's rate, refined by secant steps on
 // the segment index through the knot frequencies at the current segment, and
 // checked against the definition; the rare misses walk to the right segment.
-// The root and E = e^{i psi} G are formed once; every member then adds
-// cP (A^(s) E) and cX (A^(s) E) with its own amplitude spline A at the root
-// (A^(s): A conjugated when s < 0), in member order.
+// The root and E = e^{i psi} G are formed once; a single row adds
+// cP (A^(s) E) and cX (A^(s) E) with its amplitude spline A at the root
+// (A^(s): A conjugated when s < 0), a group of two or more rows the same sum
+// over its rows through its combined splines: (sum_t cP_t A_t)^(s) E and
+// (sum_t cX_t A_t)^(s) E.
 //   f, w: the bin frequency and 2 pi f;
 //   ms, ns: s m and s n of the piece, so that |F_V| = ms F_phi + ns F_r;
 //   neg: s < 0 (the factors of the members are then conjugated).
@@ -203,10 +205,14 @@ __device__ __forceinline__ void eval_bin(const double f, const double w, const P
     G0 = knot_freq(ms, L.knot(i).Fp, ns, L.knot(i).Fr);
     G1 = knot_freq(ms, L.knot(i + 1).Fp, ns, L.knot(i + 1).Fr);
   }
-  // the first member's amplitude coefficients, requested now so that the
-  // loads are in flight during the root solve
+  // the amplitude coefficients, requested now so that the load is in flight
+  // during the root solve: a group of two or more rows has its combined
+  // splines (sum_t c+_t A_t, sum_t cx_t A_t) in its first two rows' slots, a
+  // single row its own
+  const bool combined = M.g >= 2;
   const int mode0 = M.gm ? M.gm[0].mode : M.mode;
-  typename AmpOf<MIXED>::T a_next = AmpOf<MIXED>::load(amp, nseg, mode0, i);
+  using Seg = typename AmpOf<MIXED>::T;
+  const Seg a0 = AmpOf<MIXED>::load(amp, nseg, mode0, i);
   SegData S;
   const klds KnotRec& kr = L.knot(i);
   S.ti = kr.t;
@@ -224,21 +230,30 @@ __device__ __forceinline__ void eval_bin(const double f, const double w, const P
   S.Pri = kr.Pr;
   const Bracket B = make_bracket(P, i, S);
   const double tau = solve_root(f, dd_, S, B);
+  // the second row's slot after the solve (both in flight across it would
+  // spill registers); the phase and factor then cover its latency
+  Seg a1{};
+  if (combined) a1 = AmpOf<MIXED>::load(amp, nseg, M.gm[1].mode, i);
 
   if constexpr (!MIXED) {
     const double2 E = root_E64(f, w, tau, P.d, ms, ns, S);
-#pragma unroll 1
-    for (int t = 0; t < M.g; ++t) {
-      const AmpSeg64 a = a_next;
-      // the next member's coefficients are in flight while this one is added
-      if (t + 1 < M.g) a_next = AmpOf<false>::load(amp, nseg, M.gm[t + 1].mode, i);
+    if (combined) {
+      // conj_s(sum_t c_t A_t) E for each polarization (conj_s: conjugate
+      // when s < 0)
+      const double2 AP = amp64(a0, tau), AX = amp64(a1, tau);
+      const double py = AP.y * P.sd, xy = AX.y * P.sd;
+      acc.v[0] += AP.x * E.x - py * E.y;
+      acc.v[1] += AP.x * E.y + py * E.x;
+      acc.v[2] += AX.x * E.x - xy * E.y;
+      acc.v[3] += AX.x * E.y + xy * E.x;
+    } else {
       double2 cP = M.cP, cX = M.cX;
       if (M.gm) {
-        const GroupMember mb = M.gm[t];
+        const GroupMember mb = M.gm[0];
         cP = make_double2(mb.cp_re, neg ? -mb.cp_im : mb.cp_im);
         cX = make_double2(mb.cx_re, neg ? -mb.cx_im : mb.cx_im);
       }
-      const double2 A = amp64(a, tau);
+      const double2 A = amp64(a0, tau);
       const double ay = A.y * P.sd;  // A conjugated on s < 0 pieces
       const double Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
       acc.v[0] += cP.x * Wr - cP.y * Wi;
@@ -249,20 +264,25 @@ __device__ __forceinline__ void eval_bin(const double f, const double w, const P
   } else {
     const float2 E = root_E32(f, w, tau, P.d, ms, ns, S);
     const float u = amp_u32(tau, S);
-#pragma unroll 1
-    for (int t = 0; t < M.g; ++t) {
-      const AmpSeg32 a = a_next;
-      if (t + 1 < M.g) a_next = AmpOf<true>::load(amp, nseg, M.gm32[t + 1].mode, i);
+    const float sd = (float)P.sd;
+    if (combined) {
+      const float2 AP = amp32(a0, u), AX = amp32(a1, u);
+      const float py = AP.y * sd, xy = AX.y * sd;
+      acc.add(0, AP.x * E.x - py * E.y);
+      acc.add(1, AP.x * E.y + py * E.x);
+      acc.add(2, AX.x * E.x - xy * E.y);
+      acc.add(3, AX.x * E.y + xy * E.x);
+    } else {
       float4 c32 = M.c32;
       if (M.gm32) {
-        c32 = M.gm32[t].c;
+        c32 = M.gm32[0].c;
         if (neg) {
           c32.y = -c32.y;
           c32.w = -c32.w;
         }
       }
-      const float2 A = amp32(a, u);
-      const float ay = A.y * (float)P.sd;
+      const float2 A = amp32(a0, u);
+      const float ay = A.y * sd;
       const float Wr = A.x * E.x - ay * E.y, Wi = A.x * E.y + ay * E.x;
       const float pr = c32.x, pi = c32.y, xr = c32.z, xi = c32.w;
       acc.add(0, pr * Wr - pi * Wi);
@@ -868,20 +888,8 @@ __global__ __launch_bounds__(64 * WAVES, gather_batch_min_waves<MIXED>()) void g
 __global__ void reset_counter_kernel(int* counter) { *counter = 0; }
 
 // FP32 normalised amplitude coefficients for the mixed path when the caller
-// gives the FP64 coefficients (FDEMRI_COEFFS_GIVEN); splined amplitudes get
-// them from the spline kernels, with the same arithmetic:
-// A(t_i + u h) = sum_k (a_k h^k) u^k, u in [0, 1].
-__device__ __forceinline__ void amp32_segment(const double* __restrict__ c, double h, float* __restrict__ o) {
-  const double h2 = h * h, h3 = h2 * h;
-  o[0] = (float)c[0];
-  o[1] = (float)c[1];
-  o[2] = (float)(c[2] * h);
-  o[3] = (float)(c[3] * h);
-  o[4] = (float)(c[4] * h2);
-  o[5] = (float)(c[5] * h2);
-  o[6] = (float)(c[6] * h3);
-  o[7] = (float)(c[7] * h3);
-}
+// gives the FP64 coefficients (FDEMRI_COEFFS_GIVEN) (amp32_segment); splined
+// amplitudes get them from the spline kernels, with the same arithmetic.
 
 __global__ void amp32_kernel(int Nm, int K, const double* __restrict__ t, const double* __restrict__ acoef,
                              float* __restrict__ acoef32) {

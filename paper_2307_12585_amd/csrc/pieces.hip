@@ -523,7 +523,8 @@ __device__ void group_sort(const int32_t* __restrict__ l, const int32_t* __restr
 // Position j of the voice groups, once the sort and the row's mode table are
 // written: the group's bin range at its first position (empty elsewhere),
 // the member's polarization factors (gsize[j] and gmem[j].mode are the
-// sort's); returns the bin range written to gkr[j].
+// sort's, and the mode field is not rewritten); returns the bin range
+// written to gkr[j].
 __device__ __forceinline__ int2 group_fill(int j, const ModeConst* __restrict__ modes,
                                            const float4* __restrict__ modes32, const int2* __restrict__ mode_kr,
                                            int2* __restrict__ gkr, const int32_t* __restrict__ gsize,
@@ -532,9 +533,53 @@ __device__ __forceinline__ int2 group_fill(int j, const ModeConst* __restrict__ 
   const int2 kr = gsize[j] > 0 ? mode_kr[row] : make_int2(INT_MAX, -1);
   gkr[j] = kr;
   const ModeConst md = modes[row];
-  gmem[j] = GroupMember{md.cp_re, md.cp_im, md.cx_re, md.cx_im, row, {0, 0, 0}};
+  double2* c = (double2*)&gmem[j];
+  c[0] = make_double2(md.cp_re, md.cp_im);
+  c[1] = make_double2(md.cx_re, md.cx_im);
   if (gmem32) gmem32[j] = GroupMember32{modes32[row], row, {0, 0, 0}};
   return kr;
+}
+
+// Combined amplitude splines of the voice group of g >= 2 rows at sorted
+// position j, segment i: the coefficients of sum_t c+_t A_t and of
+// sum_t cx_t A_t over its rows t (the spline of a weighted sum of series is
+// the weighted sum of their splines, and the sum over a group's rows of
+// c_t A_t(t(f)) E is (sum_t c_t A_t)(t(f)) E), which replace the segment's
+// coefficients of the group's first and second row: in place in acoef (FP64
+// path), or in their FP32 normalised form in acoef32 (mixed path; acoef is
+// then left as it is).  The thread reads every row's coefficients of the
+// segment before it writes.
+__device__ __forceinline__ void combine_segment(int j, int g, int i, int nseg, double h,
+                                                const ModeConst* __restrict__ modes,
+                                                const GroupMember* __restrict__ gmem, double* __restrict__ acoef,
+                                                float* __restrict__ acoef32) {
+  double P[8], X[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) P[k] = X[k] = 0.0;
+  for (int q = 0; q < g; ++q) {
+    const int row = gmem[j + q].mode;
+    const ModeConst md = modes[row];
+    const double* a = acoef + ((size_t)row * nseg + i) * 8;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double ar = a[2 * k], ai = a[2 * k + 1];
+      P[2 * k] += md.cp_re * ar - md.cp_im * ai;
+      P[2 * k + 1] += md.cp_re * ai + md.cp_im * ar;
+      X[2 * k] += md.cx_re * ar - md.cx_im * ai;
+      X[2 * k + 1] += md.cx_re * ai + md.cx_im * ar;
+    }
+  }
+  const size_t sp = ((size_t)gmem[j].mode * nseg + i) * 8, sx = ((size_t)gmem[j + 1].mode * nseg + i) * 8;
+  if (acoef32) {
+    amp32_segment(P, h, acoef32 + sp);
+    amp32_segment(X, h, acoef32 + sx);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      acoef[sp + k] = P[k];
+      acoef[sx + k] = X[k];
+    }
+  }
 }
 
 // Bin envelope [env[0], env[1]] of one waveform's voices (min and max over
@@ -589,16 +634,29 @@ __global__ __launch_bounds__(kGroupThreads) void envelope_kernel(const int2* __r
   envelope_block(mode_kr, Nm, env);
 }
 
-// One grouped waveform after its set-up launch, one position per thread: the
-// groups' tables and the envelope, as the minimum and maximum over the
-// groups' ranges into env (set to {INT_MAX, -1} by the sort).
+// One grouped waveform after its set-up launch.  The first fill_blocks
+// workgroups, one position per thread: the groups' tables and the envelope,
+// as the minimum and maximum over the groups' ranges into env (set to
+// {INT_MAX, -1} by the sort).  The rest, one (position, segment) per thread:
+// the combined amplitude splines of the groups of two or more rows (with
+// acoef not NULL).
 constexpr int kFillThreads = 256;
 __global__ __launch_bounds__(kFillThreads) void group_fill_kernel(const ModeConst* __restrict__ modes,
                                                                   const float4* __restrict__ modes32,
                                                                   const int2* __restrict__ mode_kr, int Nm,
                                                                   int32_t* __restrict__ env, int2* gkr,
                                                                   const int32_t* gsize, GroupMember* gmem,
-                                                                  GroupMember32* gmem32) {
+                                                                  GroupMember32* gmem32, int fill_blocks, int nseg,
+                                                                  const double* __restrict__ t, double* acoef,
+                                                                  float* acoef32) {
+  if ((int)blockIdx.x >= fill_blocks) {
+    const long q = (long)((int)blockIdx.x - fill_blocks) * kFillThreads + threadIdx.x;
+    const int j = (int)(q / nseg), i = (int)(q % nseg);
+    if (j >= Nm) return;
+    const int g = gsize[j];
+    if (g >= 2) combine_segment(j, g, i, nseg, t[i + 1] - t[i], modes, gmem, acoef, acoef32);
+    return;
+  }
   const int j = (int)blockIdx.x * kFillThreads + (int)threadIdx.x;
   int lo = INT_MAX, hi = -1;
   if (j < Nm) {
@@ -626,6 +684,13 @@ __global__ __launch_bounds__(kGroupThreads) void envelope_batch_kernel(const Wav
   __syncthreads();  // the sort's gsize and gmem[].mode, written to global memory
   for (int j = threadIdx.x; j < w.Nm; j += kGroupThreads)
     group_fill(j, w.modes, w.modes32, w.mode_kr, w.gkr, w.gsize, w.gmem, w.gmem32);
+  // the combined amplitude splines (the mixed path writes the FP32 form)
+  const int nseg = w.K - 1;
+  for (long q = threadIdx.x; q < (long)w.Nm * nseg; q += kGroupThreads) {
+    const int j = (int)(q / nseg), i = (int)(q % nseg);
+    const int g = w.gsize[j];
+    if (g >= 2) combine_segment(j, g, i, nseg, w.t[i + 1] - w.t[i], w.modes, w.gmem, w.acoef, w.acoef32);
+  }
 }
 
 // Inputs of one waveform's checks (device pointers of the caller's arrays).
@@ -843,8 +908,8 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
                              const double* A, double* acoef, float* acoef32, double* fac, ModeConst* modes,
                              float4* modes32, int2* mode_kr, Piece* pieces, int64_t* evals, int32_t* status,
                              uint32_t* flag_word, const double* Phiphi, const double* Phir, const double* A_in,
-                             int hann, int2* gkr, int32_t* gsize, GroupMember* gmem, GroupMember32* gmem32,
-                             hipStream_t stream) {
+                             int hann, bool grouped, int2* gkr, int32_t* gsize, GroupMember* gmem,
+                             GroupMember32* gmem32, hipStream_t stream) {
   PieceArgs a;
   a.K = K;
   a.Nm = Nm;
@@ -870,7 +935,6 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
   const int amp_blocks = A ? (Nm + kSeriesPerBlock - 1) / kSeriesPerBlock : 0;
   const int checks = check_blocks(K, Nm, Nf, flags);
   const CheckArgs c{K, Nm, Nf, flags, hann, t, Fphi, Fr, Phiphi, Phir, A_in, f};
-  const bool grouped = modes_grouped(Nm);
   const int sb = grouped ? 1 : 0;  // the sort's workgroup
   int32_t* sort_gsize = grouped ? gsize : nullptr;
   if (K <= 256) {
@@ -887,9 +951,13 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
   // so that the gather skips the blocks no voice reaches without scanning the
   // table and solves each root once per group; a small table is scanned as
   // cheaply as the launch would cost
-  if (grouped)
-    group_fill_kernel<<<(Nm + kFillThreads - 1) / kFillThreads, kFillThreads, 0, stream>>>(
-        modes, modes32, mode_kr, Nm, status + 1, gkr, gsize, gmem, gmem32);
+  if (grouped) {
+    const int fill_blocks = (Nm + kFillThreads - 1) / kFillThreads;
+    const long pairs = (long)Nm * (K - 1);
+    const int combine_blocks = (int)((pairs + kFillThreads - 1) / kFillThreads);
+    group_fill_kernel<<<fill_blocks + combine_blocks, kFillThreads, 0, stream>>>(
+        modes, modes32, mode_kr, Nm, status + 1, gkr, gsize, gmem, gmem32, fill_blocks, K - 1, t, acoef, acoef32);
+  }
   else if (Nm > kEnvelopeMinModes)
     envelope_kernel<<<1, kGroupThreads, 0, stream>>>(mode_kr, Nm, status + 1);
   return hipGetLastError();
