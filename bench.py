@@ -40,6 +40,12 @@ FLOPS_PER_EVAL = 154
 # cubic, one product with E and two polarization products, 34; the lower
 # count is used).  fdemri_last_group_eval_count gives those evaluations; for
 # ungrouped tables it equals the mode-bin count.
+# The adjoint per evaluation (it reads every row's own splines, ungrouped):
+# the forward terms it recomputes (the above without the polarization
+# products and the accumulation, 126) and the contraction with the cotangent
+# into its 16 gradient sums (88).
+ADJ_FLOPS_PER_EVAL = 214
+PEAK_FP64_VALU = 78.6e12
 
 
 def algorithmic_flops(evals, group_evals):
