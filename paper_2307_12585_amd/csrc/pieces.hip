@@ -553,20 +553,46 @@ __device__ __forceinline__ void combine_segment(int j, int g, int i, int nseg, d
                                                 const ModeConst* __restrict__ modes,
                                                 const GroupMember* __restrict__ gmem, double* __restrict__ acoef,
                                                 float* __restrict__ acoef32) {
+  constexpr int U = 4;  // rows whose loads are in flight together
   double P[8], X[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) P[k] = X[k] = 0.0;
-  for (int q = 0; q < g; ++q) {
-    const int row = gmem[j + q].mode;
-    const ModeConst md = modes[row];
-    const double* a = acoef + ((size_t)row * nseg + i) * 8;
+  for (int q0 = 0; q0 < g; q0 += U) {
+    int row[U];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double ar = a[2 * k], ai = a[2 * k + 1];
-      P[2 * k] += md.cp_re * ar - md.cp_im * ai;
-      P[2 * k + 1] += md.cp_re * ai + md.cp_im * ar;
-      X[2 * k] += md.cx_re * ar - md.cx_im * ai;
-      X[2 * k + 1] += md.cx_re * ai + md.cx_im * ar;
+    for (int u = 0; u < U; ++u) row[u] = q0 + u < g ? gmem[j + q0 + u].mode : -1;
+    double2 cp[U], cx[U];
+    double a[U][8];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (row[u] >= 0) {
+        const ModeConst& md = modes[row[u]];
+        cp[u] = make_double2(md.cp_re, md.cp_im);
+        cx[u] = make_double2(md.cx_re, md.cx_im);
+        const double2* s = (const double2*)(acoef + ((size_t)row[u] * nseg + i) * 8);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double2 v = s[k];
+          a[u][2 * k] = v.x;
+          a[u][2 * k + 1] = v.y;
+        }
+      } else {
+        cp[u] = cx[u] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[u][k] = 0.0;
+      }
+    }
+    // in row order (the zero terms of absent rows change nothing)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double ar = a[u][2 * k], ai = a[u][2 * k + 1];
+        P[2 * k] += cp[u].x * ar - cp[u].y * ai;
+        P[2 * k + 1] += cp[u].x * ai + cp[u].y * ar;
+        X[2 * k] += cx[u].x * ar - cx[u].y * ai;
+        X[2 * k + 1] += cx[u].x * ai + cx[u].y * ar;
+      }
     }
   }
   const size_t sp = ((size_t)gmem[j].mode * nseg + i) * 8, sx = ((size_t)gmem[j + 1].mode * nseg + i) * 8;
@@ -650,8 +676,8 @@ __global__ __launch_bounds__(kFillThreads) void group_fill_kernel(const ModeCons
                                                                   const double* __restrict__ t, double* acoef,
                                                                   float* acoef32) {
   if ((int)blockIdx.x >= fill_blocks) {
-    const long q = (long)((int)blockIdx.x - fill_blocks) * kFillThreads + threadIdx.x;
-    const int j = (int)(q / nseg), i = (int)(q % nseg);
+    const int q = ((int)blockIdx.x - fill_blocks) * kFillThreads + (int)threadIdx.x;
+    const int j = q / nseg, i = q - j * nseg;
     if (j >= Nm) return;
     const int g = gsize[j];
     if (g >= 2) combine_segment(j, g, i, nseg, t[i + 1] - t[i], modes, gmem, acoef, acoef32);
@@ -686,8 +712,8 @@ __global__ __launch_bounds__(kGroupThreads) void envelope_batch_kernel(const Wav
     group_fill(j, w.modes, w.modes32, w.mode_kr, w.gkr, w.gsize, w.gmem, w.gmem32);
   // the combined amplitude splines (the mixed path writes the FP32 form)
   const int nseg = w.K - 1;
-  for (long q = threadIdx.x; q < (long)w.Nm * nseg; q += kGroupThreads) {
-    const int j = (int)(q / nseg), i = (int)(q % nseg);
+  for (int q = threadIdx.x; q < w.Nm * nseg; q += kGroupThreads) {
+    const int j = q / nseg, i = q - j * nseg;
     const int g = w.gsize[j];
     if (g >= 2) combine_segment(j, g, i, nseg, w.t[i + 1] - w.t[i], w.modes, w.gmem, w.acoef, w.acoef32);
   }
@@ -953,8 +979,8 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
   // cheaply as the launch would cost
   if (grouped) {
     const int fill_blocks = (Nm + kFillThreads - 1) / kFillThreads;
-    const long pairs = (long)Nm * (K - 1);
-    const int combine_blocks = (int)((pairs + kFillThreads - 1) / kFillThreads);
+    const int pairs = Nm * (K - 1);  // at most kGroupMaxModes (kMaxKnots - 1)
+    const int combine_blocks = acoef ? (pairs + kFillThreads - 1) / kFillThreads : 0;
     group_fill_kernel<<<fill_blocks + combine_blocks, kFillThreads, 0, stream>>>(
         modes, modes32, mode_kr, Nm, status + 1, gkr, gsize, gmem, gmem32, fill_blocks, K - 1, t, acoef, acoef32);
   }
