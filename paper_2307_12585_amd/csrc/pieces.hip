@@ -383,11 +383,17 @@ __device__ __forceinline__ void compare_exchange(uint32_t& a, uint32_t& b, bool 
 // Stage of stride S < KPL of the bitonic merge of blocks of `size` keys: both
 // partners are in the thread's registers.
 template <int KPL, int S>
-__device__ __forceinline__ void sort_stage_in_lane(uint32_t (&k)[KPL], int base, int size) {
+__device__ __forceinline__ void sort_stage_in_lane(uint32_t (&k)[KPL], bool up_thread, int size) {
   if constexpr (S < KPL) {
 #pragma unroll
-    for (int q = 0; q < KPL; ++q)
-      if ((q & S) == 0) compare_exchange(k[q], k[q + S], ((base + q) & size) == 0);
+    for (int q = 0; q < KPL; ++q) {
+      if ((q & S) == 0) {
+        // direction bit of position base + q: for blocks of fewer than KPL
+        // keys it lies in q (a scalar test), otherwise in the thread's base
+        const bool up = size < KPL ? (q & size) == 0 : up_thread;
+        compare_exchange(k[q], k[q + S], up);
+      }
+    }
   }
 }
 
@@ -417,37 +423,41 @@ __device__ void group_sort_kpl(const int32_t* __restrict__ l, const int32_t* __r
   }
   for (int size = 2; size <= N2; size <<= 1) {
     for (int s = size >> 1; s > 0; s >>= 1) {
+      // with s and size at least KPL the partner and the direction bits lie
+      // in the thread's base, the same for all its keys
+      const bool keep_min = ((base & s) == 0) == ((base & size) == 0);
       if (s >= WK) {
         __syncthreads();  // the previous stage's readers are done
 #pragma unroll
         for (int q = 0; q < KPL; ++q) lds[base + q] = k[q];
         __syncthreads();
+        uint32_t o[KPL];
 #pragma unroll
-        for (int q = 0; q < KPL; ++q) {
-          const int i = base + q;
-          const uint32_t o = lds[i ^ s];
-          const bool keep_min = ((i & s) == 0) == ((i & size) == 0);
-          k[q] = keep_min ? min(k[q], o) : max(k[q], o);
-        }
+        for (int q = 0; q < KPL; ++q) o[q] = lds[(base + q) ^ s];
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) k[q] = keep_min ? min(k[q], o[q]) : max(k[q], o[q]);
       } else if (s >= KPL) {
-        const int d = s / KPL;  // partner lane: lane ^ d, same register
+        // partner lane: lane ^ (s / KPL), same register; all the exchanges
+        // are issued before any is used
+        const int addr = (lane ^ (s / KPL)) << 2;
+        uint32_t o[KPL];
 #pragma unroll
-        for (int q = 0; q < KPL; ++q) {
-          const int i = base + q;
-          const uint32_t o = (uint32_t)__shfl_xor((int)k[q], d, 64);
-          const bool keep_min = ((i & s) == 0) == ((i & size) == 0);
-          k[q] = keep_min ? min(k[q], o) : max(k[q], o);
-        }
-      } else if (s == 1) {
-        sort_stage_in_lane<KPL, 1>(k, base, size);
-      } else if (s == 2) {
-        sort_stage_in_lane<KPL, 2>(k, base, size);
-      } else if (s == 4) {
-        sort_stage_in_lane<KPL, 4>(k, base, size);
-      } else if (s == 8) {
-        sort_stage_in_lane<KPL, 8>(k, base, size);
+        for (int q = 0; q < KPL; ++q) o[q] = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)k[q]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) k[q] = keep_min ? min(k[q], o[q]) : max(k[q], o[q]);
       } else {
-        sort_stage_in_lane<KPL, 16>(k, base, size);
+        const bool up_thread = (base & size) == 0;
+        if (s == 1)
+          sort_stage_in_lane<KPL, 1>(k, up_thread, size);
+        else if (s == 2)
+          sort_stage_in_lane<KPL, 2>(k, up_thread, size);
+        else if (s == 4)
+          sort_stage_in_lane<KPL, 4>(k, up_thread, size);
+        else if (s == 8)
+          sort_stage_in_lane<KPL, 8>(k, up_thread, size);
+        else
+          sort_stage_in_lane<KPL, 16>(k, up_thread, size);
       }
     }
   }
