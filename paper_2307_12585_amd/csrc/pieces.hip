@@ -747,6 +747,7 @@ struct CheckArgs {
 // every time.
 __device__ void check_block(const CheckArgs& c, int blk, int32_t* status, uint32_t* flag_word,
                             int32_t* slot = nullptr) {
+  constexpr int U = 4;
   int32_t bad = 0;
   const long na = check_amp_count(c.K, c.Nm, c.flags);
   const int nab = (int)((na + kCheckChunk - 1) / kCheckChunk);
@@ -758,20 +759,39 @@ __device__ void check_block(const CheckArgs& c, int blk, int32_t* status, uint32
         bad |= kBadValues;
     }
   } else if (blk <= nab) {
+    // U elements per thread and round, their loads issued together
     const long base = (long)(blk - 1) * kCheckChunk;
-    for (int j = threadIdx.x; j < kCheckChunk; j += blockDim.x) {
-      const long e = base + j;
-      if (e < na && !isfinite(c.A[e])) bad |= kBadValues;
+    for (int j0 = 0; j0 < kCheckChunk; j0 += U * (int)blockDim.x) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long e = base + j0 + u * (int)blockDim.x + threadIdx.x;
+        v[u] = e < na ? c.A[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (!isfinite(v[u])) bad |= kBadValues;
     }
   } else {
     const long base = (long)(blk - 1 - nab) * kCheckChunk;
     const double f1 = c.Nf > 1 ? c.f[1] : 0.0;
-    for (int j = threadIdx.x; j < kCheckChunk; j += blockDim.x) {
-      const long k = base + j;
-      if (k >= c.Nf) break;
-      const double fk = c.f[k];
-      if (!isfinite(fk) || !(fk >= 0.0) || (k > 0 && !(fk >= c.f[k - 1]))) bad |= kBadGrid;
-      if (c.hann && !(fabs(fk - (double)k * f1) <= 1e-12 * fk)) bad |= kBadHannGrid;
+    for (int j0 = 0; j0 < kCheckChunk; j0 += U * (int)blockDim.x) {
+      double v[U], prev[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long k = base + j0 + u * (int)blockDim.x + threadIdx.x;
+        v[u] = k < c.Nf ? c.f[k] : 0.0;
+        prev[u] = (k > 0 && k < c.Nf) ? c.f[k - 1] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long k = base + j0 + u * (int)blockDim.x + threadIdx.x;
+        if (k < c.Nf) {
+          const double fk = v[u];
+          if (!isfinite(fk) || !(fk >= 0.0) || (k > 0 && !(fk >= prev[u]))) bad |= kBadGrid;
+          if (c.hann && !(fabs(fk - (double)k * f1) <= 1e-12 * fk)) bad |= kBadHannGrid;
+        }
+      }
     }
   }
   if (slot) {
