@@ -169,6 +169,19 @@ def _rows(w, idx, n_shift=0):
     return r
 
 
+def test_3842_modes_more_knots_sampled_bins(ctx):
+    """The 3842-mode table on a 300-knot trajectory: the set-up's workgroups
+    have 512 threads (the voice groups' sort among them); FP64 against the
+    oracle on sampled bins."""
+    w = W.inspiral_3842_modes(K=300)
+    hp, hc = gpu_waveform(ctx, w)
+    rng = np.random.default_rng(13)
+    act = np.nonzero(w.f < 9e-3)[0]
+    idx = np.unique(np.concatenate([rng.choice(act, 600, replace=False), [0, 1, w.Nf - 1]]))
+    op, oc = oracle.waveform(w, f=w.f[idx])
+    _check64((hp[idx], hc[idx]), (op, oc), "inspiral_3842_modes K=300, sampled")
+
+
 @pytest.mark.parametrize("K", [200, 300])
 def test_voice_groups_row_order(ctx, K):
     """Rows with the same (m, n) share one root per bin (voice groups, set up
