@@ -40,11 +40,12 @@ FLOPS_PER_EVAL = 154
 # cubic, one product with E and two polarization products, 34; the lower
 # count is used).  fdemri_last_group_eval_count gives those evaluations; for
 # ungrouped tables it equals the mode-bin count.
-# The adjoint per evaluation (it reads every row's own splines, ungrouped):
-# the forward terms it recomputes (the above without the polarization
-# products and the accumulation, 126) and the contraction with the cotangent
-# into its 16 gradient sums (88).
-ADJ_FLOPS_PER_EVAL = 214
+# The adjoint per (voice group, piece, bin): the shared forward terms (root,
+# derivatives, factor, phase and E: 120), the products conj(g) E for both
+# polarizations (12), the two combined amplitude cubics (24), Im Z (8) and
+# the moment sums over four powers of u = tau / h (36); every row's gradient
+# terms follow from the moments once per (row, segment), not per bin.
+ADJ_FLOPS_PER_GROUP_EVAL = 200
 PEAK_FP64_VALU = 78.6e12
 
 
@@ -400,6 +401,7 @@ def adjoint_measure(ctx, W, fd, dev, B):
     # their unit kernel bracketed
     ctx.waveform_batch(dws, "mixed", outs=mouts)
     evals = ctx.last_eval_count()
+    group_evals = ctx.last_group_eval_count()
     ctx.profile(True, classes=["vjp"])
     ctx.profile_read()
     adjoints()
@@ -430,8 +432,9 @@ def adjoint_measure(ctx, W, fd, dev, B):
             e2e[k] = max(e2e[k], rel(g[k], ref[k]))
             vjp_only[k] = max(vjp_only[k], rel(only[k], ref[k]))
     progress("forward+adjoint: FP64 references done")
-    achieved = evals * ADJ_FLOPS_PER_EVAL / (v_ms * 1e-3)
-    return {"waveforms": B, "evals_forward": evals, "seconds": tot, "waveforms_per_s": B / tot,
+    achieved = group_evals * ADJ_FLOPS_PER_GROUP_EVAL / (v_ms * 1e-3)
+    return {"waveforms": B, "evals_forward": evals, "group_evals_forward": group_evals, "seconds": tot,
+            "waveforms_per_s": B / tot,
             "evals_per_s_forward_plus_adjoint": evals / tot,
             "forward_rel_l2_vs_fp64_max": fwd_err,
             "vjp_kernel_ms_per_waveform": v_ms / max(v_n, 1),
@@ -440,7 +443,7 @@ def adjoint_measure(ctx, W, fd, dev, B):
                          "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
                          "traffic": profile_traffic(VJP_TRAFFIC_FILE, "vjp_unit_kernel<true>"),
                          "kernel": "vjp_unit_kernel<true>", "kernel_ms_total": v_ms,
-                         "launches": v_n, "flops_per_eval": ADJ_FLOPS_PER_EVAL}}
+                         "launches": v_n, "flops_per_group_eval": ADJ_FLOPS_PER_GROUP_EVAL}}
 
 
 def main():

@@ -28,7 +28,7 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
                              const double* A, double* acoef, float* acoef32, double* fac, ModeConst* modes,
                              float4* modes32, int2* mode_kr, Piece* pieces, int64_t* evals, int32_t* status,
                              uint32_t* flag_word, const double* Phiphi, const double* Phir, const double* A_in,
-                             int hann, bool grouped, int2* gkr, int32_t* gsize, GroupMember* gmem,
+                             int hann, bool grouped, bool combine, int2* gkr, int32_t* gsize, GroupMember* gmem,
                              GroupMember32* gmem32, hipStream_t stream);
 bool setup_fusable(int K, int Nm, int Nf, uint32_t flags);
 hipError_t launch_setup_fused(int K, int Nm, int Nf, const double* t, const double* Fphi, const double* Fr,
@@ -469,7 +469,7 @@ namespace {
 // fused into one launch.
 fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, const Layout& L, Prepared& p,
                       float*& acoef32, hipStream_t stream, char* w = nullptr, bool prof = true, int hann = 0,
-                      bool fuse = false) {
+                      bool fuse = false, bool adjoint = false) {
   if (!w) w = c->ws;
   double* tcoef = (double*)(w + L.tcoef);
   // with FDEMRI_COEFFS_GIVEN the caller's coefficients (same layout) are read in place
@@ -484,10 +484,11 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
   int32_t* slots = (int32_t*)(w + L.slots);
   hipError_t e;
   const bool fused = fuse && setup_fusable(d->K, d->Nm, d->Nf, d->flags);
-  // voice groups for the forward sum only (the other users read every row's
-  // own amplitude coefficients, which the groups' combined splines replace),
-  // and only on the context's own coefficients
-  const bool grouped = fuse && !fused && !given && modes_grouped(d->Nm);
+  // voice groups for the forward sum (fuse: with the combined amplitude
+  // splines, which replace the first rows' coefficients) and the adjoint
+  // (without: it reads every row's own), not for the time-domain sum and the
+  // band, and only on the context's own coefficients
+  const bool grouped = (fuse || adjoint) && !fused && !given && modes_grouped(d->Nm);
   if (fused) {
     // trajectory splines, pieces, amplitude splines and checks in one launch
     ProfScope ps(c, FDEMRI_KERNEL_PIECES, stream, prof);
@@ -512,7 +513,7 @@ fdemri_status prepare(fdemri_ctx* c, const fdemri_waveform_desc* d, bool mixed, 
       e = launch_setup_flat(d->K, d->Nm, d->Nf, d->t, d->Fphi, d->Fr, d->f, tcoef, d->l, d->m, d->n, d->theta,
                             d->phi, d->scale, d->flags, given ? nullptr : d->A, acoef, acoef32,
                             (double*)(w + L.fac), modes, mixed ? (float4*)(w + L.modes32) : nullptr, mode_kr,
-                            pieces, evals, status, c->flag_word, d->Phiphi, d->Phir, d->A, hann, grouped,
+                            pieces, evals, status, c->flag_word, d->Phiphi, d->Phir, d->A, hann, grouped, fuse,
                             (int2*)(w + L.gkr), (int32_t*)(w + L.gsize), (GroupMember*)(w + L.gmem),
                             mixed ? (GroupMember32*)(w + L.gmem32) : nullptr, stream);
       // given coefficients were not splined: their FP32 form separately
@@ -745,7 +746,7 @@ fdemri_status fdemri_vjp(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemri_pr
   if (st != FDEMRI_OK) return st;
   Prepared p;
   float* acoef32 = nullptr;
-  st = prepare(c, d, mixed, L, p, acoef32, stream);
+  st = prepare(c, d, mixed, L, p, acoef32, stream, nullptr, true, 0, false, true);
   if (st != FDEMRI_OK) return st;
   char* w = c->ws;
   double* gA_coef = gA ? gA : (double*)(w + L.gA);

@@ -964,7 +964,7 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
                              const double* A, double* acoef, float* acoef32, double* fac, ModeConst* modes,
                              float4* modes32, int2* mode_kr, Piece* pieces, int64_t* evals, int32_t* status,
                              uint32_t* flag_word, const double* Phiphi, const double* Phir, const double* A_in,
-                             int hann, bool grouped, int2* gkr, int32_t* gsize, GroupMember* gmem,
+                             int hann, bool grouped, bool combine, int2* gkr, int32_t* gsize, GroupMember* gmem,
                              GroupMember32* gmem32, hipStream_t stream) {
   PieceArgs a;
   a.K = K;
@@ -1010,7 +1010,7 @@ hipError_t launch_setup_flat(int K, int Nm, int Nf, const double* t, const doubl
   if (grouped) {
     const int fill_blocks = (Nm + kFillThreads - 1) / kFillThreads;
     const int pairs = Nm * (K - 1);  // at most kGroupMaxModes (kMaxKnots - 1)
-    const int combine_blocks = acoef ? (pairs + kFillThreads - 1) / kFillThreads : 0;
+    const int combine_blocks = combine ? (pairs + kFillThreads - 1) / kFillThreads : 0;
     group_fill_kernel<<<fill_blocks + combine_blocks, kFillThreads, 0, stream>>>(
         modes, modes32, mode_kr, Nm, status + 1, gkr, gsize, gmem, gmem32, fill_blocks, K - 1, t, acoef, acoef32);
   }

@@ -16,11 +16,12 @@
 // and c_+, c_x depend on theta, phi and the scale (d/dphi c = i m c).
 //
 // The forward terms are recomputed, not stored: one wavefront per
-// (mode, spline segment) re-evaluates the roots of every bin whose root lies
-// in that segment (the same segment assignment, bracket and arithmetic as
-// the forward gather) and reduces its contributions in registers.  All
-// further reductions run in a fixed order, so the gradient is deterministic
-// and no atomics are used.
+// (voice group, spline segment) re-evaluates the roots of every bin whose
+// root lies in that segment (the same segment assignment, bracket and
+// arithmetic as the forward gather), reduces moments of conj(g) E in
+// registers, and forms every row's terms from them.  All further reductions
+// run in a fixed order, so the gradient is deterministic and no atomics are
+// used.
 #include "evalcore.hpp"
 #include "harmonics.hpp"
 #include "search.hpp"
@@ -84,8 +85,27 @@ constexpr int vjp_min_waves() {
   return MIXED ? 4 : 3;
 }
 
+// One unit per (voice group, spline segment): the group at sorted position j
+// (its first row; every row its own group when the table is not grouped) and
+// segment i.  The rows of a group share the pieces, roots and E, so the bin
+// loop forms, per piece, the moments
+//   Mp_k = sum over bins of u^k conj(g_+) E,  Mx_k = sum u^k conj(g_x) E,
+//   Y_k  = sum u^k Im Z,  Z = conj(g_+) Cp(u)^(s) E + conj(g_x) Cx(u)^(s) E,
+// u = tau / h, k = 0..3, with Cp(u) = sum_t c_+,t A_t (Cx likewise) the
+// group's combined amplitude, and every row's terms follow after the loop (a
+// the row's amplitude coefficients in u, a^_j = a_j h^j, c its factors):
+//   s > 0: dL/da_k = h^k conj(c_+ Mp_k + c_x Mx_k),  U_+ = sum_j a^_j Mp_j,
+//   s < 0: dL/da_k = h^k (conj(c_+) Mp_k + conj(c_x) Mx_k),  U_+ = sum_j a^_j conj(Mp_j)
+// (U_x likewise with Mx), and the group's sum s tau^k Im Z = s h^k Y_k
+// ((.)^(s): conjugate when s < 0).  The bins a unit evaluates are those of
+// the per-row form (the same segment assignment, bracket and root).  Outputs
+// per row of the group: gA (8), Upart (4) and PZ (4; the group's sum at its
+// first row, zero at the others, since the phase gradient sums m PZ over
+// the rows).
 template <bool MIXED>
 __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_unit_kernel(VjpArgs a) {
+  // each wave's combined coefficients Cp, Cx in u (re, im per power)
+  __shared__ double comb[4][16];
   const Prepared& p = a.p;
   const int nseg = p.K - 1;
   // the wave index is uniform; in a scalar register it makes the unit, and
@@ -93,13 +113,14 @@ __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_unit_kernel(V
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const long unit = (long)blockIdx.x * 4 + wave;
   if (unit >= (long)p.Nm * nseg) return;
-  const int mu = (int)(unit / nseg), i = (int)(unit % nseg);
-  const ModeConst md = ((const kconst ModeConst*)p.modes)[mu];
+  const int j = (int)(unit / nseg), i = (int)(unit % nseg);
+  const bool grouped = p.gsize != nullptr;
+  const int g = grouped ? ((const kconst int32_t*)p.gsize)[j] : 1;
+  if (g == 0) return;  // a group's other rows: their outputs are this group's unit's
+  const kconst GroupMember* gm = grouped ? (const kconst GroupMember*)p.gmem + j : nullptr;
+  const int lead = grouped ? gm[0].mode : j;
+  const ModeConst md = ((const kconst ModeConst*)p.modes)[lead];
   const double m = md.m, n = md.n;
-
-  double acc[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
 
   // segment data of this unit (wave-uniform; read-only tables through the
   // constant address space, so scalar loads)
@@ -113,18 +134,50 @@ __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_unit_kernel(V
   const kconst double* cFr = (const kconst double*)p.tcoef + ((size_t)1 * nseg + i) * 4;
   const kconst double* cPp = (const kconst double*)p.tcoef + ((size_t)2 * nseg + i) * 4;
   const kconst double* cPr = (const kconst double*)p.tcoef + ((size_t)3 * nseg + i) * 4;
-  const double* acs = p.acoef + ((size_t)mu * nseg + i) * 8;
-  const float* acs32 = MIXED ? a.acoef32 + ((size_t)mu * nseg + i) * 8 : nullptr;
   const double Ppr = reduce_2pi(((const kconst double*)p.Phiphi)[i]);
   const double Prr = reduce_2pi(((const kconst double*)p.Phir)[i]);
+  const double hp[4] = {1.0, h, h * h, h * h * h};
+  auto row_of = [&](int t) { return grouped ? gm[t].mode : j; };
+
+  // every row's outputs start at zero (each row's by the lane that adds to
+  // them); lanes 0..15 form the group's combined coefficients, in row order
+  double cv = 0.0;
+  for (int t = 0; t < g; ++t) {
+    const int row = row_of(t);
+    if (lane < 16) {
+      const ModeConst& mt = p.modes[row];
+      const int k = (lane & 7) >> 1;
+      const double* ac = p.acoef + ((size_t)row * nseg + i) * 8 + 2 * k;
+      const double ar = ac[0] * hp[k], ai = ac[1] * hp[k];
+      const double cr = lane < 8 ? mt.cp_re : mt.cx_re, ci = lane < 8 ? mt.cp_im : mt.cx_im;
+      cv += (lane & 1) ? cr * ai + ci * ar : cr * ar - ci * ai;
+    }
+  }
+  if (lane < 16) comb[wave][lane] = cv;  // read by the same wave after the fence below
+  for (int t = lane; t < g; t += 64) {
+    const size_t u = (size_t)row_of(t) * nseg + i;
+    if (a.gA) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a.gA[u * 8 + q] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      a.Upart[u * 4 + q] = 0.0;
+      a.PZ[u * 4 + q] = 0.0;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const double* cb = comb[wave];
+  double pz[4] = {0.0, 0.0, 0.0, 0.0};
 
   // a waveform whose inputs failed the checks has a zero gradient
   const int npieces = *(const kconst int32_t*)p.status != 0 ? 0 : md.npieces;
   for (int q = 0; q < npieces; ++q) {
-    const Piece P = ((const kconst Piece*)p.pieces)[(size_t)mu * kMaxPieces + q];
+    const Piece P = ((const kconst Piece*)p.pieces)[(size_t)lead * kMaxPieces + q];
     if (i < P.seg_a || i > P.seg_b || P.k_lo > P.k_hi) continue;
     const int s = P.s, d = P.d;
-    const double sd = (double)s, dd_ = (double)d;
+    const double dd_ = (double)d;
     // |F_V| and s Phi_V of this piece on segment i (sign folded into the mode numbers)
     const double ms = s < 0 ? -m : m, ns = s < 0 ? -n : n;
     SegData S;
@@ -153,19 +206,20 @@ __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_unit_kernel(V
     }
     if (kA > kB) continue;
     const Bracket B = make_bracket(P, i, S);
+    const double ih = 1.0 / h, sc = (double)s;  // sc: the sign of Im C under (.)^(s)
+    // moments: acc[2k], acc[2k+1] = Mp_k; acc[8 + 2k], acc[9 + 2k] = Mx_k; acc[16 + k] = Y_k
+    double acc[20];
+#pragma unroll
+    for (int r = 0; r < 20; ++r) acc[r] = 0.0;
     for (int k = kA + lane; k <= kB; k += 64) {
       const double f = p.f[k];
       const double w = kTwoPiHi * f;
       const double tau = solve_root(f, dd_, S, B);
-      double Er, Ei, Ar, Ai, gpr, gpi, gcr, gci;
+      double Er, Ei, gpr, gpi, gcr, gci;
       if constexpr (MIXED) {
-        float2 E, A;
-        root_terms32(f, w, tau, d, ms, ns, S, acs32, E, A);
+        const float2 E = root_E32(f, w, tau, d, ms, ns, S);
         Er = E.x;
         Ei = E.y;
-        // the FP32 amplitude is in the normalised variable u = tau / h
-        Ar = A.x;
-        Ai = A.y;
         const float2 gp = ((const float2*)a.g_hp)[k];
         const float2 gc = ((const float2*)a.g_hc)[k];
         gpr = gp.x;
@@ -173,12 +227,9 @@ __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_unit_kernel(V
         gcr = gc.x;
         gci = gc.y;
       } else {
-        double2 E, A;
-        root_terms64(f, w, tau, d, ms, ns, S, acs, E, A);
+        const double2 E = root_E64(f, w, tau, d, ms, ns, S);
         Er = E.x;
         Ei = E.y;
-        Ar = A.x;
-        Ai = A.y;
         const double2 gp = ((const double2*)a.g_hp)[k];
         const double2 gc = ((const double2*)a.g_hc)[k];
         gpr = gp.x;
@@ -186,77 +237,89 @@ __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_unit_kernel(V
         gcr = gc.x;
         gci = gc.y;
       }
-      // Q multiplies tau^k in dL/da_k
-      double Qr, Qi;
-      // W = A E (A conj(E) for s < 0) enters U_+, U_x and Z
-      double Wr, Wi;
-      if (s > 0) {
-        // (g_+ conj(c_+) + g_x conj(c_x)) conj(E)
-        const double hr = gpr * md.cp_re + gpi * md.cp_im + gcr * md.cx_re + gci * md.cx_im;
-        const double hi = gpi * md.cp_re - gpr * md.cp_im + gci * md.cx_re - gcr * md.cx_im;
-        Qr = hr * Er + hi * Ei;
-        Qi = hi * Er - hr * Ei;
-        Wr = Ar * Er - Ai * Ei;
-        Wi = Ar * Ei + Ai * Er;
-      } else {
-        // conj(g_+ c_+ + g_x c_x) E
-        const double hr = gpr * md.cp_re - gpi * md.cp_im + gcr * md.cx_re - gci * md.cx_im;
-        const double hi = -(gpr * md.cp_im + gpi * md.cp_re + gcr * md.cx_im + gci * md.cx_re);
-        Qr = hr * Er - hi * Ei;
-        Qi = hr * Ei + hi * Er;
-        Wr = Ar * Er + Ai * Ei;
-        Wi = Ai * Er - Ar * Ei;
-      }
-      // U_+ += conj(g_+) W (s > 0) or g_+ W (s < 0), likewise U_x
-      const double sgi = (s > 0) ? -1.0 : 1.0;
-      const double upr = gpr * Wr - sgi * gpi * Wi, upi = gpr * Wi + sgi * gpi * Wr;
-      const double uxr = gcr * Wr - sgi * gci * Wi, uxi = gcr * Wi + sgi * gci * Wr;
-      // Z = conj(g_+) (A c_+)^(s) E + conj(g_x) (A c_x)^(s) E; Im Z
-      double ImZ;
-      {
-        // (A c)^(s) E: s > 0: A c E = c W; s < 0: conj(A c) E = conj(c) conj(A) E = conj(c) conj(W')
-        double tpr, tpi, txr, txi;
-        if (s > 0) {
-          tpr = md.cp_re * Wr - md.cp_im * Wi;
-          tpi = md.cp_re * Wi + md.cp_im * Wr;
-          txr = md.cx_re * Wr - md.cx_im * Wi;
-          txi = md.cx_re * Wi + md.cx_im * Wr;
-        } else {
-          // conj(A) E = conj(A conj(E)) = conj(W)
-          const double vr = Wr, vi = -Wi;
-          tpr = md.cp_re * vr + md.cp_im * vi;
-          tpi = md.cp_re * vi - md.cp_im * vr;
-          txr = md.cx_re * vr + md.cx_im * vi;
-          txi = md.cx_re * vi - md.cx_im * vr;
-        }
-        ImZ = (gpr * tpi - gpi * tpr) + (gcr * txi - gci * txr);
-      }
-      double pw = 1.0;
+      // conj(g) E
+      double kpr = gpr * Er + gpi * Ei, kpi = gpr * Ei - gpi * Er;
+      double kxr = gcr * Er + gci * Ei, kxi = gcr * Ei - gci * Er;
+      const double u = tau * ih;
+      // the combined amplitudes at u, conjugated when s < 0
+      const double apr = cb[0] + u * (cb[2] + u * (cb[4] + u * cb[6]));
+      const double api = sc * (cb[1] + u * (cb[3] + u * (cb[5] + u * cb[7])));
+      const double axr = cb[8] + u * (cb[10] + u * (cb[12] + u * cb[14]));
+      const double axi = sc * (cb[9] + u * (cb[11] + u * (cb[13] + u * cb[15])));
+      double imz = (kpr * api + kpi * apr) + (kxr * axi + kxi * axr);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        acc[2 * kk] += pw * Qr;
-        acc[2 * kk + 1] += pw * Qi;
-        acc[8 + kk] += sd * pw * ImZ;
-        pw *= tau;
+        acc[2 * kk] += kpr;
+        acc[2 * kk + 1] += kpi;
+        acc[8 + 2 * kk] += kxr;
+        acc[9 + 2 * kk] += kxi;
+        acc[16 + kk] += imz;
+        kpr *= u;
+        kpi *= u;
+        kxr *= u;
+        kxi *= u;
+        imz *= u;
       }
-      acc[12] += upr;
-      acc[13] += upi;
-      acc[14] += uxr;
-      acc[15] += uxi;
+    }
+    // the wave's totals, in every lane
+    double lo16[16], hi16[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      lo16[r] = acc[r];
+      hi16[r] = r < 4 ? acc[16 + r] : 0.0;
+    }
+    const double tl = wave_sum16(lo16), th = wave_sum16(hi16);
+    double M[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) M[r] = __shfl(tl, r * 4, 64);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pz[k] += sc * hp[k] * __shfl(th, k * 4, 64);
+    const bool pos = s > 0;
+    // every row's terms, one row per lane
+    for (int t = lane; t < g; t += 64) {
+      const int row = row_of(t);
+      const size_t uo = (size_t)row * nseg + i;
+      const ModeConst& mt = p.modes[row];
+      const double* ac = p.acoef + uo * 8;
+      if (a.gA) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double mpr = M[2 * k], mpi = M[2 * k + 1], mxr = M[8 + 2 * k], mxi = M[9 + 2 * k];
+          double vr, vi;
+          if (pos) {
+            // conj(c_+ Mp + c_x Mx)
+            vr = mt.cp_re * mpr - mt.cp_im * mpi + mt.cx_re * mxr - mt.cx_im * mxi;
+            vi = -(mt.cp_re * mpi + mt.cp_im * mpr + mt.cx_re * mxi + mt.cx_im * mxr);
+          } else {
+            // conj(c_+) Mp + conj(c_x) Mx
+            vr = mt.cp_re * mpr + mt.cp_im * mpi + mt.cx_re * mxr + mt.cx_im * mxi;
+            vi = mt.cp_re * mpi - mt.cp_im * mpr + mt.cx_re * mxi - mt.cx_im * mxr;
+          }
+          a.gA[uo * 8 + 2 * k] += hp[k] * vr;
+          a.gA[uo * 8 + 2 * k + 1] += hp[k] * vi;
+        }
+      }
+      double upr = 0.0, upi = 0.0, uxr = 0.0, uxi = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double ar = ac[2 * k] * hp[k], ai = ac[2 * k + 1] * hp[k];
+        const double mpr = M[2 * k], mpi = pos ? M[2 * k + 1] : -M[2 * k + 1];
+        const double mxr = M[8 + 2 * k], mxi = pos ? M[9 + 2 * k] : -M[9 + 2 * k];
+        upr += ar * mpr - ai * mpi;
+        upi += ar * mpi + ai * mpr;
+        uxr += ar * mxr - ai * mxi;
+        uxi += ar * mxi + ai * mxr;
+      }
+      a.Upart[uo * 4 + 0] += upr;
+      a.Upart[uo * 4 + 1] += upi;
+      a.Upart[uo * 4 + 2] += uxr;
+      a.Upart[uo * 4 + 3] += uxi;
     }
   }
-  // wave reduction: lane 4 q holds the total of value q
-  const double tot = wave_sum16(acc);
-  if ((lane & 3) == 0) {
-    const int q = lane >> 2;
-    const size_t u = (size_t)mu * nseg + i;
-    if (q < 8) {
-      if (a.gA) a.gA[u * 8 + q] = tot;
-    } else if (q < 12) {
-      a.PZ[u * 4 + (q - 8)] = tot;
-    } else {
-      a.Upart[u * 4 + (q - 12)] = tot;
-    }
+  if (lane == 0) {
+    const size_t u = (size_t)lead * nseg + i;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.PZ[u * 4 + k] = pz[k];
   }
 }
 
