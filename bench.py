@@ -441,8 +441,8 @@ def adjoint_measure(ctx, W, fd, dev, B):
             "grad_rel_l2_vs_fp64_max": e2e, "adjoint_only_rel_l2_vs_fp64_max": vjp_only,
             "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
                          "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
-                         "traffic": profile_traffic(VJP_TRAFFIC_FILE, "vjp_unit_kernel<true>"),
-                         "kernel": "vjp_unit_kernel<true>", "kernel_ms_total": v_ms,
+                         "traffic": profile_traffic(VJP_TRAFFIC_FILE, "vjp_chunk_kernel<true>"),
+                         "kernel": "vjp_chunk_kernel<true>", "kernel_ms_total": v_ms,
                          "launches": v_n, "flops_per_group_eval": ADJ_FLOPS_PER_GROUP_EVAL}}
 
 

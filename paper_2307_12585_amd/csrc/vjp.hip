@@ -15,16 +15,22 @@
 //   U_+ = sum conj(g_+) A E (s > 0) + g_+ A conj(E) (s < 0), likewise U_x,
 // and c_+, c_x depend on theta, phi and the scale (d/dphi c = i m c).
 //
-// The forward terms are recomputed, not stored: one wavefront per
-// (voice group, spline segment) re-evaluates the roots of every bin whose
-// root lies in that segment (the same segment assignment, bracket and
-// arithmetic as the forward gather), reduces moments of conj(g) E in
-// registers, and forms every row's terms from them.  All further reductions
-// run in a fixed order, so the gradient is deterministic and no atomics are
-// used.
+// The forward terms are recomputed, not stored: the bins whose root lies in
+// segment i of a voice group (the same segment assignment, bracket and
+// arithmetic as the forward gather) are cut into chunks of equal size, each
+// wavefront re-evaluates the roots of the chunks it takes and reduces
+// moments of conj(g) E in registers, and every row's terms follow from the
+// moments summed per (group, segment).  Which wave takes which chunk varies
+// from run to run, but every sum runs in a fixed order (a chunk's bins, a
+// unit's chunks, the reductions after), so the gradient is deterministic;
+// the only atomics count bins and hand out chunks.
 #include "evalcore.hpp"
 #include "harmonics.hpp"
 #include "search.hpp"
+
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
+#include <rocprim/iterator/transform_iterator.hpp>
 
 namespace fdemri {
 
@@ -78,190 +84,290 @@ __device__ __forceinline__ double wave_sum16(const double v[16]) {
   return a1;
 }
 
-// Occupancy target in waves per SIMD: the mixed adjoint fits 4 (a few spills
-// outside the bin loop); the FP64 one would spill inside it and stays at 3.
+// The adjoint's work is split by bins, not by unit: a unit (voice group at
+// sorted position j, spline segment i; every row its own group when the
+// table is not grouped) owns the bins whose root the forward search places
+// in segment i of one of its pieces, and their count varies by orders of
+// magnitude (a fast chirp's last segments hold most bins).  The plan kernel
+// finds each unit's bin range per piece, the scan gives each unit a run of
+// fixed-size chunks of its (piece-concatenated) bins, the chunk kernel hands
+// the chunks out to the waves through a counter, and the finish kernel sums
+// each unit's chunks in chunk order and forms every row's terms.
+//
+// The rows of a group share the pieces, roots and E, so a chunk forms, per
+// piece, the moments
+//   Mp_k = sum over bins of u^k conj(g_+) E,  Mx_k = sum u^k conj(g_x) E,
+//   Y_k  = sum u^k Im Z,  Z = conj(g_+) Cp(u)^(s) E + conj(g_x) Cx(u)^(s) E,
+// u = tau / h, k = 0..3, with Cp(u) = sum_t c_+,t A_t (Cx likewise) the
+// group's combined amplitude, and stores them sign-folded,
+//   Qp_k = conj(Mp_k) (s > 0), Mp_k (s < 0),  Qx_k likewise,  s h^k Y_k,
+// so that they add across pieces and chunks and every row's terms follow
+// from the sums (a the row's amplitude coefficients in u, a^_j = a_j h^j,
+// c its factors):
+//   dL/da_k = h^k (conj(c_+) Qp_k + conj(c_x) Qx_k),
+//   U_+ = sum_j a^_j conj(Qp_j),  U_x = sum_j a^_j conj(Qx_j),
+// and the group's sum s tau^k Im Z is the summed s h^k Y_k.  Outputs per row
+// of the group: gA (8), Upart (4) and PZ (4; the group's sum at its first
+// row, zero at the others, since the phase gradient sums m PZ over the rows).
+
+// bins per chunk: at least kVjpMinChunkIters passes of the wave, and so many
+// that the chunks number at most the units plus kVjpChunkCap
+constexpr int kVjpMinChunkIters = 16;
+constexpr long long kVjpChunkCap = 1 << 19;
+constexpr int kVjpMom = 20;  // doubles per chunk: Qp (8), Qx (8), s h^k Y_k (4)
+
+__device__ __forceinline__ int vjp_chunk_bins(unsigned long long bins) {
+  const unsigned long long per = (bins + 64ull * kVjpChunkCap - 1) / (64ull * kVjpChunkCap);
+  return 64 * (int)max(per, (unsigned long long)kVjpMinChunkIters);
+}
+__device__ __forceinline__ int vjp_chunks(int nb, int ch) { return (nb + ch - 1) / ch; }
+
+struct VjpPlan {
+  int2* rng;                 // [Nm * nseg][kMaxPieces] bin range of each piece in the unit (empty: x > y)
+  int32_t* nb;               // [Nm * nseg] bins of the unit over its pieces (0: no work, not a group's unit)
+  int32_t* off;              // [Nm * nseg] first chunk of the unit (exclusive scan of the chunk counts)
+  unsigned long long* ctl;   // [0] bins of all units, [1] the next chunk to hand out
+  double* mom;               // [chunks][kVjpMom]
+};
+
+struct VjpChunkCount {
+  const int32_t* nb;
+  const unsigned long long* ctl;
+  __device__ int operator()(int u) const { return vjp_chunks(nb[u], vjp_chunk_bins(ctl[0])); }
+};
+
+__global__ void vjp_plan_zero_kernel(unsigned long long* ctl) {
+  ctl[0] = 0;
+  ctl[1] = 0;
+}
+
+// One thread per (row, segment) unit: the bins of each piece whose root the
+// forward search places in segment i (the largest segment j in
+// [seg_a, seg_b] with j == seg_a or d g_j < d f).
+__global__ __launch_bounds__(256) void vjp_plan_kernel(Prepared p, VjpPlan v) {
+  const int nseg = p.K - 1;
+  const long U = (long)p.Nm * nseg;
+  const long u = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long total = 0;
+  if (u < U) {
+    const int j = (int)(u / nseg), i = (int)(u % nseg);
+    const bool grouped = p.gsize != nullptr;
+    const int g = grouped ? p.gsize[j] : 1;
+    // a waveform whose inputs failed the checks has a zero gradient; a
+    // group's other rows are covered by its unit
+    if (g > 0 && *p.status == 0) {
+      const int lead = grouped ? p.gmem[j].mode : j;
+      const ModeConst md = p.modes[lead];
+      const double F0 = knot_freq(md.m, p.Fphi[i], md.n, p.Fr[i]);
+      const double F1 = knot_freq(md.m, p.Fphi[i + 1], md.n, p.Fr[i + 1]);
+      for (int q = 0; q < md.npieces; ++q) {
+        const Piece P = p.pieces[(size_t)lead * kMaxPieces + q];
+        int kA = P.k_lo, kB = P.k_hi;
+        if (i >= P.seg_a && i <= P.seg_b && P.k_lo <= P.k_hi) {
+          const double gi = P.s < 0 ? -F0 : F0, gi1 = P.s < 0 ? -F1 : F1;
+          if (P.d > 0) {
+            if (i > P.seg_a) kA = max(kA, first_gt(p.f, p.Nf, gi));
+            if (i < P.seg_b) kB = min(kB, first_gt(p.f, p.Nf, gi1) - 1);
+          } else {
+            if (i > P.seg_a) kB = min(kB, first_ge(p.f, p.Nf, gi) - 1);
+            if (i < P.seg_b) kA = max(kA, first_ge(p.f, p.Nf, gi1));
+          }
+        } else {
+          kA = 1;
+          kB = 0;
+        }
+        if (kA > kB) {
+          kA = 1;
+          kB = 0;
+        }
+        v.rng[u * kMaxPieces + q] = make_int2(kA, kB);
+        total += kB - kA + 1;
+      }
+    }
+    v.nb[u] = (int32_t)total;
+  }
+  // the wave's bins, added once
+  for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o, 64);
+  if ((threadIdx.x & 63) == 0 && total) atomicAdd(&v.ctl[0], (unsigned long long)total);
+}
+
+// Occupancy target in waves per SIMD: the mixed adjoint fits 4; the FP64 one
+// would spill inside the bin loop and stays at 3.
 template <bool MIXED>
 constexpr int vjp_min_waves() {
   return MIXED ? 4 : 3;
 }
 
-// One unit per (voice group, spline segment): the group at sorted position j
-// (its first row; every row its own group when the table is not grouped) and
-// segment i.  The rows of a group share the pieces, roots and E, so the bin
-// loop forms, per piece, the moments
-//   Mp_k = sum over bins of u^k conj(g_+) E,  Mx_k = sum u^k conj(g_x) E,
-//   Y_k  = sum u^k Im Z,  Z = conj(g_+) Cp(u)^(s) E + conj(g_x) Cx(u)^(s) E,
-// u = tau / h, k = 0..3, with Cp(u) = sum_t c_+,t A_t (Cx likewise) the
-// group's combined amplitude, and every row's terms follow after the loop (a
-// the row's amplitude coefficients in u, a^_j = a_j h^j, c its factors):
-//   s > 0: dL/da_k = h^k conj(c_+ Mp_k + c_x Mx_k),  U_+ = sum_j a^_j Mp_j,
-//   s < 0: dL/da_k = h^k (conj(c_+) Mp_k + conj(c_x) Mx_k),  U_+ = sum_j a^_j conj(Mp_j)
-// (U_x likewise with Mx), and the group's sum s tau^k Im Z = s h^k Y_k
-// ((.)^(s): conjugate when s < 0).  The bins a unit evaluates are those of
-// the per-row form (the same segment assignment, bracket and root).  Outputs
-// per row of the group: gA (8), Upart (4) and PZ (4; the group's sum at its
-// first row, zero at the others, since the phase gradient sums m PZ over
-// the rows).
+// Chunks handed out one per wave through the counter until all are taken;
+// each writes its sign-folded moments (kVjpMom doubles).
 template <bool MIXED>
-__global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_unit_kernel(VjpArgs a) {
+__global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_chunk_kernel(VjpArgs a, VjpPlan v) {
   // each wave's combined coefficients Cp, Cx in u (re, im per power)
   __shared__ double comb[4][16];
   const Prepared& p = a.p;
   const int nseg = p.K - 1;
-  // the wave index is uniform; in a scalar register it makes the unit, and
-  // every load indexed by it, scalar
+  const int U = p.Nm * nseg;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const long unit = (long)blockIdx.x * 4 + wave;
-  if (unit >= (long)p.Nm * nseg) return;
-  const int j = (int)(unit / nseg), i = (int)(unit % nseg);
+  const int ch = vjp_chunk_bins(*(const kconst unsigned long long*)v.ctl);
+  const kconst int32_t* koff = (const kconst int32_t*)v.off;
+  const int T = koff[U - 1] + vjp_chunks(((const kconst int32_t*)v.nb)[U - 1], ch);
   const bool grouped = p.gsize != nullptr;
-  const int g = grouped ? ((const kconst int32_t*)p.gsize)[j] : 1;
-  if (g == 0) return;  // a group's other rows: their outputs are this group's unit's
-  const kconst GroupMember* gm = grouped ? (const kconst GroupMember*)p.gmem + j : nullptr;
-  const int lead = grouped ? gm[0].mode : j;
-  const ModeConst md = ((const kconst ModeConst*)p.modes)[lead];
-  const double m = md.m, n = md.n;
-
-  // segment data of this unit (wave-uniform; read-only tables through the
-  // constant address space, so scalar loads)
   const kconst double* kt = (const kconst double*)p.t;
   const kconst double* kFp = (const kconst double*)p.Fphi;
   const kconst double* kFr = (const kconst double*)p.Fr;
-  const double ti = kt[i], h = kt[i + 1] - ti;
-  const double F0 = knot_freq(m, kFp[i], n, kFr[i]);
-  const double F1 = knot_freq(m, kFp[i + 1], n, kFr[i + 1]);
-  const kconst double* cFp = (const kconst double*)p.tcoef + ((size_t)0 * nseg + i) * 4;
-  const kconst double* cFr = (const kconst double*)p.tcoef + ((size_t)1 * nseg + i) * 4;
-  const kconst double* cPp = (const kconst double*)p.tcoef + ((size_t)2 * nseg + i) * 4;
-  const kconst double* cPr = (const kconst double*)p.tcoef + ((size_t)3 * nseg + i) * 4;
-  const double Ppr = reduce_2pi(((const kconst double*)p.Phiphi)[i]);
-  const double Prr = reduce_2pi(((const kconst double*)p.Phir)[i]);
-  const double hp[4] = {1.0, h, h * h, h * h * h};
-  auto row_of = [&](int t) { return grouped ? gm[t].mode : j; };
+  for (;;) {
+    int c0 = 0;
+    if (lane == 0) c0 = (int)atomicAdd(&v.ctl[1], 1ull);
+    const int c = __builtin_amdgcn_readfirstlane(__shfl(c0, 0, 64));
+    if (c >= T) break;
+    // the unit: the last with off <= c (units without chunks share the next one's offset)
+    int lo = 0, hi = U;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (koff[mid] <= c) lo = mid;
+      else hi = mid;
+    }
+    const int u = lo;
+    const int b0 = (c - koff[u]) * ch, b1 = b0 + ch;  // the chunk in the unit's concatenated bins
+    const int j = u / nseg, i = u % nseg;
+    const int g = grouped ? ((const kconst int32_t*)p.gsize)[j] : 1;
+    const kconst GroupMember* gm = grouped ? (const kconst GroupMember*)p.gmem + j : nullptr;
+    const int lead = grouped ? gm[0].mode : j;
+    const ModeConst md = ((const kconst ModeConst*)p.modes)[lead];
+    const double m = md.m, n = md.n;
+    const double ti = kt[i], h = kt[i + 1] - ti;
+    const double F0 = knot_freq(m, kFp[i], n, kFr[i]);
+    const double F1 = knot_freq(m, kFp[i + 1], n, kFr[i + 1]);
+    const kconst double* cFp = (const kconst double*)p.tcoef + ((size_t)0 * nseg + i) * 4;
+    const kconst double* cFr = (const kconst double*)p.tcoef + ((size_t)1 * nseg + i) * 4;
+    const kconst double* cPp = (const kconst double*)p.tcoef + ((size_t)2 * nseg + i) * 4;
+    const kconst double* cPr = (const kconst double*)p.tcoef + ((size_t)3 * nseg + i) * 4;
+    const double Ppr = reduce_2pi(((const kconst double*)p.Phiphi)[i]);
+    const double Prr = reduce_2pi(((const kconst double*)p.Phir)[i]);
+    const double hp[4] = {1.0, h, h * h, h * h * h};
 
-  // every row's outputs start at zero (each row's by the lane that adds to
-  // them); lanes 0..15 form the group's combined coefficients, in row order
-  double cv = 0.0;
-  for (int t = 0; t < g; ++t) {
-    const int row = row_of(t);
-    if (lane < 16) {
-      const ModeConst& mt = p.modes[row];
-      const int k = (lane & 7) >> 1;
-      const double* ac = p.acoef + ((size_t)row * nseg + i) * 8 + 2 * k;
-      const double ar = ac[0] * hp[k], ai = ac[1] * hp[k];
-      const double cr = lane < 8 ? mt.cp_re : mt.cx_re, ci = lane < 8 ? mt.cp_im : mt.cx_im;
-      cv += (lane & 1) ? cr * ai + ci * ar : cr * ar - ci * ai;
-    }
-  }
-  if (lane < 16) comb[wave][lane] = cv;  // read by the same wave after the fence below
-  for (int t = lane; t < g; t += 64) {
-    const size_t u = (size_t)row_of(t) * nseg + i;
-    if (a.gA) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) a.gA[u * 8 + q] = 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      a.Upart[u * 4 + q] = 0.0;
-      a.PZ[u * 4 + q] = 0.0;
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  const double* cb = comb[wave];
-  double pz[4] = {0.0, 0.0, 0.0, 0.0};
-
-  // a waveform whose inputs failed the checks has a zero gradient
-  const int npieces = *(const kconst int32_t*)p.status != 0 ? 0 : md.npieces;
-  for (int q = 0; q < npieces; ++q) {
-    const Piece P = ((const kconst Piece*)p.pieces)[(size_t)lead * kMaxPieces + q];
-    if (i < P.seg_a || i > P.seg_b || P.k_lo > P.k_hi) continue;
-    const int s = P.s, d = P.d;
-    const double dd_ = (double)d;
-    // |F_V| and s Phi_V of this piece on segment i (sign folded into the mode numbers)
-    const double ms = s < 0 ? -m : m, ns = s < 0 ? -n : n;
-    SegData S;
-    S.ti = ti;
-    S.h = h;
-    S.G0 = s < 0 ? -F0 : F0;
-    S.G1 = s < 0 ? -F1 : F1;
-    S.q1 = wsum(ms, cFp[1], ns, cFr[1]);
-    S.q2 = wsum(ms, cFp[2], ns, cFr[2]);
-    S.q3 = wsum(ms, cFp[3], ns, cFr[3]);
-    S.r1 = wsum(ms, cPp[1], ns, cPr[1]);
-    S.r2 = wsum(ms, cPp[2], ns, cPr[2]);
-    S.r3 = wsum(ms, cPp[3], ns, cPr[3]);
-    S.Ppi = Ppr;
-    S.Pri = Prr;
-    // bins whose root the forward search places in segment i of this piece:
-    // the largest segment j in [seg_a, seg_b] with j == seg_a or d g_j < d f
-    int kA = P.k_lo, kB = P.k_hi;
-    const double gi = S.G0, gi1 = S.G1;
-    if (d > 0) {
-      if (i > P.seg_a) kA = max(kA, first_gt(p.f, p.Nf, gi));
-      if (i < P.seg_b) kB = min(kB, first_gt(p.f, p.Nf, gi1) - 1);
-    } else {
-      if (i > P.seg_a) kB = min(kB, first_ge(p.f, p.Nf, gi) - 1);
-      if (i < P.seg_b) kA = max(kA, first_ge(p.f, p.Nf, gi1));
-    }
-    if (kA > kB) continue;
-    const Bracket B = make_bracket(P, i, S);
-    const double ih = 1.0 / h, sc = (double)s;  // sc: the sign of Im C under (.)^(s)
-    // moments: acc[2k], acc[2k+1] = Mp_k; acc[8 + 2k], acc[9 + 2k] = Mx_k; acc[16 + k] = Y_k
-    double acc[20];
-#pragma unroll
-    for (int r = 0; r < 20; ++r) acc[r] = 0.0;
-    for (int k = kA + lane; k <= kB; k += 64) {
-      const double f = p.f[k];
-      const double w = kTwoPiHi * f;
-      const double tau = solve_root(f, dd_, S, B);
-      double Er, Ei, gpr, gpi, gcr, gci;
-      if constexpr (MIXED) {
-        const float2 E = root_E32(f, w, tau, d, ms, ns, S);
-        Er = E.x;
-        Ei = E.y;
-        const float2 gp = ((const float2*)a.g_hp)[k];
-        const float2 gc = ((const float2*)a.g_hc)[k];
-        gpr = gp.x;
-        gpi = gp.y;
-        gcr = gc.x;
-        gci = gc.y;
-      } else {
-        const double2 E = root_E64(f, w, tau, d, ms, ns, S);
-        Er = E.x;
-        Ei = E.y;
-        const double2 gp = ((const double2*)a.g_hp)[k];
-        const double2 gc = ((const double2*)a.g_hc)[k];
-        gpr = gp.x;
-        gpi = gp.y;
-        gcr = gc.x;
-        gci = gc.y;
-      }
-      // conj(g) E
-      double kpr = gpr * Er + gpi * Ei, kpi = gpr * Ei - gpi * Er;
-      double kxr = gcr * Er + gci * Ei, kxi = gcr * Ei - gci * Er;
-      const double u = tau * ih;
-      // the combined amplitudes at u, conjugated when s < 0
-      const double apr = cb[0] + u * (cb[2] + u * (cb[4] + u * cb[6]));
-      const double api = sc * (cb[1] + u * (cb[3] + u * (cb[5] + u * cb[7])));
-      const double axr = cb[8] + u * (cb[10] + u * (cb[12] + u * cb[14]));
-      const double axi = sc * (cb[9] + u * (cb[11] + u * (cb[13] + u * cb[15])));
-      double imz = (kpr * api + kpi * apr) + (kxr * axi + kxi * axr);
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        acc[2 * kk] += kpr;
-        acc[2 * kk + 1] += kpi;
-        acc[8 + 2 * kk] += kxr;
-        acc[9 + 2 * kk] += kxi;
-        acc[16 + kk] += imz;
-        kpr *= u;
-        kpi *= u;
-        kxr *= u;
-        kxi *= u;
-        imz *= u;
+    // the group's combined coefficients, in row order (the previous chunk's
+    // reads of comb are done before it is overwritten)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    double cv = 0.0;
+    const int k16 = (lane & 7) >> 1;  // this lane's power of u
+    const double hk = k16 == 0 ? 1.0 : k16 == 1 ? h : k16 == 2 ? h * h : h * h * h;
+    for (int t = 0; t < g; ++t) {
+      const int row = grouped ? gm[t].mode : j;
+      if (lane < 16) {
+        const ModeConst& mt = p.modes[row];
+        const int k = k16;
+        const double* ac = p.acoef + ((size_t)row * nseg + i) * 8 + 2 * k;
+        const double ar = ac[0] * hk, ai = ac[1] * hk;
+        const double cr = lane < 8 ? mt.cp_re : mt.cx_re, ci = lane < 8 ? mt.cp_im : mt.cx_im;
+        cv += (lane & 1) ? cr * ai + ci * ar : cr * ar - ci * ai;
       }
     }
-    // the wave's totals, in every lane
+    if (lane < 16) comb[wave][lane] = cv;  // read by the same wave after the fence below
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const double* cb = comb[wave];
+
+    // moments, sign-folded per piece as they are added: acc[2k], acc[2k+1] =
+    // Qp_k; acc[8 + 2k], acc[9 + 2k] = Qx_k; acc[16 + k] = s Y_k (h^k applied
+    // by the sums)
+    double acc[kVjpMom];
+#pragma unroll
+    for (int r = 0; r < kVjpMom; ++r) acc[r] = 0.0;
+    int pos = 0;  // the piece's first bin in the unit's concatenated bins
+    for (int q = 0; q < md.npieces && pos < b1; ++q) {
+      const int2 rq = ((const kconst int2*)v.rng)[(size_t)u * kMaxPieces + q];
+      const int nq = rq.y - rq.x + 1;
+      const int lo_b = max(b0, pos), hi_b = min(b1, pos + nq);
+      const int kA = rq.x + (lo_b - pos), kB = rq.x + (hi_b - pos) - 1;
+      pos += max(nq, 0);
+      if (nq <= 0 || kA > kB) continue;
+      const Piece P = ((const kconst Piece*)p.pieces)[(size_t)lead * kMaxPieces + q];
+      const int s = P.s, d = P.d;
+      const double dd_ = (double)d;
+      // |F_V| and s Phi_V of this piece on segment i (sign folded into the mode numbers)
+      const double ms = s < 0 ? -m : m, ns = s < 0 ? -n : n;
+      SegData S;
+      S.ti = ti;
+      S.h = h;
+      S.G0 = s < 0 ? -F0 : F0;
+      S.G1 = s < 0 ? -F1 : F1;
+      S.q1 = wsum(ms, cFp[1], ns, cFr[1]);
+      S.q2 = wsum(ms, cFp[2], ns, cFr[2]);
+      S.q3 = wsum(ms, cFp[3], ns, cFr[3]);
+      S.r1 = wsum(ms, cPp[1], ns, cPr[1]);
+      S.r2 = wsum(ms, cPp[2], ns, cPr[2]);
+      S.r3 = wsum(ms, cPp[3], ns, cPr[3]);
+      S.Ppi = Ppr;
+      S.Pri = Prr;
+      // the bracket of the roots in segment i (the piece's end values at its
+      // first and last segment); i is wave-uniform, so these are branches
+      Bracket B{0.0, h, S.G0, S.G1};
+      if (!P.whole) {
+        if (i == P.seg_a) {
+          B.tl = P.tau_a;
+          B.gl = P.g_a;
+        }
+        if (i == P.seg_b) {
+          B.th = P.tau_b;
+          B.gh = P.g_b;
+        }
+      }
+      const double ih = 1.0 / h, sc = (double)s;  // sc: the sign of Im C under (.)^(s)
+      for (int k = kA + lane; k <= kB; k += 64) {
+        const double f = p.f[k];
+        const double w = kTwoPiHi * f;
+        const double tau = solve_root(f, dd_, S, B);
+        double Er, Ei, gpr, gpi, gcr, gci;
+        if constexpr (MIXED) {
+          const float2 E = root_E32(f, w, tau, d, ms, ns, S);
+          Er = E.x;
+          Ei = E.y;
+          const float2 gp = ((const float2*)a.g_hp)[k];
+          const float2 gc = ((const float2*)a.g_hc)[k];
+          gpr = gp.x;
+          gpi = gp.y;
+          gcr = gc.x;
+          gci = gc.y;
+        } else {
+          const double2 E = root_E64(f, w, tau, d, ms, ns, S);
+          Er = E.x;
+          Ei = E.y;
+          const double2 gp = ((const double2*)a.g_hp)[k];
+          const double2 gc = ((const double2*)a.g_hc)[k];
+          gpr = gp.x;
+          gpi = gp.y;
+          gcr = gc.x;
+          gci = gc.y;
+        }
+        // conj(g) E, its imaginary part negated when s > 0 (the sign fold)
+        double kpr = gpr * Er + gpi * Ei, kpi = sc * (gpi * Er - gpr * Ei);
+        double kxr = gcr * Er + gci * Ei, kxi = sc * (gci * Er - gcr * Ei);
+        const double uu = tau * ih;
+        // the combined amplitudes at u
+        const double apr = cb[0] + uu * (cb[2] + uu * (cb[4] + uu * cb[6]));
+        const double api = cb[1] + uu * (cb[3] + uu * (cb[5] + uu * cb[7]));
+        const double axr = cb[8] + uu * (cb[10] + uu * (cb[12] + uu * cb[14]));
+        const double axi = cb[9] + uu * (cb[11] + uu * (cb[13] + uu * cb[15]));
+        // s Im Z, Z = conj(g_+) Cp^(s) E + conj(g_x) Cx^(s) E
+        double imz = (kpr * api + kxr * axi) - (kpi * apr + kxi * axr);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          acc[2 * kk] += kpr;
+          acc[2 * kk + 1] += kpi;
+          acc[8 + 2 * kk] += kxr;
+          acc[9 + 2 * kk] += kxi;
+          acc[16 + kk] += imz;
+          kpr *= uu;
+          kpi *= uu;
+          kxr *= uu;
+          kxi *= uu;
+          imz *= uu;
+        }
+      }
+    }
+    // the wave's totals; lane r < 20 stores moment r
     double lo16[16], hi16[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -269,57 +375,100 @@ __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_unit_kernel(V
       hi16[r] = r < 4 ? acc[16 + r] : 0.0;
     }
     const double tl = wave_sum16(lo16), th = wave_sum16(hi16);
-    double M[16];
+    const int src = (lane < 16 ? lane : lane - 16) * 4;
+    const double vl = __shfl(tl, src, 64), vh = __shfl(th, src & 63, 64);
+    if (lane < kVjpMom) v.mom[(size_t)c * kVjpMom + lane] = lane < 16 ? vl : vh;
+  }
+}
+
+// One wave per unit: its chunks' moments summed in chunk order (lane L takes
+// chunks L, L + 64, ..., then a fixed-order wave sum), then every row's terms,
+// one row per lane.  Every row of the group is written (its other rows have
+// no unit of their own).
+__global__ __launch_bounds__(256) void vjp_finish_kernel(VjpArgs a, VjpPlan v) {
+  const Prepared& p = a.p;
+  const int nseg = p.K - 1;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const long unit = (long)blockIdx.x * 4 + wave;
+  if (unit >= (long)p.Nm * nseg) return;
+  const int u = (int)unit;
+  const int j = u / nseg, i = u % nseg;
+  const bool grouped = p.gsize != nullptr;
+  const int g = grouped ? ((const kconst int32_t*)p.gsize)[j] : 1;
+  if (g == 0) return;
+  const kconst GroupMember* gm = grouped ? (const kconst GroupMember*)p.gmem + j : nullptr;
+  const int ch = vjp_chunk_bins(*(const kconst unsigned long long*)v.ctl);
+  const int nc = vjp_chunks(((const kconst int32_t*)v.nb)[u], ch);
+  const size_t c0 = (size_t)((const kconst int32_t*)v.off)[u];
+  double sm[kVjpMom];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) M[r] = __shfl(tl, r * 4, 64);
+  for (int r = 0; r < kVjpMom; ++r) sm[r] = 0.0;
+  for (int c = lane; c < nc; c += 64) {
+    const double* mc = v.mom + (c0 + c) * kVjpMom;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pz[k] += sc * hp[k] * __shfl(th, k * 4, 64);
-    const bool pos = s > 0;
-    // every row's terms, one row per lane
-    for (int t = lane; t < g; t += 64) {
-      const int row = row_of(t);
-      const size_t uo = (size_t)row * nseg + i;
-      const ModeConst& mt = p.modes[row];
-      const double* ac = p.acoef + uo * 8;
+    for (int r = 0; r < kVjpMom; ++r) sm[r] += mc[r];
+  }
+  double lo16[16], hi16[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    lo16[r] = sm[r];
+    hi16[r] = r < 4 ? sm[16 + r] : 0.0;
+  }
+  const double tl = wave_sum16(lo16), th = wave_sum16(hi16);
+  double Q[16], Z[4];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) Q[r] = __shfl(tl, r * 4, 64);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Z[k] = __shfl(th, k * 4, 64);
+  const kconst double* kt = (const kconst double*)p.t;
+  const double h = kt[i + 1] - kt[i];
+  const double hp[4] = {1.0, h, h * h, h * h * h};
+  for (int t = lane; t < g; t += 64) {
+    const int row = grouped ? gm[t].mode : j;
+    const size_t uo = (size_t)row * nseg + i;
+    if (nc == 0) {
+      // no bins (or inputs that failed the checks): zero terms, without
+      // multiplying coefficients that may not be finite
       if (a.gA) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const double mpr = M[2 * k], mpi = M[2 * k + 1], mxr = M[8 + 2 * k], mxi = M[9 + 2 * k];
-          double vr, vi;
-          if (pos) {
-            // conj(c_+ Mp + c_x Mx)
-            vr = mt.cp_re * mpr - mt.cp_im * mpi + mt.cx_re * mxr - mt.cx_im * mxi;
-            vi = -(mt.cp_re * mpi + mt.cp_im * mpr + mt.cx_re * mxi + mt.cx_im * mxr);
-          } else {
-            // conj(c_+) Mp + conj(c_x) Mx
-            vr = mt.cp_re * mpr + mt.cp_im * mpi + mt.cx_re * mxr + mt.cx_im * mxi;
-            vi = mt.cp_re * mpi - mt.cp_im * mpr + mt.cx_re * mxi - mt.cx_im * mxr;
-          }
-          a.gA[uo * 8 + 2 * k] += hp[k] * vr;
-          a.gA[uo * 8 + 2 * k + 1] += hp[k] * vi;
-        }
+        for (int q = 0; q < 8; ++q) a.gA[uo * 8 + q] = 0.0;
       }
-      double upr = 0.0, upi = 0.0, uxr = 0.0, uxi = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a.Upart[uo * 4 + q] = 0.0;
+        a.PZ[uo * 4 + q] = 0.0;
+      }
+      continue;
+    }
+    const ModeConst& mt = p.modes[row];
+    const double* ac = p.acoef + uo * 8;
+    if (a.gA) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const double ar = ac[2 * k] * hp[k], ai = ac[2 * k + 1] * hp[k];
-        const double mpr = M[2 * k], mpi = pos ? M[2 * k + 1] : -M[2 * k + 1];
-        const double mxr = M[8 + 2 * k], mxi = pos ? M[9 + 2 * k] : -M[9 + 2 * k];
-        upr += ar * mpr - ai * mpi;
-        upi += ar * mpi + ai * mpr;
-        uxr += ar * mxr - ai * mxi;
-        uxi += ar * mxi + ai * mxr;
+        const double qpr = Q[2 * k], qpi = Q[2 * k + 1], qxr = Q[8 + 2 * k], qxi = Q[9 + 2 * k];
+        // conj(c_+) Qp + conj(c_x) Qx
+        const double vr = mt.cp_re * qpr + mt.cp_im * qpi + mt.cx_re * qxr + mt.cx_im * qxi;
+        const double vi = mt.cp_re * qpi - mt.cp_im * qpr + mt.cx_re * qxi - mt.cx_im * qxr;
+        a.gA[uo * 8 + 2 * k] = hp[k] * vr;
+        a.gA[uo * 8 + 2 * k + 1] = hp[k] * vi;
       }
-      a.Upart[uo * 4 + 0] += upr;
-      a.Upart[uo * 4 + 1] += upi;
-      a.Upart[uo * 4 + 2] += uxr;
-      a.Upart[uo * 4 + 3] += uxi;
     }
-  }
-  if (lane == 0) {
-    const size_t u = (size_t)lead * nseg + i;
+    // sum_j a^_j conj(Q_j)
+    double upr = 0.0, upi = 0.0, uxr = 0.0, uxi = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a.PZ[u * 4 + k] = pz[k];
+    for (int k = 0; k < 4; ++k) {
+      const double ar = ac[2 * k] * hp[k], ai = ac[2 * k + 1] * hp[k];
+      upr += ar * Q[2 * k] + ai * Q[2 * k + 1];
+      upi += ai * Q[2 * k] - ar * Q[2 * k + 1];
+      uxr += ar * Q[8 + 2 * k] + ai * Q[9 + 2 * k];
+      uxi += ai * Q[8 + 2 * k] - ar * Q[9 + 2 * k];
+    }
+    a.Upart[uo * 4 + 0] = upr;
+    a.Upart[uo * 4 + 1] = upi;
+    a.Upart[uo * 4 + 2] = uxr;
+    a.Upart[uo * 4 + 3] = uxi;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.PZ[uo * 4 + k] = t == 0 ? hp[k] * Z[k] : 0.0;
   }
 }
 
@@ -553,10 +702,20 @@ __global__ __launch_bounds__(NT) void spline_adjoint_kernel(int K, const double*
   }
 }
 
-// The per-(mode, segment) unit kernel of the adjoint (its partial sums into
-// gA_coef, PZ and Upart).
+// Bytes of device scratch the chunk-offset scan needs for `units` units.
+size_t vjp_scan_bytes(long units) {
+  size_t bytes = 0;
+  auto in = rocprim::make_transform_iterator(rocprim::make_counting_iterator(0), VjpChunkCount{nullptr, nullptr});
+  (void)rocprim::exclusive_scan(nullptr, bytes, in, (int32_t*)nullptr, 0, (size_t)units, rocprim::plus<int>());
+  return bytes;
+}
+
+// The adjoint's bin work: plan, chunk offsets, chunks, and the per-unit sums
+// into gA_coef, PZ and Upart.
 hipError_t launch_vjp_units(const Prepared& p, const float* acoef32, bool mixed, const void* g_hp, const void* g_hc,
-                            double* gA_coef, double* PZ, double* Upart, hipStream_t stream) {
+                            double* gA_coef, double* PZ, double* Upart, int2* rng, int32_t* nb, int32_t* off,
+                            unsigned long long* ctl, double* mom, void* scan_tmp, size_t scan_bytes,
+                            hipStream_t stream) {
   VjpArgs a;
   a.p = p;
   a.acoef32 = acoef32;
@@ -565,17 +724,32 @@ hipError_t launch_vjp_units(const Prepared& p, const float* acoef32, bool mixed,
   a.gA = gA_coef;
   a.PZ = PZ;
   a.Upart = Upart;
+  VjpPlan v{rng, nb, off, ctl, mom};
   const int nseg = p.K - 1;
   const long units = (long)p.Nm * nseg;
-  const unsigned blocks = (unsigned)((units + 3) / 4);
+  vjp_plan_zero_kernel<<<1, 1, 0, stream>>>(ctl);
+  vjp_plan_kernel<<<(unsigned)((units + 255) / 256), 256, 0, stream>>>(p, v);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  auto in = rocprim::make_transform_iterator(rocprim::make_counting_iterator(0), VjpChunkCount{nb, ctl});
+  size_t bytes = scan_bytes;
+  e = rocprim::exclusive_scan(scan_tmp, bytes, in, off, 0, (size_t)units, rocprim::plus<int>(), stream);
+  if (e != hipSuccess) return e;
+  // as many waves as the device holds at the kernel's occupancy; the chunks
+  // are handed out, so more would only find the counter exhausted
+  int dev = 0, ncu = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
   if (mixed)
-    vjp_unit_kernel<true><<<blocks, 256, 0, stream>>>(a);
+    vjp_chunk_kernel<true><<<(unsigned)(ncu * vjp_min_waves<true>()), 256, 0, stream>>>(a, v);
   else
-    vjp_unit_kernel<false><<<blocks, 256, 0, stream>>>(a);
+    vjp_chunk_kernel<false><<<(unsigned)(ncu * vjp_min_waves<false>()), 256, 0, stream>>>(a, v);
+  vjp_finish_kernel<<<(unsigned)((units + 3) / 4), 256, 0, stream>>>(a, v);
   return hipGetLastError();
 }
 
-// The reductions after the unit kernel: phase-coefficient gradients, per-mode
+// The reductions after the chunk sums: phase-coefficient gradients, per-mode
 // angle and scale terms, and the five scalars.
 hipError_t launch_vjp_reduce(const Prepared& p, double* PZ, double* Upart, double* T3, double* gPhi_coef,
                              double* g_scalars, const int32_t* l, const int32_t* m, double theta, double phi,

@@ -282,9 +282,12 @@ def test_vjp_dense_draw_sampled_cotangent(ctx):
     _compare_with_oracle(out, ref, w.traj.t, f"draw {k} (M = {prms[k]['M']:.3g}), {w.Nm} rows, 2000 bins")
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 10, 14])
 def test_vjp_central_differences_on_forward_adjoint_draws(ctx, k):
-    """The first four draws of the forward+adjoint workload at full size (all
+    """The first four draws of the forward+adjoint workload, and draws 10
+    (M = 1.1e5: 1.8e9 group-bin evaluations, so chunks longer than the
+    minimum) and 14 (single (group, segment) units of hundreds of thousands
+    of bins, split into hundreds of chunks), at full size (all
     kept modes, whole grid): the Whittle log-likelihood of data = waveform at
     the draw + noise of the closed-form PSD, for a template with perturbed
     amplitudes, Phi_phi offset and inclination; each gradient group (amplitude
@@ -358,3 +361,25 @@ def test_vjp_central_differences_on_forward_adjoint_draws(ctx, k):
     gk = out["gPhi_knots"].cpu().numpy()
     for r in range(2):
         assert abs(gk[r].sum() - gsc[3 + r]) <= 1e-9 * np.abs(gk[r]).sum()
+
+
+def test_vjp_bitwise_repeatable_on_split_units(ctx):
+    """The adjoint's chunks go to whichever wave asks first, but every sum runs
+    in a fixed order: two calls on draw 10 of the forward+adjoint workload
+    (units split into many chunks, chunk size above the minimum) give the
+    same bits, in both precisions."""
+    w = _cfg5_draw(10)
+    dev = ctx.device
+    dw = fd.DeviceWaveform.from_workload(w, device=dev)
+    rng = np.random.default_rng(5)
+    g = rng.normal(size=(4, w.Nf))
+    gp = torch.as_tensor(g[0] + 1j * g[1], device=dev)
+    gc = torch.as_tensor(g[2] + 1j * g[3], device=dev)
+    for prec in ("fp64", "mixed"):
+        a = ctx.vjp_dev(dw, gp, gc, prec)
+        b = ctx.vjp_dev(dw, gp, gc, prec)
+        torch.cuda.synchronize()
+        assert ctx.sync_flags() == 0
+        for key in a:
+            assert torch.equal(a[key], b[key]), (prec, key)
+        assert bool(torch.isfinite(torch.view_as_real(a["gA_knots"])).all())
