@@ -398,7 +398,7 @@ def adjoint_measure(ctx, W, fd, dev, B):
         return adjoints()
 
     # warm-up pass: the forward's evaluation count, then the adjoints with
-    # their unit kernel bracketed
+    # their bin work (plan, scan, chunks, sums) bracketed
     ctx.waveform_batch(dws, "mixed", outs=mouts)
     evals = ctx.last_eval_count()
     group_evals = ctx.last_group_eval_count()
