@@ -70,8 +70,8 @@ hipError_t launch_loglike(const Prepared& p, const float* acoef32, bool mixed, i
                           hipStream_t stream);
 hipError_t launch_vjp_units(const Prepared& p, const float* acoef32, bool mixed, const void* g_hp, const void* g_hc,
                             double* gA_coef, double* PZ, double* Upart, int2* rng, int32_t* nb, int32_t* off,
-                            unsigned long long* ctl, double* mom, void* scan_tmp, size_t scan_bytes,
-                            hipStream_t stream);
+                            unsigned long long* ctl, int32_t* unit_of, double* mom, void* scan_tmp,
+                            size_t scan_bytes, hipStream_t stream);
 size_t vjp_scan_bytes(long units);
 hipError_t launch_vjp_reduce(const Prepared& p, double* PZ, double* Upart, double* T3, double* gPhi_coef,
                              double* g_scalars, const int32_t* l, const int32_t* m, double theta, double phi,
@@ -201,7 +201,7 @@ struct Layout {
   size_t tcoef, fac, acoef, acoef32, modes, modes32, mode_kr, pieces, evals, status, slots;
   size_t gkr, gsize, gmem, gmem32;  // voice groups
   size_t gA, PZ, Upart, T3, gPhi, gsc;  // adjoint scratch (0 bytes unless requested)
-  size_t vrng, vnb, voff, vctl, vscan, vmom, vscan_bytes;  // the adjoint's chunk plan
+  size_t vrng, vnb, voff, vctl, vscan, vunit, vmom, vscan_bytes;  // the adjoint's chunk plan
   size_t ll_partial, ll_edge;           // likelihood scratch (0 bytes unless requested)
   size_t total;
 };
@@ -249,7 +249,9 @@ Layout layout_for(int K, int Nm, bool mixed, bool vjp = false, int ll_tiles = 0,
   L.vctl = take(vjp ? 2 * sizeof(unsigned long long) : 0);
   L.vscan_bytes = vjp ? vjp_scan_bytes((long)units) : 0;
   L.vscan = take(L.vscan_bytes);
-  L.vmom = take(vjp ? (units + ((size_t)1 << 19)) * 20 * sizeof(double) : 0);
+  const size_t max_chunks = vjp ? units + ((size_t)1 << 19) : 0;
+  L.vunit = take(max_chunks * sizeof(int32_t));
+  L.vmom = take(max_chunks * 20 * sizeof(double));
   L.ll_partial = take(ll_partial * sizeof(double));
   L.ll_edge = take((size_t)ll_tiles * 16 * sizeof(double));
   L.total = off;
@@ -771,8 +773,8 @@ fdemri_status fdemri_vjp(fdemri_ctx* c, const fdemri_waveform_desc* d, fdemri_pr
     ProfScope ps(c, FDEMRI_KERNEL_VJP, stream);
     e = launch_vjp_units(p, acoef32, mixed, g_hp, g_hc, gA_coef, (double*)(w + L.PZ), (double*)(w + L.Upart),
                          (int2*)(w + L.vrng), (int32_t*)(w + L.vnb), (int32_t*)(w + L.voff),
-                         (unsigned long long*)(w + L.vctl), (double*)(w + L.vmom), w + L.vscan, L.vscan_bytes,
-                         stream);
+                         (unsigned long long*)(w + L.vctl), (int32_t*)(w + L.vunit), (double*)(w + L.vmom),
+                         w + L.vscan, L.vscan_bytes, stream);
   }
   if (e == hipSuccess)
     e = launch_vjp_reduce(p, (double*)(w + L.PZ), (double*)(w + L.Upart), (double*)(w + L.T3), gPhi_coef, gsc, d->l,

@@ -90,8 +90,9 @@ __device__ __forceinline__ double wave_sum16(const double v[16]) {
 // in segment i of one of its pieces, and their count varies by orders of
 // magnitude (a fast chirp's last segments hold most bins).  The plan kernel
 // finds each unit's bin range per piece, the scan gives each unit a run of
-// fixed-size chunks of its (piece-concatenated) bins, the chunk kernel hands
-// the chunks out to the waves through a counter, and the finish kernel sums
+// fixed-size chunks of its (piece-concatenated) bins and a map records each
+// chunk's unit, the chunk kernel hands the chunks out to the waves through a
+// counter, and the finish kernel sums
 // each unit's chunks in chunk order and forms every row's terms.
 //
 // The rows of a group share the pieces, roots and E, so a chunk forms, per
@@ -112,7 +113,7 @@ __device__ __forceinline__ double wave_sum16(const double v[16]) {
 
 // bins per chunk: at least kVjpMinChunkIters passes of the wave, and so many
 // that the chunks number at most the units plus kVjpChunkCap
-constexpr int kVjpMinChunkIters = 16;
+constexpr int kVjpMinChunkIters = 32;
 constexpr long long kVjpChunkCap = 1 << 19;
 constexpr int kVjpMom = 20;  // doubles per chunk: Qp (8), Qx (8), s h^k Y_k (4)
 
@@ -127,6 +128,7 @@ struct VjpPlan {
   int32_t* nb;               // [Nm * nseg] bins of the unit over its pieces (0: no work, not a group's unit)
   int32_t* off;              // [Nm * nseg] first chunk of the unit (exclusive scan of the chunk counts)
   unsigned long long* ctl;   // [0] bins of all units, [1] the next chunk to hand out
+  int32_t* unit_of;          // [chunks] the unit of each chunk
   double* mom;               // [chunks][kVjpMom]
 };
 
@@ -191,6 +193,15 @@ __global__ __launch_bounds__(256) void vjp_plan_kernel(Prepared p, VjpPlan v) {
   if ((threadIdx.x & 63) == 0 && total) atomicAdd(&v.ctl[0], (unsigned long long)total);
 }
 
+// One thread per unit: its chunks' entries of the chunk-to-unit map.
+__global__ __launch_bounds__(256) void vjp_map_kernel(int U, VjpPlan v) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= U) return;
+  const int nc = vjp_chunks(v.nb[u], vjp_chunk_bins(v.ctl[0]));
+  const int o = v.off[u];
+  for (int k = 0; k < nc; ++k) v.unit_of[o + k] = u;
+}
+
 // Occupancy target in waves per SIMD: the mixed adjoint fits 4; the FP64 one
 // would spill inside the bin loop and stays at 3.
 template <bool MIXED>
@@ -220,14 +231,7 @@ __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_chunk_kernel(
     if (lane == 0) c0 = (int)atomicAdd(&v.ctl[1], 1ull);
     const int c = __builtin_amdgcn_readfirstlane(__shfl(c0, 0, 64));
     if (c >= T) break;
-    // the unit: the last with off <= c (units without chunks share the next one's offset)
-    int lo = 0, hi = U;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (koff[mid] <= c) lo = mid;
-      else hi = mid;
-    }
-    const int u = lo;
+    const int u = ((const kconst int32_t*)v.unit_of)[c];
     const int b0 = (c - koff[u]) * ch, b1 = b0 + ch;  // the chunk in the unit's concatenated bins
     const int j = u / nseg, i = u % nseg;
     const int g = grouped ? ((const kconst int32_t*)p.gsize)[j] : 1;
@@ -714,8 +718,8 @@ size_t vjp_scan_bytes(long units) {
 // into gA_coef, PZ and Upart.
 hipError_t launch_vjp_units(const Prepared& p, const float* acoef32, bool mixed, const void* g_hp, const void* g_hc,
                             double* gA_coef, double* PZ, double* Upart, int2* rng, int32_t* nb, int32_t* off,
-                            unsigned long long* ctl, double* mom, void* scan_tmp, size_t scan_bytes,
-                            hipStream_t stream) {
+                            unsigned long long* ctl, int32_t* unit_of, double* mom, void* scan_tmp,
+                            size_t scan_bytes, hipStream_t stream) {
   VjpArgs a;
   a.p = p;
   a.acoef32 = acoef32;
@@ -724,7 +728,7 @@ hipError_t launch_vjp_units(const Prepared& p, const float* acoef32, bool mixed,
   a.gA = gA_coef;
   a.PZ = PZ;
   a.Upart = Upart;
-  VjpPlan v{rng, nb, off, ctl, mom};
+  VjpPlan v{rng, nb, off, ctl, unit_of, mom};
   const int nseg = p.K - 1;
   const long units = (long)p.Nm * nseg;
   vjp_plan_zero_kernel<<<1, 1, 0, stream>>>(ctl);
@@ -735,6 +739,7 @@ hipError_t launch_vjp_units(const Prepared& p, const float* acoef32, bool mixed,
   size_t bytes = scan_bytes;
   e = rocprim::exclusive_scan(scan_tmp, bytes, in, off, 0, (size_t)units, rocprim::plus<int>(), stream);
   if (e != hipSuccess) return e;
+  vjp_map_kernel<<<(unsigned)((units + 255) / 256), 256, 0, stream>>>((int)units, v);
   // as many waves as the device holds at the kernel's occupancy; the chunks
   // are handed out, so more would only find the counter exhausted
   int dev = 0, ncu = 0;
