@@ -42,10 +42,11 @@ FLOPS_PER_EVAL = 154
 # ungrouped tables it equals the mode-bin count.
 # The adjoint per (voice group, piece, bin): the shared forward terms (root,
 # derivatives, factor, phase and E: 120), the products conj(g) E for both
-# polarizations (12), the two combined amplitude cubics (24), Im Z (8) and
-# the moment sums over four powers of u = tau / h (36); every row's gradient
-# terms follow from the moments once per (row, segment), not per bin.
-ADJ_FLOPS_PER_GROUP_EVAL = 200
+# polarizations with their sign fold (14), u = tau / h and its powers to u^6
+# (6), and the moment sums of four values over seven powers of u (52); the
+# group's Im Z sums and every row's gradient terms follow from the moments
+# once per (group, segment), not per bin.
+ADJ_FLOPS_PER_GROUP_EVAL = 192
 PEAK_FP64_VALU = 78.6e12
 
 

@@ -98,16 +98,17 @@ __device__ __forceinline__ double wave_sum16(const double v[16]) {
 // The rows of a group share the pieces, roots and E, so a chunk forms, per
 // piece, the moments
 //   Mp_k = sum over bins of u^k conj(g_+) E,  Mx_k = sum u^k conj(g_x) E,
-//   Y_k  = sum u^k Im Z,  Z = conj(g_+) Cp(u)^(s) E + conj(g_x) Cx(u)^(s) E,
-// u = tau / h, k = 0..3, with Cp(u) = sum_t c_+,t A_t (Cx likewise) the
-// group's combined amplitude, and stores them sign-folded,
-//   Qp_k = conj(Mp_k) (s > 0), Mp_k (s < 0),  Qx_k likewise,  s h^k Y_k,
+// u = tau / h, k = 0..6, and stores them sign-folded,
+//   Qp_k = conj(Mp_k) (s > 0), Mp_k (s < 0),  Qx_k likewise,
 // so that they add across pieces and chunks and every row's terms follow
 // from the sums (a the row's amplitude coefficients in u, a^_j = a_j h^j,
 // c its factors):
 //   dL/da_k = h^k (conj(c_+) Qp_k + conj(c_x) Qx_k),
-//   U_+ = sum_j a^_j conj(Qp_j),  U_x = sum_j a^_j conj(Qx_j),
-// and the group's sum s tau^k Im Z is the summed s h^k Y_k.  Outputs per row
+//   U_+ = sum_j a^_j conj(Qp_j),  U_x = sum_j a^_j conj(Qx_j)   (k, j = 0..3),
+// and the group's sum s tau^k Im Z, Z = conj(g_+) Cp(u)^(s) E + conj(g_x)
+// Cx(u)^(s) E with Cp(u) = sum_j Cp_j u^j = sum_t c_+,t A_t(u) (Cx likewise)
+// the group's combined amplitude, is
+//   s sum u^k Im Z = -h^k sum_j Im(conj(Cp_j) Qp_{j+k} + conj(Cx_j) Qx_{j+k}).  Outputs per row
 // of the group: gA (8), Upart (4) and PZ (4; the group's sum at its first
 // row, zero at the others, since the phase gradient sums m PZ over the rows).
 
@@ -115,7 +116,7 @@ __device__ __forceinline__ double wave_sum16(const double v[16]) {
 // that the chunks number at most the units plus kVjpChunkCap
 constexpr int kVjpMinChunkIters = 32;
 constexpr long long kVjpChunkCap = 1 << 19;
-constexpr int kVjpMom = 20;  // doubles per chunk: Qp (8), Qx (8), s h^k Y_k (4)
+constexpr int kVjpMom = 28;  // doubles per chunk: Qp_0..6 (14), Qx_0..6 (14)
 
 __device__ __forceinline__ int vjp_chunk_bins(unsigned long long bins) {
   const unsigned long long per = (bins + 64ull * kVjpChunkCap - 1) / (64ull * kVjpChunkCap);
@@ -213,12 +214,10 @@ constexpr int vjp_min_waves() {
 // each writes its sign-folded moments (kVjpMom doubles).
 template <bool MIXED>
 __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_chunk_kernel(VjpArgs a, VjpPlan v) {
-  // each wave's combined coefficients Cp, Cx in u (re, im per power)
-  __shared__ double comb[4][16];
   const Prepared& p = a.p;
   const int nseg = p.K - 1;
   const int U = p.Nm * nseg;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
   const int ch = vjp_chunk_bins(*(const kconst unsigned long long*)v.ctl);
   const kconst int32_t* koff = (const kconst int32_t*)v.off;
   const int T = koff[U - 1] + vjp_chunks(((const kconst int32_t*)v.nb)[U - 1], ch);
@@ -248,34 +247,9 @@ __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_chunk_kernel(
     const kconst double* cPr = (const kconst double*)p.tcoef + ((size_t)3 * nseg + i) * 4;
     const double Ppr = reduce_2pi(((const kconst double*)p.Phiphi)[i]);
     const double Prr = reduce_2pi(((const kconst double*)p.Phir)[i]);
-    const double hp[4] = {1.0, h, h * h, h * h * h};
-
-    // the group's combined coefficients, in row order (the previous chunk's
-    // reads of comb are done before it is overwritten)
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    double cv = 0.0;
-    const int k16 = (lane & 7) >> 1;  // this lane's power of u
-    const double hk = k16 == 0 ? 1.0 : k16 == 1 ? h : k16 == 2 ? h * h : h * h * h;
-    for (int t = 0; t < g; ++t) {
-      const int row = grouped ? gm[t].mode : j;
-      if (lane < 16) {
-        const ModeConst& mt = p.modes[row];
-        const int k = k16;
-        const double* ac = p.acoef + ((size_t)row * nseg + i) * 8 + 2 * k;
-        const double ar = ac[0] * hk, ai = ac[1] * hk;
-        const double cr = lane < 8 ? mt.cp_re : mt.cx_re, ci = lane < 8 ? mt.cp_im : mt.cx_im;
-        cv += (lane & 1) ? cr * ai + ci * ar : cr * ar - ci * ai;
-      }
-    }
-    if (lane < 16) comb[wave][lane] = cv;  // read by the same wave after the fence below
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const double* cb = comb[wave];
 
     // moments, sign-folded per piece as they are added: acc[2k], acc[2k+1] =
-    // Qp_k; acc[8 + 2k], acc[9 + 2k] = Qx_k; acc[16 + k] = s Y_k (h^k applied
-    // by the sums)
+    // Qp_k; acc[14 + 2k], acc[15 + 2k] = Qx_k
     double acc[kVjpMom];
 #pragma unroll
     for (int r = 0; r < kVjpMom; ++r) acc[r] = 0.0;
@@ -349,34 +323,29 @@ __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_chunk_kernel(
         double kpr = gpr * Er + gpi * Ei, kpi = sc * (gpi * Er - gpr * Ei);
         double kxr = gcr * Er + gci * Ei, kxi = sc * (gci * Er - gcr * Ei);
         const double uu = tau * ih;
-        // the combined amplitudes at u
-        const double apr = cb[0] + uu * (cb[2] + uu * (cb[4] + uu * cb[6]));
-        const double api = cb[1] + uu * (cb[3] + uu * (cb[5] + uu * cb[7]));
-        const double axr = cb[8] + uu * (cb[10] + uu * (cb[12] + uu * cb[14]));
-        const double axi = cb[9] + uu * (cb[11] + uu * (cb[13] + uu * cb[15]));
-        // s Im Z, Z = conj(g_+) Cp^(s) E + conj(g_x) Cx^(s) E
-        double imz = (kpr * api + kxr * axi) - (kpi * apr + kxi * axr);
+        double up[7];
+        up[0] = 1.0;
+        up[1] = uu;
+        up[2] = uu * uu;
+        up[3] = up[2] * uu;
+        up[4] = up[2] * up[2];
+        up[5] = up[4] * uu;
+        up[6] = up[3] * up[3];
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          acc[2 * kk] += kpr;
-          acc[2 * kk + 1] += kpi;
-          acc[8 + 2 * kk] += kxr;
-          acc[9 + 2 * kk] += kxi;
-          acc[16 + kk] += imz;
-          kpr *= uu;
-          kpi *= uu;
-          kxr *= uu;
-          kxi *= uu;
-          imz *= uu;
+        for (int kk = 0; kk < 7; ++kk) {
+          acc[2 * kk] += kpr * up[kk];
+          acc[2 * kk + 1] += kpi * up[kk];
+          acc[14 + 2 * kk] += kxr * up[kk];
+          acc[15 + 2 * kk] += kxi * up[kk];
         }
       }
     }
-    // the wave's totals; lane r < 20 stores moment r
+    // the wave's totals; lane r < kVjpMom stores moment r
     double lo16[16], hi16[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       lo16[r] = acc[r];
-      hi16[r] = r < 4 ? acc[16 + r] : 0.0;
+      hi16[r] = r < kVjpMom - 16 ? acc[16 + r] : 0.0;
     }
     const double tl = wave_sum16(lo16), th = wave_sum16(hi16);
     const int src = (lane < 16 ? lane : lane - 16) * 4;
@@ -416,17 +385,48 @@ __global__ __launch_bounds__(256) void vjp_finish_kernel(VjpArgs a, VjpPlan v) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     lo16[r] = sm[r];
-    hi16[r] = r < 4 ? sm[16 + r] : 0.0;
+    hi16[r] = r < kVjpMom - 16 ? sm[16 + r] : 0.0;
   }
   const double tl = wave_sum16(lo16), th = wave_sum16(hi16);
-  double Q[16], Z[4];
+  // Q[2k], Q[2k+1] = Qp_k; Q[14 + 2k], Q[15 + 2k] = Qx_k (k = 0..6)
+  double Q[kVjpMom];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) Q[r] = __shfl(tl, r * 4, 64);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) Z[k] = __shfl(th, k * 4, 64);
+  for (int r = 0; r < kVjpMom; ++r) Q[r] = r < 16 ? __shfl(tl, r * 4, 64) : __shfl(th, (r - 16) * 4, 64);
   const kconst double* kt = (const kconst double*)p.t;
   const double h = kt[i + 1] - kt[i];
   const double hp[4] = {1.0, h, h * h, h * h * h};
+  // the group's combined coefficients in u (Cp_j, Cx_j: re, im), in row order,
+  // and Z[k] = s sum u^k Im Z over the unit's bins
+  double Z[4] = {0.0, 0.0, 0.0, 0.0};
+  if (nc > 0) {
+    double C[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) C[r] = 0.0;
+    const kconst double* kac = (const kconst double*)p.acoef;
+    for (int t = 0; t < g; ++t) {
+      const int row = grouped ? gm[t].mode : j;
+      const ModeConst mt = ((const kconst ModeConst*)p.modes)[row];
+      const kconst double* ac = kac + ((size_t)row * nseg + i) * 8;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double ar = ac[2 * k] * hp[k], ai = ac[2 * k + 1] * hp[k];
+        C[2 * k] += mt.cp_re * ar - mt.cp_im * ai;
+        C[2 * k + 1] += mt.cp_re * ai + mt.cp_im * ar;
+        C[8 + 2 * k] += mt.cx_re * ar - mt.cx_im * ai;
+        C[9 + 2 * k] += mt.cx_re * ai + mt.cx_im * ar;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int q = jj + k;
+        // -Im(conj(C) Q) = C.im Q.re - C.re Q.im
+        Z[k] += C[2 * jj + 1] * Q[2 * q] - C[2 * jj] * Q[2 * q + 1];
+        Z[k] += C[9 + 2 * jj] * Q[14 + 2 * q] - C[8 + 2 * jj] * Q[15 + 2 * q];
+      }
+    }
+  }
   for (int t = lane; t < g; t += 64) {
     const int row = grouped ? gm[t].mode : j;
     const size_t uo = (size_t)row * nseg + i;
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(256) void vjp_finish_kernel(VjpArgs a, VjpPlan v) {
     if (a.gA) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const double qpr = Q[2 * k], qpi = Q[2 * k + 1], qxr = Q[8 + 2 * k], qxi = Q[9 + 2 * k];
+        const double qpr = Q[2 * k], qpi = Q[2 * k + 1], qxr = Q[14 + 2 * k], qxi = Q[15 + 2 * k];
         // conj(c_+) Qp + conj(c_x) Qx
         const double vr = mt.cp_re * qpr + mt.cp_im * qpi + mt.cx_re * qxr + mt.cx_im * qxi;
         const double vi = mt.cp_re * qpi - mt.cp_im * qpr + mt.cx_re * qxi - mt.cx_im * qxr;
@@ -464,8 +464,8 @@ __global__ __launch_bounds__(256) void vjp_finish_kernel(VjpArgs a, VjpPlan v) {
       const double ar = ac[2 * k] * hp[k], ai = ac[2 * k + 1] * hp[k];
       upr += ar * Q[2 * k] + ai * Q[2 * k + 1];
       upi += ai * Q[2 * k] - ar * Q[2 * k + 1];
-      uxr += ar * Q[8 + 2 * k] + ai * Q[9 + 2 * k];
-      uxi += ai * Q[8 + 2 * k] - ar * Q[9 + 2 * k];
+      uxr += ar * Q[14 + 2 * k] + ai * Q[15 + 2 * k];
+      uxi += ai * Q[14 + 2 * k] - ar * Q[15 + 2 * k];
     }
     a.Upart[uo * 4 + 0] = upr;
     a.Upart[uo * 4 + 1] = upi;
