@@ -73,6 +73,8 @@ hipError_t launch_vjp_units(const Prepared& p, const float* acoef32, bool mixed,
                             unsigned long long* ctl, int32_t* unit_of, double* mom, void* scan_tmp,
                             size_t scan_bytes, hipStream_t stream);
 size_t vjp_scan_bytes(long units);
+long vjp_max_chunks(long units);
+size_t vjp_mom_bytes(long units);
 hipError_t launch_vjp_reduce(const Prepared& p, double* PZ, double* Upart, double* T3, double* gPhi_coef,
                              double* g_scalars, const int32_t* l, const int32_t* m, double theta, double phi,
                              double scale, uint32_t flags, hipStream_t stream);
@@ -241,17 +243,16 @@ Layout layout_for(int K, int Nm, bool mixed, bool vjp = false, int ll_tiles = 0,
   L.gPhi = take(vjp ? 2 * nseg * 4 * sizeof(double) : 0);
   L.gsc = take(vjp ? 8 * sizeof(double) : 0);
   // the chunk plan: per unit its pieces' bin ranges, bins and first chunk;
-  // the chunks number at most the units plus 2^19 (the chunk size grows with
-  // the total bins), each holding 20 doubles
+  // per chunk its unit and moments (at most vjp_max_chunks chunks)
   L.vrng = take(units * kMaxPieces * sizeof(int2));
   L.vnb = take(units * sizeof(int32_t));
   L.voff = take(units * sizeof(int32_t));
   L.vctl = take(vjp ? 2 * sizeof(unsigned long long) : 0);
   L.vscan_bytes = vjp ? vjp_scan_bytes((long)units) : 0;
   L.vscan = take(L.vscan_bytes);
-  const size_t max_chunks = vjp ? units + ((size_t)1 << 19) : 0;
+  const size_t max_chunks = vjp ? (size_t)vjp_max_chunks((long)units) : 0;
   L.vunit = take(max_chunks * sizeof(int32_t));
-  L.vmom = take(max_chunks * 20 * sizeof(double));
+  L.vmom = take(vjp ? vjp_mom_bytes((long)units) : 0);
   L.ll_partial = take(ll_partial * sizeof(double));
   L.ll_edge = take((size_t)ll_tiles * 16 * sizeof(double));
   L.total = off;

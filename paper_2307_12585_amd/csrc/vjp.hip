@@ -706,6 +706,11 @@ __global__ __launch_bounds__(NT) void spline_adjoint_kernel(int K, const double*
   }
 }
 
+// The most chunks a call can have (units plus kVjpChunkCap: the chunk size
+// grows with the total bins to keep within it) and the bytes of their moments.
+long vjp_max_chunks(long units) { return units + kVjpChunkCap; }
+size_t vjp_mom_bytes(long units) { return (size_t)vjp_max_chunks(units) * kVjpMom * sizeof(double); }
+
 // Bytes of device scratch the chunk-offset scan needs for `units` units.
 size_t vjp_scan_bytes(long units) {
   size_t bytes = 0;
