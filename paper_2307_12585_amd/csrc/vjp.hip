@@ -354,37 +354,46 @@ __global__ __launch_bounds__(256, vjp_min_waves<MIXED>()) void vjp_chunk_kernel(
   }
 }
 
-// One thread per unit: its chunks' moments summed in chunk order, then every
-// row's terms.  Every row of the group is written (its other rows have no
-// unit of their own).
+// One wave per unit: its chunks' moments summed in chunk order (lane L takes
+// chunks L, L + 64, ..., then a fixed-order wave sum), then every row's terms,
+// one row per lane.  Every row of the group is written (its other rows have
+// no unit of their own).
 __global__ __launch_bounds__(256) void vjp_finish_kernel(VjpArgs a, VjpPlan v) {
   const Prepared& p = a.p;
   const int nseg = p.K - 1;
-  const long unit = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const long unit = (long)blockIdx.x * 4 + wave;
   if (unit >= (long)p.Nm * nseg) return;
   const int u = (int)unit;
   const int j = u / nseg, i = u % nseg;
   const bool grouped = p.gsize != nullptr;
-  const int g = grouped ? p.gsize[j] : 1;
+  const int g = grouped ? ((const kconst int32_t*)p.gsize)[j] : 1;
   if (g == 0) return;
-  const GroupMember* gm = grouped ? p.gmem + j : nullptr;
+  const kconst GroupMember* gm = grouped ? (const kconst GroupMember*)p.gmem + j : nullptr;
   const int ch = vjp_chunk_bins(*(const kconst unsigned long long*)v.ctl);
-  const int nc = vjp_chunks(v.nb[u], ch);
-  const size_t c0 = (size_t)v.off[u];
+  const int nc = vjp_chunks(((const kconst int32_t*)v.nb)[u], ch);
+  const size_t c0 = (size_t)((const kconst int32_t*)v.off)[u];
+  double sm[kVjpMom];
+#pragma unroll
+  for (int r = 0; r < kVjpMom; ++r) sm[r] = 0.0;
+  for (int c = lane; c < nc; c += 64) {
+    const double* mc = v.mom + (c0 + c) * kVjpMom;
+#pragma unroll
+    for (int r = 0; r < kVjpMom; ++r) sm[r] += mc[r];
+  }
+  double lo16[16], hi16[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    lo16[r] = sm[r];
+    hi16[r] = r < kVjpMom - 16 ? sm[16 + r] : 0.0;
+  }
+  const double tl = wave_sum16(lo16), th = wave_sum16(hi16);
   // Q[2k], Q[2k+1] = Qp_k; Q[14 + 2k], Q[15 + 2k] = Qx_k (k = 0..6)
   double Q[kVjpMom];
 #pragma unroll
-  for (int r = 0; r < kVjpMom; ++r) Q[r] = 0.0;
-  for (int c = 0; c < nc; ++c) {
-    const double2* mc = (const double2*)(v.mom + (c0 + c) * kVjpMom);
-#pragma unroll
-    for (int r = 0; r < kVjpMom / 2; ++r) {
-      const double2 x = mc[r];
-      Q[2 * r] += x.x;
-      Q[2 * r + 1] += x.y;
-    }
-  }
-  const double h = p.t[i + 1] - p.t[i];
+  for (int r = 0; r < kVjpMom; ++r) Q[r] = r < 16 ? __shfl(tl, r * 4, 64) : __shfl(th, (r - 16) * 4, 64);
+  const kconst double* kt = (const kconst double*)p.t;
+  const double h = kt[i + 1] - kt[i];
   const double hp[4] = {1.0, h, h * h, h * h * h};
   // the group's combined coefficients in u (Cp_j, Cx_j: re, im), in row order,
   // and Z[k] = s sum u^k Im Z over the unit's bins
@@ -393,10 +402,11 @@ __global__ __launch_bounds__(256) void vjp_finish_kernel(VjpArgs a, VjpPlan v) {
     double C[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) C[r] = 0.0;
+    const kconst double* kac = (const kconst double*)p.acoef;
     for (int t = 0; t < g; ++t) {
       const int row = grouped ? gm[t].mode : j;
-      const ModeConst mt = p.modes[row];
-      const double* ac = p.acoef + ((size_t)row * nseg + i) * 8;
+      const ModeConst mt = ((const kconst ModeConst*)p.modes)[row];
+      const kconst double* ac = kac + ((size_t)row * nseg + i) * 8;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const double ar = ac[2 * k] * hp[k], ai = ac[2 * k + 1] * hp[k];
@@ -417,7 +427,7 @@ __global__ __launch_bounds__(256) void vjp_finish_kernel(VjpArgs a, VjpPlan v) {
       }
     }
   }
-  for (int t = 0; t < g; ++t) {
+  for (int t = lane; t < g; t += 64) {
     const int row = grouped ? gm[t].mode : j;
     const size_t uo = (size_t)row * nseg + i;
     if (nc == 0) {
@@ -745,7 +755,7 @@ hipError_t launch_vjp_units(const Prepared& p, const float* acoef32, bool mixed,
     vjp_chunk_kernel<true><<<(unsigned)(ncu * vjp_min_waves<true>()), 256, 0, stream>>>(a, v);
   else
     vjp_chunk_kernel<false><<<(unsigned)(ncu * vjp_min_waves<false>()), 256, 0, stream>>>(a, v);
-  vjp_finish_kernel<<<(unsigned)((units + 255) / 256), 256, 0, stream>>>(a, v);
+  vjp_finish_kernel<<<(unsigned)((units + 3) / 4), 256, 0, stream>>>(a, v);
   return hipGetLastError();
 }
 
